@@ -1,0 +1,48 @@
+"""The pins must be able to fail: plant plausible mistakes in a copy of the oracle, on the CPU,
+and check that the pin suite rejects every one of them."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, snippet of the oracle, planted mistake); every snippet must occur exactly once
+MUTANTS = [
+    ("idw_inverse_square", "double w = 1.0 / v_norm(e);", "double w = 1.0 / v_dot(e, e);"),
+    ("cut_from_wrong_end", "double lam = (iso - aw) / (ad - aw);", "double lam = (iso - ad) / (aw - ad);"),
+    ("printed_aplus2", "return sw->c1 + sw->c2 * (1.0 - q * q);",
+     "return sw->c1 + sw->c2 * (1.0 - (1.0 - q) * (1.0 - q));"),
+    ("first_piece_integral_factor", "I += sw->c1 * (b - a) * (ra * ra + ra * rb + rb * rb) / 3.0;",
+     "I += sw->c1 * (b - a) * (ra * ra + ra * rb + rb * rb) / 2.0;"),
+    ("no_dry_fraction_for_receding_plane", "return un > 0 ? I : dt - I;", "return I;"),
+    ("update_sign", "sum += m->ce_sign[e] * dV[m->ce_flux[e]];", "sum -= m->ce_sign[e] * dV[m->ce_flux[e]];"),
+    ("bulk_flux_ignores_alpha", "dV[fid] = alpha[c] * ph * dt;", "dV[fid] = ph * dt;"),
+    ("x41_ratio_inverted", "double r = v_dot(x21, nS) / v_dot(x31, nS);",
+     "double r = v_dot(x31, nS) / v_dot(x21, nS);"),
+    ("equal_triangle_weights", "double Ai = 0.5 * v_norm(cr);", "double Ai = 0.5;"),
+    ("isoface_centre_is_vertex_mean", "for (int d = 0; d < 3; ++d) out->xS[d] = xs[d] / wsum;",
+     "for (int d = 0; d < 3; ++d) out->xS[d] = o[d] + 0.0 * xs[d] / wsum;"),
+    ("isoface_edges_reversed",
+     "for (int d = 0; d < 3; ++d) { seg_a[nseg][d] = cp[d]; seg_b[nseg][d] = last_exit[d]; }",
+     "for (int d = 0; d < 3; ++d) { seg_b[nseg][d] = cp[d]; seg_a[nseg][d] = last_exit[d]; }"),
+    ("velocity_components_swapped", "double Uc[3] = {U[c], U[nc + c], U[2 * nc + c]};",
+     "double Uc[3] = {U[c], U[2 * nc + c], U[nc + c]};"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_reject_planted_mistake(tmp_path, name, old, new):
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, f"snippet for mutant {name} no longer matches the oracle"
+    mutant_src = tmp_path / "mutant.c"
+    mutant_src.write_text(src.replace(old, new))
+    lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
