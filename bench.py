@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X isoAdvector step (FP64 cell-steps/s) with a roofline line.
+
+Default workload: the 3D graded 256x128x128 hexahedral box (4.19M cells) with a water column
+plus a 3D wave, advected by a uniform stream plus a Taylor-Green vortex at Courant 0.5,
+100 steps (synthetic inputs from wavegen, generated on the host, uploaded before timing).
+
+Prints ONE JSON line.  Fields beyond the basic contract:
+  roofline      dominant kernel: algorithmic bytes (or flops) per launch / mean launch time,
+                measured with HIP events recorded around each kernel on the step's stream
+                during the timed steps; traffic from committed rocprofv3 counters when they
+                belong to the current kernel source, else null
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the same workload
+  step_roofline the whole step's algorithmic bytes per cell-step x cell-steps/s / 8 TB/s
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 isoAdvector cell-steps/s + % HBM roofline; batched vs plain; adjoint/fwd ratio"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+KERNEL_SRC = os.path.join(ROOT, "paper_1804_01130_amd", "csrc", "kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    import wavegen as W
+    if name == "violent_3d":
+        return W.violent_3d()
+    if name == "airy_2d":
+        return W.airy_1024x256()
+    if name == "cosine_2d":
+        return W.cosine_uniform()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def committed_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+    path = os.path.join(PROFILES, f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def algorithmic(kernel, mesh_info, n_surface, n_flux, n_cells):
+    """(quantity per launch, unit, bound) of each kernel's compulsory work; see the design doc."""
+    if kernel == "update":
+        # alpha, V read + alpha_new written (8 B each) per cell; per flux face phi (8 B) and the
+        # owner/neighbour pair (2 x 4 B); dV of interface-upwind faces (8 B, <= 6 per interface cell)
+        return (24.0 * n_cells + 16.0 * n_flux + 8.0 * 3 * n_surface), "GB/s", "hbm"
+    if kernel == "find_surface":
+        return (8.0 * n_cells + 4.0 * n_surface), "GB/s", "hbm"
+    if kernel == "surface":
+        return None, None, "alu"
+    return None, None, "hbm"
+
+
+def step_bytes_per_cell(n_cells, n_flux, n_surface):
+    """Algorithmic bytes of one whole step per cell: alpha in/out, V, phi and connectivity per flux
+    face, and ~1.1 KB per interface cell (vertex stencils, coordinates, velocity, face writes)."""
+    return (24.0 * n_cells + 16.0 * n_flux + 1100.0 * n_surface) / n_cells
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The oracle as it stands on a bounded number of steps of the same workload."""
+    from oracle import oracle as O
+    O.build()
+    om = O.OracleMesh(w.mesh)
+    phi, U = w.phi_U(0)
+    a = np.array(w.alpha0, copy=True)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        if not w.steady:
+            phi, U = w.phi_U(steps)
+        a, _ = om.step(a, phi, U, w.dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= w.n_steps or el / steps * (steps + 1) > 1.5 * budget_s:
+            break
+    return {"value": w.mesh.n_cells * steps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} of {w.n_steps} steps of the same workload, single thread, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="violent_3d", choices=["violent_3d", "airy_2d", "cosine_2d"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step has no multi-GPU path in this "
+              f"build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1804_01130_amd import Mesh, Plan
+
+    t0 = time.time()
+    w = build_workload(args.workload)
+    log(f"[bench] workload {w.name}: {w.mesh.n_cells} cells, generated in {time.time() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    gm = Mesh.from_arrays(w.mesh)
+    info = gm.info()
+    plan = Plan(gm)
+    n_steps_total = args.warmup + args.steps
+    if w.steady:
+        phi, U = w.phi_U(0)
+        phis = [torch.tensor(phi, device=dev)]
+        Us = [torch.tensor(U, device=dev)]
+    else:
+        phis, Us = [], []
+        for n in range(n_steps_total):
+            phi, U = w.phi_U(n)
+            phis.append(torch.tensor(phi, device=dev))
+            Us.append(torch.tensor(U, device=dev))
+    a = torch.tensor(w.alpha0, device=dev)
+    b = torch.empty_like(a)
+    sel = (lambda n: 0) if w.steady else (lambda n: n)
+    for n in range(args.warmup):
+        plan.step(a, phis[sel(n)], Us[sel(n)], w.dt, out=b)
+        a, b = b, a
+    _, st = plan.step(a, phis[sel(args.warmup)], Us[sel(args.warmup)], w.dt, out=b, stats=True)
+    n_surface = st["n_surface"]
+    plan.set_timing(args.steps)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for n in range(args.warmup, n_steps_total):
+        plan.step(a, phis[sel(n)], Us[sel(n)], w.dt, out=b)
+        a, b = b, a
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kms, nrec = plan.timing()
+    ms_per_step = ms / args.steps
+    cells = w.mesh.n_cells
+    value = cells * args.steps / (ms * 1e-3)
+    log(f"[bench] {args.steps} steps in {ms:.3f} ms ({ms_per_step * 1e3:.1f} us/step); kernels (ms total): "
+        + ", ".join(f"{k} {v:.3f}" for k, v in kms.items()))
+
+    # dominant kernel and its roofline
+    dom = max(kms, key=kms.get)
+    mean_s = kms[dom] / max(nrec, 1) * 1e-3
+    n_flux = info["n_flux_faces"]
+    q, unit, bound = algorithmic(dom, info, n_surface, n_flux, cells)
+    if bound == "hbm" and q is not None:
+        achieved = q / mean_s / 1e9
+        peak = HBM_PEAK_GBS
+        traffic = committed_traffic(dom, args.workload)
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s",
+                "frac": achieved / peak, "traffic": traffic, "mean_launch_us": mean_s * 1e6,
+                "algorithmic_bytes_per_launch": q}
+    else:
+        roof = {"kernel": dom, "bound": bound, "achieved": None, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": None, "traffic": None, "mean_launch_us": mean_s * 1e6}
+    b_alg = step_bytes_per_cell(cells, n_flux, n_surface)
+    step_frac = b_alg * value / (HBM_PEAK_GBS * 1e9)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a sample of the same workload")
+        cpu = cpu_baseline(w, args.cpu_budget)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "cells": cells, "flux_faces": n_flux, "interface_cells": n_surface,
+                   "courant": 0.5 if args.workload != "cosine_2d" else 0.25, "dt": w.dt},
+        "roofline": roof,
+        "step_roofline": {"bytes_per_cell_step": b_alg, "achieved_GBs": b_alg * value / 1e9,
+                          "frac": step_frac},
+        "kernel_ms_per_step": {k: v / max(nrec, 1) for k, v in kms.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

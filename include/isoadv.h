@@ -1,0 +1,153 @@
+/*
+ * isoadv.h — C interface of the MI355X (gfx950) isoAdvector advection step.
+ *
+ * The operation (Vukcevic, Roenby, Gatin & Jasak, "A sharp free surface finite
+ * volume method applied to gravity wave flows", Section 3.2, problem statement):
+ * from the cell volume fractions alpha_P(t), the cell velocities U_P and the
+ * volumetric face fluxes phi_f, predict alpha_P(t + dt) by the flux-form update
+ *     alpha_P(t+dt) = alpha_P(t) - (1/V_P) sum_f dV_f,
+ * where dV_f = phi_f * (time integral over the step of the submerged area
+ * fraction of face f) is obtained by sweeping the upwind interface cell's
+ * isoface across the face (Eqs. dV, alphaf, tv, x_41, aplus1, aplus2,
+ * intaplus), and dV_f = alpha_upwind * phi_f * dt when the upwind cell is not an
+ * interface cell (the special cases after Eq. dVdef).  The isoface of a cell is
+ * the isosurface of the vertex-interpolated volume fraction (inverse
+ * centre-to-vertex distance weights) whose sub-cell volume equals alpha_P V_P.
+ * A bounding step (volume-preserving redistribution, then optional chopping to
+ * [0,1]) ends the step (last paragraph of Section 3.2).
+ *
+ * Conventions
+ *  - Meshes are face based (points; faces as point lists; owner of every face;
+ *    neighbour of every interior face), interior faces first, boundary faces
+ *    grouped into patches.  The points of a face run counter-clockwise seen
+ *    from outside its owner, so phi_f > 0 is flow from owner to neighbour (or
+ *    out of the domain).  This kernel path takes hexahedral cells (6
+ *    quadrilateral faces, 8 points); other cells give ISO_EUNSUPPORTED.
+ *  - Patch kinds: WALL and EMPTY faces carry no flux (their phi is ignored);
+ *    INOUT faces carry flux, inflow carrying the patch's alpha_in; CYCLIC
+ *    patches come in pairs (face n of a patch matches face n of its partner,
+ *    x_partner = x_this + translation).  For a cyclic pair the flux is read from
+ *    the face of the patch with the lower index (positive: out of that face's
+ *    owner); the partner face's phi entry is ignored.
+ *  - Arrays passed to iso_mesh_create are HOST arrays, copied; the caller keeps
+ *    ownership.  Arrays passed to the step functions are DEVICE arrays owned by
+ *    the caller (e.g. torch tensors), read/written on the plan's HIP stream.
+ *    Step calls are asynchronous unless a stats pointer is given.
+ *  - Every function returns a status; nothing aborts or throws across the
+ *    interface.  iso_last_error() gives a message for the last failure on the
+ *    calling thread.  A device fault surfaces as ISO_EDEVICE.
+ *  - FP64 throughout.  Indices are int32 (meshes up to 2^31-1 faces).
+ */
+#ifndef ISOADV_H
+#define ISOADV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ISO_OK = 0,
+    ISO_EINVAL = 1,        /* bad argument (null, size, aliasing, non-finite dt, ...) */
+    ISO_ENOMEM = 2,        /* device or host allocation failed */
+    ISO_EDEVICE = 3,       /* HIP runtime error or device fault */
+    ISO_ENOSPACE = 4,      /* interface cells exceed the plan's capacity */
+    ISO_ECOURANT = 5,      /* input check: a cell Courant number exceeds max_courant */
+    ISO_EMESH = 6,         /* inconsistent mesh (indices, orientation, cyclic matching, volume) */
+    ISO_EUNSUPPORTED = 7   /* valid mesh the kernels do not take (non-hexahedral cells) */
+} iso_status;
+
+enum { ISO_PATCH_WALL = 0, ISO_PATCH_EMPTY = 1, ISO_PATCH_INOUT = 2, ISO_PATCH_CYCLIC = 3 };
+
+typedef struct iso_mesh iso_mesh;
+typedef struct iso_plan iso_plan;
+
+typedef struct {
+    double eps_surf;        /* interface cell iff eps < alpha < 1-eps (default 1e-8) */
+    double flat_tol;        /* max-min vertex value at or below which an interface cell is
+                               treated as bulk (default 1e-12) */
+    double bound_tol;       /* excursions of alpha beyond [−tol, 1+tol] are redistributed;
+                               smaller ones are chopped when clip is on (default 1e-12) */
+    double max_courant;     /* limit for check_inputs (default 1.0) */
+    int32_t root_max_iter;  /* isovalue iterations (default 100) */
+    int32_t n_bound_iter;   /* Jacobi redistribution sweeps (default 3) */
+    int32_t clip;           /* chop alpha to [0,1] after redistribution (default 1) */
+    int32_t check_inputs;   /* validate inputs on the host before each step (syncs; default 0) */
+    int32_t block_cells;    /* threads per block of the per-cell kernels (0 = 256) */
+    int32_t block_surface;  /* threads per block of the interface-cell kernel (0 = 64) */
+    int32_t max_surface;    /* capacity of the interface-cell list (0 = n_cells) */
+    int32_t reserved;
+} iso_options;
+
+typedef struct {
+    int64_t n_surface;       /* interface cells this step */
+    int64_t n_flat;          /* interface cells treated as bulk (flat vertex data) */
+    int64_t n_nonconverged;  /* isovalue searches that hit root_max_iter */
+    int64_t n_bound_active;  /* cells needing redistribution in the first sweep */
+    int32_t max_root_iter;
+    int32_t reserved;
+    double vol_before, vol_after, vol_clipped, alpha_min, alpha_max;
+} iso_step_stats;
+
+/* Optional per-step intermediates (DEVICE pointers, each may be NULL), for testing. */
+typedef struct {
+    double *vert_alpha;   /* [8*n_cells] vertex values of interface cells, canonical vertex order */
+    int32_t *kind;        /* [n_cells] 0 bulk, 1 reconstructed interface cell, 2 flat interface cell */
+    double *iso;          /* [n_cells] isovalue of reconstructed cells */
+    double *rec;          /* [7*n_cells] isoface centre x_S (3), unit normal n_S (3), U_S.n_S */
+    double *dV;           /* [n_faces] dV per flux face (indexed by the face that carries its phi) */
+    double *alpha_raw;    /* [n_cells] alpha after the update, before bounding */
+    int32_t *iters;       /* [n_cells] isovalue iterations */
+} iso_trace;
+
+void iso_options_default(iso_options *opt);
+const char *iso_status_string(iso_status s);
+const char *iso_last_error(void);
+
+/* Mesh setup (once, host arrays, copied).  Section 3: collocated polyhedral mesh with
+ * owner/neighbour connectivity.  Builds the device geometry of the step. */
+iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py, const double *pz,
+                           int32_t n_faces, const int32_t *face_ptr /* [n_faces+1] */,
+                           const int32_t *face_pts, const int32_t *owner /* [n_faces] */,
+                           int32_t n_internal, const int32_t *neighbour /* [n_internal] */, int32_t n_cells,
+                           int32_t n_patches, const int32_t *patch_start, const int32_t *patch_size,
+                           const int32_t *patch_kind, const int32_t *patch_partner /* -1 if not cyclic */,
+                           const double *patch_translation /* [3*n_patches] */,
+                           const double *patch_alpha_in /* [n_patches] */, iso_mesh **out);
+void iso_mesh_destroy(iso_mesh *mesh);
+/* info[0..7] = n_cells, n_points, n_faces, n_flux_faces, n_point_classes, slots per cell,
+ *              device bytes held, reserved */
+iso_status iso_mesh_info(const iso_mesh *mesh, int64_t *info);
+/* host out[8*n_cells]: user point id of each canonical vertex of each cell */
+iso_status iso_mesh_cell_points(const iso_mesh *mesh, int32_t *out);
+/* host out[n_cells]: cell volumes; xc (nullable) [3*n_cells]: cell centres */
+iso_status iso_mesh_geometry(const iso_mesh *mesh, double *vol, double *xc);
+
+/* Plan: options, workspace (sized for max_surface interface cells) and the HIP stream
+ * (hipStream_t passed as void*, NULL = default stream).  The mesh must outlive the plan. */
+iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *hip_stream, iso_plan **out);
+iso_status iso_plan_set_stream(iso_plan *plan, void *hip_stream);
+void iso_plan_destroy(iso_plan *plan);
+
+/* One advection step (Section 3.2).  alpha [n_cells], phi [n_faces], U structure-of-arrays
+ * [3*n_cells] (all Ux, then Uy, then Uz), alpha_new [n_cells]: device arrays; alpha_new must
+ * not overlap alpha, phi or U.  stats (host, nullable): filled after a device sync. */
+iso_status iso_advect_step(iso_plan *plan, const double *alpha, const double *phi, const double *U, double dt,
+                           double *alpha_new, iso_step_stats *stats);
+/* Same step, also writing the intermediates named in trace (device pointers). */
+iso_status iso_advect_step_traced(iso_plan *plan, const double *alpha, const double *phi, const double *U,
+                                  double dt, double *alpha_new, iso_step_stats *stats, const iso_trace *trace);
+
+/* Kernel timing (measurement support).  iso_plan_set_timing(plan, n) records HIP events on the
+ * plan's stream around each of the step's kernels for the next n steps (0 disables; events are
+ * created here, not in the step).  iso_plan_timing syncs the stream and returns, per kernel
+ * (0 interface-cell list, 1 interface cells, 2 update, 3 bounding), the summed milliseconds over the
+ * recorded steps, and the number of recorded steps; it then clears the record. */
+iso_status iso_plan_set_timing(iso_plan *plan, int32_t max_steps);
+iso_status iso_plan_timing(iso_plan *plan, double *kernel_ms /* [4] */, int32_t *n_steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -20,14 +20,18 @@
  *   R1  vertex values: inverse centre-to-vertex distance weights, power 1, over
  *       the cells sharing the point; periodic images translated into the point's frame.
  *   R2  interface cell: eps < alpha_P < 1 - eps.
- *   R3  isovalue: pure bisection on [min a_v, max a_v] to round-off.
+ *   R3  isovalue: bracket between consecutive vertex values, take the vertex
+ *       value itself if the sub-volume jumps across alpha_P there, else
+ *       bisection to round-off.
  *   R4  vertex v is wet iff a_v > alpha0; an edge is cut iff exactly one end is
  *       wet; the cut point is computed from the wet end.
  *   R5  wet part of a face = its vertex walk emitting wet vertices and cut points;
  *       isoface edges = the cut-to-cut parts of those walks; sub-volume by the
- *       divergence theorem over fan triangles.
- *   R6  isoface normal from the summed fan area vector (out of the wet part),
- *       centre = area-weighted fan centroid; U_S = U_P.
+ *       divergence theorem over fan triangles (apex: R6).
+ *   R6  polygons (isoface, wet parts of faces) are fanned about their perimeter
+ *       centroid, which keeps the sub-volume continuous when a cut point meets a
+ *       vertex; isoface normal from the summed fan area vector (out of the wet
+ *       part), centre = area-weighted fan centroid; U_S = U_P.
  *   R7  face triangles: fan about the vertex mean; A_f = sum of triangle areas.
  *   R8  Eq. aplus2 as printed is not continuous; the reading used is
  *       alpha+(tau) = alpha+(t2) + (A234/A) [1 - ((t3 - tau)/(t3 - t2))^2].
@@ -475,7 +479,7 @@ typedef struct {
     double S[3];         /* isoface area vector, out of the wet part */
     double xS[3];        /* isoface centre */
     double Swet[3];      /* sum of the area vectors of the wet parts of the cell faces */
-    int n_cut;           /* distinct cut edges */
+    int n_cut;           /* isoface edges */
 } or_cut;
 
 #define OR_MAXCUT 128
@@ -498,13 +502,29 @@ static void fan(const double (*poly)[3], int n, const double *apex, const double
     }
 }
 
-int or_cell_cut(const or_mesh *m, int c, const double *a_pts, double iso, or_cut *out) {
+/* Fan apex of a polygon given by its boundary edges (a[i] -> b[i]; for a closed loop b[i] = a[i+1]):
+ * the length-weighted mean of the edge midpoints (perimeter centroid).  When a cut point reaches a
+ * vertex the polygon gains or loses a zero-length edge, which does not move this apex, so the fan
+ * surface, the sub-volume and the isoface centre stay continuous in the isovalue (reading R6).
+ * If every edge has zero length the mean of the edge start points is used. */
+static void perimeter_centroid(double (*a)[3], double (*b)[3], int n, int closed_loop, double *out) {
+    double L = 0, acc[3] = {0, 0, 0}, mean[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        const double *p = a[i], *q = closed_loop ? a[(i + 1) % n] : b[i];
+        double e[3];
+        v_sub(q, p, e);
+        double l = v_norm(e);
+        L += l;
+        for (int d = 0; d < 3; ++d) { acc[d] += l * 0.5 * (p[d] + q[d]); mean[d] += p[d]; }
+    }
+    for (int d = 0; d < 3; ++d) out[d] = L > 0 ? acc[d] / L : mean[d] / n;
+}
+
+/* tie_wet = 0: vertex wet iff a_v > iso (R4); tie_wet = 1: a_v >= iso, the limit from below at iso */
+static int cell_cut(const or_mesh *m, int c, const double *a_pts, double iso, int tie_wet, or_cut *out) {
     const double *xref = m->xc + 3 * c;
     int fp[OR_MAXFP];
     double poly[2 * OR_MAXFP][3];
-    int cut_key_a[OR_MAXCUT], cut_key_b[OR_MAXCUT];
-    double cut_pos[OR_MAXCUT][3];
-    int ncut = 0;
     double seg_a[OR_MAXCUT][3], seg_b[OR_MAXCUT][3];  /* isoface boundary edges, oriented */
     int nseg = 0;
     double vol = 0;
@@ -513,13 +533,13 @@ int or_cell_cut(const or_mesh *m, int c, const double *a_pts, double iso, or_cut
         int f = m->cfaces[k];
         int n = face_points_for(m, f, c, fp);
         int np_ = 0;
-        double first_exit[3] = {0, 0, 0}, last_exit[3] = {0, 0, 0};
-        int have_exit = 0, pending = 0, first_is_entry = 0;
+        double last_exit[3] = {0, 0, 0};
+        int pending = 0, first_is_entry = 0;
         double first_entry[3] = {0, 0, 0};
         for (int i = 0; i < n; ++i) {
             int qi = fp[i], qj = fp[(i + 1) % n];
             double ai = a_pts[qi], aj = a_pts[qj];
-            int wi = ai > iso, wj = aj > iso;
+            int wi = tie_wet ? ai >= iso : ai > iso, wj = tie_wet ? aj >= iso : aj > iso;
             const double *xi = m->P + 3 * qi, *xj = m->P + 3 * qj;
             if (wi) { for (int d = 0; d < 3; ++d) poly[np_][d] = xi[d]; ++np_; }
             if (wi != wj) {
@@ -527,19 +547,9 @@ int or_cell_cut(const or_mesh *m, int c, const double *a_pts, double iso, or_cut
                 if (wi) cut_point(xi, ai, xj, aj, iso, cp); else cut_point(xj, aj, xi, ai, iso, cp);
                 for (int d = 0; d < 3; ++d) poly[np_][d] = cp[d];
                 ++np_;
-                /* distinct cut edges for the isoface apex */
-                int ka = qi < qj ? qi : qj, kb = qi < qj ? qj : qi, seen = 0;
-                for (int u = 0; u < ncut; ++u) if (cut_key_a[u] == ka && cut_key_b[u] == kb) { seen = 1; break; }
-                if (!seen) {
-                    if (ncut >= OR_MAXCUT) return -1;
-                    cut_key_a[ncut] = ka; cut_key_b[ncut] = kb;
-                    for (int d = 0; d < 3; ++d) cut_pos[ncut][d] = cp[d];
-                    ++ncut;
-                }
                 if (wi) {  /* leaving the wet part of the face */
                     for (int d = 0; d < 3; ++d) last_exit[d] = cp[d];
-                    if (!have_exit) { for (int d = 0; d < 3; ++d) first_exit[d] = cp[d]; }
-                    have_exit = 1; pending = 1;
+                    pending = 1;
                 } else {   /* re-entering: the face walk went exit -> entry; the isoface edge runs entry -> exit */
                     if (pending) {
                         if (nseg >= OR_MAXCUT) return -1;
@@ -557,22 +567,19 @@ int or_cell_cut(const or_mesh *m, int c, const double *a_pts, double iso, or_cut
             for (int d = 0; d < 3; ++d) { seg_a[nseg][d] = first_entry[d]; seg_b[nseg][d] = last_exit[d]; }
             ++nseg;
         }
-        (void)first_exit;
         if (np_ >= 3) {
-            double apex[3] = {0, 0, 0};
-            for (int i = 0; i < np_; ++i) for (int d = 0; d < 3; ++d) apex[d] += poly[i][d];
-            for (int d = 0; d < 3; ++d) apex[d] /= np_;
+            double apex[3];
+            perimeter_centroid(poly, poly, np_, 1, apex);
             fan((const double(*)[3])poly, np_, apex, xref, &vol, Swet);
         }
     }
     out->Swet[0] = Swet[0]; out->Swet[1] = Swet[1]; out->Swet[2] = Swet[2];
     out->S[0] = out->S[1] = out->S[2] = 0;
     out->xS[0] = out->xS[1] = out->xS[2] = 0;
-    out->n_cut = ncut;
-    if (ncut > 0 && nseg > 0) {
-        double o[3] = {0, 0, 0};
-        for (int u = 0; u < ncut; ++u) for (int d = 0; d < 3; ++d) o[d] += cut_pos[u][d];
-        for (int d = 0; d < 3; ++d) o[d] /= ncut;
+    out->n_cut = nseg;
+    if (nseg > 0) {
+        double o[3];
+        perimeter_centroid(seg_a, seg_b, nseg, 0, o);
         double S[3] = {0, 0, 0};
         for (int s = 0; s < nseg; ++s) {
             double e0[3], e1[3], St[3], g[3], r[3];
@@ -602,26 +609,45 @@ int or_cell_cut(const or_mesh *m, int c, const double *a_pts, double iso, or_cut
 }
 
 /* ------------------------------------------------------------------ R3 isovalue by bisection */
-double or_cell_isovalue(const or_mesh *m, int c, const double *a_pts, double alpha_c, int max_iter, int *iters) {
-    double lo = 1e300, hi = -1e300;
-    for (int i = m->cpptr[c]; i < m->cpptr[c + 1]; ++i) {
-        double a = a_pts[m->cpts[i]];
-        if (a < lo) lo = a;
-        if (a > hi) hi = a;
-    }
+int or_cell_cut(const or_mesh *m, int c, const double *a_pts, double iso, or_cut *out) {
+    return cell_cut(m, c, a_pts, iso, 0, out);
+}
+
+static double vol_frac_minus_alpha(const or_mesh *m, int c, const double *a_pts, double iso, int tie_wet, double alpha_c) {
     or_cut cut;
-    double V = m->V[c];
-    or_cell_cut(m, c, a_pts, lo, &cut);
-    double flo = cut.vsub / V - alpha_c;
-    or_cell_cut(m, c, a_pts, hi, &cut);
-    double fhi = cut.vsub / V - alpha_c;
+    cell_cut(m, c, a_pts, iso, tie_wet, &cut);
+    return cut.vsub / m->V[c] - alpha_c;
+}
+
+/* R3 isovalue.  The sub-volume is a smooth (cubic) function of the isovalue between consecutive
+ * vertex values and can only jump at a vertex value (the functional form the paper's search
+ * exploits).  So: find consecutive distinct vertex values lo < hi with f(lo) > 0 >= f(hi); if the
+ * limit of f from below at hi is still positive, f jumps across zero there and the isovalue is hi;
+ * otherwise bisect (lo, hi) down to adjacent doubles. */
+double or_cell_isovalue(const or_mesh *m, int c, const double *a_pts, double alpha_c, int max_iter, int *iters) {
+    double s[OR_MAXFP * 8] = {0};
+    int n = 0;
+    for (int i = m->cpptr[c]; i < m->cpptr[c + 1]; ++i) s[n++] = a_pts[m->cpts[i]];
+    for (int i = 1; i < n; ++i)
+        for (int j = i; j > 0 && s[j - 1] > s[j]; --j) { double t = s[j]; s[j] = s[j - 1]; s[j - 1] = t; }
+    int u = 0;
+    for (int i = 0; i < n; ++i) if (i == 0 || s[i] != s[i - 1]) s[u++] = s[i];
     int it = 0;
+    double lo = s[0], hi = s[u - 1], flo = 1.0 - alpha_c;
+    for (int j = 1; j < u; ++j) {
+        ++it;
+        double fj = vol_frac_minus_alpha(m, c, a_pts, s[j], 0, alpha_c);
+        if (fj <= 0.0) { lo = s[j - 1]; hi = s[j]; break; }
+        flo = fj;
+    }
+    ++it;
+    double fhi = vol_frac_minus_alpha(m, c, a_pts, hi, 1, alpha_c);  /* limit from below at hi */
+    if (fhi > 0.0) { if (iters) *iters = it; return hi; }
     while (it < max_iter) {
         double mid = lo + 0.5 * (hi - lo);
         if (!(mid > lo && mid < hi)) break;  /* bracket is down to adjacent doubles */
         ++it;
-        or_cell_cut(m, c, a_pts, mid, &cut);
-        double fm = cut.vsub / V - alpha_c;
+        double fm = vol_frac_minus_alpha(m, c, a_pts, mid, 0, alpha_c);
         if (fm == 0.0) { lo = hi = mid; flo = fhi = 0.0; break; }
         if (fm > 0) { lo = mid; flo = fm; } else { hi = mid; fhi = fm; }
     }

@@ -43,7 +43,7 @@ class Stats(C.Structure):
 
 def compile_oracle(src: str, out: str) -> str:
     """gcc build of an oracle source file (no FMA contraction, so rounding follows the source)."""
-    tmp = out + ".tmp"
+    tmp = f"{out}.tmp{os.getpid()}"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
                            "-shared", "-Wall", "-Wno-unused-function", "-o", tmp, src, "-lm"])
     os.replace(tmp, out)

@@ -1,0 +1,280 @@
+"""ctypes binding of libisoadv.so: argument marshalling only.
+
+Every step of the advection runs in the HIP kernels behind the C interface
+(include/isoadv.h).  PyTorch supplies device memory and the current HIP stream.
+If the library is not built this module raises at load time; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libisoadv.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "isoadv.h")
+
+ISO_OK, ISO_EINVAL, ISO_ENOMEM, ISO_EDEVICE, ISO_ENOSPACE, ISO_ECOURANT, ISO_EMESH, ISO_EUNSUPPORTED = range(8)
+PATCH_WALL, PATCH_EMPTY, PATCH_INOUT, PATCH_CYCLIC = range(4)
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_vp = C.c_void_p
+
+
+class IsoOptions(C.Structure):
+    _fields_ = [("eps_surf", C.c_double), ("flat_tol", C.c_double), ("bound_tol", C.c_double),
+                ("max_courant", C.c_double), ("root_max_iter", C.c_int32), ("n_bound_iter", C.c_int32),
+                ("clip", C.c_int32), ("check_inputs", C.c_int32), ("block_cells", C.c_int32),
+                ("block_surface", C.c_int32), ("max_surface", C.c_int32), ("reserved", C.c_int32)]
+
+
+class IsoStepStats(C.Structure):
+    _fields_ = [("n_surface", C.c_int64), ("n_flat", C.c_int64), ("n_nonconverged", C.c_int64),
+                ("n_bound_active", C.c_int64), ("max_root_iter", C.c_int32), ("reserved", C.c_int32),
+                ("vol_before", C.c_double), ("vol_after", C.c_double), ("vol_clipped", C.c_double),
+                ("alpha_min", C.c_double), ("alpha_max", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class IsoTrace(C.Structure):
+    _fields_ = [("vert_alpha", _vp), ("kind", _vp), ("iso", _vp), ("rec", _vp), ("dV", _vp),
+                ("alpha_raw", _vp), ("iters", _vp)]
+
+
+class IsoError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"isoadv error {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        # PyTorch carries its own HIP runtime.  Loading it first lets the library's libamdhip64.so.7
+        # dependency bind to that same runtime (matched by soname), so device pointers and streams
+        # of torch tensors are valid in the library.  Two runtimes in one process do not work.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        _check_single_runtime()
+        L.iso_options_default.argtypes = [C.POINTER(IsoOptions)]
+        L.iso_options_default.restype = None
+        L.iso_status_string.argtypes = [C.c_int]
+        L.iso_status_string.restype = C.c_char_p
+        L.iso_last_error.argtypes = []
+        L.iso_last_error.restype = C.c_char_p
+        L.iso_mesh_create.argtypes = [C.c_int32, _dp, _dp, _dp, C.c_int32, _ip, _ip, _ip, C.c_int32, _ip, C.c_int32,
+                                      C.c_int32, _ip, _ip, _ip, _ip, _dp, _dp, C.POINTER(_vp)]
+        L.iso_mesh_create.restype = C.c_int
+        L.iso_mesh_destroy.argtypes = [_vp]
+        L.iso_mesh_destroy.restype = None
+        L.iso_mesh_info.argtypes = [_vp, C.POINTER(C.c_int64)]
+        L.iso_mesh_info.restype = C.c_int
+        L.iso_mesh_cell_points.argtypes = [_vp, _ip]
+        L.iso_mesh_cell_points.restype = C.c_int
+        L.iso_mesh_geometry.argtypes = [_vp, _dp, _dp]
+        L.iso_mesh_geometry.restype = C.c_int
+        L.iso_plan_create.argtypes = [_vp, C.POINTER(IsoOptions), _vp, C.POINTER(_vp)]
+        L.iso_plan_create.restype = C.c_int
+        L.iso_plan_set_stream.argtypes = [_vp, _vp]
+        L.iso_plan_set_stream.restype = C.c_int
+        L.iso_plan_destroy.argtypes = [_vp]
+        L.iso_plan_destroy.restype = None
+        L.iso_advect_step.argtypes = [_vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats)]
+        L.iso_advect_step.restype = C.c_int
+        L.iso_advect_step_traced.argtypes = [_vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats),
+                                             C.POINTER(IsoTrace)]
+        L.iso_advect_step_traced.restype = C.c_int
+        L.iso_plan_set_timing.argtypes = [_vp, C.c_int32]
+        L.iso_plan_set_timing.restype = C.c_int
+        L.iso_plan_timing.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
+        L.iso_plan_timing.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check_single_runtime():
+    try:
+        maps = open("/proc/self/maps").read()
+    except OSError:
+        return
+    paths = set(re.findall(r"\S*/libamdhip64\.so\S*", maps))
+    if len(paths) > 1:
+        raise RuntimeError("two HIP runtimes are loaded in this process: " + ", ".join(sorted(paths)))
+
+
+def header_functions():
+    """Names of the functions declared in include/isoadv.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(iso_[a-z_]+)\s*\(", txt)))
+
+
+def check(status):
+    if status != ISO_OK:
+        msg = lib().iso_last_error().decode()
+        raise IsoError(status, msg or lib().iso_status_string(status).decode())
+
+
+def default_options(**kw) -> IsoOptions:
+    o = IsoOptions()
+    lib().iso_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64/int32 CUDA (HIP) tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Mesh:
+    """A face-based hexahedral mesh uploaded to the device (iso_mesh_create).
+
+    ``points`` (n,3) float64; ``face_ptr``/``face_pts`` the face point lists; ``owner``
+    per face; ``neighbour`` per interior face; patches as parallel arrays.
+    """
+
+    def __init__(self, points, face_ptr, face_pts, owner, neighbour, n_cells, patch_start, patch_size, patch_kind,
+                 patch_partner, patch_translation, patch_alpha_in):
+        L = lib()
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        px, py, pz = (np.ascontiguousarray(pts[:, i]) for i in range(3))
+        arrs = dict(face_ptr=np.ascontiguousarray(face_ptr, dtype=np.int32),
+                    face_pts=np.ascontiguousarray(face_pts, dtype=np.int32),
+                    owner=np.ascontiguousarray(owner, dtype=np.int32),
+                    neighbour=np.ascontiguousarray(neighbour if len(neighbour) else np.zeros(1), dtype=np.int32),
+                    ps=np.ascontiguousarray(patch_start, dtype=np.int32),
+                    pn=np.ascontiguousarray(patch_size, dtype=np.int32),
+                    pk=np.ascontiguousarray(patch_kind, dtype=np.int32),
+                    pp=np.ascontiguousarray(patch_partner, dtype=np.int32))
+        pt = np.ascontiguousarray(patch_translation, dtype=np.float64).reshape(-1)
+        pa = np.ascontiguousarray(patch_alpha_in, dtype=np.float64)
+        h = _vp()
+        ip = lambda a: a.ctypes.data_as(_ip)
+        dp = lambda a: a.ctypes.data_as(_dp)
+        n_faces = len(arrs["owner"])
+        st = L.iso_mesh_create(len(pts), dp(px), dp(py), dp(pz), n_faces, ip(arrs["face_ptr"]), ip(arrs["face_pts"]),
+                               ip(arrs["owner"]), len(neighbour), ip(arrs["neighbour"]), int(n_cells),
+                               len(arrs["ps"]), ip(arrs["ps"]), ip(arrs["pn"]), ip(arrs["pk"]), ip(arrs["pp"]),
+                               dp(pt), dp(pa), C.byref(h))
+        check(st)
+        self.h = h
+        self.n_cells = int(n_cells)
+        self.n_faces = n_faces
+        self.n_points = len(pts)
+
+    @classmethod
+    def from_arrays(cls, m):
+        """From any object with the attributes of a face-based mesh (points, face_ptr, face_pts, owner,
+        neighbour, n_cells, patch_arrays())."""
+        ps, pn, pk, pp, pt, pa = m.patch_arrays()
+        return cls(m.points, m.face_ptr, m.face_pts, m.owner, m.neighbour, m.n_cells, ps, pn, pk, pp, pt, pa)
+
+    def info(self):
+        out = (C.c_int64 * 8)()
+        check(lib().iso_mesh_info(self.h, out))
+        keys = ["n_cells", "n_points", "n_faces", "n_flux_faces", "n_point_classes", "slots", "device_bytes"]
+        return {k: int(out[i]) for i, k in enumerate(keys)}
+
+    def cell_points(self):
+        out = np.zeros(8 * self.n_cells, dtype=np.int32)
+        check(lib().iso_mesh_cell_points(self.h, out.ctypes.data_as(_ip)))
+        return out.reshape(-1, 8)
+
+    def geometry(self):
+        vol = np.zeros(self.n_cells)
+        xc = np.zeros(3 * self.n_cells)
+        check(lib().iso_mesh_geometry(self.h, vol.ctypes.data_as(_dp), xc.ctypes.data_as(_dp)))
+        return vol, xc.reshape(-1, 3)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().iso_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Options + workspace + stream for stepping one mesh (iso_plan_create)."""
+
+    def __init__(self, mesh: Mesh, options: IsoOptions | None = None, stream=None):
+        self.mesh = mesh
+        self.options = options or default_options()
+        h = _vp()
+        check(lib().iso_plan_create(mesh.h, C.byref(self.options), _stream_handle(stream), C.byref(h)))
+        self.h = h
+
+    def set_stream(self, stream):
+        check(lib().iso_plan_set_stream(self.h, _stream_handle(stream)))
+
+    def step(self, alpha, phi, U, dt, out=None, stats=False, trace=None):
+        """alpha_new = isoAdvector step (device tensors, float64).  Returns (alpha_new, stats dict or None)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(alpha)
+        st = IsoStepStats() if stats else None
+        self.set_stream(None)
+        if trace is None:
+            check(lib().iso_advect_step(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt), _ptr(out),
+                                        C.byref(st) if st is not None else None))
+        else:
+            tr = IsoTrace(*[(_ptr(trace[k]).value if trace.get(k) is not None else None)
+                            for k in ("vert_alpha", "kind", "iso", "rec", "dV", "alpha_raw", "iters")])
+            check(lib().iso_advect_step_traced(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt), _ptr(out),
+                                               C.byref(st) if st is not None else None, C.byref(tr)))
+        return out, (st.as_dict() if st is not None else None)
+
+    KERNELS = ("find_surface", "surface", "update", "bound")
+
+    def set_timing(self, max_steps):
+        check(lib().iso_plan_set_timing(self.h, int(max_steps)))
+
+    def timing(self):
+        """Summed per-kernel milliseconds over the recorded steps, and the number of steps."""
+        ms = (C.c_double * 4)()
+        n = C.c_int32(0)
+        check(lib().iso_plan_timing(self.h, ms, C.byref(n)))
+        return {k: ms[i] for i, k in enumerate(self.KERNELS)}, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().iso_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

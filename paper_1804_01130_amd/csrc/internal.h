@@ -1,0 +1,114 @@
+// Internal declarations shared by the host plan and the HIP kernels of the isoAdvector step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "isoadv.h"
+
+namespace isoadv {
+
+// A slot of a cell's flux list packs the flux-face id and the side of the cell:
+// v >= 0: face v, phi > 0 leaves the cell; v < 0 (and not kEmpty): face ~v, phi > 0 enters it.
+constexpr int32_t kEmpty = INT32_MIN;
+__host__ __device__ inline int32_t pack_face(int32_t fid, int sign) { return sign > 0 ? fid : ~fid; }
+
+// Canonical hexahedron: vertices 0-3 bottom loop, 4-7 above them; faces listed counter-clockwise
+// seen from outside (bottom, top, y-, x+, y+, x- for an axis-aligned box).
+constexpr int kHexFace[6][4] = {{0, 3, 2, 1}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}};
+
+// Device view of a mesh, passed to kernels by value.
+struct DevMesh {
+    int32_t n_cells = 0, n_faces = 0, n_classes = 0, W = 0, n_patches = 0;
+    const double *cxyz = nullptr;      // [24*n_cells] canonical vertex coordinates, cell-major
+    const int32_t *cpt = nullptr;      // [8*n_cells] point class of each canonical vertex
+    const double *vol = nullptr;       // [n_cells]
+    const int32_t *slot_face = nullptr;  // [W][n_cells] packed flux faces, ascending face id, kEmpty last
+    const int32_t *slot_nbr = nullptr;   // [W][n_cells] cell across the face, or -1-patch on the boundary
+    const int32_t *lface = nullptr;      // [6*n_cells] packed flux face of each canonical face, or kEmpty
+    const int32_t *st_ptr = nullptr;     // [n_classes+1] vertex stencils
+    const int32_t *st_cell = nullptr;
+    const double *st_w = nullptr;        // normalised inverse-distance weights
+    const double *patch_alpha = nullptr; // [n_patches]
+};
+
+// Workspace of a plan (device pointers).
+struct DevWork {
+    int32_t *counters = nullptr;   // [16] see kCnt* below
+    int32_t *surf = nullptr;       // [cap] interface cells
+    double *dvs = nullptr;         // [n_faces] dV written by interface upwind cells
+    int32_t *olist = nullptr;      // [n_cells] cells needing redistribution (two halves ping-pong)
+    int32_t *tlist = nullptr;      // [n_cells] cells touched by a sweep
+    int32_t *flist = nullptr;      // [n_faces] faces whose dV changed during bounding
+    int32_t *cmark = nullptr;      // [n_cells] zero between steps
+    int32_t *fmark = nullptr;      // [n_faces] zero between steps
+    double *delta = nullptr;       // [n_faces] zero between steps
+    double *dvcur = nullptr;       // [n_faces] current dV of faces in flist
+    double *red = nullptr;         // [64] reductions for stats
+    int32_t cap = 0;
+};
+
+enum : int {
+    kCntSurf = 0,       // interface cells found
+    kCntOff = 1,        // cells needing redistribution (first list)
+    kCntOverflow = 2,   // interface cells beyond capacity
+    kCntFlat = 3,
+    kCntNonconv = 4,
+    kCntMaxIter = 5,
+    kCntActive0 = 6,    // n_bound_active of the last step
+    kCntFaces = 7,      // flist length
+    kCntNum = 16
+};
+
+struct StepArgs {
+    const double *alpha;
+    const double *phi;
+    const double *U;
+    double *alpha_new;
+    double dt;
+};
+
+struct Params {
+    double eps_surf, flat_tol, bound_tol;
+    int32_t root_max_iter, n_bound_iter, clip;
+};
+
+// kernels.hip
+// ev: nullptr, or 5 events recorded before each of the 4 kernels and after the last
+hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, const StepArgs &a,
+                       const iso_trace *trace, int block_cells, int block_surface, bool want_stats,
+                       hipStream_t s, hipEvent_t *ev);
+hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha, const double *alpha_new,
+                        hipStream_t s);
+
+}  // namespace isoadv
+
+struct iso_mesh {
+    isoadv::DevMesh dev;
+    int32_t n_points = 0, n_faces = 0, n_internal = 0, n_cells = 0, n_flux = 0, n_classes = 0, W = 0;
+    std::vector<int32_t> cell_pts;   // [8*n_cells] user point ids, canonical order
+    std::vector<double> vol, xc;
+    std::vector<double> patch_alpha;
+    std::vector<void *> allocations;
+    int64_t device_bytes = 0;
+    int device = 0;
+};
+
+struct iso_plan {
+    const iso_mesh *mesh = nullptr;
+    iso_options opt{};
+    hipStream_t stream = nullptr;
+    isoadv::DevWork work;
+    std::vector<void *> allocations;
+    int32_t *host_counters = nullptr;  // pinned [16]
+    double *host_red = nullptr;        // pinned [64]
+    std::vector<hipEvent_t> events;    // 5 per recorded step
+    int32_t timing_cap = 0, timing_used = 0;
+};
+
+namespace isoadv {
+iso_status fail(iso_status s, const std::string &msg);
+}

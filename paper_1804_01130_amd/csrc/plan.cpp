@@ -1,0 +1,623 @@
+// Host side of the isoAdvector library: mesh validation and device layout, plans, and the
+// C entry points.  Geometry follows Section 3 of the paper (collocated polyhedral cells with
+// owner/neighbour faces); the per-step work is in kernels.hip.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+using namespace isoadv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+
+template <class T>
+iso_status upload(iso_mesh *m, const std::vector<T> &h, const T **dptr) {
+    void *p = nullptr;
+    size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) return fail(ISO_ENOMEM, "hipMalloc failed for mesh array");
+    m->allocations.push_back(p);
+    m->device_bytes += (int64_t)bytes;
+    if (!h.empty() && hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ISO_EDEVICE, "hipMemcpy failed for mesh array");
+    *dptr = static_cast<const T *>(p);
+    return ISO_OK;
+}
+
+// weighted union-find over points: x_p + off[p] is p's position in the frame of parent[p]
+struct FrameUnion {
+    std::vector<int32_t> parent;
+    std::vector<V3> off;
+    explicit FrameUnion(int n) : parent(n), off(n, V3{0, 0, 0}) { std::iota(parent.begin(), parent.end(), 0); }
+    int32_t find(int32_t p, V3 *to_root) {
+        V3 acc{0, 0, 0};
+        int32_t r = p;
+        while (parent[r] != r) {
+            acc = acc + off[r];
+            r = parent[r];
+        }
+        // compress
+        V3 run = acc;
+        int32_t q = p;
+        while (parent[q] != q) {
+            int32_t nx = parent[q];
+            V3 oq = off[q];
+            parent[q] = r;
+            off[q] = run;
+            run = run - oq;
+            q = nx;
+        }
+        *to_root = acc;
+        return r;
+    }
+    // x_b = x_a + T (same physical point seen from two frames)
+    bool unite(int32_t a, int32_t b, V3 T) {
+        V3 da, db;
+        int32_t ra = find(a, &da), rb = find(b, &db);
+        if (ra == rb) return true;
+        // frame ra -> frame a: -da; frame a -> frame b: +T; frame b -> frame rb: +db
+        parent[ra] = rb;
+        off[ra] = T + db - da;
+        return true;
+    }
+};
+
+}  // namespace
+
+namespace isoadv {
+iso_status fail(iso_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+}  // namespace isoadv
+
+extern "C" {
+
+const char *iso_last_error(void) { return g_last_error.c_str(); }
+
+const char *iso_status_string(iso_status s) {
+    switch (s) {
+        case ISO_OK: return "ok";
+        case ISO_EINVAL: return "invalid argument";
+        case ISO_ENOMEM: return "out of memory";
+        case ISO_EDEVICE: return "device error";
+        case ISO_ENOSPACE: return "interface-cell capacity exceeded";
+        case ISO_ECOURANT: return "Courant number above limit";
+        case ISO_EMESH: return "inconsistent mesh";
+        case ISO_EUNSUPPORTED: return "unsupported cell type";
+    }
+    return "unknown status";
+}
+
+void iso_options_default(iso_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->eps_surf = 1e-8;
+    o->flat_tol = 1e-12;
+    o->bound_tol = 1e-12;
+    o->max_courant = 1.0;
+    o->root_max_iter = 100;
+    o->n_bound_iter = 3;
+    o->clip = 1;
+}
+
+void iso_mesh_destroy(iso_mesh *m) {
+    if (!m) return;
+    for (void *p : m->allocations) (void)hipFree(p);
+    delete m;
+}
+
+iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py, const double *pz, int32_t n_faces,
+                           const int32_t *face_ptr, const int32_t *face_pts, const int32_t *owner,
+                           int32_t n_internal, const int32_t *neighbour, int32_t n_cells, int32_t n_patches,
+                           const int32_t *patch_start, const int32_t *patch_size, const int32_t *patch_kind,
+                           const int32_t *patch_partner, const double *patch_translation,
+                           const double *patch_alpha_in, iso_mesh **out) {
+    if (!out) return fail(ISO_EINVAL, "out is null");
+    *out = nullptr;
+    if (n_points <= 0 || n_faces <= 0 || n_cells <= 0 || n_internal < 0 || n_internal > n_faces || n_patches < 0)
+        return fail(ISO_EINVAL, "bad mesh sizes");
+    if (!px || !py || !pz || !face_ptr || !face_pts || !owner || (n_internal > 0 && !neighbour))
+        return fail(ISO_EINVAL, "null mesh array");
+    if (n_patches > 0 && (!patch_start || !patch_size || !patch_kind || !patch_partner || !patch_translation ||
+                          !patch_alpha_in))
+        return fail(ISO_EINVAL, "null patch array");
+
+    // ---- connectivity checks
+    if (face_ptr[0] != 0) return fail(ISO_EMESH, "face_ptr[0] != 0");
+    for (int32_t f = 0; f < n_faces; ++f) {
+        if (face_ptr[f + 1] < face_ptr[f]) return fail(ISO_EMESH, "face_ptr not monotone");
+        if (owner[f] < 0 || owner[f] >= n_cells) return fail(ISO_EMESH, "owner out of range at face " + std::to_string(f));
+    }
+    for (int32_t k = 0; k < face_ptr[n_faces]; ++k)
+        if (face_pts[k] < 0 || face_pts[k] >= n_points) return fail(ISO_EMESH, "face point out of range");
+    for (int32_t f = 0; f < n_internal; ++f)
+        if (neighbour[f] < 0 || neighbour[f] >= n_cells || neighbour[f] == owner[f])
+            return fail(ISO_EMESH, "neighbour out of range at face " + std::to_string(f));
+    std::vector<int32_t> fpatch(n_faces, -1);
+    for (int32_t p = 0; p < n_patches; ++p) {
+        if (patch_start[p] < n_internal || patch_size[p] < 0 || patch_start[p] + patch_size[p] > n_faces)
+            return fail(ISO_EMESH, "patch range out of the boundary faces");
+        if (patch_kind[p] < ISO_PATCH_WALL || patch_kind[p] > ISO_PATCH_CYCLIC) return fail(ISO_EMESH, "bad patch kind");
+        for (int32_t f = patch_start[p]; f < patch_start[p] + patch_size[p]; ++f) {
+            if (fpatch[f] >= 0) return fail(ISO_EMESH, "patches overlap");
+            fpatch[f] = p;
+        }
+        if (patch_kind[p] == ISO_PATCH_CYCLIC) {
+            int32_t q = patch_partner[p];
+            if (q < 0 || q >= n_patches || q == p || patch_kind[q] != ISO_PATCH_CYCLIC || patch_partner[q] != p ||
+                patch_size[q] != patch_size[p])
+                return fail(ISO_EMESH, "cyclic patch " + std::to_string(p) + " has no matching partner");
+        }
+    }
+    for (int32_t f = n_internal; f < n_faces; ++f)
+        if (fpatch[f] < 0) return fail(ISO_EMESH, "boundary face " + std::to_string(f) + " in no patch");
+
+    auto P = [&](int32_t i) { return V3{px[i], py[i], pz[i]}; };
+
+    // ---- cells: six quadrilateral faces each
+    std::vector<int32_t> ncf(n_cells, 0);
+    for (int32_t f = 0; f < n_faces; ++f) {
+        ncf[owner[f]]++;
+        if (f < n_internal) ncf[neighbour[f]]++;
+    }
+    for (int32_t c = 0; c < n_cells; ++c)
+        if (ncf[c] != 6) return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " is not a hexahedron");
+    for (int32_t f = 0; f < n_faces; ++f)
+        if (face_ptr[f + 1] - face_ptr[f] != 4) return fail(ISO_EUNSUPPORTED, "face " + std::to_string(f) + " is not a quadrilateral");
+    std::vector<int32_t> cfaces(6 * (size_t)n_cells);
+    std::fill(ncf.begin(), ncf.end(), 0);
+    for (int32_t f = 0; f < n_faces; ++f) {  // ascending face id per cell
+        cfaces[6 * (size_t)owner[f] + ncf[owner[f]]++] = f;
+        if (f < n_internal) cfaces[6 * (size_t)neighbour[f] + ncf[neighbour[f]]++] = f;
+    }
+    auto outward = [&](int32_t f, int32_t c, std::array<int32_t, 4> &q) {
+        const int32_t *fp = face_pts + face_ptr[f];
+        if (owner[f] == c) for (int i = 0; i < 4; ++i) q[i] = fp[i];
+        else for (int i = 0; i < 4; ++i) q[i] = fp[3 - i];
+    };
+
+    iso_mesh *m = new iso_mesh();
+    m->n_points = n_points; m->n_faces = n_faces; m->n_internal = n_internal; m->n_cells = n_cells;
+    m->cell_pts.resize(8 * (size_t)n_cells);
+    std::vector<int32_t> lface_actual(6 * (size_t)n_cells);
+
+    for (int32_t c = 0; c < n_cells; ++c) {
+        std::array<std::array<int32_t, 4>, 6> fq;
+        for (int k = 0; k < 6; ++k) outward(cfaces[6 * (size_t)c + k], c, fq[k]);
+        // bottom = first face; its outward loop is canonical (0,3,2,1)
+        int32_t v[8];
+        v[0] = fq[0][0]; v[3] = fq[0][1]; v[2] = fq[0][2]; v[1] = fq[0][3];
+        // vertex above each bottom vertex: the one joined to it by an edge not on the bottom face
+        auto on_bottom = [&](int32_t p) { return p == v[0] || p == v[1] || p == v[2] || p == v[3]; };
+        bool ok = true;
+        for (int b = 0; b < 4 && ok; ++b) {
+            int32_t above = -1;
+            for (int k = 1; k < 6; ++k)
+                for (int i = 0; i < 4; ++i) {
+                    int32_t a = fq[k][i], bb = fq[k][(i + 1) % 4];
+                    int32_t other = a == v[b] ? bb : (bb == v[b] ? a : -1);
+                    if (other >= 0 && !on_bottom(other)) {
+                        if (above >= 0 && above != other) ok = false;
+                        above = other;
+                    }
+                }
+            if (above < 0) ok = false;
+            v[4 + b] = above;
+        }
+        if (ok) {
+            int32_t s[8];
+            std::copy(v, v + 8, s);
+            std::sort(s, s + 8);
+            ok = std::adjacent_find(s, s + 8) == s + 8;
+        }
+        if (!ok) { iso_mesh_destroy(m); return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " is not a hexahedron"); }
+        // match canonical faces to actual faces, with orientation
+        for (int k = 0; k < 6; ++k) {
+            int found = -1;
+            for (int j = 0; j < 6 && found < 0; ++j) {
+                for (int r = 0; r < 4; ++r) {
+                    bool same = true;
+                    for (int i = 0; i < 4; ++i) same = same && fq[j][(i + r) % 4] == v[kHexFace[k][i]];
+                    if (same) { found = j; break; }
+                }
+            }
+            if (found < 0) {
+                iso_mesh_destroy(m);
+                return fail(ISO_EMESH, "cell " + std::to_string(c) + ": faces inconsistently oriented");
+            }
+            lface_actual[6 * (size_t)c + k] = cfaces[6 * (size_t)c + found];
+        }
+        for (int i = 0; i < 8; ++i) m->cell_pts[8 * (size_t)c + i] = v[i];
+    }
+
+    // ---- volumes and centroids: tetrahedra (vertex mean, face vertex mean, edge) over outward faces
+    m->vol.resize(n_cells);
+    m->xc.resize(3 * (size_t)n_cells);
+    for (int32_t c = 0; c < n_cells; ++c) {
+        const int32_t *v = &m->cell_pts[8 * (size_t)c];
+        V3 xm{0, 0, 0};
+        for (int i = 0; i < 8; ++i) xm = xm + P(v[i]);
+        xm = 0.125 * xm;
+        double vol = 0;
+        V3 mom{0, 0, 0};
+        for (int k = 0; k < 6; ++k) {
+            V3 q[4];
+            for (int i = 0; i < 4; ++i) q[i] = P(v[kHexFace[k][i]]);
+            V3 ap = 0.25 * (q[0] + q[1] + q[2] + q[3]);
+            for (int i = 0; i < 4; ++i) {
+                V3 a = ap - xm, b = q[i] - xm, cc = q[(i + 1) % 4] - xm;
+                double tv = dot(a, cross(b, cc)) / 6.0;
+                vol += tv;
+                mom = mom + (tv * 0.25) * (xm + ap + q[i] + q[(i + 1) % 4]);
+            }
+        }
+        if (!(vol > 0)) { iso_mesh_destroy(m); return fail(ISO_EMESH, "cell " + std::to_string(c) + " has non-positive volume"); }
+        m->vol[c] = vol;
+        V3 x = (1.0 / vol) * mom;
+        m->xc[3 * c] = x.x; m->xc[3 * c + 1] = x.y; m->xc[3 * c + 2] = x.z;
+    }
+
+    // ---- flux faces: interior, cyclic pairs (lower patch index carries phi), inflow/outflow
+    // per (face): fid, sign seen from the face's owner, cell across (or -1-patch)
+    std::vector<int32_t> f_fid(n_faces, -1), f_sign(n_faces, 0), f_other(n_faces, -1);
+    int32_t n_flux = 0;
+    for (int32_t f = 0; f < n_faces; ++f) {
+        if (f < n_internal) { f_fid[f] = f; f_sign[f] = 1; f_other[f] = neighbour[f]; ++n_flux; continue; }
+        int32_t p = fpatch[f];
+        if (patch_kind[p] == ISO_PATCH_INOUT) { f_fid[f] = f; f_sign[f] = 1; f_other[f] = -1 - p; ++n_flux; }
+        else if (patch_kind[p] == ISO_PATCH_CYCLIC) {
+            int32_t q = patch_partner[p];
+            int32_t g = patch_start[q] + (f - patch_start[p]);
+            int32_t primary = p < q ? f : g;
+            f_fid[f] = primary;
+            f_sign[f] = primary == f ? 1 : -1;
+            f_other[f] = owner[g];
+            if (primary == f) ++n_flux;
+        }
+    }
+    m->n_flux = n_flux;
+    // slots per cell sorted by face id
+    int W = 0;
+    std::vector<std::vector<std::array<int32_t, 3>>> slots(n_cells);
+    for (int32_t c = 0; c < n_cells; ++c) {
+        for (int k = 0; k < 6; ++k) {
+            int32_t f = cfaces[6 * (size_t)c + k];
+            if (f_fid[f] < 0) continue;
+            int s; int32_t other;
+            if (f < n_internal) { s = owner[f] == c ? 1 : -1; other = owner[f] == c ? neighbour[f] : owner[f]; }
+            else { s = f_sign[f]; other = f_other[f]; }
+            slots[c].push_back({f_fid[f], s, other});
+        }
+        std::sort(slots[c].begin(), slots[c].end(), [](const auto &a, const auto &b) { return a[0] < b[0]; });
+        W = std::max<int>(W, (int)slots[c].size());
+    }
+    W = std::max(W, 1);
+    m->W = W;
+    std::vector<int32_t> slot_face((size_t)W * n_cells, kEmpty), slot_nbr((size_t)W * n_cells, -1);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (size_t k = 0; k < slots[c].size(); ++k) {
+            slot_face[k * n_cells + c] = pack_face(slots[c][k][0], slots[c][k][1]);
+            slot_nbr[k * n_cells + c] = slots[c][k][2];
+        }
+    std::vector<int32_t> lface(6 * (size_t)n_cells, kEmpty);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int k = 0; k < 6; ++k) {
+            int32_t f = lface_actual[6 * (size_t)c + k];
+            if (f_fid[f] < 0) continue;
+            int s = f < n_internal ? (owner[f] == c ? 1 : -1) : f_sign[f];
+            lface[6 * (size_t)c + k] = pack_face(f_fid[f], s);
+        }
+
+    // ---- periodic point classes: match the points of paired cyclic faces
+    FrameUnion fu(n_points);
+    for (int32_t p = 0; p < n_patches; ++p) {
+        if (patch_kind[p] != ISO_PATCH_CYCLIC || patch_partner[p] < p) continue;
+        int32_t q = patch_partner[p];
+        V3 T{patch_translation[3 * p], patch_translation[3 * p + 1], patch_translation[3 * p + 2]};
+        for (int32_t i = 0; i < patch_size[p]; ++i) {
+            int32_t f = patch_start[p] + i, g = patch_start[q] + i;
+            const int32_t *fa = face_pts + face_ptr[f], *gb = face_pts + face_ptr[g];
+            V3 ctr = 0.25 * (P(fa[0]) + P(fa[1]) + P(fa[2]) + P(fa[3]));
+            double h = 0;
+            for (int a = 0; a < 4; ++a) h = std::max(h, norm(P(fa[a]) - ctr));
+            for (int a = 0; a < 4; ++a) {
+                V3 tgt = P(fa[a]) + T;
+                int32_t hit = -1;
+                for (int b = 0; b < 4; ++b)
+                    if (norm(P(gb[b]) - tgt) <= 1e-8 * h) hit = gb[b];
+                if (hit < 0) {
+                    iso_mesh_destroy(m);
+                    return fail(ISO_EMESH, "cyclic face " + std::to_string(f) + " does not match its partner");
+                }
+                fu.unite(fa[a], hit, T);
+            }
+        }
+    }
+    std::vector<int32_t> cls(n_points, -1), root_cls(n_points, -1);
+    std::vector<V3> to_root(n_points);
+    int32_t n_classes = 0;
+    std::vector<int32_t> cls_root;
+    for (int32_t p = 0; p < n_points; ++p) {
+        int32_t r = fu.find(p, &to_root[p]);
+        if (root_cls[r] < 0) { root_cls[r] = n_classes++; cls_root.push_back(r); }
+        cls[p] = root_cls[r];
+    }
+    m->n_classes = n_classes;
+    // stencil of each class: every (cell, vertex) whose point is in the class, centre in the root frame
+    std::vector<int32_t> cnt(n_classes + 1, 0);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int i = 0; i < 8; ++i) cnt[cls[m->cell_pts[8 * (size_t)c + i]] + 1]++;
+    for (int32_t k = 0; k < n_classes; ++k) cnt[k + 1] += cnt[k];
+    std::vector<int32_t> st_cell(cnt[n_classes]);
+    std::vector<double> st_w(cnt[n_classes]);
+    std::vector<int32_t> fillc(n_classes, 0);
+    for (int32_t c = 0; c < n_cells; ++c)  // ascending cell id within each stencil
+        for (int i = 0; i < 8; ++i) {
+            int32_t p = m->cell_pts[8 * (size_t)c + i];
+            int32_t k = cls[p];
+            int32_t e = cnt[k] + fillc[k]++;
+            st_cell[e] = c;
+            V3 xc{m->xc[3 * c], m->xc[3 * c + 1], m->xc[3 * c + 2]};
+            V3 xr = P(cls_root[k]);
+            st_w[e] = 1.0 / norm(xr - (xc + to_root[p]));  // R: inverse centre-to-vertex distance
+        }
+    for (int32_t k = 0; k < n_classes; ++k) {
+        double s = 0;
+        for (int32_t e = cnt[k]; e < cnt[k + 1]; ++e) s += st_w[e];
+        for (int32_t e = cnt[k]; e < cnt[k + 1]; ++e) st_w[e] /= s;
+    }
+    std::vector<int32_t> cpt(8 * (size_t)n_cells);
+    for (size_t i = 0; i < cpt.size(); ++i) cpt[i] = cls[m->cell_pts[i]];
+    std::vector<double> cxyz(24 * (size_t)n_cells);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int i = 0; i < 8; ++i) {
+            V3 x = P(m->cell_pts[8 * (size_t)c + i]);
+            cxyz[24 * (size_t)c + 3 * i] = x.x;
+            cxyz[24 * (size_t)c + 3 * i + 1] = x.y;
+            cxyz[24 * (size_t)c + 3 * i + 2] = x.z;
+        }
+    m->patch_alpha.assign(std::max(n_patches, 1), 0.0);
+    for (int32_t p = 0; p < n_patches; ++p) m->patch_alpha[p] = patch_alpha_in[p];
+
+    // ---- device
+    if (hipGetDevice(&m->device) != hipSuccess) { iso_mesh_destroy(m); return fail(ISO_EDEVICE, "no HIP device"); }
+    DevMesh &d = m->dev;
+    d.n_cells = n_cells; d.n_faces = n_faces; d.n_classes = n_classes; d.W = W; d.n_patches = n_patches;
+    iso_status st = ISO_OK;
+    if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||
+        (st = upload(m, slot_face, &d.slot_face)) || (st = upload(m, slot_nbr, &d.slot_nbr)) ||
+        (st = upload(m, lface, &d.lface)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
+        (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha))) {
+        iso_mesh_destroy(m);
+        return st;
+    }
+    *out = m;
+    return ISO_OK;
+}
+
+iso_status iso_mesh_info(const iso_mesh *m, int64_t *info) {
+    if (!m || !info) return fail(ISO_EINVAL, "null argument");
+    info[0] = m->n_cells; info[1] = m->n_points; info[2] = m->n_faces; info[3] = m->n_flux;
+    info[4] = m->n_classes; info[5] = m->W; info[6] = m->device_bytes; info[7] = 0;
+    return ISO_OK;
+}
+
+iso_status iso_mesh_cell_points(const iso_mesh *m, int32_t *out) {
+    if (!m || !out) return fail(ISO_EINVAL, "null argument");
+    std::memcpy(out, m->cell_pts.data(), m->cell_pts.size() * sizeof(int32_t));
+    return ISO_OK;
+}
+
+iso_status iso_mesh_geometry(const iso_mesh *m, double *vol, double *xc) {
+    if (!m || !vol) return fail(ISO_EINVAL, "null argument");
+    std::memcpy(vol, m->vol.data(), m->vol.size() * sizeof(double));
+    if (xc) std::memcpy(xc, m->xc.data(), m->xc.size() * sizeof(double));
+    return ISO_OK;
+}
+
+void iso_plan_destroy(iso_plan *p) {
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    for (void *a : p->allocations) (void)hipFree(a);
+    if (p->host_counters) (void)hipHostFree(p->host_counters);
+    if (p->host_red) (void)hipHostFree(p->host_red);
+    delete p;
+}
+
+iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *stream, iso_plan **out) {
+    if (!out || !mesh) return fail(ISO_EINVAL, "null argument");
+    *out = nullptr;
+    iso_plan *p = new iso_plan();
+    p->mesh = mesh;
+    if (opt) p->opt = *opt; else iso_options_default(&p->opt);
+    const iso_options &o = p->opt;
+    if (!(o.eps_surf >= 0 && o.eps_surf < 0.5) || !(o.flat_tol >= 0) || !(o.bound_tol >= 0) || o.root_max_iter < 1 ||
+        o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 || o.block_surface < 0 || o.block_surface > 1024 ||
+        o.max_surface < 0) {
+        delete p;
+        return fail(ISO_EINVAL, "bad options");
+    }
+    p->stream = static_cast<hipStream_t>(stream);
+    const int32_t nc = mesh->n_cells, nf = mesh->n_faces;
+    DevWork &w = p->work;
+    w.cap = o.max_surface > 0 ? std::min(o.max_surface, nc) : nc;
+    auto alloc = [&](void **ptr, size_t bytes) -> bool {
+        if (hipMalloc(ptr, std::max<size_t>(bytes, 256)) != hipSuccess) return false;
+        p->allocations.push_back(*ptr);
+        return hipMemset(*ptr, 0, std::max<size_t>(bytes, 256)) == hipSuccess;
+    };
+    bool ok = alloc((void **)&w.counters, kCntNum * sizeof(int32_t)) && alloc((void **)&w.surf, sizeof(int32_t) * w.cap) &&
+              alloc((void **)&w.dvs, sizeof(double) * nf) && alloc((void **)&w.olist, sizeof(int32_t) * 2 * (size_t)nc) &&
+              alloc((void **)&w.tlist, sizeof(int32_t) * nc) && alloc((void **)&w.flist, sizeof(int32_t) * nf) &&
+              alloc((void **)&w.cmark, sizeof(int32_t) * nc) && alloc((void **)&w.fmark, sizeof(int32_t) * nf) &&
+              alloc((void **)&w.delta, sizeof(double) * nf) && alloc((void **)&w.dvcur, sizeof(double) * nf) &&
+              alloc((void **)&w.red, sizeof(double) * 64);
+    if (!ok || hipHostMalloc((void **)&p->host_counters, kCntNum * sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&p->host_red, 64 * sizeof(double)) != hipSuccess) {
+        iso_plan_destroy(p);
+        return fail(ISO_ENOMEM, "plan workspace allocation failed");
+    }
+    if (hipDeviceSynchronize() != hipSuccess) { iso_plan_destroy(p); return fail(ISO_EDEVICE, "device error at plan creation"); }
+    *out = p;
+    return ISO_OK;
+}
+
+iso_status iso_plan_set_stream(iso_plan *p, void *stream) {
+    if (!p) return fail(ISO_EINVAL, "null plan");
+    p->stream = static_cast<hipStream_t>(stream);
+    return ISO_OK;
+}
+
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+static iso_status check_inputs_host(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt) {
+    const iso_mesh *m = p->mesh;
+    std::vector<double> a(m->n_cells), f(m->n_faces), u(3 * (size_t)m->n_cells);
+    if (hipStreamSynchronize(p->stream) != hipSuccess ||
+        hipMemcpy(a.data(), alpha, a.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(f.data(), phi, f.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(u.data(), U, u.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(ISO_EDEVICE, "copy for input check failed");
+    for (double x : a) if (!std::isfinite(x)) return fail(ISO_EINVAL, "non-finite alpha");
+    for (double x : f) if (!std::isfinite(x)) return fail(ISO_EINVAL, "non-finite phi");
+    for (double x : u) if (!std::isfinite(x)) return fail(ISO_EINVAL, "non-finite U");
+    // Courant number 0.5 dt sum|phi| / V over each cell's flux faces
+    std::vector<int32_t> sf((size_t)m->W * m->n_cells);
+    if (hipMemcpy(sf.data(), m->dev.slot_face, sf.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(ISO_EDEVICE, "copy for input check failed");
+    for (int32_t c = 0; c < m->n_cells; ++c) {
+        double s = 0;
+        for (int k = 0; k < m->W; ++k) {
+            int32_t v = sf[(size_t)k * m->n_cells + c];
+            if (v == kEmpty) continue;
+            s += std::fabs(f[v >= 0 ? v : ~v]);
+        }
+        double co = 0.5 * dt * s / m->vol[c];
+        if (co > p->opt.max_courant)
+            return fail(ISO_ECOURANT, "Courant number " + std::to_string(co) + " in cell " + std::to_string(c));
+    }
+    return ISO_OK;
+}
+
+static iso_status step_impl(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt,
+                            double *alpha_new, iso_step_stats *stats, const iso_trace *trace) {
+    if (!p) return fail(ISO_EINVAL, "null plan");
+    if (!alpha || !phi || !U || !alpha_new) return fail(ISO_EINVAL, "null array");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(ISO_EINVAL, "dt must be positive and finite");
+    const iso_mesh *m = p->mesh;
+    size_t nc = (size_t)m->n_cells * 8, nf = (size_t)m->n_faces * 8;
+    if (overlaps(alpha_new, nc, alpha, nc) || overlaps(alpha_new, nc, phi, nf) || overlaps(alpha_new, nc, U, 3 * nc))
+        return fail(ISO_EINVAL, "alpha_new overlaps an input");
+    if (p->opt.check_inputs) {
+        iso_status s = check_inputs_host(p, alpha, phi, U, dt);
+        if (s != ISO_OK) return s;
+    }
+    (void)hipGetLastError();
+    Params prm{p->opt.eps_surf, p->opt.flat_tol, p->opt.bound_tol, p->opt.root_max_iter, p->opt.n_bound_iter,
+               p->opt.clip};
+    StepArgs args{alpha, phi, U, alpha_new, dt};
+    int bc = p->opt.block_cells > 0 ? p->opt.block_cells : 256;
+    int bs = p->opt.block_surface > 0 ? p->opt.block_surface : 64;
+    hipEvent_t *ev = nullptr;
+    if (p->timing_used < p->timing_cap) ev = &p->events[5 * (size_t)p->timing_used++];
+    hipError_t e = launch_step(m->dev, p->work, prm, args, trace, bc, bs, stats != nullptr, p->stream, ev);
+    if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    if (p->work.cap < m->n_cells && !stats) {  // a limited interface-cell list: check it was enough
+        e = hipMemcpyAsync(p->host_counters, p->work.counters, kCntNum * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("device error: ") + hipGetErrorString(e));
+        if (p->host_counters[8 + kCntOverflow] > 0) return fail(ISO_ENOSPACE, "interface cells exceed max_surface");
+    }
+    if (stats) {
+        e = launch_stats(m->dev, p->work, alpha, alpha_new, p->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(p->host_counters, p->work.counters, kCntNum * sizeof(int32_t),
+                                                hipMemcpyDeviceToHost, p->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(p->host_red, p->work.red, 64 * sizeof(double), hipMemcpyDeviceToHost,
+                                                p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("device error: ") + hipGetErrorString(e));
+        const int32_t *hc = p->host_counters + 8;  // counters of the step just finished
+        const double *hr = p->host_red;
+        std::memset(stats, 0, sizeof(*stats));
+        stats->n_surface = hc[kCntSurf];
+        stats->n_flat = hc[kCntFlat];
+        stats->n_nonconverged = hc[kCntNonconv];
+        stats->n_bound_active = hc[kCntActive0];
+        stats->max_root_iter = hc[kCntMaxIter];
+        stats->vol_before = hr[0];
+        stats->vol_after = hr[1];
+        stats->alpha_min = hr[2];
+        stats->alpha_max = hr[3];
+        stats->vol_clipped = hr[4];
+        if (hc[kCntOverflow] > 0) return fail(ISO_ENOSPACE, "interface cells exceed max_surface");
+    }
+    return ISO_OK;
+}
+
+iso_status iso_advect_step(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt,
+                           double *alpha_new, iso_step_stats *stats) {
+    return step_impl(p, alpha, phi, U, dt, alpha_new, stats, nullptr);
+}
+
+iso_status iso_advect_step_traced(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt,
+                                  double *alpha_new, iso_step_stats *stats, const iso_trace *trace) {
+    return step_impl(p, alpha, phi, U, dt, alpha_new, stats, trace);
+}
+
+iso_status iso_plan_set_timing(iso_plan *p, int32_t max_steps) {
+    if (!p || max_steps < 0) return fail(ISO_EINVAL, "bad argument");
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(ISO_EDEVICE, "stream sync failed");
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    p->events.clear();
+    p->timing_cap = p->timing_used = 0;
+    for (int32_t i = 0; i < 5 * max_steps; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return fail(ISO_EDEVICE, "hipEventCreate failed");
+        p->events.push_back(e);
+    }
+    p->timing_cap = max_steps;
+    return ISO_OK;
+}
+
+iso_status iso_plan_timing(iso_plan *p, double *kernel_ms, int32_t *n_steps) {
+    if (!p || !kernel_ms || !n_steps) return fail(ISO_EINVAL, "null argument");
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(ISO_EDEVICE, "stream sync failed");
+    for (int k = 0; k < 4; ++k) kernel_ms[k] = 0.0;
+    for (int32_t st = 0; st < p->timing_used; ++st)
+        for (int k = 0; k < 4; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p->events[5 * (size_t)st + k], p->events[5 * (size_t)st + k + 1]) != hipSuccess)
+                return fail(ISO_EDEVICE, "hipEventElapsedTime failed");
+            kernel_ms[k] += ms;
+        }
+    *n_steps = p->timing_used;
+    p->timing_used = 0;
+    return ISO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+"""Parity at the full sizes of the workloads, in the launch configuration the benchmark times."""
+import numpy as np
+import pytest
+
+import wavegen as W
+from tests.gpuutil import gpu_plan, gpu_trajectory, oracle_trajectory, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_airy_1024x256_full_trajectory(oracle_lib):
+    """Linear Airy wave, 262,144 cells, 200 steps at Courant 0.5, time-varying fluxes: every cell
+    within 1e-10 of the oracle after the whole run."""
+    w = W.airy_1024x256()
+    say(f"[gpu] {w.name}: {w.mesh.n_cells} cells x {w.n_steps} steps")
+    gm, plan = gpu_plan(w.mesh)
+    g = gpu_trajectory(plan, w, w.n_steps)
+    say("[gpu]   oracle trajectory")
+    om = oracle_lib.OracleMesh(w.mesh)
+    o = oracle_trajectory(om, w, w.n_steps)
+    err = np.abs(g - o).max()
+    say(f"[gpu]   max |gpu - oracle| = {err:.3e}")
+    assert err <= 1e-10
+    assert g.min() >= 0.0 and g.max() <= 1.0
+
+
+def test_violent_3d_full_size_steps(oracle_lib):
+    """4.19M-cell graded 3D box: the first step from the initial field and a later step from the GPU's
+    own state (identical inputs to both sides) agree per cell within 1e-10."""
+    import torch
+    w = W.violent_3d()
+    say(f"[gpu] {w.name}: {w.mesh.n_cells} cells")
+    gm, plan = gpu_plan(w.mesh)
+    om = oracle_lib.OracleMesh(w.mesh)
+    phi, U = w.phi_U(0)
+    tphi, tU = to_dev(phi), to_dev(U)
+    a = to_dev(w.alpha0)
+    b = torch.empty_like(a)
+    states = [w.alpha0]
+    for n in range(6):
+        plan.step(a, tphi, tU, w.dt, out=b)
+        a, b = b, a
+        states.append(a.cpu().numpy())
+    for n in (0, 5):
+        say(f"[gpu]   oracle step from state {n}")
+        o, _ = om.step(states[n], phi, U, w.dt)
+        err = np.abs(states[n + 1] - o).max()
+        say(f"[gpu]   step {n}: max |gpu - oracle| = {err:.3e}")
+        assert err <= 1e-10

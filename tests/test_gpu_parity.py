@@ -1,0 +1,120 @@
+"""GPU path (through the C interface) against the CPU oracle, element by element.
+
+Bar: 1e-10 per cell in FP64 for whole trajectories; intermediates of one step from identical
+inputs are compared tighter (they differ only by rounding order).  Interface classification and
+cell kinds must agree exactly.
+"""
+import numpy as np
+import pytest
+
+import wavegen as W
+from tests.gpuutil import gpu_plan, gpu_traced_step, gpu_trajectory, oracle_trajectory, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_TRAJ = 1e-10
+
+
+def small_cases():
+    band_mesh = W.hex_block(np.linspace(0, 1, 17), np.linspace(0, 1.5, 25), [0.0, 1 / 16], periodic_x=True,
+                            periodic_y=True, kinds={"zmin": W.PATCH_EMPTY, "zmax": W.PATCH_EMPTY})
+    phi_b = W.fluxes_from_edge_integral(band_mesh, lambda x, y, z0, z1: (0.7 * y - 0.6 * x) * (z1 - z0))
+    U_b = np.concatenate([np.full(band_mesh.n_cells, 0.7), np.full(band_mesh.n_cells, 0.6), np.zeros(band_mesh.n_cells)])
+    a_b = W.alpha_cosine_2d(band_mesh, 0.9021, 0.0, 1.0) - W.alpha_cosine_2d(band_mesh, 0.3137, 0.0, 1.0)
+    band = W.Workload("band_periodic", band_mesh, a_b, W.courant_dt(band_mesh, phi_b, 0.45), 8,
+                      lambda n: (phi_b, U_b), steady=True)
+    return {
+        "cosine_64x32": W.cosine_uniform(),
+        "airy_128x64": W.airy_slab(128, 64, 32, 0.07, 0.5, 30, "airy_128x64"),
+        "violent_32x16x16": W.violent_3d(nx=32, ny=16, nz=16, steps=10),
+        "band_periodic": band,
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_step_intermediates(O, name):
+    w = CASES[name]
+    say(f"[gpu] one-step intermediates: {name} cells={w.mesh.n_cells}")
+    gm, plan = gpu_plan(w.mesh)
+    om = O.OracleMesh(w.mesh)
+    phi, U = w.phi_U(0)
+    g_new, g_st, g = gpu_traced_step(plan, gm, w.alpha0, phi, U, w.dt)
+    o_new, o_st, o = om.step(w.alpha0, phi, U, w.dt, trace=True)
+    _, V = om.geometry()
+    vol, _ = gm.geometry()
+    assert np.abs(vol - V).max() <= 1e-15 * V.max()
+    # classification
+    assert np.array_equal(g["kind"], o["kind"]), np.nonzero(g["kind"] != o["kind"])[0][:10]
+    assert g_st["n_surface"] == o_st["n_surface"]
+    surf = np.nonzero(o["kind"] > 0)[0]
+    rec = np.nonzero(o["kind"] == 1)[0]
+    assert len(rec) > 0
+    # vertex values of interface cells (inverse-distance interpolation)
+    cp = gm.cell_points()
+    # normalised weights vs. sum-then-divide: a few ulps of a value <= 1
+    assert np.abs(g["vert_alpha"][surf] - o["a_pts"][cp[surf]]).max() <= 16 * np.finfo(float).eps
+    # the GPU isovalue cuts off alpha V to 1e-12, judged by the oracle's sub-volume; where the
+    # sub-volume jumps across alpha V at a vertex value, both sides take that vertex value
+    for c in rec[:: max(1, len(rec) // 40)]:
+        fo = om.cut(c, o["a_pts"], o["iso"][c])["vsub"] / V[c] - w.alpha0[c]
+        if abs(fo) <= 1e-12:
+            cut = om.cut(c, o["a_pts"], g["iso"][c])
+            assert abs(cut["vsub"] / V[c] - w.alpha0[c]) <= 1e-12
+        else:
+            assert abs(g["iso"][c] - o["iso"][c]) <= 8 * np.finfo(float).eps
+    # isoface centre, normal, normal speed
+    h = np.cbrt(V[rec])[:, None]
+    assert np.abs(g["rec"][rec, 0:3] - o["rec"][rec, 0:3]).max() <= 1e-11 * h.max()
+    assert np.abs(g["rec"][rec, 3:6] - o["rec"][rec, 3:6]).max() <= 1e-11
+    assert np.abs(g["rec"][rec, 6] - o["rec"][rec, 6]).max() <= 1e-11 * max(1.0, np.abs(U).max())
+    # face volumes
+    fl = np.abs(phi).max() * w.dt
+    flux_faces = ~np.isnan(g["dV"])
+    assert np.abs(g["dV"][flux_faces] - o["dV"][flux_faces]).max() <= 1e-13 * fl
+    # update and bounding
+    assert np.abs(g["alpha_raw"] - o["alpha_raw"]).max() <= 1e-13
+    assert np.abs(g_new - o_new).max() <= 1e-13
+    assert g_st["n_bound_active"] == o_st["n_bound_active"]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_trajectory(O, name):
+    w = CASES[name]
+    say(f"[gpu] trajectory: {name} steps={w.n_steps}")
+    gm, plan = gpu_plan(w.mesh)
+    om = O.OracleMesh(w.mesh)
+    g = gpu_trajectory(plan, w, w.n_steps)
+    o = oracle_trajectory(om, w, w.n_steps)
+    err = np.abs(g - o).max()
+    say(f"[gpu]   max |gpu - oracle| = {err:.3e}")
+    assert err <= TOL_TRAJ
+
+
+def test_planar_transport_exact_on_gpu(O):
+    """The exactness pin of the oracle holds for the GPU path too (clip off)."""
+    w = CASES["band_periodic"]
+    say("[gpu] planar band transport")
+    gm, plan = gpu_plan(w.mesh, clip=0)
+    a = gpu_trajectory(plan, w, 8)
+    exact = W.alpha_cosine_2d(w.mesh, 0.9021 + 0.6 * 8 * w.dt, 0.0, 1.0) - \
+        W.alpha_cosine_2d(w.mesh, 0.3137 + 0.6 * 8 * w.dt, 0.0, 1.0)
+    assert np.abs(a - exact).max() <= 1e-12
+
+
+def test_determinism_across_launch_shapes():
+    w = CASES["violent_32x16x16"]
+    say("[gpu] determinism across block sizes")
+    outs = []
+    for bc, bs in ((256, 64), (64, 32), (1024, 256), (128, 128)):
+        gm, plan = gpu_plan(w.mesh, block_cells=bc, block_surface=bs)
+        outs.append(gpu_trajectory(plan, w, 5))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])

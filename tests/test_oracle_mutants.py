@@ -29,6 +29,8 @@ MUTANTS = [
     ("isoface_edges_reversed",
      "for (int d = 0; d < 3; ++d) { seg_a[nseg][d] = cp[d]; seg_b[nseg][d] = last_exit[d]; }",
      "for (int d = 0; d < 3; ++d) { seg_b[nseg][d] = cp[d]; seg_a[nseg][d] = last_exit[d]; }"),
+    ("isoface_apex_mean_of_cut_points", "perimeter_centroid(seg_a, seg_b, nseg, 0, o);",
+     "perimeter_centroid(seg_a, seg_a, nseg, 0, o);"),
     ("velocity_components_swapped", "double Uc[3] = {U[c], U[nc + c], U[2 * nc + c]};",
      "double Uc[3] = {U[c], U[2 * nc + c], U[nc + c]};"),
 ]

@@ -438,3 +438,67 @@ def test_face_integral_on_trapezoidal_faces(oracle_lib):
                 / (A1 + A2)
             got = om.face_integral(f, mesh.owner[f], xS, nS, un, dt)
             assert abs(got - ref) <= 1e-13 * dt, (f, got, ref)
+
+
+def test_subvolume_and_isoface_continuous_across_vertex_ties(oracle_lib):
+    """Away from saddle faces (diagonal wet corners), the cut points that merge or split when the
+    isovalue crosses a vertex value must not move the sub-volume or the isoface centre: both are
+    continuous there.  Vertex data = a linear field plus a perturbation (non-planar isofaces)."""
+    mesh = single_cell_mesh(np.array([[1.0, 0.2, 0.1], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]]))
+    om = oracle_lib.OracleMesh(mesh)
+    _, V = om.geometry()
+    rng = np.random.default_rng(31)
+    worst_v, worst_x, ties = 0.0, 0.0, 0
+    fp = mesh.face_pts.reshape(-1, 4)
+
+    def saddle(a_pts, iso):
+        w = a_pts[fp] > iso
+        return np.any((w[:, 0] == w[:, 2]) & (w[:, 1] == w[:, 3]) & (w[:, 0] != w[:, 1]))
+
+    for _ in range(300):
+        g = rng.normal(size=3)
+        a_pts = 0.5 - mesh.points @ g
+        a_pts = a_pts + 0.08 * np.ptp(a_pts) * rng.uniform(-1, 1, mesh.n_points)
+        s = np.sort(a_pts)
+        for tie in s[1:-1]:
+            d = 1e-10
+            if saddle(a_pts, tie - d) or saddle(a_pts, tie + d):
+                continue
+            # a jump keeps its size as the gap closes; a continuous function's difference shrinks with it
+            jv, jx = [], []
+            for dd in (d, 0.01 * d):
+                lo = om.cut(0, a_pts, tie - dd)
+                hi = om.cut(0, a_pts, tie + dd)
+                jv.append(abs(lo["vsub"] - hi["vsub"]) / V[0])
+                jx.append(np.abs(lo["xS"] - hi["xS"]).max())
+            if jv[0] > 1e-12 and jv[1] > 0.1 * jv[0]:
+                worst_v = max(worst_v, jv[0])
+            if jx[0] > 1e-12 and jx[1] > 0.1 * jx[0]:
+                worst_x = max(worst_x, jx[0])
+            ties += 1
+    assert ties > 1000
+    assert worst_v == 0.0 and worst_x == 0.0, (worst_v, worst_x)
+
+
+def test_isovalue_is_root_or_jump(oracle_lib):
+    """The sub-volume is non-increasing in the isovalue; with arbitrary vertex data (saddle faces) it can
+    jump at a vertex value.  The isovalue is the root where the volume fraction is continuous, and the
+    vertex value itself where the volume fraction jumps across alpha_P."""
+    mesh = single_cell_mesh(np.array([[1.0, 0.2, 0.1], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]]))
+    om = oracle_lib.OracleMesh(mesh)
+    _, V = om.geometry()
+    rng = np.random.default_rng(32)
+    jumps = 0
+    for _ in range(300):
+        a_pts = rng.uniform(0, 1, mesh.n_points)
+        grid = np.linspace(a_pts.min(), a_pts.max(), 41)
+        vs = [om.cut(0, a_pts, x)["vsub"] for x in grid]
+        assert np.all(np.diff(vs) <= 1e-14 * V[0])
+        alpha = rng.uniform(0.02, 0.98)
+        iso, _ = om.isovalue(0, a_pts, alpha)
+        f = om.cut(0, a_pts, iso)["vsub"] / V[0] - alpha
+        if abs(f) > 1e-12:
+            jumps += 1
+            assert np.any(a_pts == iso)
+            assert f < 0 and om.cut(0, a_pts, np.nextafter(iso, -1))["vsub"] / V[0] - alpha > 0
+    assert jumps > 0

@@ -226,8 +226,16 @@ def face_vertical_edges(mesh: Mesh):
 
     Returns (face index, x, y, z_from, z_to) arrays for every pair of consecutive
     face points that share x and y; walking the face counter-clockwise from
-    outside gives the edge direction.
+    outside gives the edge direction.  Cached on the mesh.
     """
+    cached = getattr(mesh, "_vertical_edges", None)
+    if cached is not None:
+        return cached
+    mesh._vertical_edges = _face_vertical_edges(mesh)
+    return mesh._vertical_edges
+
+
+def _face_vertical_edges(mesh: Mesh):
     nf = mesh.n_faces
     fp = mesh.face_pts.reshape(nf, 4)
     P = mesh.points
