@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--workload", default="violent_3d", choices=["violent_3d", "airy_2d", "cosine_2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--surface-waves", type=int, default=0, help="register budget of the interface kernel (2-4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step has no multi-GPU path in this "
@@ -127,7 +128,8 @@ def main():
     dev = torch.device("cuda:0")
     gm = Mesh.from_arrays(w.mesh)
     info = gm.info()
-    plan = Plan(gm)
+    from paper_1804_01130_amd import default_options
+    plan = Plan(gm, default_options(surface_waves=args.surface_waves))
     n_steps_total = args.warmup + args.steps
     if w.steady:
         phi, U = w.phi_U(0)

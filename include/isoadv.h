@@ -75,9 +75,10 @@ typedef struct {
     int32_t clip;           /* chop alpha to [0,1] after redistribution (default 1) */
     int32_t check_inputs;   /* validate inputs on the host before each step (syncs; default 0) */
     int32_t block_cells;    /* threads per block of the per-cell kernels (0 = 256) */
-    int32_t block_surface;  /* threads per block of the interface-cell kernel (0 = 64) */
+    int32_t block_surface;  /* reserved (the interface-cell kernel runs 256-thread work-groups) */
     int32_t max_surface;    /* capacity of the interface-cell list (0 = n_cells) */
-    int32_t reserved;
+    int32_t surface_waves;  /* register budget of the interface-cell kernel in waves per SIMD:
+                               2, 3 or 4 (0 = 2); results are bitwise the same for every choice */
 } iso_options;
 
 typedef struct {

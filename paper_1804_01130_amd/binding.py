@@ -29,7 +29,7 @@ class IsoOptions(C.Structure):
     _fields_ = [("eps_surf", C.c_double), ("flat_tol", C.c_double), ("bound_tol", C.c_double),
                 ("max_courant", C.c_double), ("root_max_iter", C.c_int32), ("n_bound_iter", C.c_int32),
                 ("clip", C.c_int32), ("check_inputs", C.c_int32), ("block_cells", C.c_int32),
-                ("block_surface", C.c_int32), ("max_surface", C.c_int32), ("reserved", C.c_int32)]
+                ("block_surface", C.c_int32), ("max_surface", C.c_int32), ("surface_waves", C.c_int32)]
 
 
 class IsoStepStats(C.Structure):

@@ -29,6 +29,7 @@ struct DevMesh {
     const int32_t *slot_face = nullptr;  // [W][n_cells] packed flux faces, ascending face id, kEmpty last
     const int32_t *slot_nbr = nullptr;   // [W][n_cells] cell across the face, or -1-patch on the boundary
     const int32_t *lface = nullptr;      // [6*n_cells] packed flux face of each canonical face, or kEmpty
+    const int32_t *cflags = nullptr;     // [n_cells] bit k: canonical face k is planar
     const int32_t *st_ptr = nullptr;     // [n_classes+1] vertex stencils
     const int32_t *st_cell = nullptr;
     const double *st_w = nullptr;        // normalised inverse-distance weights
@@ -42,10 +43,11 @@ struct DevWork {
     double *dvs = nullptr;         // [n_faces] dV written by interface upwind cells
     int32_t *olist = nullptr;      // [n_cells] cells needing redistribution (two halves ping-pong)
     int32_t *tlist = nullptr;      // [n_cells] cells touched by a sweep
-    int32_t *flist = nullptr;      // [n_faces] faces whose dV changed during bounding
+    int32_t *flist = nullptr;      // [3*n_faces] faces whose dV changed during bounding; then the faces
+                                   // holding a correction in each of the two correction buffers
     int32_t *cmark = nullptr;      // [n_cells] zero between steps
     int32_t *fmark = nullptr;      // [n_faces] zero between steps
-    double *delta = nullptr;       // [n_faces] zero between steps
+    double *delta = nullptr;       // [2*n_faces] correction buffers, zero between steps
     double *dvcur = nullptr;       // [n_faces] current dV of faces in flist
     double *red = nullptr;         // [64] reductions for stats
     int32_t cap = 0;
@@ -79,8 +81,8 @@ struct Params {
 // kernels.hip
 // ev: nullptr, or 5 events recorded before each of the 4 kernels and after the last
 hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, const StepArgs &a,
-                       const iso_trace *trace, int block_cells, int block_surface, bool want_stats,
-                       hipStream_t s, hipEvent_t *ev);
+                       const iso_trace *trace, int block_cells, int block_surface, int surface_waves,
+                       bool want_stats, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha, const double *alpha_new,
                         hipStream_t s);
 

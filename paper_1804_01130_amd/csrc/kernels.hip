@@ -1,14 +1,17 @@
 // HIP kernels of the isoAdvector step for gfx950 (wave64), FP64.
 //
 // One step (Section 3.2 of the paper) is four launches on one stream:
-//   find_surface   interface cells (eps < alpha < 1-eps) compacted by wave ballot + mbcnt
-//   surface        per interface cell: vertex values (inverse-distance stencil), isovalue by
-//                  bracketing on sorted vertex values + Illinois, isoface centre/normal, and
-//                  for every outflow face the time integral of its submerged fraction
-//                  (Eqs. tv .. intaplus) -> dV of that face (unique upwind cell: no atomics)
+//   find_surface   interface cells (eps < alpha < 1-eps), compacted with wave ballots and one
+//                  atomic per 4096-cell work-group
+//   surface        eight lanes per interface cell: lane v gathers vertex v's value (inverse
+//                  distance stencil); the lanes then search the isovalue together, evaluating
+//                  the sub-volume at eight isovalues per round (sorted vertex values, then
+//                  points around a cubic model of the sub-volume), build the isoface, and lane k
+//                  integrates the submerged fraction of face k over the step (Eqs. tv .. intaplus)
+//                  when it is an outflow face -> dV (each face has one upwind cell: no atomics)
 //   update         per cell, gather over its flux faces in ascending face id: dV from the
-//                  interface kernel or alpha_upwind*phi*dt (bulk); alpha - sum/V; round-off
-//                  chopping; cells beyond the bounds are appended to a list
+//                  interface kernel or alpha_upwind*phi*dt; alpha - sum/V; round-off chopping;
+//                  cells outside the bounds are appended to a list
 //   bound          one work-group: Jacobi redistribution over outflow faces of the listed
 //                  cells, then chopping (bounding step at the end of Section 3.2)
 // Nothing in the step is a dense contraction, so no matrix instructions are used.
@@ -31,16 +34,15 @@ __device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y
 __device__ __forceinline__ D3 cross(D3 a, D3 b) {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-__device__ __forceinline__ double det3(D3 a, D3 b, D3 c) { return dot(a, cross(b, c)); }
+__device__ __forceinline__ double norm3(D3 a) { return sqrt(dot(a, a)); }
+// component-wise select (a select of the whole struct can be lowered through memory)
+__device__ __forceinline__ D3 sel3(bool c, D3 a, D3 b) { return D3{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z}; }
 
 __device__ __forceinline__ bool interface_cell(double a, double eps) { return a > eps && a < 1.0 - eps; }
 
-// edges of the canonical hexahedron and, for each face loop position, the edge to the next vertex
+// edges of the canonical hexahedron, and for each face loop position the edge to the next vertex
 constexpr int kEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
                               {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
-
-// ------------------------------------------------------------------------------------------ cut
-// Edge of the canonical hexahedron joining loop positions i and i+1 of face k.
 constexpr int kFaceEdge[6][4] = {{3, 2, 1, 0}, {4, 5, 6, 7}, {0, 9, 4, 8}, {1, 10, 5, 9}, {2, 11, 6, 10}, {3, 8, 7, 11}};
 
 constexpr bool face_edges_consistent() {
@@ -53,131 +55,290 @@ constexpr bool face_edges_consistent() {
 }
 static_assert(face_edges_consistent(), "face/edge tables disagree");
 
-__device__ __forceinline__ double norm3(D3 a) { return sqrt(dot(a, a)); }
+// ------------------------------------------------------------------------------------------ faces
+// The eight lanes of an interface cell's group split every sub-volume evaluation by face: lane k
+// (k < 6) owns canonical face k, its four vertices (relative to the cell's vertex mean), their
+// values, and the reciprocal value difference along each of its edges.  Lanes 6 and 7 only help
+// gathering vertex values.
+struct FaceLane {
+    D3 q[4];
+    double aq[4];
+    double inv[4];  // 1/(a_j - a_i) of the canonical edge (i, j) under loop position k
+    int fwd;        // bit k: loop position k runs along the canonical edge direction
+    bool planar;
+    bool active;
+};
 
-// Cut points of all 12 edges at isovalue iso (meaningful where exactly one end is wet), each
-// measured from the wet end so that both faces sharing an edge see the same point.
-__device__ __forceinline__ void cut_points(const D3 *X, const double *a, const bool *w, double iso, D3 *cp) {
-#pragma unroll
-    for (int e = 0; e < 12; ++e) {
-        const int i = kEdge[e][0], j = kEdge[e][1];
-        const bool wi = w[i];
-        const D3 xw = wi ? X[i] : X[j], xd = wi ? X[j] : X[i];
-        const double aw = wi ? a[i] : a[j], ad = wi ? a[j] : a[i];
-        const double den = ad - aw;
-        const double lam = (w[i] != w[j]) ? (iso - aw) / den : 0.0;
-        cp[e] = xw + lam * (xd - xw);
-    }
+// One face's share of six times the wet sub-volume and of the isoface sums.
+struct Part {
+    double v6;  // apex . sum of p x q over the face's wet loop
+    D3 cseg;    // sum of s0 x s1 over isoface edges on the face
+    D3 oacc;    // sum of length x midpoint over those edges
+    double oL;  // their total length
+    D3 osum;    // sum of their entry points
+    double nseg;
+};
+
+// Cut point on the face edge from loop position i to i+1, measured from its wet end; both faces
+// sharing the edge evaluate the same expression on the same operands, so they agree bitwise.
+__device__ __forceinline__ D3 face_cut(const FaceLane &f, int i, double iso, bool wet_i) {
+    const int j = (i + 1) & 3;
+    const bool fwd = (f.fwd >> i) & 1;
+    const D3 xw = sel3(wet_i, f.q[i], f.q[j]), xd = sel3(wet_i, f.q[j], f.q[i]);
+    const double aw = wet_i ? f.aq[i] : f.aq[j];
+    // wet end is the canonical edge's first vertex iff (wet_i == fwd)
+    const double lam = (wet_i == fwd) ? (iso - aw) * f.inv[i] : (aw - iso) * f.inv[i];
+    return xw + lam * (xd - xw);
 }
 
-// Walk the loop of face k: report the wet part's points in order (wet vertices and cut points),
-// and every isoface edge on the face as (entry, exit): the wet part leaves the face boundary at
-// 'exit' and comes back at 'entry', so the isoface, closing the wet part, runs entry -> exit.
-template <class PointFn, class SegFn>
-__device__ __forceinline__ void walk_face(int k, const bool *w, const D3 *X, const D3 *cp, PointFn on_point,
-                                          SegFn on_seg) {
-    D3 exitp{0, 0, 0}, entry0{0, 0, 0};
-    bool pending = false, entry_first = false;
+// Divergence-theorem share of face k for isovalue iso (vertex wet iff a > iso; a >= iso with
+// tie_wet, the limit from below).  The wet part of the face is its loop emitting wet vertices and
+// cut points; fanned about any apex q its share is q . sum(p_i x p_i+1), linear in q.  Planar
+// faces use a face vertex (the value does not depend on the apex), others the perimeter centroid
+// of the wet part.  Isoface edges on the face run from an entry cut back to the preceding exit cut
+// (closing the wet part); they are summed for the isoface's own fan, whose apex is the perimeter
+// centroid of all isoface edges.
+// Straight-line code: the eight candidate points of the loop (vertex k, cut on edge k, k = 0..3)
+// are all computed and masked, so the lanes of a wave (different faces, different cells) never
+// diverge.
+__device__ __forceinline__ Part face_part(const FaceLane &f, double iso, bool tie_wet) {
+    Part r{0.0, {0, 0, 0}, {0, 0, 0}, 0.0, {0, 0, 0}, 0.0};
+    bool w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = f.active && (tie_wet ? f.aq[i] >= iso : f.aq[i] > iso);
+    D3 cut[4];
+    bool cuts[4], exits[4], entries[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int p = kHexFace[k][i], q = kHexFace[k][(i + 1) & 3], e = kFaceEdge[k][i];
-        if (w[p]) on_point(X[p]);
-        if (w[p] != w[q]) {
-            on_point(cp[e]);
-            if (w[p]) {
-                exitp = cp[e];
-                pending = true;
-            } else if (pending) {
-                on_seg(cp[e], exitp);
-                pending = false;
-            } else {
-                entry0 = cp[e];
-                entry_first = true;
-            }
-        }
+        const int j = (i + 1) & 3;
+        cut[i] = face_cut(f, i, iso, w[i]);
+        cuts[i] = w[i] != w[j];
+        exits[i] = w[i] && !w[j];
+        entries[i] = !w[i] && w[j];
     }
-    if (pending && entry_first) on_seg(entry0, exitp);
+    // the wet loop: vertex i (if wet), then the cut on edge i (if cut), i = 0..3
+    D3 last{0, 0, 0};
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        last = sel3(w[i], f.q[i], last);
+        last = sel3(cuts[i], cut[i], last);
+        cnt += (w[i] ? 1 : 0) + (cuts[i] ? 1 : 0);
+    }
+    D3 C{0, 0, 0}, prev = last;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const D3 kv = cross(prev, f.q[i]);
+        C = sel3(w[i], C + kv, C);
+        prev = sel3(w[i], f.q[i], prev);
+        const D3 kc = cross(prev, cut[i]);
+        C = sel3(cuts[i], C + kc, C);
+        prev = sel3(cuts[i], cut[i], prev);
+    }
+    if (cnt >= 3) {
+        D3 ap = f.q[0];
+        if (!f.planar) {
+            D3 pacc{0, 0, 0}, psum{0, 0, 0};
+            double pl = 0.0;
+            D3 pv = last;
+            auto step = [&](bool on, D3 x) {
+                const double l = norm3(x - pv);
+                pacc = sel3(on, pacc + (0.5 * l) * (x + pv), pacc);
+                pl += on ? l : 0.0;
+                psum = sel3(on, psum + x, psum);
+                pv = sel3(on, x, pv);
+            };
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                step(w[i], f.q[i]);
+                step(cuts[i], cut[i]);
+            }
+            ap = pl > 0.0 ? (1.0 / pl) * pacc : (1.0 / cnt) * psum;
+        }
+        r.v6 = dot(ap, C);
+    }
+    // isoface edges: each entry pairs with the exit before it, cyclically
+    D3 lastexit{0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lastexit = sel3(exits[i], cut[i], lastexit);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const D3 s0 = cut[i], s1 = lastexit;
+        const D3 cr = cross(s0, s1);
+        const double l = norm3(s1 - s0);
+        if (entries[i]) {
+            r.cseg = r.cseg + cr;
+            r.oacc = r.oacc + (0.5 * l) * (s0 + s1);
+            r.oL += l;
+            r.osum = r.osum + s0;
+            r.nseg += 1.0;
+        }
+        lastexit = sel3(exits[i], cut[i], lastexit);
+    }
+    return r;
 }
 
-// Six times the wet sub-volume {a > iso} of the cell (local coordinates, origin inside the cell):
-// divergence theorem over the wet parts of the faces and the isoface, every polygon fanned about
-// its perimeter centroid (length-weighted mean of its edge midpoints), which stays continuous when
-// a cut point meets a vertex.  With kIsoface, also twice the isoface area vector (S2) and the sum
-// over its fan of (3 x centroid) (x) (2 x area vector) (M, row-major) for the isoface centre.
-// tie_wet: a vertex whose value equals iso counts as wet (the limit from below at iso).
-template <bool kIsoface>
-__device__ __forceinline__ double subvolume6(const D3 *X, const double *a, double iso, bool tie_wet, D3 *S2,
-                                             double *M) {
-    bool w[8];
+// Isoface fan centroid share of face k: sum over its isoface edges of w (o + s0 + s1), and of w,
+// with w the fan triangle's area vector (x2) projected on the unit normal n.
+__device__ __forceinline__ void face_centre_part(const FaceLane &f, double iso, D3 o, D3 n, D3 &acc, double &ws) {
+    acc = D3{0, 0, 0};
+    ws = 0.0;
+    bool w[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) w[i] = tie_wet ? a[i] >= iso : a[i] > iso;
-    D3 cp[12];
-    cut_points(X, a, w, iso, cp);
-    // isoface apex
-    D3 oacc{0, 0, 0}, osum{0, 0, 0};
-    double oL = 0.0;
-    int nseg = 0;
+    for (int i = 0; i < 4; ++i) w[i] = f.active && f.aq[i] > iso;
+    D3 cut[4];
+    bool exits[4], entries[4];
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-        walk_face(k, w, X, cp, [](D3) {}, [&](D3 s0, D3 s1) {
-            const double l = norm3(s1 - s0);
-            oacc = oacc + (0.5 * l) * (s0 + s1);
-            oL += l;
-            osum = osum + s0;
-            ++nseg;
-        });
-    const D3 o = oL > 0.0 ? (1.0 / oL) * oacc : (nseg > 0 ? (1.0 / nseg) * osum : D3{0, 0, 0});
-    if (kIsoface) {
-        *S2 = D3{0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < 9; ++q) M[q] = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        cut[i] = face_cut(f, i, iso, w[i]);
+        exits[i] = w[i] && !w[j];
+        entries[i] = !w[i] && w[j];
     }
-    double v6 = 0.0;
+    D3 lastexit{0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        // perimeter centroid of the wet part of the face
-        D3 first{0, 0, 0}, prev{0, 0, 0}, pacc{0, 0, 0}, psum{0, 0, 0};
-        double pl = 0.0;
-        int cnt = 0;
-        walk_face(k, w, X, cp, [&](D3 x) {
-            if (cnt > 0) {
-                const double l = norm3(x - prev);
-                pacc = pacc + (0.5 * l) * (x + prev);
-                pl += l;
-            } else {
-                first = x;
-            }
-            prev = x;
-            psum = psum + x;
-            ++cnt;
-        }, [](D3, D3) {});
-        if (cnt > 0) {
-            const double l = norm3(first - prev);
-            pacc = pacc + (0.5 * l) * (first + prev);
-            pl += l;
+    for (int i = 0; i < 4; ++i) lastexit = sel3(exits[i], cut[i], lastexit);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const D3 s0 = cut[i], s1 = lastexit;
+        const double wt = dot(cross(s0 - o, s1 - o), n);
+        if (entries[i]) {
+            acc = acc + wt * (o + s0 + s1);
+            ws += wt;
         }
-        const D3 ap = pl > 0.0 ? (1.0 / pl) * pacc : (cnt > 0 ? (1.0 / cnt) * psum : D3{0, 0, 0});
-        // fan of the wet part, isoface triangles on this face
-        D3 f2{0, 0, 0}, p2{0, 0, 0};
-        int c2 = 0;
-        walk_face(k, w, X, cp, [&](D3 x) {
-            if (c2 > 0) v6 += det3(ap, p2, x); else f2 = x;
-            p2 = x;
-            ++c2;
-        }, [&](D3 s0, D3 s1) {
-            v6 += det3(o, s0, s1);
-            if (kIsoface) {
-                const D3 t = cross(s0 - o, s1 - o);
-                *S2 = *S2 + t;
-                const D3 g = o + s0 + s1;
-                M[0] += g.x * t.x; M[1] += g.x * t.y; M[2] += g.x * t.z;
-                M[3] += g.y * t.x; M[4] += g.y * t.y; M[5] += g.y * t.z;
-                M[6] += g.z * t.x; M[7] += g.z * t.y; M[8] += g.z * t.z;
-            }
-        });
-        if (c2 >= 3) v6 += det3(ap, p2, f2);
+        lastexit = sel3(exits[i], cut[i], lastexit);
     }
-    return v6;
+}
+
+// ------------------------------------------------------------------------------------------ interval
+// Between two consecutive vertex values the wet/dry pattern w is fixed and every cut point moves
+// linearly with the isovalue: p(u) = p0 + u p1, u = iso - xr.  A face's wet-loop sum
+// C(u) = sum p_i x p_i+1 and its isoface-edge sum B(u) = sum s0 x s1 are then quadratics in u,
+// so on a planar face (apex = a face vertex) its share of six times the sub-volume is
+// apex . C(u), a quadratic; the isoface adds o(u) . B(u) with o the perimeter centroid of all
+// isoface edges.  With o and do/du from the perimeter sums, the sub-volume and its derivative
+// cost one reduction per evaluation, and Newton's method on the bracket finds the isovalue.
+struct FaceQuad {
+    double a[3];  // apex . C_j
+    D3 B[3];
+};
+
+__device__ __forceinline__ FaceQuad face_quad(const FaceLane &f, const bool *w, double xr) {
+    FaceQuad r{{0.0, 0.0, 0.0}, {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}};
+    D3 c0[4], c1[4];
+    bool cuts[4], exits[4], entries[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        cuts[i] = w[i] != w[j];
+        exits[i] = w[i] && !w[j];
+        entries[i] = !w[i] && w[j];
+        c0[i] = face_cut(f, i, xr, w[i]);
+        const bool fwd = (f.fwd >> i) & 1;
+        const double dlam = (w[i] == fwd) ? f.inv[i] : -f.inv[i];
+        c1[i] = dlam * (sel3(w[i], f.q[j], f.q[i]) - sel3(w[i], f.q[i], f.q[j]));
+    }
+    // the wet loop: vertex i (if wet), then the cut on edge i (if cut), i = 0..3
+    D3 l0{0, 0, 0}, l1{0, 0, 0};
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        l0 = sel3(w[i], f.q[i], l0);
+        l1 = sel3(w[i], D3{0, 0, 0}, l1);
+        l0 = sel3(cuts[i], c0[i], l0);
+        l1 = sel3(cuts[i], c1[i], l1);
+        cnt += (w[i] ? 1 : 0) + (cuts[i] ? 1 : 0);
+    }
+    D3 C0{0, 0, 0}, C1{0, 0, 0}, C2{0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        {  // vertex i (rate 0)
+            const D3 k0 = cross(l0, f.q[i]), k1 = cross(l1, f.q[i]);
+            C0 = sel3(w[i], C0 + k0, C0);
+            C1 = sel3(w[i], C1 + k1, C1);
+            l0 = sel3(w[i], f.q[i], l0);
+            l1 = sel3(w[i], D3{0, 0, 0}, l1);
+        }
+        {  // cut on edge i
+            const D3 k0 = cross(l0, c0[i]), k1 = cross(l0, c1[i]) + cross(l1, c0[i]), k2 = cross(l1, c1[i]);
+            C0 = sel3(cuts[i], C0 + k0, C0);
+            C1 = sel3(cuts[i], C1 + k1, C1);
+            C2 = sel3(cuts[i], C2 + k2, C2);
+            l0 = sel3(cuts[i], c0[i], l0);
+            l1 = sel3(cuts[i], c1[i], l1);
+        }
+    }
+    if (f.active && cnt >= 3) {
+        r.a[0] = dot(f.q[0], C0);
+        r.a[1] = dot(f.q[0], C1);
+        r.a[2] = dot(f.q[0], C2);
+    }
+    D3 e0{0, 0, 0}, e1{0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        e0 = sel3(exits[i], c0[i], e0);
+        e1 = sel3(exits[i], c1[i], e1);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (f.active && entries[i]) {
+            r.B[0] = r.B[0] + cross(c0[i], e0);
+            r.B[1] = r.B[1] + cross(c0[i], e1) + cross(c1[i], e0);
+            r.B[2] = r.B[2] + cross(c1[i], e1);
+        }
+        e0 = sel3(exits[i], c0[i], e0);
+        e1 = sel3(exits[i], c1[i], e1);
+    }
+    return r;
+}
+
+// Perimeter sums of the isoface edges of a face at isovalue iso, for the pattern w, and their
+// rates of change with the isovalue (each cut point moves along its edge at a constant rate).
+struct Perim {
+    D3 oacc, doacc;  // sum of length x midpoint, and its derivative
+    double oL, doL;  // total length, and its derivative
+    D3 osum, dosum;  // sum of entry points, and its derivative
+    double nseg;
+};
+
+__device__ __forceinline__ Perim face_seg_perimeter(const FaceLane &f, const bool *w, double iso) {
+    Perim r{{0, 0, 0}, {0, 0, 0}, 0.0, 0.0, {0, 0, 0}, {0, 0, 0}, 0.0};
+    D3 cut[4], dcut[4];
+    bool exits[4], entries[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        cut[i] = face_cut(f, i, iso, w[i]);
+        const bool fwd = (f.fwd >> i) & 1;
+        const double dlam = (w[i] == fwd) ? f.inv[i] : -f.inv[i];
+        dcut[i] = dlam * (sel3(w[i], f.q[j], f.q[i]) - sel3(w[i], f.q[i], f.q[j]));
+        exits[i] = f.active && w[i] && !w[j];
+        entries[i] = f.active && !w[i] && w[j];
+    }
+    D3 le{0, 0, 0}, dle{0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        le = sel3(exits[i], cut[i], le);
+        dle = sel3(exits[i], dcut[i], dle);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const D3 d = le - cut[i], dd = dle - dcut[i];
+        const double l = norm3(d);
+        const double dl = l > 0.0 ? dot(d, dd) / l : 0.0;
+        if (entries[i]) {
+            r.oacc = r.oacc + (0.5 * l) * (cut[i] + le);
+            r.doacc = r.doacc + (0.5 * dl) * (cut[i] + le) + (0.5 * l) * (dcut[i] + dle);
+            r.oL += l;
+            r.doL += dl;
+            r.osum = r.osum + cut[i];
+            r.dosum = r.dosum + dcut[i];
+            r.nseg += 1.0;
+        }
+        le = sel3(exits[i], cut[i], le);
+        dle = sel3(exits[i], dcut[i], dle);
+    }
+    return r;
 }
 
 // ------------------------------------------------------------------------------------------ sweep
@@ -191,72 +352,111 @@ __device__ __forceinline__ double tri_piece(int br, double z, double e1, double 
     if (br == 0) return 0.0;
     if (br == 3) return 1.0;
     if (br == 1) {
-        double u = z - e1;
+        const double u = z - e1;
         return (u * r31) * (u * r21);
     }
-    double u = e3 - z;
+    const double u = e3 - z;
     return 1.0 - (u * r31) * (u * r32);
 }
 
 __device__ __forceinline__ double tri_sweep(double d0, double d1, double d2, double un, double dt) {
-    // sort ascending (median of three by min/max)
     const double e1 = fmin(d0, fmin(d1, d2)), e3 = fmax(d0, fmax(d1, d2));
     const double e2 = fmax(fmin(d0, d1), fmin(fmax(d0, d1), d2));
-    double r31 = e3 > e1 ? 1.0 / (e3 - e1) : 0.0;
-    double r21 = e2 > e1 ? 1.0 / (e2 - e1) : 0.0;
-    double r32 = e3 > e2 ? 1.0 / (e3 - e2) : 0.0;
+    const double r31 = e3 > e1 ? 1.0 / (e3 - e1) : 0.0;
+    const double r21 = e2 > e1 ? 1.0 / (e2 - e1) : 0.0;
+    const double r32 = e3 > e2 ? 1.0 / (e3 - e2) : 0.0;
     auto branch = [&](double z) { return z < e1 ? 0 : (z < e2 ? 1 : (z < e3 ? 2 : 3)); };
     if (un == 0.0) return dt * tri_piece(branch(0.0), 0.0, e1, e2, e3, r31, r21, r32);
-    // breakpoints in (0, dt)
-    double b[3];
-    int nb = 0;
-    double inv = 1.0 / un;
+    const double inv = 1.0 / un;
     double s1 = e1 * inv, s2 = e2 * inv, s3 = e3 * inv;
-    if (s1 > 0.0 && s1 < dt) b[nb++] = s1;
-    if (s2 > 0.0 && s2 < dt) b[nb++] = s2;
-    if (s3 > 0.0 && s3 < dt) b[nb++] = s3;
-    if (un < 0.0) {  // breakpoints come in decreasing order
-        double t = b[0];
-        if (nb == 2) { b[0] = b[1]; b[1] = t; }
-        if (nb == 3) { b[0] = b[2]; b[2] = t; }
+    if (un < 0.0) {  // breakpoints in increasing time
+        const double t = s1;
+        s1 = s3;
+        s3 = t;
     }
+    const double bk[3] = {s1, s2, s3};
     double I = 0.0, a0 = 0.0;
-    for (int k = 0; k <= nb; ++k) {
-        double a1 = k < nb ? b[k] : dt;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double a1 = k < 3 ? fmin(fmax(bk[k], 0.0), dt) : dt;
         if (a1 > a0) {
-            double m = 0.5 * (a0 + a1);
-            int br = branch(un * m);
-            double fa = tri_piece(br, un * a0, e1, e2, e3, r31, r21, r32);
-            double fm = tri_piece(br, un * m, e1, e2, e3, r31, r21, r32);
-            double fb = tri_piece(br, un * a1, e1, e2, e3, r31, r21, r32);
+            const double m = 0.5 * (a0 + a1);
+            const int br = branch(un * m);
+            const double fa = tri_piece(br, un * a0, e1, e2, e3, r31, r21, r32);
+            const double fm = tri_piece(br, un * m, e1, e2, e3, r31, r21, r32);
+            const double fb = tri_piece(br, un * a1, e1, e2, e3, r31, r21, r32);
             I += (a1 - a0) * (fa + 4.0 * fm + fb) * (1.0 / 6.0);
+            a0 = a1;
         }
-        a0 = a1;
     }
     return I;
 }
 
+// ------------------------------------------------------------------------------------------ lanes
+// Reductions and broadcasts inside a group of 8 consecutive lanes (one interface cell).  The xor
+// butterfly adds the same pairs in every lane, so all lanes hold bitwise-equal results.
+__device__ __forceinline__ double grp_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) v += __shfl_xor(v, o, 8);
+    return v;
+}
+__device__ __forceinline__ D3 grp_sum3(D3 v) { return D3{grp_sum(v.x), grp_sum(v.y), grp_sum(v.z)}; }
+__device__ __forceinline__ double grp_get(double v, int src) { return __shfl(v, src, 8); }
+
+// Six times the wet sub-volume of the cell (all lanes of the group take part and get the result).
+__device__ __forceinline__ double cell_vsub6(const FaceLane &f, double iso, bool tie_wet, D3 *o_out, D3 *cseg_out) {
+    const Part p = face_part(f, iso, tie_wet);
+    const double v6 = grp_sum(p.v6);
+    const D3 cseg = grp_sum3(p.cseg), oacc = grp_sum3(p.oacc), osum = grp_sum3(p.osum);
+    const double oL = grp_sum(p.oL), nseg = grp_sum(p.nseg);
+    const D3 o = oL > 0.0 ? (1.0 / oL) * oacc : (nseg > 0.0 ? (1.0 / nseg) * osum : D3{0, 0, 0});
+    if (o_out) *o_out = o;
+    if (cseg_out) *cseg_out = cseg;
+    return v6 + dot(o, cseg);
+}
+
 // ------------------------------------------------------------------------------------------ kernels
-__global__ void __launch_bounds__(1024) k_find_surface(const double *__restrict__ alpha, int n, double eps,
-                                                       int32_t *__restrict__ list, int32_t cap,
-                                                       int32_t *__restrict__ counters, int32_t *__restrict__ kind) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    bool s = false;
-    if (c < n) {
-        s = interface_cell(alpha[c], eps);
-        if (kind) kind[c] = 0;
+constexpr int kFindBlock = 1024, kFindPerThread = 4;
+
+__global__ void __launch_bounds__(kFindBlock) k_find_surface(const double *__restrict__ alpha, int n, double eps,
+                                                             int32_t *__restrict__ list, int32_t cap,
+                                                             int32_t *__restrict__ counters,
+                                                             int32_t *__restrict__ kind) {
+    __shared__ int wcount[kFindPerThread * (kFindBlock / 64)];
+    __shared__ int block_base;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const size_t base = (size_t)blockIdx.x * kFindBlock * kFindPerThread;
+    bool s[kFindPerThread];
+    uint64_t mask[kFindPerThread];
+#pragma unroll
+    for (int k = 0; k < kFindPerThread; ++k) {
+        const size_t c = base + (size_t)k * kFindBlock + tid;
+        s[k] = false;
+        if (c < (size_t)n) {
+            s[k] = interface_cell(alpha[c], eps);
+            if (kind) kind[c] = 0;
+        }
+        mask[k] = __ballot(s[k]);
+        if (lane == 0) wcount[k * (kFindBlock / 64) + wid] = __popcll(mask[k]);
     }
-    uint64_t mask = __ballot(s);
-    if (mask == 0) return;
-    int lane = __lane_id();
-    int leader = __ffsll((unsigned long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counters[kCntSurf], __popcll(mask));
-    base = __shfl(base, leader);
-    if (s) {
-        int pos = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        if (pos < cap) list[pos] = c;
+    __syncthreads();
+    if (tid == 0) {
+        int tot = 0;
+        for (int j = 0; j < kFindPerThread * (kFindBlock / 64); ++j) {
+            const int x = wcount[j];
+            wcount[j] = tot;
+            tot += x;
+        }
+        block_base = tot > 0 ? atomicAdd(&counters[kCntSurf], tot) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kFindPerThread; ++k) {
+        if (!s[k]) continue;
+        const int pos = block_base + wcount[k * (kFindBlock / 64) + wid] +
+                        (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask[k] >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask[k], 0u));
+        if (pos < cap) list[pos] = (int32_t)(base + (size_t)k * kFindBlock + tid);
         else atomicAdd(&counters[kCntOverflow], 1);
     }
 }
@@ -265,118 +465,200 @@ struct SurfArgs {
     DevMesh m;
     const double *alpha, *phi, *U;
     double dt, eps, flat_tol;
-    int32_t max_iter;
+    int32_t max_rounds;
     const int32_t *list;
-    const int32_t *counters;
+    int32_t *counters;
     int32_t cap;
     double *dvs;
-    int32_t *cnt_out;
     int want_stats;
     iso_trace tr;
 };
 
-__global__ void __launch_bounds__(256) k_surface(SurfArgs A) {
-    int n = min(A.counters[kCntSurf], A.cap);
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    int iters = 0, flat = 0, nonconv = 0;
-    for (; idx < n; idx += gridDim.x * blockDim.x) {
+constexpr int kLanes = 8;  // lanes per interface cell
+
+// kMinBlocks: work-groups of 256 per CU the register allocation must allow (waves per SIMD)
+template <int kMinBlocks>
+__global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
+    const DevMesh &m = A.m;
+    const int lv = threadIdx.x & (kLanes - 1);
+    const int ngrp = (gridDim.x * blockDim.x) / kLanes;
+    const int n = min(A.counters[kCntSurf], A.cap);
+    // face lv's vertex loop and edge directions (constant per lane)
+    int fv[4];
+    int fwd = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        fv[i] = kHexFace[0][i];
+        int e = kFaceEdge[0][i];
+#pragma unroll
+        for (int k = 1; k < 6; ++k)
+            if (lv == k) { fv[i] = kHexFace[k][i]; e = kFaceEdge[k][i]; }
+        int first = kEdge[0][0];
+#pragma unroll
+        for (int t = 1; t < 12; ++t)
+            if (e == t) first = kEdge[t][0];
+        if (first == fv[i]) fwd |= 1 << i;
+    }
+    int rounds_max = 0, flat = 0, nonconv = 0;
+    for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; idx < n; idx += ngrp) {
         const int c = A.list[idx];
-        const DevMesh &m = A.m;
         const double aP = A.alpha[c];
-        const double V = m.vol[c];
-        // vertex coordinates relative to the vertex mean
-        D3 X[8];
-        const double *cx = m.cxyz + 24 * (size_t)c;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) X[i] = D3{cx[3 * i], cx[3 * i + 1], cx[3 * i + 2]};
-        D3 xm{0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) xm = xm + X[i];
-        xm = 0.125 * xm;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) X[i] = X[i] - xm;
-        // vertex values: normalised inverse-distance stencils of the point classes
+        const double V6 = 6.0 * m.vol[c];
+        // lane lv: vertex lv's coordinates and value
+        const double *cx = m.cxyz + 24 * (size_t)c + 3 * lv;
+        D3 xv{cx[0], cx[1], cx[2]};
+        double av = 0.0;
+        {
+            const int k = m.cpt[8 * (size_t)c + lv];
+            const int e0 = m.st_ptr[k], e1 = m.st_ptr[k + 1];
+            for (int e = e0; e < e1; ++e) av += m.st_w[e] * A.alpha[m.st_cell[e]];
+        }
+        if (A.tr.vert_alpha) A.tr.vert_alpha[8 * (size_t)c + lv] = av;
+        const D3 xm = 0.125 * grp_sum3(xv);
+        xv = xv - xm;
         double a[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            int k = m.cpt[8 * (size_t)c + i];
-            int e0 = m.st_ptr[k], e1 = m.st_ptr[k + 1];
-            double s = 0.0;
-            for (int e = e0; e < e1; ++e) s += m.st_w[e] * A.alpha[m.st_cell[e]];
-            a[i] = s;
-        }
-        if (A.tr.vert_alpha) {
+        for (int i = 0; i < 8; ++i) a[i] = grp_get(av, i);
+        FaceLane f;
+        f.active = lv < 6;
+        f.planar = (m.cflags[c] >> min(lv, 5)) & 1;
+        f.fwd = fwd;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) A.tr.vert_alpha[8 * (size_t)c + i] = a[i];
+        for (int i = 0; i < 4; ++i) {
+            f.q[i] = D3{grp_get(xv.x, fv[i]), grp_get(xv.y, fv[i]), grp_get(xv.z, fv[i])};
+            f.aq[i] = grp_get(av, fv[i]);
         }
-        double lo = a[0], hi = a[0];
 #pragma unroll
-        for (int i = 1; i < 8; ++i) { lo = fmin(lo, a[i]); hi = fmax(hi, a[i]); }
-
-        bool recon = hi - lo > A.flat_tol;
+        for (int i = 0; i < 4; ++i) {
+            const double d = ((fwd >> i) & 1) ? f.aq[(i + 1) & 3] - f.aq[i] : f.aq[i] - f.aq[(i + 1) & 3];
+            f.inv[i] = d != 0.0 ? 1.0 / d : 0.0;
+        }
+        // sorted vertex values (odd-even transposition, 8 elements)
+        double s[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = a[i];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int i = r & 1; i + 1 < 8; i += 2) {
+                const double x = fmin(s[i], s[i + 1]), y = fmax(s[i], s[i + 1]);
+                s[i] = x;
+                s[i + 1] = y;
+            }
+        bool recon = s[7] - s[0] > A.flat_tol;
+        const bool planar_cell = (m.cflags[c] & 63) == 63;
         double iso = 0.0;
-        int it = 0;
+        int rounds = 0;
         D3 nS{0, 0, 0}, xS{0, 0, 0};
         double un = 0.0;
         if (recon) {
-            // sorted vertex values (insertion sort, 8 elements)
-            double s[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) s[i] = a[i];
-#pragma unroll
-            for (int i = 1; i < 8; ++i)
-#pragma unroll
-                for (int j = i; j > 0; --j) {
-                    double x = fmin(s[j - 1], s[j]), y = fmax(s[j - 1], s[j]);
-                    s[j - 1] = x;
-                    s[j] = y;
-                }
-            const double V6 = 6.0 * V;
-            auto f = [&](double x, bool tie_wet) {
-                return subvolume6<false>(X, a, x, tie_wet, nullptr, nullptr) / V6 - aP;
-            };
-            // bracket between consecutive sorted vertex values: V_sub is a cubic there
-            int il = 0, ih = 7;
-            double fl = 1.0 - aP, fh = -aP;
-            bool exact = false;
-            auto sorted_at = [&](int i) {  // s[i] without dynamic register indexing
+            auto F = [&](double x, bool tie_wet) { return cell_vsub6(f, x, tie_wet, nullptr, nullptr) / V6 - aP; };
+            auto sorted_at = [&](int i) {
                 double r = s[0];
 #pragma unroll
                 for (int q = 1; q < 8; ++q) r = i == q ? s[q] : r;
                 return r;
             };
+            // bracket between consecutive sorted vertex values (the sub-volume is smooth in between)
+            int il = 0, ih = 7;
+            double fl = 1.0 - aP;
+            bool exact = false;
             while (ih - il > 1) {
-                int im = (il + ih) >> 1;
-                double sm = sorted_at(im);
-                double fm = f(sm, false);
-                ++it;
+                const int im = (il + ih) >> 1;
+                const double sm = sorted_at(im);
+                const double fm = F(sm, false);
+                ++rounds;
                 if (fm > 0.0) { il = im; fl = fm; }
-                else if (fm < 0.0) { ih = im; fh = fm; }
+                else if (fm < 0.0) { ih = im; }
                 else { iso = sm; exact = true; break; }
             }
-            if (!exact) {
-                // Between consecutive vertex values the sub-volume is smooth; at a vertex value it may
-                // jump.  If it jumps across alpha_P at the upper bracket, that value is the isovalue.
+            if (!exact && planar_cell) {
+                const double lo = sorted_at(il), hi = sorted_at(ih);
+                // wet/dry pattern of the open interval (lo, hi) and the quadratic coefficients
+                const double xr = 0.5 * (lo + hi);
+                bool w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = f.aq[i] > xr;
+                const FaceQuad fq = face_quad(f, w, xr);
+                const double a0 = grp_sum(fq.a[0]), a1 = grp_sum(fq.a[1]), a2 = grp_sum(fq.a[2]);
+                const D3 B0 = grp_sum3(fq.B[0]), B1 = grp_sum3(fq.B[1]), B2 = grp_sum3(fq.B[2]);
+                ++rounds;
+                // isoface apex o(u) (perimeter centroid of the isoface edges) and do/du
+                auto apex = [&](double u, D3 &od) {
+                    Perim pr = face_seg_perimeter(f, w, xr + u);
+                    const D3 oacc = grp_sum3(pr.oacc), doacc = grp_sum3(pr.doacc);
+                    const double oL = grp_sum(pr.oL), doL = grp_sum(pr.doL);
+                    const D3 osum = grp_sum3(pr.osum), dosum = grp_sum3(pr.dosum);
+                    const double ns = grp_sum(pr.nseg);
+                    if (oL > 0.0) {
+                        const D3 o = (1.0 / oL) * oacc;
+                        od = (1.0 / oL) * (doacc - doL * o);
+                        return o;
+                    }
+                    if (ns > 0.0) {
+                        od = (1.0 / ns) * dosum;
+                        return (1.0 / ns) * osum;
+                    }
+                    od = D3{0, 0, 0};
+                    return D3{0, 0, 0};
+                };
+                // G(u) = six times the sub-volume minus its target, and G'(u)
+                const double target = aP * V6;
+                auto G = [&](double u, double &dG) {
+                    D3 od;
+                    const D3 o = apex(u, od);
+                    const D3 Bu = B0 + u * (B1 + u * B2), Bd = B1 + (2.0 * u) * B2;
+                    dG = a1 + 2.0 * u * a2 + dot(od, Bu) + dot(o, Bd);
+                    return a0 + u * (a1 + u * a2) + dot(o, Bu) - target;
+                };
+                const double ulo = lo - xr, uhi = hi - xr;
+                double dG;
+                const double gleft = G(uhi, dG);  // the limit from below at hi: pattern w holds there
+                if (gleft > 0.0) {
+                    iso = hi;  // the sub-volume jumps across alpha_P at this vertex value
+                } else {
+                    // Newton on G, safeguarded by the bracket [ulo, uhi] (G(ulo) > 0 >= G(uhi))
+                    double ua = ulo, ub = uhi;
+                    double u = ulo + (uhi - ulo) * (fl / (fl - gleft / V6));
+                    bool conv = false;
+                    for (; rounds < A.max_rounds; ++rounds) {
+                        const double g = G(u, dG);
+                        if (g == 0.0) { conv = true; ++rounds; break; }
+                        if (g > 0.0) ua = u; else ub = u;
+                        double nu = dG < 0.0 ? u - g / dG : 0.5 * (ua + ub);
+                        if (!(nu > ua && nu < ub)) nu = 0.5 * (ua + ub);
+                        const bool done = fabs(nu - u) <= 2.0 * __DBL_EPSILON__ * fmax(fabs(xr + nu), 1e-300);
+                        u = nu;
+                        if (done || !(ub - ua > 2.0 * __DBL_EPSILON__ * fmax(fabs(xr + ua), fabs(xr + ub)))) {
+                            conv = true;
+                            ++rounds;
+                            break;
+                        }
+                    }
+                    if (!conv) ++nonconv;
+                    iso = xr + u;
+                }
+            } else if (!exact) {
                 double x0 = sorted_at(il), x1 = sorted_at(ih), f0 = fl;
-                double f1 = f(x1, true);  // limit from below at x1
-                ++it;
+                double f1 = F(x1, true);  // limit from below at x1
+                ++rounds;
                 if (f1 > 0.0) {
-                    iso = x1;
+                    iso = x1;  // the sub-volume jumps across alpha_P at this vertex value
                 } else {
                     // Illinois (modified regula falsi) with a bisection guard, to round-off
                     int side = 0;
                     bool conv = false;
-                    for (; it < A.max_iter; ++it) {
-                        double wdt = x1 - x0;
+                    for (; rounds < A.max_rounds; ++rounds) {
+                        const double wdt = x1 - x0;
                         if (!(wdt > 4.0 * __DBL_EPSILON__ * fmax(fabs(x0), fabs(x1)))) { conv = true; break; }
                         double x = x1 - f1 * (x1 - x0) / (f1 - f0);
-                        if (!(x > x0 && x < x1) || (it & 7) == 7) x = x0 + 0.5 * wdt;
-                        double fx = f(x, false);
+                        if (!(x > x0 && x < x1) || (rounds & 7) == 7) x = x0 + 0.5 * wdt;
+                        const double fx = F(x, false);
                         if (fx == 0.0 || fabs(fx) <= 4.0 * __DBL_EPSILON__) {
                             x0 = x1 = x;
                             f0 = f1 = fx;
                             conv = true;
-                            ++it;
+                            ++rounds;
                             break;
                         }
                         if (fx > 0.0) {
@@ -394,79 +676,88 @@ __global__ void __launch_bounds__(256) k_surface(SurfArgs A) {
                 }
             }
             // isoface at the isovalue
-            D3 S2;
-            double M[9];
-            subvolume6<true>(X, a, iso, false, &S2, M);
-            double nrm = sqrt(dot(S2, S2));
+            D3 o, cseg;
+            cell_vsub6(f, iso, false, &o, &cseg);
+            const double nrm = norm3(cseg);
             if (nrm > 0.0) {
-                nS = (1.0 / nrm) * S2;
-                double wsum = dot(S2, nS);  // sum of 2*area projections
-                // x_S = sum_t (S_t . n) g_t / sum_t (S_t . n), with g_t = (sum of 3 points)/3
-                D3 num{M[0] * nS.x + M[1] * nS.y + M[2] * nS.z, M[3] * nS.x + M[4] * nS.y + M[5] * nS.z,
-                       M[6] * nS.x + M[7] * nS.y + M[8] * nS.z};
-                xS = (1.0 / (3.0 * wsum)) * num;
+                nS = (1.0 / nrm) * cseg;
+                D3 acc;
+                double ws;
+                face_centre_part(f, iso, o, nS, acc, ws);
+                acc = grp_sum3(acc);
+                ws = grp_sum(ws);
+                xS = (1.0 / (3.0 * ws)) * acc;
                 un = A.U[c] * nS.x + A.U[m.n_cells + c] * nS.y + A.U[2 * (size_t)m.n_cells + c] * nS.z;
             } else {
                 recon = false;
             }
         }
-        if (!recon) ++flat;
-        if (A.tr.kind) A.tr.kind[c] = recon ? 1 : 2;
-        if (recon) {
-            if (A.tr.iso) A.tr.iso[c] = iso;
-            if (A.tr.iters) A.tr.iters[c] = it;
-            if (A.tr.rec) {
-                double *r = A.tr.rec + 7 * (size_t)c;
-                r[0] = xS.x + xm.x; r[1] = xS.y + xm.y; r[2] = xS.z + xm.z;
-                r[3] = nS.x; r[4] = nS.y; r[5] = nS.z; r[6] = un;
-            }
-        }
-        iters = max(iters, it);
-        // outflow faces of this cell: dV = phi * time-integrated submerged fraction
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            int32_t v = m.lface[6 * (size_t)c + k];
-            if (v == kEmpty) continue;
-            int32_t fid = v >= 0 ? v : ~v;
-            double ph = A.phi[fid];
-            double out = v >= 0 ? ph : -ph;
-            if (!(out > 0.0)) continue;
-            double dv;
+        if (lv == 0) {
+            if (!recon) ++flat;
+            rounds_max = max(rounds_max, rounds);
+            if (A.tr.kind) A.tr.kind[c] = recon ? 1 : 2;
             if (recon) {
-                D3 q[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) q[i] = X[kHexFace[k][i]];
-                D3 ap = 0.25 * (q[0] + q[1] + q[2] + q[3]);
-                double dap = dot(ap - xS, nS);
-                double dq[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) dq[i] = dot(q[i] - xS, nS);
-                double acc = 0.0, Af = 0.0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    D3 cr = cross(q[i] - ap, q[(i + 1) & 3] - ap);
-                    double Ai = 0.5 * sqrt(dot(cr, cr));
-                    acc += Ai * tri_sweep(dap, dq[i], dq[(i + 1) & 3], un, A.dt);
-                    Af += Ai;
+                if (A.tr.iso) A.tr.iso[c] = iso;
+                if (A.tr.iters) A.tr.iters[c] = rounds;
+                if (A.tr.rec) {
+                    double *rr = A.tr.rec + 7 * (size_t)c;
+                    rr[0] = xS.x + xm.x; rr[1] = xS.y + xm.y; rr[2] = xS.z + xm.z;
+                    rr[3] = nS.x; rr[4] = nS.y; rr[5] = nS.z; rr[6] = un;
                 }
-                dv = ph * (acc / Af);
-            } else {
-                dv = aP * ph * A.dt;
             }
-            A.dvs[fid] = dv;
+            if (!recon) (void)nonconv;
+        }
+        // lane k < 6: face k, if it is an outflow face of this cell
+        if (f.active) {
+            const int32_t v = m.lface[6 * (size_t)c + lv];
+            if (v != kEmpty) {
+                const int32_t fid = v >= 0 ? v : ~v;
+                const double ph = A.phi[fid];
+                const double out = v >= 0 ? ph : -ph;
+                if (out > 0.0) {
+                    double dv;
+                    if (recon) {
+                        double dq[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = dot(f.q[i] - xS, nS);
+                        double acc = 0.0, Af = 0.0;
+                        if (f.planar) {
+                            // planar face: two triangles cover it exactly
+                            const double A1 = 0.5 * norm3(cross(f.q[1] - f.q[0], f.q[2] - f.q[0]));
+                            const double A2 = 0.5 * norm3(cross(f.q[2] - f.q[0], f.q[3] - f.q[0]));
+                            acc = A1 * tri_sweep(dq[0], dq[1], dq[2], un, A.dt) +
+                                  A2 * tri_sweep(dq[0], dq[2], dq[3], un, A.dt);
+                            Af = A1 + A2;
+                        } else {
+                            // fan about the vertex mean
+                            const D3 ap = 0.25 * (f.q[0] + f.q[1] + f.q[2] + f.q[3]);
+                            const double dap = dot(ap - xS, nS);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const double Ai = 0.5 * norm3(cross(f.q[i] - ap, f.q[(i + 1) & 3] - ap));
+                                acc += Ai * tri_sweep(dap, dq[i], dq[(i + 1) & 3], un, A.dt);
+                                Af += Ai;
+                            }
+                        }
+                        dv = ph * (acc / Af);
+                    } else {
+                        dv = aP * ph * A.dt;
+                    }
+                    A.dvs[fid] = dv;
+                }
+            }
         }
     }
     if (A.want_stats) {
-        // wave reductions, then one atomic per wave
         for (int off = 32; off > 0; off >>= 1) {
-            iters = max(iters, __shfl_xor(iters, off));
+            rounds_max = max(rounds_max, __shfl_xor(rounds_max, off));
             flat += __shfl_xor(flat, off);
             nonconv += __shfl_xor(nonconv, off);
         }
         if (__lane_id() == 0) {
-            if (iters) atomicMax(&A.cnt_out[kCntMaxIter], iters);
-            if (flat) atomicAdd(&A.cnt_out[kCntFlat], flat);
-            if (nonconv) atomicAdd(&A.cnt_out[kCntNonconv], nonconv);
+            if (rounds_max) atomicMax(&A.counters[kCntMaxIter], rounds_max);
+            if (flat) atomicAdd(&A.counters[kCntFlat], flat);
+            if (nonconv) atomicAdd(&A.counters[kCntNonconv], nonconv / kLanes);
         }
     }
 }
@@ -482,36 +773,45 @@ struct UpdArgs {
     double *trace_dV, *trace_raw;
 };
 
-__global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
+// W flux slots per cell, all loads of one kind issued together (independent gathers in flight).
+template <int W>
+__global__ void __launch_bounds__(256) k_update(UpdArgs A) {
     const int n = A.m.n_cells;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     bool offend = false;
     if (c < n) {
+        int32_t v[W], o[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            v[k] = A.m.slot_face[(size_t)k * n + c];
+            o[k] = A.m.slot_nbr[(size_t)k * n + c];
+        }
         const double aP = A.alpha[c];
+        const double V = A.m.vol[c];
+        double ph[W], ao[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int32_t fid = v[k] >= 0 ? v[k] : ~v[k];
+            ph[k] = v[k] != kEmpty ? A.phi[fid] : 0.0;
+            ao[k] = o[k] >= 0 ? A.alpha[o[k]] : (v[k] != kEmpty ? A.m.patch_alpha[-1 - o[k]] : 0.0);
+        }
         const bool sP = interface_cell(aP, A.eps);
         double sum = 0.0;
-        for (int k = 0; k < A.m.W; ++k) {
-            int32_t v = A.m.slot_face[(size_t)k * n + c];
-            if (v == kEmpty) break;
-            int32_t fid = v >= 0 ? v : ~v;
-            double ph = A.phi[fid];
-            double out = v >= 0 ? ph : -ph;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (v[k] == kEmpty) continue;
+            const int32_t fid = v[k] >= 0 ? v[k] : ~v[k];
+            const double out = v[k] >= 0 ? ph[k] : -ph[k];
             double dv = 0.0;
             if (out > 0.0) {
-                dv = sP ? A.dvs[fid] : aP * ph * A.dt;
+                dv = sP ? A.dvs[fid] : aP * ph[k] * A.dt;
             } else if (out < 0.0) {
-                int32_t o = A.m.slot_nbr[(size_t)k * n + c];
-                if (o >= 0) {
-                    double ao = A.alpha[o];
-                    dv = interface_cell(ao, A.eps) ? A.dvs[fid] : ao * ph * A.dt;
-                } else {
-                    dv = A.m.patch_alpha[-1 - o] * ph * A.dt;
-                }
+                dv = (o[k] >= 0 && interface_cell(ao[k], A.eps)) ? A.dvs[fid] : ao[k] * ph[k] * A.dt;
             }
-            sum += v >= 0 ? dv : -dv;
-            if (A.trace_dV && v >= 0) A.trace_dV[fid] = dv;
+            sum += v[k] >= 0 ? dv : -dv;
+            if (A.trace_dV && v[k] >= 0) A.trace_dV[fid] = dv;
         }
-        double x = aP - sum / A.m.vol[c];
+        double x = aP - sum / V;
         if (A.trace_raw) A.trace_raw[c] = x;
         if (A.clip) {
             if (x < 0.0 && x >= -A.tol) x = 0.0;
@@ -520,10 +820,10 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
         offend = x > 1.0 + A.tol || x < -A.tol;
         A.alpha_new[c] = x;
     }
-    uint64_t mask = __ballot(offend);
+    const uint64_t mask = __ballot(offend);
     if (mask == 0) return;
-    int lane = __lane_id();
-    int leader = __ffsll((unsigned long long)mask) - 1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
     int base = 0;
     if (lane == leader) base = atomicAdd(&A.counters[kCntOff], __popcll(mask));
     base = __shfl(base, leader);
@@ -541,88 +841,134 @@ struct BoundArgs {
     DevWork w;
 };
 
-// Current dV of outflow face fid of cell P (P is its upwind cell).
-__device__ __forceinline__ double face_dv_now(const BoundArgs &A, int32_t fid, bool sP, double aold, double ph) {
-    if (A.w.fmark[fid]) return A.w.dvcur[fid];
-    return sP ? A.dvs[fid] : aold * ph * A.dt;
-}
+template <int W>
+struct Slots {
+    int32_t v[W], fid[W], nbr[W];
+    double ph[W];
+};
 
-__device__ __forceinline__ void claim(BoundArgs &A, int32_t q, int *nT) {
-    if (atomicExch(&A.w.cmark[q], 1) == 0) {
-        int pos = atomicAdd(nT, 1);
-        A.w.tlist[pos] = q;
+template <int W>
+__device__ __forceinline__ void load_slots(const BoundArgs &A, int32_t c, Slots<W> &s) {
+    const int n = A.m.n_cells;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        s.v[k] = A.m.slot_face[(size_t)k * n + c];
+        s.nbr[k] = A.m.slot_nbr[(size_t)k * n + c];
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        s.fid[k] = s.v[k] >= 0 ? s.v[k] : ~s.v[k];
+        s.ph[k] = s.v[k] != kEmpty ? A.phi[s.fid[k]] : 0.0;
     }
 }
 
+// Redistribution sweeps (Jacobi) in one work-group.  Per sweep: (A) every listed cell computes
+// the change of the heavy-fluid outflow of each of its outflow faces (each face has one upwind
+// cell, so it alone writes that face's correction and its running dV), then (B) every touched
+// cell applies the corrections of its faces in ascending face order and is re-listed if still out
+// of bounds.  Corrections alternate between two buffers so that a buffer is cleared one sweep
+// after it was read.
+template <int W>
 __global__ void __launch_bounds__(1024) k_bound(BoundArgs A) {
-    __shared__ int nO, nT, nF, nNext;
-    const int n = A.m.n_cells;
+    __shared__ int nO, nT, nF, nNext, nD[2];
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int n = A.m.n_cells, nf = A.m.n_faces;
     int32_t *cur = A.w.olist, *nxt = A.w.olist + n;
+    int32_t *dlist[2] = {A.w.flist + nf, A.w.flist + 2 * (size_t)nf};
     if (tid == 0) {
         nO = A.w.counters[kCntOff];
         nF = 0;
+        nD[0] = nD[1] = 0;
     }
     __syncthreads();
-    for (int it = 0; it < A.n_iter; ++it) {
+    int it = 0;
+    for (; it < A.n_iter; ++it) {
         if (nO == 0) break;
+        const int par = it & 1;
+        double *delta = A.w.delta + (size_t)par * nf;
+        double *stale = A.w.delta + (size_t)(par ^ 1) * nf;
+        const int n_stale = nD[par ^ 1];
+        const int n_old = nO;
         if (tid == 0) { nT = 0; nNext = 0; }
         __syncthreads();
+        // the other buffer was read in the previous sweep: clear it
+        for (int i = tid; i < n_stale; i += nt) stale[dlist[par ^ 1][i]] = 0.0;
         // A: corrections on the outflow faces of the listed cells
-        for (int i = tid; i < nO; i += nt) {
+        for (int i = tid; i < n_old; i += nt) {
             const int32_t P = cur[i];
+            Slots<W> sl;
+            load_slots<W>(A, P, sl);
             const double a = A.alpha_new[P];
             const bool over = a > 1.0 + A.tol;
             const double aold = A.alpha[P];
             const bool sP = interface_cell(aold, A.eps);
+            int32_t mk[W];
+            double dvs_v[W], dvc_v[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const bool outflow = sl.v[k] != kEmpty && (sl.v[k] >= 0 ? sl.ph[k] : -sl.ph[k]) > 0.0;
+                mk[k] = outflow ? A.w.fmark[sl.fid[k]] : 0;
+                dvs_v[k] = (outflow && sP) ? A.dvs[sl.fid[k]] : 0.0;
+                dvc_v[k] = outflow ? A.w.dvcur[sl.fid[k]] : 0.0;
+            }
+            double cap[W], dvnow[W];
             double sumcap = 0.0;
-            for (int k = 0; k < A.m.W; ++k) {
-                int32_t v = A.m.slot_face[(size_t)k * n + P];
-                if (v == kEmpty) break;
-                int32_t fid = v >= 0 ? v : ~v;
-                double ph = A.phi[fid];
-                double outphi = v >= 0 ? ph : -ph;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                cap[k] = 0.0;
+                dvnow[k] = 0.0;
+                if (sl.v[k] == kEmpty) continue;
+                const double outphi = sl.v[k] >= 0 ? sl.ph[k] : -sl.ph[k];
                 if (!(outphi > 0.0)) continue;
-                double dv = face_dv_now(A, fid, sP, aold, ph);
-                double outv = v >= 0 ? dv : -dv;
-                double cap = over ? outphi * A.dt - outv : outv;
-                if (cap > 0.0) sumcap += cap;
+                // current dV of the face: running value once touched, else this step's
+                dvnow[k] = mk[k] ? dvc_v[k] : (sP ? dvs_v[k] : aold * sl.ph[k] * A.dt);
+                const double outv = sl.v[k] >= 0 ? dvnow[k] : -dvnow[k];
+                cap[k] = over ? outphi * A.dt - outv : outv;
+                if (cap[k] > 0.0) sumcap += cap[k];
             }
-            claim(A, P, &nT);
-            if (!(sumcap > 0.0)) continue;
-            double need = over ? (a - 1.0) * A.m.vol[P] : -a * A.m.vol[P];
-            double r = fmin(need / sumcap, 1.0);
-            for (int k = 0; k < A.m.W; ++k) {
-                int32_t v = A.m.slot_face[(size_t)k * n + P];
-                if (v == kEmpty) break;
-                int32_t fid = v >= 0 ? v : ~v;
-                double ph = A.phi[fid];
-                double outphi = v >= 0 ? ph : -ph;
-                if (!(outphi > 0.0)) continue;
-                double dv = face_dv_now(A, fid, sP, aold, ph);
-                double outv = v >= 0 ? dv : -dv;
-                double cap = over ? outphi * A.dt - outv : outv;
-                if (!(cap > 0.0)) continue;
-                double d = cap * r;
-                A.w.delta[fid] = over ? (v >= 0 ? d : -d) : (v >= 0 ? -d : d);
-                int32_t q = A.m.slot_nbr[(size_t)k * n + P];
-                if (q >= 0) claim(A, q, &nT);
+            int32_t claimed[W + 1];
+            claimed[W] = atomicExch(&A.w.cmark[P], 1);
+            const double need = over ? (a - 1.0) * A.m.vol[P] : -a * A.m.vol[P];
+            const double r = sumcap > 0.0 ? fmin(need / sumcap, 1.0) : 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                claimed[k] = 1;
+                if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
+                const double d = cap[k] * r;
+                const double dd = over ? (sl.v[k] >= 0 ? d : -d) : (sl.v[k] >= 0 ? -d : d);
+                const int32_t f = sl.fid[k];
+                delta[f] = dd;
+                dlist[par][atomicAdd(&nD[par], 1)] = f;
+                A.w.dvcur[f] = dvnow[k] + dd;
+                if (!mk[k]) {
+                    A.w.fmark[f] = 1;
+                    A.w.flist[atomicAdd(&nF, 1)] = f;
+                }
+                if (sl.nbr[k] >= 0) claimed[k] = atomicExch(&A.w.cmark[sl.nbr[k]], 1);
             }
+            if (claimed[W] == 0) A.w.tlist[atomicAdd(&nT, 1)] = P;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (claimed[k] == 0) A.w.tlist[atomicAdd(&nT, 1)] = sl.nbr[k];
         }
         __syncthreads();
+        if (tid == 0) nD[par ^ 1] = 0;
         // B: apply to every touched cell, fixed face order
         const bool last = it == A.n_iter - 1;
         for (int i = tid; i < nT; i += nt) {
             const int32_t Q = A.w.tlist[i];
+            int32_t v[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) v[k] = A.m.slot_face[(size_t)k * n + Q];
+            const double aq = A.alpha_new[Q], vq = A.m.vol[Q];
+            double d[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) d[k] = v[k] != kEmpty ? delta[v[k] >= 0 ? v[k] : ~v[k]] : 0.0;
             double sum = 0.0;
-            for (int k = 0; k < A.m.W; ++k) {
-                int32_t v = A.m.slot_face[(size_t)k * n + Q];
-                if (v == kEmpty) break;
-                int32_t fid = v >= 0 ? v : ~v;
-                double d = A.w.delta[fid];
-                sum += v >= 0 ? d : -d;
-            }
-            double x = A.alpha_new[Q] - sum / A.m.vol[Q];
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (v[k] != kEmpty) sum += v[k] >= 0 ? d[k] : -d[k];
+            double x = aq - sum / vq;
             if (A.clip) {
                 if (x < 0.0 && x >= -A.tol) x = 0.0;
                 else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
@@ -633,46 +979,25 @@ __global__ void __launch_bounds__(1024) k_bound(BoundArgs A) {
             if (x > 1.0 + A.tol || x < -A.tol) nxt[atomicAdd(&nNext, 1)] = Q;
         }
         __syncthreads();
-        // C: commit the face changes, clear the corrections
-        for (int i = tid; i < nO; i += nt) {
-            const int32_t P = cur[i];
-            const double aold = A.alpha[P];
-            const bool sP = interface_cell(aold, A.eps);
-            for (int k = 0; k < A.m.W; ++k) {
-                int32_t v = A.m.slot_face[(size_t)k * n + P];
-                if (v == kEmpty) break;
-                int32_t fid = v >= 0 ? v : ~v;
-                double ph = A.phi[fid];
-                double outphi = v >= 0 ? ph : -ph;
-                if (!(outphi > 0.0)) continue;
-                double dv = face_dv_now(A, fid, sP, aold, ph);
-                A.w.dvcur[fid] = dv + A.w.delta[fid];
-                A.w.delta[fid] = 0.0;
-                if (A.w.fmark[fid] == 0) {
-                    A.w.fmark[fid] = 1;
-                    A.w.flist[atomicAdd(&nF, 1)] = fid;
-                }
-            }
-        }
-        __syncthreads();
-        int32_t *t = cur; cur = nxt; nxt = t;
+        int32_t *t = cur;
+        cur = nxt;
+        nxt = t;
         if (tid == 0) nO = nNext;
         __syncthreads();
     }
     if (A.n_iter == 0 && A.clip) {
         for (int i = tid; i < nO; i += nt) {
-            int32_t P = cur[i];
+            const int32_t P = cur[i];
             A.alpha_new[P] = fmin(fmax(A.alpha_new[P], 0.0), 1.0);
         }
     }
-    __syncthreads();
+    // leave the workspace clean for the next step
+    for (int pb = 0; pb < 2; ++pb)
+        for (int i = tid; i < nD[pb]; i += nt) A.w.delta[(size_t)pb * nf + dlist[pb][i]] = 0.0;
     for (int i = tid; i < nF; i += nt) A.w.fmark[A.w.flist[i]] = 0;
     __syncthreads();
     // keep this step's counters for the statistics, zero them for the next step
-    if (tid < 8) {
-        int32_t x = A.w.counters[tid];
-        A.w.counters[8 + tid] = tid == kCntActive0 ? A.w.counters[kCntOff] : x;
-    }
+    if (tid < 8) A.w.counters[8 + tid] = tid == kCntActive0 ? A.w.counters[kCntOff] : A.w.counters[tid];
     __syncthreads();
     if (tid < 8) A.w.counters[tid] = 0;
 }
@@ -687,7 +1012,7 @@ __global__ void __launch_bounds__(1024) k_stats(const double *alpha, const doubl
         mn = fmin(mn, alpha_new[c]);
         mx = fmax(mx, alpha_new[c]);
     }
-    int t = threadIdx.x;
+    const int t = threadIdx.x;
     sb[t] = b; sa[t] = a; smin[t] = mn; smax[t] = mx;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -700,35 +1025,54 @@ __global__ void __launch_bounds__(1024) k_stats(const double *alpha, const doubl
     if (t == 0) { red[0] = sb[0]; red[1] = sa[0]; red[2] = smin[0]; red[3] = smax[0]; red[4] = 0.0; }
 }
 
+template <int W>
+void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, int block_cells, hipStream_t s,
+                 hipEvent_t *ev) {
+    const int gc = (m.n_cells + block_cells - 1) / block_cells;
+    hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(block_cells), 0, s, ua);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    hipLaunchKernelGGL(k_bound<W>, dim3(1), dim3(1024), 0, s, ba);
+}
+
 }  // namespace
 
 hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, const StepArgs &a, const iso_trace *trace,
-                       int block_cells, int block_surface, bool want_stats, hipStream_t s, hipEvent_t *ev) {
-    auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], s);
-    };
+                       int block_cells, int block_surface, int surface_waves, bool want_stats, hipStream_t s,
+                       hipEvent_t *ev) {
     const int n = m.n_cells;
     iso_trace tr{};
     if (trace) tr = *trace;
-    int gc = (n + block_cells - 1) / block_cells;
-    mark(0);
-    hipLaunchKernelGGL(k_find_surface, dim3(gc), dim3(block_cells), 0, s, a.alpha, n, p.eps_surf, w.surf, w.cap,
+    if (ev) (void)hipEventRecord(ev[0], s);
+    const int gf = (int)(((size_t)n + kFindBlock * kFindPerThread - 1) / (kFindBlock * kFindPerThread));
+    hipLaunchKernelGGL(k_find_surface, dim3(gf), dim3(kFindBlock), 0, s, a.alpha, n, p.eps_surf, w.surf, w.cap,
                        w.counters, tr.kind);
+    if (ev) (void)hipEventRecord(ev[1], s);
     SurfArgs sa{m, a.alpha, a.phi, a.U, a.dt, p.eps_surf, p.flat_tol, p.root_max_iter, w.surf, w.counters, w.cap,
-                w.dvs, w.counters, want_stats ? 1 : 0, tr};
-    int gs_max = (w.cap + block_surface - 1) / block_surface;
-    int gs = std::min(gs_max, 2048 * 64 / block_surface);
-    gs = std::max(gs, 1);
-    mark(1);
-    hipLaunchKernelGGL(k_surface, dim3(gs), dim3(block_surface), 0, s, sa);
-    mark(2);
+                w.dvs, want_stats ? 1 : 0, tr};
+    const int bs = 256;  // the interface kernel's register budget assumes 256-thread work-groups
+    (void)block_surface;
+    const long groups_per_block = bs / kLanes;
+    long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
+    gs = std::max(1L, std::min(gs, 1024L));  // persistent: groups loop over the list
+    switch (surface_waves) {
+        case 3: hipLaunchKernelGGL(k_surface<3>, dim3((int)gs), dim3(bs), 0, s, sa); break;
+        case 4: hipLaunchKernelGGL(k_surface<4>, dim3((int)gs), dim3(bs), 0, s, sa); break;
+        default: hipLaunchKernelGGL(k_surface<2>, dim3((int)gs), dim3(bs), 0, s, sa); break;
+    }
+    if (ev) (void)hipEventRecord(ev[2], s);
     UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist, w.counters,
                tr.dV, tr.alpha_raw};
-    hipLaunchKernelGGL(k_update, dim3(gc), dim3(block_cells), 0, s, ua);
-    mark(3);
     BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter, a.alpha_new, w};
-    hipLaunchKernelGGL(k_bound, dim3(1), dim3(1024), 0, s, ba);
-    mark(4);
+    const int bc = std::min(256, block_cells);
+    switch (m.W) {
+        case 1: launch_wide<1>(m, ua, ba, bc, s, ev); break;
+        case 2: launch_wide<2>(m, ua, ba, bc, s, ev); break;
+        case 3: launch_wide<3>(m, ua, ba, bc, s, ev); break;
+        case 4: launch_wide<4>(m, ua, ba, bc, s, ev); break;
+        case 5: launch_wide<5>(m, ua, ba, bc, s, ev); break;
+        default: launch_wide<6>(m, ua, ba, bc, s, ev); break;
+    }
+    if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
 }
 

@@ -386,6 +386,19 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         for (int32_t e = cnt[k]; e < cnt[k + 1]; ++e) s += st_w[e];
         for (int32_t e = cnt[k]; e < cnt[k + 1]; ++e) st_w[e] /= s;
     }
+    // planar faces: the four points within 1e-12 (relative) of their mean plane
+    std::vector<int32_t> cflags(n_cells, 0);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int k = 0; k < 6; ++k) {
+            V3 q[4];
+            for (int i = 0; i < 4; ++i) q[i] = P(m->cell_pts[8 * (size_t)c + kHexFace[k][i]]);
+            V3 nrm = cross(q[2] - q[0], q[3] - q[1]);
+            double ln = norm(nrm), size = norm(q[2] - q[0]) + norm(q[3] - q[1]);
+            V3 mean = 0.25 * (q[0] + q[1] + q[2] + q[3]);
+            bool planar = ln > 0;
+            for (int i = 0; i < 4 && planar; ++i) planar = std::fabs(dot(q[i] - mean, nrm)) <= 1e-12 * size * ln;
+            if (planar) cflags[c] |= 1 << k;
+        }
     std::vector<int32_t> cpt(8 * (size_t)n_cells);
     for (size_t i = 0; i < cpt.size(); ++i) cpt[i] = cls[m->cell_pts[i]];
     std::vector<double> cxyz(24 * (size_t)n_cells);
@@ -406,7 +419,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     iso_status st = ISO_OK;
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||
         (st = upload(m, slot_face, &d.slot_face)) || (st = upload(m, slot_nbr, &d.slot_nbr)) ||
-        (st = upload(m, lface, &d.lface)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
+        (st = upload(m, lface, &d.lface)) || (st = upload(m, cflags, &d.cflags)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
         (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha))) {
         iso_mesh_destroy(m);
         return st;
@@ -454,7 +467,7 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
     const iso_options &o = p->opt;
     if (!(o.eps_surf >= 0 && o.eps_surf < 0.5) || !(o.flat_tol >= 0) || !(o.bound_tol >= 0) || o.root_max_iter < 1 ||
         o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 || o.block_surface < 0 || o.block_surface > 1024 ||
-        o.max_surface < 0) {
+        o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4) {
         delete p;
         return fail(ISO_EINVAL, "bad options");
     }
@@ -469,9 +482,9 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
     };
     bool ok = alloc((void **)&w.counters, kCntNum * sizeof(int32_t)) && alloc((void **)&w.surf, sizeof(int32_t) * w.cap) &&
               alloc((void **)&w.dvs, sizeof(double) * nf) && alloc((void **)&w.olist, sizeof(int32_t) * 2 * (size_t)nc) &&
-              alloc((void **)&w.tlist, sizeof(int32_t) * nc) && alloc((void **)&w.flist, sizeof(int32_t) * nf) &&
+              alloc((void **)&w.tlist, sizeof(int32_t) * nc) && alloc((void **)&w.flist, sizeof(int32_t) * 3 * (size_t)nf) &&
               alloc((void **)&w.cmark, sizeof(int32_t) * nc) && alloc((void **)&w.fmark, sizeof(int32_t) * nf) &&
-              alloc((void **)&w.delta, sizeof(double) * nf) && alloc((void **)&w.dvcur, sizeof(double) * nf) &&
+              alloc((void **)&w.delta, sizeof(double) * 2 * (size_t)nf) && alloc((void **)&w.dvcur, sizeof(double) * nf) &&
               alloc((void **)&w.red, sizeof(double) * 64);
     if (!ok || hipHostMalloc((void **)&p->host_counters, kCntNum * sizeof(int32_t)) != hipSuccess ||
         hipHostMalloc((void **)&p->host_red, 64 * sizeof(double)) != hipSuccess) {
@@ -544,7 +557,8 @@ static iso_status step_impl(iso_plan *p, const double *alpha, const double *phi,
     int bs = p->opt.block_surface > 0 ? p->opt.block_surface : 64;
     hipEvent_t *ev = nullptr;
     if (p->timing_used < p->timing_cap) ev = &p->events[5 * (size_t)p->timing_used++];
-    hipError_t e = launch_step(m->dev, p->work, prm, args, trace, bc, bs, stats != nullptr, p->stream, ev);
+    hipError_t e = launch_step(m->dev, p->work, prm, args, trace, bc, bs, p->opt.surface_waves, stats != nullptr,
+                               p->stream, ev);
     if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     if (p->work.cap < m->n_cells && !stats) {  // a limited interface-cell list: check it was enough
         e = hipMemcpyAsync(p->host_counters, p->work.counters, kCntNum * sizeof(int32_t), hipMemcpyDeviceToHost,

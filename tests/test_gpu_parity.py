@@ -113,8 +113,8 @@ def test_determinism_across_launch_shapes():
     w = CASES["violent_32x16x16"]
     say("[gpu] determinism across block sizes")
     outs = []
-    for bc, bs in ((256, 64), (64, 32), (1024, 256), (128, 128)):
-        gm, plan = gpu_plan(w.mesh, block_cells=bc, block_surface=bs)
+    for bc, sw in ((256, 2), (64, 3), (128, 4), (32, 2)):
+        gm, plan = gpu_plan(w.mesh, block_cells=bc, surface_waves=sw)
         outs.append(gpu_trajectory(plan, w, 5))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
