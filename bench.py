@@ -30,8 +30,26 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 isoAdvector cell-steps/s + % HBM roofline; batched vs plain; adjoint/fwd ratio"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
-KERNEL_SRC = os.path.join(ROOT, "paper_1804_01130_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_01130_amd", "csrc", n) for n in ("kernels.hip", "internal.h")]
 PROFILES = os.path.join(ROOT, "profiles")
+# FP64 operations credited per interface cell for vertex interpolation, the isovalue search, the
+# isoface and the swept-face integrals (a fixed per-unit figure, independent of the iteration
+# counts of this implementation)
+FLOP_PER_SURFACE_CELL = 11000.0
+COPY_N = 1 << 27  # doubles moved by the calibration copy (1 GiB read, 1 GiB written)
+KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update", "k_bound": "bound",
+               "k_stats": "stats"}
+# the commands whose rocprofv3 output --summarize-profiles reads
+PROFILE_COMMANDS = {
+    "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
+             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w}",
+    "fetch": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -T -f csv "
+             "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} "
+             "--steps 5 --warmup 2 --no-cpu-baseline --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
+    "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
+             "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} "
+             "--steps 5 --warmup 2 --no-cpu-baseline --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
+}
 
 
 def log(*a):
@@ -50,18 +68,38 @@ def build_workload(name):
 
 
 def kernel_source_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(workload):
+    return os.path.join(PROFILES, f"hbm_traffic_{workload}.txt")
+
+
+def read_kv(path):
+    out = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        out[k.strip()] = v.strip()
+    return out
 
 
 def committed_traffic(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
-    path = os.path.join(PROFILES, f"pmc_{kernel}_{workload}.json")
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, if the counters
+    were taken on the current kernel source (else None)."""
+    path = traffic_path(workload)
     if not os.path.exists(path):
         return None
-    d = json.load(open(path))
+    d = read_kv(path)
     if d.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return d.get("bytes_per_launch")
+    v = d.get(f"{kernel}.bytes_per_launch")
+    return float(v) if v is not None else None
 
 
 def algorithmic(kernel, mesh_info, n_surface, n_flux, n_cells):
@@ -73,7 +111,7 @@ def algorithmic(kernel, mesh_info, n_surface, n_flux, n_cells):
     if kernel == "find_surface":
         return (8.0 * n_cells + 4.0 * n_surface), "GB/s", "hbm"
     if kernel == "surface":
-        return None, None, "alu"
+        return FLOP_PER_SURFACE_CELL * n_surface, "TFLOP/s", "alu"
     return None, None, "hbm"
 
 
@@ -104,6 +142,102 @@ def cpu_baseline(w, budget_s=20.0):
             "sample": f"first {steps} of {w.n_steps} steps of the same workload, single thread, {el:.1f} s"}
 
 
+def copy_calibration(dev):
+    """A plain streaming copy kernel (elementwise multiply by one) of COPY_N doubles, three times."""
+    import torch
+    src = torch.ones(COPY_N, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: {COPY_N * 8} bytes read and written per launch, 3 launches")
+
+
+def _find(dirname, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(ROOT, dirname, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {dirname}")
+    return hits[-1]
+
+
+def _kernel_key(name):
+    for k, v in KERNEL_KEYS.items():
+        if k in name:
+            return v
+    if "elementwise" in name or "Mul" in name or "mul" in name:
+        return "copy"
+    return None
+
+
+def _pmc_per_dispatch(path, counter):
+    import csv
+    vals = {}
+    for row in csv.DictReader(open(path)):
+        if row.get("Counter_Name") != counter:
+            continue
+        key = _kernel_key(row.get("Kernel_Name", ""))
+        if key is None:
+            continue
+        vals.setdefault(key, []).append(float(row["Counter_Value"]))
+    return vals
+
+
+def summarize_profiles(workload):
+    """profiles/kernel_stats_<workload>.txt and profiles/hbm_traffic_<workload>.txt from the
+    rocprofv3 output of PROFILE_COMMANDS (kernel trace; FETCH_SIZE and WRITE_SIZE counter passes,
+    each scaled by what the counter reads for the calibration copy of known size)."""
+    import csv
+    os.makedirs(PROFILES, exist_ok=True)
+    cmds = {k: v.format(w=workload) for k, v in PROFILE_COMMANDS.items()}
+    stats = _find("gpurun_out/prof_stats", "kernel_stats.csv")
+    rows = list(csv.DictReader(open(stats)))
+    lines = [f"# rocprofv3 kernel statistics, workload {workload}",
+             f"# command (repository root): {cmds['stats']}",
+             "# name | calls | total ms | average us | min us | max us | share %"]
+    for r in rows:
+        lines.append(f"{r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}")
+    open(os.path.join(PROFILES, f"kernel_stats_{workload}.txt"), "w").write("\n".join(lines) + "\n")
+
+    fetch = _pmc_per_dispatch(_find("gpurun_out/prof_fetch", "counter_collection.csv"), "FETCH_SIZE")
+    write = _pmc_per_dispatch(_find("gpurun_out/prof_write", "counter_collection.csv"), "WRITE_SIZE")
+    shas = set()
+    for d in ("gpurun_out/prof_fetch", "gpurun_out/prof_write"):
+        out = json.loads(open(os.path.join(ROOT, d, "bench.json")).read())
+        shas.add(out["kernel_source_sha"])
+    if len(shas) != 1:
+        raise SystemExit(f"counter passes ran on different kernel sources: {shas}")
+    copy_bytes = COPY_N * 8.0
+    # the copy dispatches are the largest elementwise launches of the run
+    cf = max(fetch.get("copy", [0.0])) * 1024.0
+    cw = max(write.get("copy", [0.0])) * 1024.0
+    if cf <= 0 or cw <= 0:
+        raise SystemExit("calibration copy not found in the counter output")
+    sf, sw = copy_bytes / cf, copy_bytes / cw
+    lines = [f"# HBM traffic per launch from rocprofv3 counters, workload {workload}",
+             f"# FETCH_SIZE pass: {cmds['fetch']}",
+             f"# WRITE_SIZE pass: {cmds['write']}",
+             f"# calibration: elementwise copy of {COPY_N} doubles ({copy_bytes:.0f} B read, {copy_bytes:.0f} B "
+             f"written); counters read {cf:.0f} B fetched and {cw:.0f} B written",
+             "# <kernel>.fetch_kib / .write_kib: mean counter value per dispatch (KiB);"
+             " bytes_per_launch = fetch x scale_fetch + write x scale_write",
+             f"kernel_source_sha: {shas.pop()}",
+             f"scale_fetch: {sf:.6f}",
+             f"scale_write: {sw:.6f}"]
+    for k in ("find_surface", "surface", "update", "bound"):
+        if k not in fetch or k not in write:
+            continue
+        fk = float(np.mean(fetch[k]))
+        wk = float(np.mean(write[k]))
+        lines += [f"{k}.dispatches: {len(fetch[k])}", f"{k}.fetch_kib: {fk:.1f}", f"{k}.write_kib: {wk:.1f}",
+                  f"{k}.bytes_per_launch: {fk * 1024.0 * sf + wk * 1024.0 * sw:.0f}"]
+    open(traffic_path(workload), "w").write("\n".join(lines) + "\n")
+    log(f"[bench] wrote profiles for {workload}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,7 +247,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--surface-waves", type=int, default=0, help="register budget of the interface kernel (2-4)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, run a plain copy kernel of known size (scale of the HBM counters)")
+    ap.add_argument("--summarize-profiles", action="store_true",
+                    help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step has no multi-GPU path in this "
               f"build", file=sys.stderr)
@@ -178,11 +319,19 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s",
                 "frac": achieved / peak, "traffic": traffic, "mean_launch_us": mean_s * 1e6,
                 "algorithmic_bytes_per_launch": q}
+    elif bound == "alu" and q is not None:
+        achieved = q / mean_s / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_TFLOPS, "traffic": committed_traffic(dom, args.workload),
+                "mean_launch_us": mean_s * 1e6, "algorithmic_flop_per_launch": q}
     else:
-        roof = {"kernel": dom, "bound": bound, "achieved": None, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+        roof = {"kernel": dom, "bound": bound, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "mean_launch_us": mean_s * 1e6}
     b_alg = step_bytes_per_cell(cells, n_flux, n_surface)
     step_frac = b_alg * value / (HBM_PEAK_GBS * 1e9)
+
+    if args.copy_calibration:
+        copy_calibration(dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -199,6 +348,7 @@ def main():
         "step_roofline": {"bytes_per_cell_step": b_alg, "achieved_GBs": b_alg * value / 1e9,
                           "frac": step_frac},
         "kernel_ms_per_step": {k: v / max(nrec, 1) for k, v in kms.items()},
+        "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

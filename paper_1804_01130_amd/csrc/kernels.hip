@@ -393,11 +393,25 @@ __device__ __forceinline__ double tri_sweep(double d0, double d1, double d2, dou
 }
 
 // ------------------------------------------------------------------------------------------ lanes
-// Reductions and broadcasts inside a group of 8 consecutive lanes (one interface cell).  The xor
-// butterfly adds the same pairs in every lane, so all lanes hold bitwise-equal results.
+// Reductions and broadcasts inside a group of 8 consecutive lanes (one interface cell).  The sum
+// is a butterfly on DPP lane moves (swap neighbours, swap pairs inside a quad, mirror the two
+// quads of the half-row): each step adds the same two partial sums in both partner lanes, so all
+// lanes hold bitwise-equal results.  All 8 lanes of a group are active together (every branch
+// around a reduction depends only on group-uniform values).
+template <int Ctrl>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, Ctrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), Ctrl, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int kDppSwap1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror: lane i <- lane 7-i within 8
 __device__ __forceinline__ double grp_sum(double v) {
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) v += __shfl_xor(v, o, 8);
+    v += dpp_move<kDppSwap1>(v);
+    v += dpp_move<kDppSwap2>(v);
+    v += dpp_move<kDppHalfMirror>(v);
     return v;
 }
 __device__ __forceinline__ D3 grp_sum3(D3 v) { return D3{grp_sum(v.x), grp_sum(v.y), grp_sum(v.z)}; }
