@@ -78,7 +78,7 @@ typedef struct {
     int32_t block_surface;  /* reserved (the interface-cell kernel runs 256-thread work-groups) */
     int32_t max_surface;    /* capacity of the interface-cell list (0 = n_cells) */
     int32_t surface_waves;  /* register budget of the interface-cell kernel in waves per SIMD:
-                               2, 3 or 4 (0 = 2); results are bitwise the same for every choice */
+                               1, 2, 3 or 4 (0 = 2); results are bitwise the same for every choice */
 } iso_options;
 
 typedef struct {

@@ -38,7 +38,7 @@ struct DevMesh {
 
 // Workspace of a plan (device pointers).
 struct DevWork {
-    int32_t *counters = nullptr;   // [16] see kCnt* below
+    int32_t *counters = nullptr;   // [kCntNum] see kCnt* below
     int32_t *surf = nullptr;       // [cap] interface cells
     double *dvs = nullptr;         // [n_faces] dV written by interface upwind cells
     int32_t *olist = nullptr;      // [n_cells] cells needing redistribution (two halves ping-pong)
@@ -62,7 +62,8 @@ enum : int {
     kCntMaxIter = 5,
     kCntActive0 = 6,    // n_bound_active of the last step
     kCntFaces = 7,      // flist length
-    kCntNum = 16
+    kCntBound = 16,     // [16, 25): three rotating slots of per-sweep bounding counters
+    kCntNum = 32
 };
 
 struct StepArgs {
@@ -105,7 +106,7 @@ struct iso_plan {
     hipStream_t stream = nullptr;
     isoadv::DevWork work;
     std::vector<void *> allocations;
-    int32_t *host_counters = nullptr;  // pinned [16]
+    int32_t *host_counters = nullptr;  // pinned [kCntNum]
     double *host_red = nullptr;        // pinned [64]
     std::vector<hipEvent_t> events;    // 5 per recorded step
     int32_t timing_cap = 0, timing_used = 0;

@@ -219,124 +219,124 @@ __device__ __forceinline__ void face_centre_part(const FaceLane &f, double iso, 
 // isoface edges.  With o and do/du from the perimeter sums, the sub-volume and its derivative
 // cost one reduction per evaluation, and Newton's method on the bracket finds the isovalue.
 struct FaceQuad {
-    double a[3];  // apex . C_j
-    D3 B[3];
+    // the face's isoface edges (at most two on a quadrilateral): entry point s0 + u s1 to exit
+    // point e0 + u e1
+    D3 s0[2], s1[2], e0[2], e1[2];
+    bool on[2];
 };
 
-__device__ __forceinline__ FaceQuad face_quad(const FaceLane &f, const bool *w, double xr) {
-    FaceQuad r{{0.0, 0.0, 0.0}, {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}};
-    D3 c0[4], c1[4];
-    bool cuts[4], exits[4], entries[4];
+// Cut point on edge i (loop position) at xr and its rate of change with the isovalue.
+__device__ __forceinline__ void face_cut_rate(const FaceLane &f, int i, double xr, bool wet_i, D3 &c0, D3 &c1) {
+    const int j = (i + 1) & 3;
+    c0 = face_cut(f, i, xr, wet_i);
+    const bool fwd = (f.fwd >> i) & 1;
+    const double dlam = (wet_i == fwd) ? f.inv[i] : -f.inv[i];
+    c1 = dlam * (sel3(wet_i, f.q[j], f.q[i]) - sel3(wet_i, f.q[i], f.q[j]));
+}
+
+// Coefficients of the face's share for the wet pattern w, about u = iso - xr: the wet loop is
+// walked once around the face; each point is p0 + u p1, and every cross product of two
+// consecutive points contributes to the u^0, u^1 and u^2 terms of C(u) = sum p_i x p_i+1.
+__device__ __forceinline__ void face_quad_share(const FaceLane &f, const bool *w, double xr, double *acoef) {
+    const D3 Z{0, 0, 0};
+    D3 C0 = Z, C1 = Z, C2 = Z;
+    D3 first0 = Z, first1 = Z, prev0 = Z, prev1 = Z;  // first and previous points of the wet loop
+    bool have = false;
+    int cnt = 0;
+    auto emit = [&](bool on, D3 p0, D3 p1) {
+        const D3 k0 = cross(prev0, p0), k1 = cross(prev0, p1) + cross(prev1, p0), k2 = cross(prev1, p1);
+        const bool link = on && have;
+        C0 = sel3(link, C0 + k0, C0);
+        C1 = sel3(link, C1 + k1, C1);
+        C2 = sel3(link, C2 + k2, C2);
+        first0 = sel3(on && !have, p0, first0);
+        first1 = sel3(on && !have, p1, first1);
+        prev0 = sel3(on, p0, prev0);
+        prev1 = sel3(on, p1, prev1);
+        have = have || on;
+        cnt += on ? 1 : 0;
+    };
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int j = (i + 1) & 3;
-        cuts[i] = w[i] != w[j];
-        exits[i] = w[i] && !w[j];
-        entries[i] = !w[i] && w[j];
-        c0[i] = face_cut(f, i, xr, w[i]);
-        const bool fwd = (f.fwd >> i) & 1;
-        const double dlam = (w[i] == fwd) ? f.inv[i] : -f.inv[i];
-        c1[i] = dlam * (sel3(w[i], f.q[j], f.q[i]) - sel3(w[i], f.q[i], f.q[j]));
+        emit(w[i], f.q[i], Z);
+        D3 c0, c1;
+        face_cut_rate(f, i, xr, w[i], c0, c1);
+        emit(w[i] != w[j], c0, c1);
     }
-    // the wet loop: vertex i (if wet), then the cut on edge i (if cut), i = 0..3
-    D3 l0{0, 0, 0}, l1{0, 0, 0};
-    int cnt = 0;
+    // close the loop
+    C0 = C0 + cross(prev0, first0);
+    C1 = C1 + cross(prev0, first1) + cross(prev1, first0);
+    C2 = C2 + cross(prev1, first1);
+    const bool use = f.active && cnt >= 3;
+    acoef[0] = use ? dot(f.q[0], C0) : 0.0;
+    acoef[1] = use ? dot(f.q[0], C1) : 0.0;
+    acoef[2] = use ? dot(f.q[0], C2) : 0.0;
+}
+
+// The face's isoface edges for the wet pattern w (at most two on a quadrilateral): each runs from
+// an entry cut back to the preceding exit cut around the face, points p0 + u p1.
+__device__ __forceinline__ FaceQuad face_quad_segs(const FaceLane &f, const bool *w, double xr) {
+    const D3 Z{0, 0, 0};
+    FaceQuad r{{Z, Z}, {Z, Z}, {Z, Z}, {Z, Z}, {false, false}};
+    int nsg = 0;
+    D3 le0 = Z, le1 = Z, pe0 = Z, pe1 = Z;  // last exit cut; an entry met before any exit
+    bool have_le = false, have_pe = false;
+    auto seg = [&](bool on, D3 s0, D3 s1, D3 e0, D3 e1) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        l0 = sel3(w[i], f.q[i], l0);
-        l1 = sel3(w[i], D3{0, 0, 0}, l1);
-        l0 = sel3(cuts[i], c0[i], l0);
-        l1 = sel3(cuts[i], c1[i], l1);
-        cnt += (w[i] ? 1 : 0) + (cuts[i] ? 1 : 0);
-    }
-    D3 C0{0, 0, 0}, C1{0, 0, 0}, C2{0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        {  // vertex i (rate 0)
-            const D3 k0 = cross(l0, f.q[i]), k1 = cross(l1, f.q[i]);
-            C0 = sel3(w[i], C0 + k0, C0);
-            C1 = sel3(w[i], C1 + k1, C1);
-            l0 = sel3(w[i], f.q[i], l0);
-            l1 = sel3(w[i], D3{0, 0, 0}, l1);
+        for (int k = 0; k < 2; ++k) {
+            const bool to = on && nsg == k;
+            r.s0[k] = sel3(to, s0, r.s0[k]);
+            r.s1[k] = sel3(to, s1, r.s1[k]);
+            r.e0[k] = sel3(to, e0, r.e0[k]);
+            r.e1[k] = sel3(to, e1, r.e1[k]);
+            r.on[k] = r.on[k] || to;
         }
-        {  // cut on edge i
-            const D3 k0 = cross(l0, c0[i]), k1 = cross(l0, c1[i]) + cross(l1, c0[i]), k2 = cross(l1, c1[i]);
-            C0 = sel3(cuts[i], C0 + k0, C0);
-            C1 = sel3(cuts[i], C1 + k1, C1);
-            C2 = sel3(cuts[i], C2 + k2, C2);
-            l0 = sel3(cuts[i], c0[i], l0);
-            l1 = sel3(cuts[i], c1[i], l1);
-        }
-    }
-    if (f.active && cnt >= 3) {
-        r.a[0] = dot(f.q[0], C0);
-        r.a[1] = dot(f.q[0], C1);
-        r.a[2] = dot(f.q[0], C2);
-    }
-    D3 e0{0, 0, 0}, e1{0, 0, 0};
+        nsg += on ? 1 : 0;
+    };
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        e0 = sel3(exits[i], c0[i], e0);
-        e1 = sel3(exits[i], c1[i], e1);
+        const int j = (i + 1) & 3;
+        const bool exit_ = f.active && w[i] && !w[j], entry = f.active && !w[i] && w[j];
+        D3 c0, c1;
+        face_cut_rate(f, i, xr, w[i], c0, c1);
+        seg(entry && have_le, c0, c1, le0, le1);
+        pe0 = sel3(entry && !have_le, c0, pe0);
+        pe1 = sel3(entry && !have_le, c1, pe1);
+        have_pe = have_pe || (entry && !have_le);
+        le0 = sel3(exit_, c0, le0);
+        le1 = sel3(exit_, c1, le1);
+        have_le = have_le || exit_;
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (f.active && entries[i]) {
-            r.B[0] = r.B[0] + cross(c0[i], e0);
-            r.B[1] = r.B[1] + cross(c0[i], e1) + cross(c1[i], e0);
-            r.B[2] = r.B[2] + cross(c1[i], e1);
-        }
-        e0 = sel3(exits[i], c0[i], e0);
-        e1 = sel3(exits[i], c1[i], e1);
-    }
+    seg(have_pe, pe0, pe1, le0, le1);
     return r;
 }
 
-// Perimeter sums of the isoface edges of a face at isovalue iso, for the pattern w, and their
-// rates of change with the isovalue (each cut point moves along its edge at a constant rate).
+// Per face at u: perimeter sums of its isoface edges and their rates of change with u, and the
+// edge sum B(u) = sum s x e with its derivative.
 struct Perim {
     D3 oacc, doacc;  // sum of length x midpoint, and its derivative
     double oL, doL;  // total length, and its derivative
-    D3 osum, dosum;  // sum of entry points, and its derivative
-    double nseg;
+    D3 Bu, Bd;       // B(u), B'(u)
 };
 
-__device__ __forceinline__ Perim face_seg_perimeter(const FaceLane &f, const bool *w, double iso) {
-    Perim r{{0, 0, 0}, {0, 0, 0}, 0.0, 0.0, {0, 0, 0}, {0, 0, 0}, 0.0};
-    D3 cut[4], dcut[4];
-    bool exits[4], entries[4];
+__device__ __forceinline__ Perim seg_eval(const FaceQuad &fq, double u) {
+    const D3 Z{0, 0, 0};
+    Perim r{Z, Z, 0.0, 0.0, Z, Z};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int j = (i + 1) & 3;
-        cut[i] = face_cut(f, i, iso, w[i]);
-        const bool fwd = (f.fwd >> i) & 1;
-        const double dlam = (w[i] == fwd) ? f.inv[i] : -f.inv[i];
-        dcut[i] = dlam * (sel3(w[i], f.q[j], f.q[i]) - sel3(w[i], f.q[i], f.q[j]));
-        exits[i] = f.active && w[i] && !w[j];
-        entries[i] = f.active && !w[i] && w[j];
-    }
-    D3 le{0, 0, 0}, dle{0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        le = sel3(exits[i], cut[i], le);
-        dle = sel3(exits[i], dcut[i], dle);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const D3 d = le - cut[i], dd = dle - dcut[i];
+    for (int k = 0; k < 2; ++k) {
+        const D3 sp = fq.s0[k] + u * fq.s1[k], ep = fq.e0[k] + u * fq.e1[k];
+        const D3 d = ep - sp, dd = fq.e1[k] - fq.s1[k];
         const double l = norm3(d);
         const double dl = l > 0.0 ? dot(d, dd) / l : 0.0;
-        if (entries[i]) {
-            r.oacc = r.oacc + (0.5 * l) * (cut[i] + le);
-            r.doacc = r.doacc + (0.5 * dl) * (cut[i] + le) + (0.5 * l) * (dcut[i] + dle);
-            r.oL += l;
-            r.doL += dl;
-            r.osum = r.osum + cut[i];
-            r.dosum = r.dosum + dcut[i];
-            r.nseg += 1.0;
-        }
-        le = sel3(exits[i], cut[i], le);
-        dle = sel3(exits[i], dcut[i], dle);
+        const D3 ao = (0.5 * l) * (sp + ep), dao = (0.5 * dl) * (sp + ep) + (0.5 * l) * (fq.s1[k] + fq.e1[k]);
+        const bool on = fq.on[k];
+        r.oacc = sel3(on, r.oacc + ao, r.oacc);
+        r.doacc = sel3(on, r.doacc + dao, r.doacc);
+        r.oL += on ? l : 0.0;
+        r.doL += on ? dl : 0.0;
+        r.Bu = sel3(on, r.Bu + cross(sp, ep), r.Bu);
+        r.Bd = sel3(on, r.Bd + cross(fq.s1[k], ep) + cross(sp, fq.e1[k]), r.Bd);
     }
     return r;
 }
@@ -593,37 +593,29 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 bool w[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) w[i] = f.aq[i] > xr;
-                const FaceQuad fq = face_quad(f, w, xr);
-                const double a0 = grp_sum(fq.a[0]), a1 = grp_sum(fq.a[1]), a2 = grp_sum(fq.a[2]);
-                const D3 B0 = grp_sum3(fq.B[0]), B1 = grp_sum3(fq.B[1]), B2 = grp_sum3(fq.B[2]);
+                double ac[3];
+                face_quad_share(f, w, xr, ac);
+                const FaceQuad fq = face_quad_segs(f, w, xr);
                 ++rounds;
-                // isoface apex o(u) (perimeter centroid of the isoface edges) and do/du
-                auto apex = [&](double u, D3 &od) {
-                    Perim pr = face_seg_perimeter(f, w, xr + u);
-                    const D3 oacc = grp_sum3(pr.oacc), doacc = grp_sum3(pr.doacc);
-                    const double oL = grp_sum(pr.oL), doL = grp_sum(pr.doL);
-                    const D3 osum = grp_sum3(pr.osum), dosum = grp_sum3(pr.dosum);
-                    const double ns = grp_sum(pr.nseg);
-                    if (oL > 0.0) {
-                        const D3 o = (1.0 / oL) * oacc;
-                        od = (1.0 / oL) * (doacc - doL * o);
-                        return o;
-                    }
-                    if (ns > 0.0) {
-                        od = (1.0 / ns) * dosum;
-                        return (1.0 / ns) * osum;
-                    }
-                    od = D3{0, 0, 0};
-                    return D3{0, 0, 0};
-                };
-                // G(u) = six times the sub-volume minus its target, and G'(u)
+
+                // G(u) = six times the sub-volume minus its target, and G'(u): each face adds its
+                // wet-loop share plus o(u) . B(u), with o the perimeter centroid of all isoface
+                // edges (with no isoface length B vanishes and o does not enter)
                 const double target = aP * V6;
                 auto G = [&](double u, double &dG) {
-                    D3 od;
-                    const D3 o = apex(u, od);
-                    const D3 Bu = B0 + u * (B1 + u * B2), Bd = B1 + (2.0 * u) * B2;
-                    dG = a1 + 2.0 * u * a2 + dot(od, Bu) + dot(o, Bd);
-                    return a0 + u * (a1 + u * a2) + dot(o, Bu) - target;
+                    const Perim pr = seg_eval(fq, u);
+                    const D3 oacc = grp_sum3(pr.oacc), doacc = grp_sum3(pr.doacc);
+                    const double oL = grp_sum(pr.oL), doL = grp_sum(pr.doL);
+                    D3 o{0, 0, 0}, od{0, 0, 0};
+                    if (oL > 0.0) {
+                        const double il = 1.0 / oL;
+                        o = il * oacc;
+                        od = il * (doacc - doL * o);
+                    }
+                    const double gl = ac[0] + u * (ac[1] + u * ac[2]) + dot(o, pr.Bu);
+                    const double dgl = ac[1] + 2.0 * u * ac[2] + dot(od, pr.Bu) + dot(o, pr.Bd);
+                    dG = grp_sum(dgl);
+                    return grp_sum(gl) - target;
                 };
                 const double ulo = lo - xr, uhi = hi - xr;
                 double dG;
@@ -876,39 +868,63 @@ __device__ __forceinline__ void load_slots(const BoundArgs &A, int32_t c, Slots<
     }
 }
 
-// Redistribution sweeps (Jacobi) in one work-group.  Per sweep: (A) every listed cell computes
-// the change of the heavy-fluid outflow of each of its outflow faces (each face has one upwind
-// cell, so it alone writes that face's correction and its running dV), then (B) every touched
-// cell applies the corrections of its faces in ascending face order and is re-listed if still out
-// of bounds.  Corrections alternate between two buffers so that a buffer is cleared one sweep
-// after it was read.
-template <int W>
-__global__ void __launch_bounds__(1024) k_bound(BoundArgs A) {
-    __shared__ int nO, nT, nF, nNext, nD[2];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int n = A.m.n_cells, nf = A.m.n_faces;
-    int32_t *cur = A.w.olist, *nxt = A.w.olist + n;
-    int32_t *dlist[2] = {A.w.flist + nf, A.w.flist + 2 * (size_t)nf};
-    if (tid == 0) {
-        nO = A.w.counters[kCntOff];
-        nF = 0;
-        nD[0] = nD[1] = 0;
+// Append `count` entries per lane to a device-wide list: one atomic per wave.  Returns the index of
+// this lane's first entry.  Every lane of the wave must call it (count may be 0).
+__device__ __forceinline__ int wave_append(int count, int32_t *counter) {
+    const int lane = __lane_id();
+    int incl = count;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
     }
-    __syncthreads();
-    int it = 0;
-    for (; it < A.n_iter; ++it) {
-        if (nO == 0) break;
-        const int par = it & 1;
-        double *delta = A.w.delta + (size_t)par * nf;
+    const int total = __shfl(incl, 63, 64);
+    int base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(counter, total);
+    base = __shfl(base, 63, 64);
+    return base + incl - count;
+}
+
+// Bounding counters of sweep `it` live in one of three rotating slots: a slot is read by the two
+// kernels of its sweep and by phase A of the next sweep, and cleared by phase B of the sweep after.
+__device__ __forceinline__ int32_t *bound_slot(int32_t *counters, int it) { return counters + kCntBound + 3 * (it % 3); }
+enum : int { kSlotTouched = 0, kSlotNext = 1, kSlotDelta = 2 };
+
+// Redistribution sweeps (Jacobi), two grid-wide kernels per sweep.  (A) every listed cell computes
+// the change of the heavy-fluid outflow of each of its outflow faces (each face has one upwind
+// cell, so it alone writes that face's correction and its running dV); (B) every touched cell
+// applies the corrections of its faces in ascending face order and is listed for the next sweep
+// if still out of bounds.  Corrections alternate between two buffers; phase A of a sweep clears
+// the buffer read by the previous sweep.  List order never affects a result.
+template <int W>
+__global__ void __launch_bounds__(256) k_bound_a(BoundArgs A, int it) {
+    const int n = A.m.n_cells, nf = A.m.n_faces;
+    int32_t *counters = A.w.counters;
+    int32_t *slot = bound_slot(counters, it);
+    const int par = it & 1;
+    const int32_t *cur = A.w.olist + (par ? n : 0);
+    double *delta = A.w.delta + (size_t)par * nf;
+    int32_t *dlist = A.w.flist + (size_t)(1 + par) * nf;
+    const int n_old = it == 0 ? counters[kCntOff] : bound_slot(counters, it - 1)[kSlotNext];
+    const int stride = gridDim.x * blockDim.x;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (it > 0) {  // the other buffer was read by the previous sweep: clear it
+        const int n_stale = bound_slot(counters, it - 1)[kSlotDelta];
         double *stale = A.w.delta + (size_t)(par ^ 1) * nf;
-        const int n_stale = nD[par ^ 1];
-        const int n_old = nO;
-        if (tid == 0) { nT = 0; nNext = 0; }
-        __syncthreads();
-        // the other buffer was read in the previous sweep: clear it
-        for (int i = tid; i < n_stale; i += nt) stale[dlist[par ^ 1][i]] = 0.0;
-        // A: corrections on the outflow faces of the listed cells
-        for (int i = tid; i < n_old; i += nt) {
+        const int32_t *slist = A.w.flist + (size_t)(2 - par) * nf;
+        for (int i = t0; i < n_stale; i += stride) stale[slist[i]] = 0.0;
+    }
+    const int nloop = (n_old + 255) & ~255;  // whole work-groups iterate together
+    for (int i0 = blockIdx.x * blockDim.x; i0 < nloop; i0 += stride) {
+        const int i = i0 + threadIdx.x;
+        const bool valid = i < n_old;
+        int ndl = 0, nfl = 0, ntl = 0;
+        int32_t fsel[W], tsel[W + 1];
+        bool newf[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) { fsel[k] = -1; newf[k] = false; tsel[k] = -1; }
+        tsel[W] = -1;
+        if (valid) {
             const int32_t P = cur[i];
             Slots<W> sl;
             load_slots<W>(A, P, sl);
@@ -940,37 +956,64 @@ __global__ void __launch_bounds__(1024) k_bound(BoundArgs A) {
                 cap[k] = over ? outphi * A.dt - outv : outv;
                 if (cap[k] > 0.0) sumcap += cap[k];
             }
-            int32_t claimed[W + 1];
-            claimed[W] = atomicExch(&A.w.cmark[P], 1);
+            if (atomicExch(&A.w.cmark[P], 1) == 0) tsel[W] = P;
             const double need = over ? (a - 1.0) * A.m.vol[P] : -a * A.m.vol[P];
             const double r = sumcap > 0.0 ? fmin(need / sumcap, 1.0) : 0.0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-                claimed[k] = 1;
                 if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
                 const double d = cap[k] * r;
                 const double dd = over ? (sl.v[k] >= 0 ? d : -d) : (sl.v[k] >= 0 ? -d : d);
                 const int32_t f = sl.fid[k];
                 delta[f] = dd;
-                dlist[par][atomicAdd(&nD[par], 1)] = f;
                 A.w.dvcur[f] = dvnow[k] + dd;
+                fsel[k] = f;
                 if (!mk[k]) {
                     A.w.fmark[f] = 1;
-                    A.w.flist[atomicAdd(&nF, 1)] = f;
+                    newf[k] = true;
                 }
-                if (sl.nbr[k] >= 0) claimed[k] = atomicExch(&A.w.cmark[sl.nbr[k]], 1);
+                if (sl.nbr[k] >= 0 && atomicExch(&A.w.cmark[sl.nbr[k]], 1) == 0) tsel[k] = sl.nbr[k];
             }
-            if (claimed[W] == 0) A.w.tlist[atomicAdd(&nT, 1)] = P;
 #pragma unroll
-            for (int k = 0; k < W; ++k)
-                if (claimed[k] == 0) A.w.tlist[atomicAdd(&nT, 1)] = sl.nbr[k];
+            for (int k = 0; k < W; ++k) {
+                ndl += fsel[k] >= 0 ? 1 : 0;
+                nfl += newf[k] ? 1 : 0;
+            }
+#pragma unroll
+            for (int k = 0; k <= W; ++k) ntl += tsel[k] >= 0 ? 1 : 0;
         }
-        __syncthreads();
-        if (tid == 0) nD[par ^ 1] = 0;
-        // B: apply to every touched cell, fixed face order
-        const bool last = it == A.n_iter - 1;
-        for (int i = tid; i < nT; i += nt) {
-            const int32_t Q = A.w.tlist[i];
+        int bd = wave_append(ndl, &slot[kSlotDelta]);
+        int bf = wave_append(nfl, &counters[kCntFaces]);
+        int bt = wave_append(ntl, &slot[kSlotTouched]);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (fsel[k] >= 0) dlist[bd++] = fsel[k];
+            if (newf[k]) A.w.flist[bf++] = fsel[k];
+        }
+#pragma unroll
+        for (int k = 0; k <= W; ++k)
+            if (tsel[k] >= 0) A.w.tlist[bt++] = tsel[k];
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(256) k_bound_b(BoundArgs A, int it, int last) {
+    const int n = A.m.n_cells, nf = A.m.n_faces;
+    int32_t *counters = A.w.counters;
+    int32_t *slot = bound_slot(counters, it);
+    const int par = it & 1;
+    int32_t *nxt = A.w.olist + (par ? 0 : n);
+    const double *delta = A.w.delta + (size_t)par * nf;
+    const int nT = slot[kSlotTouched];
+    const int stride = gridDim.x * blockDim.x;
+    if (it > 0 && blockIdx.x == 0 && threadIdx.x < 3) bound_slot(counters, it - 1)[threadIdx.x] = 0;
+    const int nloop = (nT + 255) & ~255;
+    for (int i0 = blockIdx.x * blockDim.x; i0 < nloop; i0 += stride) {
+        const int i = i0 + threadIdx.x;
+        bool again = false;
+        int32_t Q = 0;
+        if (i < nT) {
+            Q = A.w.tlist[i];
             int32_t v[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) v[k] = A.m.slot_face[(size_t)k * n + Q];
@@ -990,30 +1033,42 @@ __global__ void __launch_bounds__(1024) k_bound(BoundArgs A) {
             }
             A.alpha_new[Q] = x;
             A.w.cmark[Q] = 0;
-            if (x > 1.0 + A.tol || x < -A.tol) nxt[atomicAdd(&nNext, 1)] = Q;
+            again = x > 1.0 + A.tol || x < -A.tol;
         }
-        __syncthreads();
-        int32_t *t = cur;
-        cur = nxt;
-        nxt = t;
-        if (tid == 0) nO = nNext;
-        __syncthreads();
+        const int b = wave_append(again ? 1 : 0, &slot[kSlotNext]);
+        if (again) nxt[b] = Q;
     }
-    if (A.n_iter == 0 && A.clip) {
-        for (int i = tid; i < nO; i += nt) {
-            const int32_t P = cur[i];
-            A.alpha_new[P] = fmin(fmax(A.alpha_new[P], 0.0), 1.0);
+}
+
+// End of the step (one work-group): chop the listed cells when no sweep ran, clear the correction
+// buffer of the last sweep and the face marks, keep this step's counters for the statistics and
+// zero them for the next step.
+__global__ void __launch_bounds__(1024) k_bound_end(BoundArgs A) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nf = A.m.n_faces;
+    int32_t *counters = A.w.counters;
+    if (A.n_iter == 0) {
+        if (A.clip) {
+            const int nO = counters[kCntOff];
+            for (int i = tid; i < nO; i += nt) {
+                const int32_t P = A.w.olist[i];
+                A.alpha_new[P] = fmin(fmax(A.alpha_new[P], 0.0), 1.0);
+            }
         }
+    } else {
+        const int it = A.n_iter - 1, par = it & 1;
+        const int nd = bound_slot(counters, it)[kSlotDelta];
+        const int32_t *dl = A.w.flist + (size_t)(1 + par) * nf;
+        double *delta = A.w.delta + (size_t)par * nf;
+        for (int i = tid; i < nd; i += nt) delta[dl[i]] = 0.0;
     }
-    // leave the workspace clean for the next step
-    for (int pb = 0; pb < 2; ++pb)
-        for (int i = tid; i < nD[pb]; i += nt) A.w.delta[(size_t)pb * nf + dlist[pb][i]] = 0.0;
+    const int nF = counters[kCntFaces];
     for (int i = tid; i < nF; i += nt) A.w.fmark[A.w.flist[i]] = 0;
     __syncthreads();
-    // keep this step's counters for the statistics, zero them for the next step
-    if (tid < 8) A.w.counters[8 + tid] = tid == kCntActive0 ? A.w.counters[kCntOff] : A.w.counters[tid];
+    if (tid < 8) counters[8 + tid] = tid == kCntActive0 ? counters[kCntOff] : counters[tid];
     __syncthreads();
-    if (tid < 8) A.w.counters[tid] = 0;
+    if (tid < 8) counters[tid] = 0;
+    if (tid >= kCntBound && tid < kCntBound + 9) counters[tid] = 0;
 }
 
 __global__ void __launch_bounds__(1024) k_stats(const double *alpha, const double *alpha_new, const double *vol, int n,
@@ -1039,13 +1094,19 @@ __global__ void __launch_bounds__(1024) k_stats(const double *alpha, const doubl
     if (t == 0) { red[0] = sb[0]; red[1] = sa[0]; red[2] = smin[0]; red[3] = smax[0]; red[4] = 0.0; }
 }
 
+constexpr int kBoundGrid = 512;  // work-groups of the bounding sweeps (grid-stride over device-side counts)
+
 template <int W>
 void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, int block_cells, hipStream_t s,
                  hipEvent_t *ev) {
     const int gc = (m.n_cells + block_cells - 1) / block_cells;
     hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(block_cells), 0, s, ua);
     if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_bound<W>, dim3(1), dim3(1024), 0, s, ba);
+    for (int it = 0; it < ba.n_iter; ++it) {
+        hipLaunchKernelGGL(k_bound_a<W>, dim3(kBoundGrid), dim3(256), 0, s, ba, it);
+        hipLaunchKernelGGL(k_bound_b<W>, dim3(kBoundGrid), dim3(256), 0, s, ba, it, it == ba.n_iter - 1 ? 1 : 0);
+    }
+    hipLaunchKernelGGL(k_bound_end, dim3(1), dim3(1024), 0, s, ba);
 }
 
 }  // namespace
@@ -1069,6 +1130,7 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
     gs = std::max(1L, std::min(gs, 1024L));  // persistent: groups loop over the list
     switch (surface_waves) {
+        case 1: hipLaunchKernelGGL(k_surface<1>, dim3((int)gs), dim3(bs), 0, s, sa); break;
         case 3: hipLaunchKernelGGL(k_surface<3>, dim3((int)gs), dim3(bs), 0, s, sa); break;
         case 4: hipLaunchKernelGGL(k_surface<4>, dim3((int)gs), dim3(bs), 0, s, sa); break;
         default: hipLaunchKernelGGL(k_surface<2>, dim3((int)gs), dim3(bs), 0, s, sa); break;
