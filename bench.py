@@ -42,13 +42,13 @@ KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_upda
 # the commands whose rocprofv3 output --summarize-profiles reads
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
-             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w}",
+             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble",
     "fetch": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
     "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
 }
 
 
@@ -238,6 +238,93 @@ def summarize_profiles(workload):
     log(f"[bench] wrote profiles for {workload}")
 
 
+def ensemble_bench(steps, warmup, tune_cache=None):
+    """64 Airy domains of uneven sizes: the batched path (one launch per kernel over all members,
+    autotuned launch shapes, a captured graph of the whole run) against the plain path (each
+    member's own plan, step by step), on the same per-step fields resident in HBM."""
+    import torch
+    import wavegen as W
+    from wavegen.device import EnsembleAiryFields
+    from paper_1804_01130_amd import Batch, Mesh, Plan, default_options
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    ws = W.airy_ensemble(64, seed=1, steps=steps)
+    meshes = [Mesh.from_arrays(w.mesh) for w in ws]
+    batch = Batch(meshes, default_options())
+    N, F = batch.n_cells, batch.n_faces
+    co, fo = batch.layout()
+    S = warmup + steps
+    ef = EnsembleAiryFields(ws, dev)
+    phi_all = torch.empty((S, F), dtype=torch.float64, device=dev)
+    U_all = torch.empty((S, 3 * N), dtype=torch.float64, device=dev)
+    for n in range(S):
+        ef.fields(n, phi_all[n], U_all[n])
+    dts = np.array([w.dt for w in ws])
+    alpha0 = torch.tensor(batch.concat_cells([w.alpha0 for w in ws]), device=dev)
+    log(f"[bench] ensemble: {len(ws)} members, {N} cells, {F} faces, fields for {S} steps, set up in "
+        f"{time.time() - t0:.1f} s")
+    cfg, tune_ms = batch.tune(alpha0, phi_all[0], U_all[0], dts, n_trial=3, cache_path=tune_cache)
+    # warm-up steps, then the timed run from the state they reach
+    a = alpha0.clone()
+    batch.advect(a, phi_all, U_all, dts, warmup, F, 3 * N)
+    start = a.clone()
+    phi_t, U_t = phi_all[warmup:], U_all[warmup:]
+    batch.advect(a, phi_t, U_t, dts, steps, F, 3 * N)  # captures the run's graph
+    a.copy_(start)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    batch.advect(a, phi_t, U_t, dts, steps, F, 3 * N)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    n_s = int(((start > 1e-8) & (start < 1.0 - 1e-8)).sum().item())
+    batched = a.cpu().numpy()
+    # plain: every member through its own plan, step by step
+    plans = [Plan(m, default_options()) for m in meshes]
+    st = [start[co[d]:co[d + 1]].clone() for d in range(len(ws))]
+    tmp = [torch.empty_like(x) for x in st]
+    Um = []
+    for d in range(len(ws)):
+        nd = int(co[d + 1] - co[d])
+        u = torch.empty((steps, 3 * nd), dtype=torch.float64, device=dev)
+        for k in range(3):
+            u[:, k * nd:(k + 1) * nd] = U_t[:, k * N + co[d]:k * N + co[d + 1]]
+        Um.append(u)
+    phis = [[phi_t[n, fo[d]:fo[d + 1]] for d in range(len(ws))] for n in range(steps)]
+    for d, p in enumerate(plans):  # one untimed step each
+        p.step(st[d], phis[0][d], Um[d][0], dts[d], out=tmp[d])
+    for d in range(len(ws)):
+        st[d].copy_(start[co[d]:co[d + 1]])
+    torch.cuda.synchronize()
+    e0.record()
+    for n in range(steps):
+        for d, p in enumerate(plans):
+            p.step(st[d], phis[n][d], Um[d][n], dts[d], out=tmp[d])
+            st[d], tmp[d] = tmp[d], st[d]
+    e1.record()
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    plain = torch.cat(st).cpu().numpy()
+    nflux = sum(m.info()["n_flux_faces"] for m in meshes)
+    b_alg = (24.0 * N + 16.0 * nflux + 1100.0 * n_s) / N
+    vb = N * steps / (ms_b * 1e-3)
+    out = {"workload": f"airy_ensemble_64 ({len(ws)} members, {N} cells)", "steps": steps, "cells": N,
+           "interface_cells": n_s, "batched_cell_steps_per_s": vb,
+           "plain_cell_steps_per_s": N * steps / (ms_p * 1e-3), "speedup": ms_p / ms_b,
+           "batched_ms_per_step": ms_b / steps, "plain_ms_per_step": ms_p / steps,
+           "bitwise_equal": bool(np.array_equal(batched, plain)), "tuned_config": cfg,
+           "hbm_frac": b_alg * vb / (HBM_PEAK_GBS * 1e9), "bytes_per_cell_step": b_alg}
+    log(f"[bench] ensemble: batched {ms_b / steps * 1e3:.1f} us/step, plain {ms_p / steps * 1e3:.1f} us/step, "
+        f"speed-up {ms_p / ms_b:.1f}, bitwise equal {out['bitwise_equal']}, config {cfg}")
+    for p in plans:
+        p.close()
+    batch.close()
+    del phi_all, U_all, Um, phis, phi_t, U_t
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +336,7 @@ def main():
     ap.add_argument("--surface-waves", type=int, default=0, help="register budget of the interface kernel (2-4)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain copy kernel of known size (scale of the HBM counters)")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-vs-plain ensemble measurement")
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
@@ -333,6 +421,12 @@ def main():
     if args.copy_calibration:
         copy_calibration(dev)
 
+    ens = None
+    if not args.no_ensemble:
+        del phis, Us, a, b, plan, gm
+        torch.cuda.empty_cache()
+        ens = ensemble_bench(args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample of the same workload")
@@ -350,6 +444,7 @@ def main():
         "kernel_ms_per_step": {k: v / max(nrec, 1) for k, v in kms.items()},
         "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
+        "ensemble": ens,
     }
     print(json.dumps(out), flush=True)
 

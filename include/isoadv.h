@@ -74,11 +74,15 @@ typedef struct {
     int32_t n_bound_iter;   /* Jacobi redistribution sweeps (default 3) */
     int32_t clip;           /* chop alpha to [0,1] after redistribution (default 1) */
     int32_t check_inputs;   /* validate inputs on the host before each step (syncs; default 0) */
-    int32_t block_cells;    /* threads per block of the per-cell kernels (0 = 256) */
-    int32_t block_surface;  /* reserved (the interface-cell kernel runs 256-thread work-groups) */
+    int32_t block_cells;    /* threads per block of the per-cell kernels, up to 1024 (0 = 256) */
+    int32_t surface_blocks; /* work-groups of the interface-cell kernel, which loops over the list
+                               (0 = up to 1024, from the list capacity); at most 65535 */
     int32_t max_surface;    /* capacity of the interface-cell list (0 = n_cells) */
     int32_t surface_waves;  /* register budget of the interface-cell kernel in waves per SIMD:
-                               1, 2, 3 or 4 (0 = 2); results are bitwise the same for every choice */
+                               1, 2, 3 or 4 (0 = 2) */
+    int32_t bound_blocks;   /* work-groups of the bounding sweeps (0 = 512); at most 65535.
+                               Results are bitwise the same for every choice of the launch shapes
+                               block_cells, surface_blocks, surface_waves and bound_blocks. */
 } iso_options;
 
 typedef struct {
@@ -147,6 +151,44 @@ iso_status iso_advect_step_traced(iso_plan *plan, const double *alpha, const dou
  * recorded steps, and the number of recorded steps; it then clears the record. */
 iso_status iso_plan_set_timing(iso_plan *plan, int32_t max_steps);
 iso_status iso_plan_timing(iso_plan *plan, double *kernel_ms /* [4] */, int32_t *n_steps);
+
+/* ---- Ensembles ---------------------------------------------------------------------------
+ * Many independent meshes advanced together (batched execution; not part of the paper's
+ * method).  The members' device arrays are concatenated into one mesh, so each kernel of a step
+ * is a single launch over all members, and a run of up to 256 steps is captured once as a HIP
+ * graph and replayed while its arguments stay the same (longer runs are launched step by step).
+ * Every member computes bit for bit what iso_advect_step computes on its own mesh with the same
+ * options and time step.  The ensemble copies the member meshes: they may be destroyed after. */
+typedef struct iso_batch iso_batch;
+
+/* meshes [n] (each created on the current device); opt as for a plan (NULL = defaults);
+ * hip_stream: the caller's stream (NULL = the null stream) that ensemble calls are ordered on. */
+iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_options *opt, void *hip_stream,
+                            iso_batch **out);
+void iso_batch_destroy(iso_batch *batch);
+/* host out cell_off[n+1], face_off[n+1]: member d owns cells [cell_off[d], cell_off[d+1]) and
+ * faces [face_off[d], face_off[d+1]) of the concatenated arrays. */
+iso_status iso_batch_layout(const iso_batch *batch, int64_t *cell_off, int64_t *face_off);
+/* n_steps steps of every member (Section 3.2 step, as iso_advect_step).  alpha: DEVICE [N], in/out,
+ * concatenated by member.  phi: DEVICE, step s reads the F faces at phi + s*phi_stride; U: DEVICE,
+ * step s reads U + s*U_stride, [3N] structure of arrays over the concatenated cells; a stride of 0
+ * reuses the same fields every step.  dt: HOST [n], each member's time step.  Asynchronous: ordered
+ * after the caller's earlier work on its stream, and later work on that stream waits for it.
+ * alpha must not overlap the fields (ISO_EINVAL). */
+iso_status iso_batch_advect(iso_batch *batch, double *alpha, const double *phi, int64_t phi_stride, const double *U,
+                            int64_t U_stride, const double *dt, int32_t n_steps);
+/* Launch shapes in use: cfg[0..3] = block_cells, surface_blocks, surface_waves, bound_blocks.
+ * They never change a result. */
+iso_status iso_batch_config(const iso_batch *batch, int32_t *cfg);
+iso_status iso_batch_set_config(iso_batch *batch, const int32_t *cfg);
+/* Autotuner: times n_trial steps of every candidate launch shape (coordinate search over the
+ * interface kernel's register budget and work-group count, the per-cell block size and the
+ * bounding grid) from state alpha with the fields phi, U of one step (alpha is not modified)
+ * and keeps the fastest.  cache_path (nullable): text file of earlier choices keyed by the
+ * ensemble's layout; a match skips the trials, a new choice is appended.  best_ms (nullable): the
+ * chosen shape's ms per step.  Synchronous. */
+iso_status iso_batch_tune(iso_batch *batch, const double *alpha, const double *phi, const double *U, const double *dt,
+                          int32_t n_trial, const char *cache_path, double *best_ms);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,6 @@ The package holds the kernels and host plan (csrc/), their build (build.py) and 
 thin ctypes binding (binding.py).  Input generation lives in the separate
 ``wavegen`` package and the CPU reference in ``oracle``.
 """
-from .binding import (IsoError, IsoOptions, IsoStepStats, Mesh, Plan, default_options, header_functions, lib)
+from .binding import (Batch, IsoError, IsoOptions, IsoStepStats, Mesh, Plan, default_options, header_functions, lib)
 
-__all__ = ["IsoError", "IsoOptions", "IsoStepStats", "Mesh", "Plan", "default_options", "header_functions", "lib"]
+__all__ = ["Batch", "IsoError", "IsoOptions", "IsoStepStats", "Mesh", "Plan", "default_options", "header_functions", "lib"]

@@ -29,7 +29,8 @@ class IsoOptions(C.Structure):
     _fields_ = [("eps_surf", C.c_double), ("flat_tol", C.c_double), ("bound_tol", C.c_double),
                 ("max_courant", C.c_double), ("root_max_iter", C.c_int32), ("n_bound_iter", C.c_int32),
                 ("clip", C.c_int32), ("check_inputs", C.c_int32), ("block_cells", C.c_int32),
-                ("block_surface", C.c_int32), ("max_surface", C.c_int32), ("surface_waves", C.c_int32)]
+                ("surface_blocks", C.c_int32), ("max_surface", C.c_int32), ("surface_waves", C.c_int32),
+                ("bound_blocks", C.c_int32)]
 
 
 class IsoStepStats(C.Structure):
@@ -99,6 +100,20 @@ def lib():
         L.iso_plan_set_timing.restype = C.c_int
         L.iso_plan_timing.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
         L.iso_plan_timing.restype = C.c_int
+        L.iso_batch_create.argtypes = [C.POINTER(_vp), C.c_int32, C.POINTER(IsoOptions), _vp, C.POINTER(_vp)]
+        L.iso_batch_create.restype = C.c_int
+        L.iso_batch_destroy.argtypes = [_vp]
+        L.iso_batch_destroy.restype = None
+        L.iso_batch_layout.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.iso_batch_layout.restype = C.c_int
+        L.iso_batch_advect.argtypes = [_vp, _vp, _vp, C.c_int64, _vp, C.c_int64, _dp, C.c_int32]
+        L.iso_batch_advect.restype = C.c_int
+        L.iso_batch_config.argtypes = [_vp, _ip]
+        L.iso_batch_config.restype = C.c_int
+        L.iso_batch_set_config.argtypes = [_vp, _ip]
+        L.iso_batch_set_config.restype = C.c_int
+        L.iso_batch_tune.argtypes = [_vp, _vp, _vp, _vp, _dp, C.c_int32, C.c_char_p, _dp]
+        L.iso_batch_tune.restype = C.c_int
         _lib = L
     return _lib
 
@@ -271,6 +286,86 @@ class Plan:
     def close(self):
         if getattr(self, "h", None):
             lib().iso_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent meshes advanced together (iso_batch_create): one launch per kernel for all
+    members and a captured HIP graph per multi-step run.  The state and fields are concatenated
+    by member; ``layout()`` gives the offsets.  U is structure of arrays over the concatenated
+    cells (all Ux, then all Uy, then all Uz)."""
+
+    CONFIG_KEYS = ("block_cells", "surface_blocks", "surface_waves", "bound_blocks")
+
+    def __init__(self, meshes, options: IsoOptions | None = None, stream=None):
+        self.meshes = list(meshes)  # kept alive only for the caller's convenience; the batch copies them
+        self.options = options or default_options()
+        arr = (_vp * len(self.meshes))(*[m.h.value for m in self.meshes])
+        h = _vp()
+        check(lib().iso_batch_create(arr, len(self.meshes), C.byref(self.options), _stream_handle(stream), C.byref(h)))
+        self.h = h
+        co = (C.c_int64 * (len(self.meshes) + 1))()
+        fo = (C.c_int64 * (len(self.meshes) + 1))()
+        check(lib().iso_batch_layout(self.h, co, fo))
+        self.cell_off = np.array(co[:], dtype=np.int64)
+        self.face_off = np.array(fo[:], dtype=np.int64)
+        self.n_cells = int(self.cell_off[-1])
+        self.n_faces = int(self.face_off[-1])
+
+    def layout(self):
+        return self.cell_off.copy(), self.face_off.copy()
+
+    def concat_cells(self, per_member):
+        """Concatenate per-member cell arrays (numpy) into the batch layout."""
+        return np.concatenate([np.asarray(a, dtype=np.float64) for a in per_member])
+
+    def concat_U(self, per_member):
+        """Concatenate per-member SoA velocity arrays [3 n_d] into the batch SoA layout [3 N]."""
+        parts = [np.asarray(u, dtype=np.float64).reshape(3, -1) for u in per_member]
+        return np.concatenate([np.concatenate([p[k] for p in parts]) for k in range(3)])
+
+    def split_cells(self, a):
+        a = np.asarray(a)
+        return [a[self.cell_off[d]:self.cell_off[d + 1]] for d in range(len(self.meshes))]
+
+    def advect(self, alpha, phi, U, dt, n_steps, phi_stride=0, U_stride=0, stream=None):
+        """In place: alpha (device, float64 [N]) after n_steps steps.  phi/U: device tensors holding one
+        step's fields (strides 0) or several steps' fields at the given element strides."""
+        dts = np.ascontiguousarray(dt, dtype=np.float64)
+        if dts.shape != (len(self.meshes),):
+            raise ValueError("dt needs one time step per member")
+        check(lib().iso_batch_advect(self.h, _ptr(alpha), _ptr(phi), int(phi_stride), _ptr(U), int(U_stride),
+                                     dts.ctypes.data_as(_dp), int(n_steps)))
+        return alpha
+
+    def config(self):
+        c = (C.c_int32 * 4)()
+        check(lib().iso_batch_config(self.h, c))
+        return dict(zip(self.CONFIG_KEYS, c[:]))
+
+    def set_config(self, **kw):
+        cur = self.config()
+        cur.update(kw)
+        c = (C.c_int32 * 4)(*[int(cur[k]) for k in self.CONFIG_KEYS])
+        check(lib().iso_batch_set_config(self.h, c))
+
+    def tune(self, alpha, phi, U, dt, n_trial=3, cache_path=None):
+        """Autotune the launch shapes on n_trial steps (alpha is not modified).  Returns (config, ms/step)."""
+        dts = np.ascontiguousarray(dt, dtype=np.float64)
+        best = C.c_double(0.0)
+        check(lib().iso_batch_tune(self.h, _ptr(alpha), _ptr(phi), _ptr(U), dts.ctypes.data_as(_dp), int(n_trial),
+                                   cache_path.encode() if cache_path else None, C.byref(best)))
+        return self.config(), best.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().iso_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -34,6 +34,10 @@ struct DevMesh {
     const int32_t *st_cell = nullptr;
     const double *st_w = nullptr;        // normalised inverse-distance weights
     const double *patch_alpha = nullptr; // [n_patches]
+    // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
+    // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
+    int32_t n_dom = 0;
+    const int32_t *dom_off = nullptr;    // [n_dom+1]
 };
 
 // Workspace of a plan (device pointers).
@@ -72,6 +76,15 @@ struct StepArgs {
     const double *U;
     double *alpha_new;
     double dt;
+    const double *dt_dom;  // [n_dom] per-member time steps of an ensemble, or nullptr
+};
+
+// Launch shapes of a step (none of them changes a result).
+struct LaunchCfg {
+    int block_cells;    // threads per block of the per-cell kernels
+    int surface_blocks; // work-groups of the interface kernel (0: from the list capacity)
+    int surface_waves;  // register budget of the interface kernel, waves per SIMD (1-4)
+    int bound_blocks;   // work-groups of the bounding sweeps
 };
 
 struct Params {
@@ -82,8 +95,13 @@ struct Params {
 // kernels.hip
 // ev: nullptr, or 5 events recorded before each of the 4 kernels and after the last
 hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, const StepArgs &a,
-                       const iso_trace *trace, int block_cells, int block_surface, int surface_waves,
-                       bool want_stats, hipStream_t s, hipEvent_t *ev);
+                       const iso_trace *trace, const LaunchCfg &cfg, bool want_stats, hipStream_t s, hipEvent_t *ev);
+// dst[i] = src[i] with offsets (ensemble meshes).  mode 0: v >= 0 -> v + off1;  mode 1 (packed flux
+// face): kEmpty kept, v >= 0 -> v + off1, else ~(~v + off1);  mode 2 (cell across a face): v >= 0 ->
+// v + off1, else -1 - (-1 - v + off2).  src == nullptr fills dst with off1.
+hipError_t launch_offset_copy(const int32_t *src, int32_t *dst, int64_t n, int mode, int32_t off1, int32_t off2,
+                              hipStream_t s);
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha, const double *alpha_new,
                         hipStream_t s);
 
@@ -95,6 +113,7 @@ struct iso_mesh {
     std::vector<int32_t> cell_pts;   // [8*n_cells] user point ids, canonical order
     std::vector<double> vol, xc;
     std::vector<double> patch_alpha;
+    int64_t st_nnz = 0;              // entries of the vertex stencils
     std::vector<void *> allocations;
     int64_t device_bytes = 0;
     int device = 0;
@@ -114,4 +133,6 @@ struct iso_plan {
 
 namespace isoadv {
 iso_status fail(iso_status s, const std::string &msg);
+LaunchCfg launch_cfg(const iso_options &o);
+Params step_params(const iso_options &o);
 }

@@ -40,6 +40,18 @@ __device__ __forceinline__ D3 sel3(bool c, D3 a, D3 b) { return D3{c ? a.x : b.x
 
 __device__ __forceinline__ bool interface_cell(double a, double eps) { return a > eps && a < 1.0 - eps; }
 
+// Time step of cell c: the scalar one, or its ensemble member's (binary search over the members'
+// cell offsets, a table of at most a few hundred bytes that stays in cache).
+__device__ __forceinline__ double cell_dt(const DevMesh &m, const double *dt_dom, double dt, int c) {
+    if (m.n_dom <= 0) return dt;
+    int lo = 0, hi = m.n_dom;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m.dom_off[mid] <= c) lo = mid; else hi = mid;
+    }
+    return dt_dom[lo];
+}
+
 // edges of the canonical hexahedron, and for each face loop position the edge to the next vertex
 constexpr int kEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
                               {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
@@ -478,7 +490,9 @@ __global__ void __launch_bounds__(kFindBlock) k_find_surface(const double *__res
 struct SurfArgs {
     DevMesh m;
     const double *alpha, *phi, *U;
-    double dt, eps, flat_tol;
+    double dt;
+    const double *dt_dom;
+    double eps, flat_tol;
     int32_t max_rounds;
     const int32_t *list;
     int32_t *counters;
@@ -518,6 +532,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
         const int c = A.list[idx];
         const double aP = A.alpha[c];
         const double V6 = 6.0 * m.vol[c];
+        const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
         // lane lv: vertex lv's coordinates and value
         const double *cx = m.cxyz + 24 * (size_t)c + 3 * lv;
         D3 xv{cx[0], cx[1], cx[2]};
@@ -731,8 +746,8 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                             // planar face: two triangles cover it exactly
                             const double A1 = 0.5 * norm3(cross(f.q[1] - f.q[0], f.q[2] - f.q[0]));
                             const double A2 = 0.5 * norm3(cross(f.q[2] - f.q[0], f.q[3] - f.q[0]));
-                            acc = A1 * tri_sweep(dq[0], dq[1], dq[2], un, A.dt) +
-                                  A2 * tri_sweep(dq[0], dq[2], dq[3], un, A.dt);
+                            acc = A1 * tri_sweep(dq[0], dq[1], dq[2], un, dtc) +
+                                  A2 * tri_sweep(dq[0], dq[2], dq[3], un, dtc);
                             Af = A1 + A2;
                         } else {
                             // fan about the vertex mean
@@ -741,13 +756,13 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const double Ai = 0.5 * norm3(cross(f.q[i] - ap, f.q[(i + 1) & 3] - ap));
-                                acc += Ai * tri_sweep(dap, dq[i], dq[(i + 1) & 3], un, A.dt);
+                                acc += Ai * tri_sweep(dap, dq[i], dq[(i + 1) & 3], un, dtc);
                                 Af += Ai;
                             }
                         }
                         dv = ph * (acc / Af);
                     } else {
-                        dv = aP * ph * A.dt;
+                        dv = aP * ph * dtc;
                     }
                     A.dvs[fid] = dv;
                 }
@@ -771,7 +786,9 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
 struct UpdArgs {
     DevMesh m;
     const double *alpha, *phi, *dvs;
-    double dt, eps, tol;
+    double dt;
+    const double *dt_dom;
+    double eps, tol;
     int clip;
     double *alpha_new;
     int32_t *olist;
@@ -780,8 +797,9 @@ struct UpdArgs {
 };
 
 // W flux slots per cell, all loads of one kind issued together (independent gathers in flight).
+// Any block size up to 1024 (the block_cells option) is valid.
 template <int W>
-__global__ void __launch_bounds__(256) k_update(UpdArgs A) {
+__global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     const int n = A.m.n_cells;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     bool offend = false;
@@ -802,6 +820,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs A) {
             ao[k] = o[k] >= 0 ? A.alpha[o[k]] : (v[k] != kEmpty ? A.m.patch_alpha[-1 - o[k]] : 0.0);
         }
         const bool sP = interface_cell(aP, A.eps);
+        const double dtc = cell_dt(A.m, A.dt_dom, A.dt, c);
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -810,9 +829,9 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs A) {
             const double out = v[k] >= 0 ? ph[k] : -ph[k];
             double dv = 0.0;
             if (out > 0.0) {
-                dv = sP ? A.dvs[fid] : aP * ph[k] * A.dt;
+                dv = sP ? A.dvs[fid] : aP * ph[k] * dtc;
             } else if (out < 0.0) {
-                dv = (o[k] >= 0 && interface_cell(ao[k], A.eps)) ? A.dvs[fid] : ao[k] * ph[k] * A.dt;
+                dv = (o[k] >= 0 && interface_cell(ao[k], A.eps)) ? A.dvs[fid] : ao[k] * ph[k] * dtc;
             }
             sum += v[k] >= 0 ? dv : -dv;
             if (A.trace_dV && v[k] >= 0) A.trace_dV[fid] = dv;
@@ -841,7 +860,9 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs A) {
 struct BoundArgs {
     DevMesh m;
     const double *alpha, *phi, *dvs;
-    double dt, eps, tol;
+    double dt;
+    const double *dt_dom;
+    double eps, tol;
     int clip, n_iter;
     double *alpha_new;
     DevWork w;
@@ -932,6 +953,7 @@ __global__ void __launch_bounds__(256) k_bound_a(BoundArgs A, int it) {
             const bool over = a > 1.0 + A.tol;
             const double aold = A.alpha[P];
             const bool sP = interface_cell(aold, A.eps);
+            const double dtc = cell_dt(A.m, A.dt_dom, A.dt, P);
             int32_t mk[W];
             double dvs_v[W], dvc_v[W];
 #pragma unroll
@@ -951,9 +973,9 @@ __global__ void __launch_bounds__(256) k_bound_a(BoundArgs A, int it) {
                 const double outphi = sl.v[k] >= 0 ? sl.ph[k] : -sl.ph[k];
                 if (!(outphi > 0.0)) continue;
                 // current dV of the face: running value once touched, else this step's
-                dvnow[k] = mk[k] ? dvc_v[k] : (sP ? dvs_v[k] : aold * sl.ph[k] * A.dt);
+                dvnow[k] = mk[k] ? dvc_v[k] : (sP ? dvs_v[k] : aold * sl.ph[k] * dtc);
                 const double outv = sl.v[k] >= 0 ? dvnow[k] : -dvnow[k];
-                cap[k] = over ? outphi * A.dt - outv : outv;
+                cap[k] = over ? outphi * dtc - outv : outv;
                 if (cap[k] > 0.0) sumcap += cap[k];
             }
             if (atomicExch(&A.w.cmark[P], 1) == 0) tsel[W] = P;
@@ -1094,26 +1116,45 @@ __global__ void __launch_bounds__(1024) k_stats(const double *alpha, const doubl
     if (t == 0) { red[0] = sb[0]; red[1] = sa[0]; red[2] = smin[0]; red[3] = smax[0]; red[4] = 0.0; }
 }
 
-constexpr int kBoundGrid = 512;  // work-groups of the bounding sweeps (grid-stride over device-side counts)
-
 template <int W>
-void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, int block_cells, hipStream_t s,
+void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, const LaunchCfg &cfg, hipStream_t s,
                  hipEvent_t *ev) {
-    const int gc = (m.n_cells + block_cells - 1) / block_cells;
-    hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(block_cells), 0, s, ua);
+    const int gc = (m.n_cells + cfg.block_cells - 1) / cfg.block_cells;
+    hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(cfg.block_cells), 0, s, ua);
     if (ev) (void)hipEventRecord(ev[3], s);
     for (int it = 0; it < ba.n_iter; ++it) {
-        hipLaunchKernelGGL(k_bound_a<W>, dim3(kBoundGrid), dim3(256), 0, s, ba, it);
-        hipLaunchKernelGGL(k_bound_b<W>, dim3(kBoundGrid), dim3(256), 0, s, ba, it, it == ba.n_iter - 1 ? 1 : 0);
+        hipLaunchKernelGGL(k_bound_a<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
+        hipLaunchKernelGGL(k_bound_b<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it, it == ba.n_iter - 1 ? 1 : 0);
     }
     hipLaunchKernelGGL(k_bound_end, dim3(1), dim3(1024), 0, s, ba);
+}
+
+__global__ void k_offset_copy(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int64_t n, int mode,
+                              int32_t off1, int32_t off2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!src) { dst[i] = off1; continue; }
+        const int32_t v = src[i];
+        int32_t r;
+        if (mode == 0) r = v >= 0 ? v + off1 : v;
+        else if (mode == 1) r = v == kEmpty ? v : (v >= 0 ? v + off1 : ~(~v + off1));
+        else r = v >= 0 ? v + off1 : -1 - (-1 - v + off2);
+        dst[i] = r;
+    }
+}
+
+__global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 }  // namespace
 
 hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, const StepArgs &a, const iso_trace *trace,
-                       int block_cells, int block_surface, int surface_waves, bool want_stats, hipStream_t s,
-                       hipEvent_t *ev) {
+                       const LaunchCfg &cfg, bool want_stats, hipStream_t s, hipEvent_t *ev) {
+    // launch shapes must stay within what each kernel was compiled for
+    if (cfg.block_cells < 1 || cfg.block_cells > 1024 || cfg.surface_blocks < 0 || cfg.surface_blocks > 65535 ||
+        cfg.surface_waves < 1 || cfg.surface_waves > 4 || cfg.bound_blocks < 1 || cfg.bound_blocks > 65535)
+        return hipErrorInvalidValue;
     const int n = m.n_cells;
     iso_trace tr{};
     if (trace) tr = *trace;
@@ -1122,33 +1163,48 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     hipLaunchKernelGGL(k_find_surface, dim3(gf), dim3(kFindBlock), 0, s, a.alpha, n, p.eps_surf, w.surf, w.cap,
                        w.counters, tr.kind);
     if (ev) (void)hipEventRecord(ev[1], s);
-    SurfArgs sa{m, a.alpha, a.phi, a.U, a.dt, p.eps_surf, p.flat_tol, p.root_max_iter, w.surf, w.counters, w.cap,
-                w.dvs, want_stats ? 1 : 0, tr};
+    SurfArgs sa{m, a.alpha, a.phi, a.U, a.dt, a.dt_dom, p.eps_surf, p.flat_tol, p.root_max_iter, w.surf, w.counters,
+                w.cap, w.dvs, want_stats ? 1 : 0, tr};
     const int bs = 256;  // the interface kernel's register budget assumes 256-thread work-groups
-    (void)block_surface;
     const long groups_per_block = bs / kLanes;
     long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
-    gs = std::max(1L, std::min(gs, 1024L));  // persistent: groups loop over the list
-    switch (surface_waves) {
+    // persistent: groups loop over the list, which is only known on the device
+    gs = std::max(1L, std::min(gs, cfg.surface_blocks > 0 ? (long)cfg.surface_blocks : 1024L));
+    switch (cfg.surface_waves) {
         case 1: hipLaunchKernelGGL(k_surface<1>, dim3((int)gs), dim3(bs), 0, s, sa); break;
         case 3: hipLaunchKernelGGL(k_surface<3>, dim3((int)gs), dim3(bs), 0, s, sa); break;
         case 4: hipLaunchKernelGGL(k_surface<4>, dim3((int)gs), dim3(bs), 0, s, sa); break;
         default: hipLaunchKernelGGL(k_surface<2>, dim3((int)gs), dim3(bs), 0, s, sa); break;
     }
     if (ev) (void)hipEventRecord(ev[2], s);
-    UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist, w.counters,
-               tr.dV, tr.alpha_raw};
-    BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter, a.alpha_new, w};
-    const int bc = std::min(256, block_cells);
+    UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist,
+               w.counters, tr.dV, tr.alpha_raw};
+    BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
+                 a.alpha_new, w};
     switch (m.W) {
-        case 1: launch_wide<1>(m, ua, ba, bc, s, ev); break;
-        case 2: launch_wide<2>(m, ua, ba, bc, s, ev); break;
-        case 3: launch_wide<3>(m, ua, ba, bc, s, ev); break;
-        case 4: launch_wide<4>(m, ua, ba, bc, s, ev); break;
-        case 5: launch_wide<5>(m, ua, ba, bc, s, ev); break;
-        default: launch_wide<6>(m, ua, ba, bc, s, ev); break;
+        case 1: launch_wide<1>(m, ua, ba, cfg, s, ev); break;
+        case 2: launch_wide<2>(m, ua, ba, cfg, s, ev); break;
+        case 3: launch_wide<3>(m, ua, ba, cfg, s, ev); break;
+        case 4: launch_wide<4>(m, ua, ba, cfg, s, ev); break;
+        case 5: launch_wide<5>(m, ua, ba, cfg, s, ev); break;
+        default: launch_wide<6>(m, ua, ba, cfg, s, ev); break;
     }
     if (ev) (void)hipEventRecord(ev[4], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_offset_copy(const int32_t *src, int32_t *dst, int64_t n, int mode, int32_t off1, int32_t off2,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int g = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_offset_copy, dim3(g), dim3(256), 0, s, src, dst, n, mode, off1, off2);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int g = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_copy_f64, dim3(g), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

@@ -88,6 +88,17 @@ iso_status fail(iso_status s, const std::string &msg) {
     g_last_error = msg;
     return s;
 }
+LaunchCfg launch_cfg(const iso_options &o) {
+    LaunchCfg c;
+    c.block_cells = o.block_cells > 0 ? o.block_cells : 256;
+    c.surface_blocks = o.surface_blocks;
+    c.surface_waves = o.surface_waves > 0 ? o.surface_waves : 2;
+    c.bound_blocks = o.bound_blocks > 0 ? o.bound_blocks : 512;
+    return c;
+}
+Params step_params(const iso_options &o) {
+    return Params{o.eps_surf, o.flat_tol, o.bound_tol, o.root_max_iter, o.n_bound_iter, o.clip};
+}
 }  // namespace isoadv
 
 extern "C" {
@@ -368,6 +379,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     for (int32_t c = 0; c < n_cells; ++c)
         for (int i = 0; i < 8; ++i) cnt[cls[m->cell_pts[8 * (size_t)c + i]] + 1]++;
     for (int32_t k = 0; k < n_classes; ++k) cnt[k + 1] += cnt[k];
+    m->st_nnz = cnt[n_classes];
     std::vector<int32_t> st_cell(cnt[n_classes]);
     std::vector<double> st_w(cnt[n_classes]);
     std::vector<int32_t> fillc(n_classes, 0);
@@ -466,7 +478,8 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
     if (opt) p->opt = *opt; else iso_options_default(&p->opt);
     const iso_options &o = p->opt;
     if (!(o.eps_surf >= 0 && o.eps_surf < 0.5) || !(o.flat_tol >= 0) || !(o.bound_tol >= 0) || o.root_max_iter < 1 ||
-        o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 || o.block_surface < 0 || o.block_surface > 1024 ||
+        o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 ||
+        o.surface_blocks < 0 || o.surface_blocks > 65535 || o.bound_blocks < 0 || o.bound_blocks > 65535 ||
         o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4) {
         delete p;
         return fail(ISO_EINVAL, "bad options");
@@ -501,6 +514,7 @@ iso_status iso_plan_set_stream(iso_plan *p, void *stream) {
     p->stream = static_cast<hipStream_t>(stream);
     return ISO_OK;
 }
+
 
 static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
     auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
@@ -550,15 +564,11 @@ static iso_status step_impl(iso_plan *p, const double *alpha, const double *phi,
         if (s != ISO_OK) return s;
     }
     (void)hipGetLastError();
-    Params prm{p->opt.eps_surf, p->opt.flat_tol, p->opt.bound_tol, p->opt.root_max_iter, p->opt.n_bound_iter,
-               p->opt.clip};
-    StepArgs args{alpha, phi, U, alpha_new, dt};
-    int bc = p->opt.block_cells > 0 ? p->opt.block_cells : 256;
-    int bs = p->opt.block_surface > 0 ? p->opt.block_surface : 64;
+    const Params prm = step_params(p->opt);
+    StepArgs args{alpha, phi, U, alpha_new, dt, nullptr};
     hipEvent_t *ev = nullptr;
     if (p->timing_used < p->timing_cap) ev = &p->events[5 * (size_t)p->timing_used++];
-    hipError_t e = launch_step(m->dev, p->work, prm, args, trace, bc, bs, p->opt.surface_waves, stats != nullptr,
-                               p->stream, ev);
+    hipError_t e = launch_step(m->dev, p->work, prm, args, trace, launch_cfg(p->opt), stats != nullptr, p->stream, ev);
     if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     if (p->work.cap < m->n_cells && !stats) {  // a limited interface-cell list: check it was enough
         e = hipMemcpyAsync(p->host_counters, p->work.counters, kCntNum * sizeof(int32_t), hipMemcpyDeviceToHost,

@@ -65,3 +65,18 @@ def test_cyclic_mismatch_detected():
     with pytest.raises(B.IsoError) as e:
         _create(m, pt=pt2)
     assert e.value.status in (B.ISO_EMESH, B.ISO_EDEVICE)
+
+
+def test_batch_entry_points_reject_null_arguments():
+    """Ensemble calls check their arguments before any device work."""
+    L = B.lib()
+    h = C.c_void_p()
+    assert L.iso_batch_create(None, 0, None, None, C.byref(h)) == B.ISO_EINVAL
+    assert L.iso_batch_create(None, 2, None, None, None) == B.ISO_EINVAL
+    dt = (C.c_double * 1)(1.0)
+    assert L.iso_batch_advect(None, None, None, 0, None, 0, dt, 1) == B.ISO_EINVAL
+    cfg = (C.c_int32 * 4)()
+    assert L.iso_batch_config(None, cfg) == B.ISO_EINVAL
+    assert L.iso_batch_set_config(None, cfg) == B.ISO_EINVAL
+    assert L.iso_batch_tune(None, None, None, None, dt, 1, None, None) == B.ISO_EINVAL
+    assert L.iso_batch_layout(None, None, None) == B.ISO_EINVAL
