@@ -19,67 +19,10 @@
 
 #include <algorithm>
 
-#include "internal.h"
+#include "device_common.h"
 
 namespace isoadv {
 namespace {
-
-struct D3 {
-    double x, y, z;
-};
-__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ D3 operator*(double s, D3 a) { return {s * a.x, s * a.y, s * a.z}; }
-__device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ D3 cross(D3 a, D3 b) {
-    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
-__device__ __forceinline__ double norm3(D3 a) { return sqrt(dot(a, a)); }
-// component-wise select (a select of the whole struct can be lowered through memory)
-__device__ __forceinline__ D3 sel3(bool c, D3 a, D3 b) { return D3{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z}; }
-
-__device__ __forceinline__ bool interface_cell(double a, double eps) { return a > eps && a < 1.0 - eps; }
-
-// Time step of cell c: the scalar one, or its ensemble member's (binary search over the members'
-// cell offsets, a table of at most a few hundred bytes that stays in cache).
-__device__ __forceinline__ double cell_dt(const DevMesh &m, const double *dt_dom, double dt, int c) {
-    if (m.n_dom <= 0) return dt;
-    int lo = 0, hi = m.n_dom;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (m.dom_off[mid] <= c) lo = mid; else hi = mid;
-    }
-    return dt_dom[lo];
-}
-
-// edges of the canonical hexahedron, and for each face loop position the edge to the next vertex
-constexpr int kEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
-                              {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
-constexpr int kFaceEdge[6][4] = {{3, 2, 1, 0}, {4, 5, 6, 7}, {0, 9, 4, 8}, {1, 10, 5, 9}, {2, 11, 6, 10}, {3, 8, 7, 11}};
-
-constexpr bool face_edges_consistent() {
-    for (int k = 0; k < 6; ++k)
-        for (int i = 0; i < 4; ++i) {
-            const int p = kHexFace[k][i], q = kHexFace[k][(i + 1) & 3], e = kFaceEdge[k][i];
-            if (!((kEdge[e][0] == p && kEdge[e][1] == q) || (kEdge[e][0] == q && kEdge[e][1] == p))) return false;
-        }
-    return true;
-}
-static_assert(face_edges_consistent(), "face/edge tables disagree");
-
-// ------------------------------------------------------------------------------------------ faces
-// The eight lanes of an interface cell's group split every sub-volume evaluation by face: lane k
-// (k < 6) owns canonical face k, its four vertices (relative to the cell's vertex mean), their
-// values, and the reciprocal value difference along each of its edges.  Lanes 6 and 7 only help
-// gathering vertex values.
-struct FaceLane {
-    D3 q[4];
-    double aq[4];
-    double inv[4];  // 1/(a_j - a_i) of the canonical edge (i, j) under loop position k
-    int fwd;        // bit k: loop position k runs along the canonical edge direction
-    bool planar;
-    bool active;
-};
 
 // One face's share of six times the wet sub-volume and of the isoface sums.
 struct Part {
@@ -90,18 +33,6 @@ struct Part {
     D3 osum;    // sum of their entry points
     double nseg;
 };
-
-// Cut point on the face edge from loop position i to i+1, measured from its wet end; both faces
-// sharing the edge evaluate the same expression on the same operands, so they agree bitwise.
-__device__ __forceinline__ D3 face_cut(const FaceLane &f, int i, double iso, bool wet_i) {
-    const int j = (i + 1) & 3;
-    const bool fwd = (f.fwd >> i) & 1;
-    const D3 xw = sel3(wet_i, f.q[i], f.q[j]), xd = sel3(wet_i, f.q[j], f.q[i]);
-    const double aw = wet_i ? f.aq[i] : f.aq[j];
-    // wet end is the canonical edge's first vertex iff (wet_i == fwd)
-    const double lam = (wet_i == fwd) ? (iso - aw) * f.inv[i] : (aw - iso) * f.inv[i];
-    return xw + lam * (xd - xw);
-}
 
 // Divergence-theorem share of face k for isovalue iso (vertex wet iff a > iso; a >= iso with
 // tie_wet, the limit from below).  The wet part of the face is its loop emitting wet vertices and
@@ -404,31 +335,6 @@ __device__ __forceinline__ double tri_sweep(double d0, double d1, double d2, dou
     return I;
 }
 
-// ------------------------------------------------------------------------------------------ lanes
-// Reductions and broadcasts inside a group of 8 consecutive lanes (one interface cell).  The sum
-// is a butterfly on DPP lane moves (swap neighbours, swap pairs inside a quad, mirror the two
-// quads of the half-row): each step adds the same two partial sums in both partner lanes, so all
-// lanes hold bitwise-equal results.  All 8 lanes of a group are active together (every branch
-// around a reduction depends only on group-uniform values).
-template <int Ctrl>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, Ctrl, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), Ctrl, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-constexpr int kDppSwap1 = 0xB1;       // quad_perm [1,0,3,2]
-constexpr int kDppSwap2 = 0x4E;       // quad_perm [2,3,0,1]
-constexpr int kDppHalfMirror = 0x141; // row_half_mirror: lane i <- lane 7-i within 8
-__device__ __forceinline__ double grp_sum(double v) {
-    v += dpp_move<kDppSwap1>(v);
-    v += dpp_move<kDppSwap2>(v);
-    v += dpp_move<kDppHalfMirror>(v);
-    return v;
-}
-__device__ __forceinline__ D3 grp_sum3(D3 v) { return D3{grp_sum(v.x), grp_sum(v.y), grp_sum(v.z)}; }
-__device__ __forceinline__ double grp_get(double v, int src) { return __shfl(v, src, 8); }
-
 // Six times the wet sub-volume of the cell (all lanes of the group take part and get the result).
 __device__ __forceinline__ double cell_vsub6(const FaceLane &f, double iso, bool tie_wet, D3 *o_out, D3 *cseg_out) {
     const Part p = face_part(f, iso, tie_wet);
@@ -502,7 +408,6 @@ struct SurfArgs {
     iso_trace tr;
 };
 
-constexpr int kLanes = 8;  // lanes per interface cell
 
 // kMinBlocks: work-groups of 256 per CU the register allocation must allow (waves per SIMD)
 template <int kMinBlocks>
@@ -513,20 +418,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
     const int n = min(A.counters[kCntSurf], A.cap);
     // face lv's vertex loop and edge directions (constant per lane)
     int fv[4];
-    int fwd = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        fv[i] = kHexFace[0][i];
-        int e = kFaceEdge[0][i];
-#pragma unroll
-        for (int k = 1; k < 6; ++k)
-            if (lv == k) { fv[i] = kHexFace[k][i]; e = kFaceEdge[k][i]; }
-        int first = kEdge[0][0];
-#pragma unroll
-        for (int t = 1; t < 12; ++t)
-            if (e == t) first = kEdge[t][0];
-        if (first == fv[i]) fwd |= 1 << i;
-    }
+    const int fwd = lane_face_loop(lv, fv);
     int rounds_max = 0, flat = 0, nonconv = 0;
     for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; idx < n; idx += ngrp) {
         const int c = A.list[idx];
@@ -887,23 +779,6 @@ __device__ __forceinline__ void load_slots(const BoundArgs &A, int32_t c, Slots<
         s.fid[k] = s.v[k] >= 0 ? s.v[k] : ~s.v[k];
         s.ph[k] = s.v[k] != kEmpty ? A.phi[s.fid[k]] : 0.0;
     }
-}
-
-// Append `count` entries per lane to a device-wide list: one atomic per wave.  Returns the index of
-// this lane's first entry.  Every lane of the wave must call it (count may be 0).
-__device__ __forceinline__ int wave_append(int count, int32_t *counter) {
-    const int lane = __lane_id();
-    int incl = count;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
-    const int total = __shfl(incl, 63, 64);
-    int base = 0;
-    if (lane == 63 && total > 0) base = atomicAdd(counter, total);
-    base = __shfl(base, 63, 64);
-    return base + incl - count;
 }
 
 // Bounding counters of sweep `it` live in one of three rotating slots: a slot is read by the two
