@@ -624,7 +624,8 @@ static double vol_frac_minus_alpha(const or_mesh *m, int c, const double *a_pts,
  * exploits).  So: find consecutive distinct vertex values lo < hi with f(lo) > 0 >= f(hi); if the
  * limit of f from below at hi is still positive, f jumps across zero there and the isovalue is hi;
  * otherwise bisect (lo, hi) down to adjacent doubles. */
-double or_cell_isovalue(const or_mesh *m, int c, const double *a_pts, double alpha_c, int max_iter, int *iters) {
+static double cell_isovalue(const or_mesh *m, int c, const double *a_pts, double alpha_c, int max_iter, int *iters,
+                            int *jump) {
     double s[OR_MAXFP * 8] = {0};
     int n = 0;
     for (int i = m->cpptr[c]; i < m->cpptr[c + 1]; ++i) s[n++] = a_pts[m->cpts[i]];
@@ -642,6 +643,7 @@ double or_cell_isovalue(const or_mesh *m, int c, const double *a_pts, double alp
     }
     ++it;
     double fhi = vol_frac_minus_alpha(m, c, a_pts, hi, 1, alpha_c);  /* limit from below at hi */
+    if (jump) *jump = fhi > 0.0;
     if (fhi > 0.0) { if (iters) *iters = it; return hi; }
     while (it < max_iter) {
         double mid = lo + 0.5 * (hi - lo);
@@ -653,6 +655,10 @@ double or_cell_isovalue(const or_mesh *m, int c, const double *a_pts, double alp
     }
     if (iters) *iters = it;
     return fabs(flo) <= fabs(fhi) ? lo : hi;
+}
+
+double or_cell_isovalue(const or_mesh *m, int c, const double *a_pts, double alpha_c, int max_iter, int *iters) {
+    return cell_isovalue(m, c, a_pts, alpha_c, max_iter, iters, NULL);
 }
 
 /* ------------------------------------------------------------------ Eqs. tv, x_41, aplus1/2, intaplus */
@@ -970,4 +976,389 @@ int or_cell_cut_flat(const or_mesh *m, int c, const double *a_pts, double iso, d
     for (int d = 0; d < 3; ++d) { out[1 + d] = cut.S[d]; out[4 + d] = cut.xS[d]; out[7 + d] = cut.Swet[d]; }
     out[10] = cut.n_cut;
     return r;
+}
+
+/* ==================================================================================================
+ * Tangent of the step (directional derivative with respect to alpha and phi), by the complex step.
+ *
+ * Every quantity that depends on alpha or phi is carried as x + i h x' with h tiny, through the same
+ * arithmetic as the step above; branches, comparisons and sorting use the real parts, so the real
+ * parts reproduce the step and Im(result)/h is its exact derivative along (x') (no subtraction,
+ * hence no cancellation).  Lengths are sqrt(v . v) without conjugation, which keeps every
+ * operation analytic.  The isovalue is found on the real parts by the search above; its
+ * derivative follows from the volume constraint vsub(iso; a)/V = alpha_P (implicit function):
+ * iso' = -(d/dt [vsub(iso; a + t a')/V - alpha_P - t alpha_P'])/(d vsub/d iso / V), both derivatives
+ * taken by complex steps.  Where the isovalue sits at a jump of the sub-volume (R3) it is the
+ * vertex value itself and moves with it.  Chopped or clipped values are constants.
+ * ================================================================================================== */
+#include <complex.h>
+typedef double complex cplx;
+
+/* h is so small that h^2 underflows to zero: products of two perturbations never reach the real
+ * parts, which therefore stay exactly those of the step (a product of a perturbed alpha and a
+ * perturbed phi in an empty cell would otherwise leave a real part of order h^2 and flip a chop). */
+#define OR_CSTEP 1e-200
+
+static cplx c_dot3(const cplx *a, const cplx *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void c_cross3(const cplx *a, const cplx *b, cplx *o) {
+    cplx x = a[1] * b[2] - a[2] * b[1], y = a[2] * b[0] - a[0] * b[2], z = a[0] * b[1] - a[1] * b[0];
+    o[0] = x; o[1] = y; o[2] = z;
+}
+static cplx c_norm3(const cplx *a) { return csqrt(c_dot3(a, a)); }
+static void c_sub3(const cplx *a, const cplx *b, cplx *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static void c_of(const double *a, cplx *o) { o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; }
+
+static void cs_point_values(const or_mesh *m, const cplx *alpha, cplx *a_pts) {
+    for (int p = 0; p < m->n_points; ++p) {
+        if (m->prep[p] != p) continue;
+        const double *xp = m->P + 3 * p;
+        cplx num = 0;
+        double den = 0;
+        for (int s = m->stptr[p]; s < m->stptr[p + 1]; ++s) {
+            int c = m->st_cell[s];
+            double xcs[3], e[3];
+            for (int d = 0; d < 3; ++d) xcs[d] = m->xc[3 * c + d] + m->st_off[3 * s + d];
+            v_sub(xp, xcs, e);
+            double w = 1.0 / v_norm(e);
+            num += w * alpha[c];
+            den += w;
+        }
+        a_pts[p] = num / den;
+    }
+    for (int p = 0; p < m->n_points; ++p) a_pts[p] = a_pts[m->prep[p]];
+}
+
+typedef struct {
+    cplx vsub, S[3], xS[3];
+    int n_cut;
+} cs_cut;
+
+static void cs_cut_point(const double *xw, cplx aw, const double *xd, cplx ad, cplx iso, cplx *out) {
+    cplx lam = (iso - aw) / (ad - aw);
+    for (int d = 0; d < 3; ++d) out[d] = xw[d] + lam * (xd[d] - xw[d]);
+}
+
+static void cs_fan(cplx (*poly)[3], int n, const cplx *apex, const double *xref, cplx *vol) {
+    for (int i = 0; i < n; ++i) {
+        const cplx *p0 = poly[i], *p1 = poly[(i + 1) % n];
+        cplx e0[3], e1[3], St[3], r[3];
+        c_sub3(p0, apex, e0); c_sub3(p1, apex, e1); c_cross3(e0, e1, St);
+        for (int d = 0; d < 3; ++d) { St[d] *= 0.5; r[d] = (apex[d] + p0[d] + p1[d]) / 3.0 - xref[d]; }
+        *vol += c_dot3(St, r) / 3.0;
+    }
+}
+
+static void cs_perimeter_centroid(cplx (*a)[3], cplx (*b)[3], int n, int closed_loop, cplx *out) {
+    cplx L = 0, acc[3] = {0, 0, 0}, mean[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        const cplx *p = a[i], *q = closed_loop ? a[(i + 1) % n] : b[i];
+        cplx e[3];
+        c_sub3(q, p, e);
+        cplx l = c_norm3(e);
+        L += l;
+        for (int d = 0; d < 3; ++d) { acc[d] += l * 0.5 * (p[d] + q[d]); mean[d] += p[d]; }
+    }
+    for (int d = 0; d < 3; ++d) out[d] = creal(L) > 0 ? acc[d] / L : mean[d] / n;
+}
+
+/* cell_cut with complex vertex values and isovalue (same walk, same readings R4-R6) */
+static int cs_cell_cut(const or_mesh *m, int c, const cplx *a_pts, cplx iso, int tie_wet, cs_cut *out) {
+    const double *xref = m->xc + 3 * c;
+    int fp[OR_MAXFP];
+    cplx poly[2 * OR_MAXFP][3];
+    cplx seg_a[OR_MAXCUT][3], seg_b[OR_MAXCUT][3];
+    int nseg = 0;
+    cplx vol = 0;
+    double isor = creal(iso);
+    for (int k = m->cfptr[c]; k < m->cfptr[c + 1]; ++k) {
+        int f = m->cfaces[k];
+        int n = face_points_for(m, f, c, fp);
+        int np_ = 0;
+        cplx last_exit[3] = {0, 0, 0}, first_entry[3] = {0, 0, 0};
+        int pending = 0, first_is_entry = 0;
+        for (int i = 0; i < n; ++i) {
+            int qi = fp[i], qj = fp[(i + 1) % n];
+            cplx ai = a_pts[qi], aj = a_pts[qj];
+            int wi = tie_wet ? creal(ai) >= isor : creal(ai) > isor;
+            int wj = tie_wet ? creal(aj) >= isor : creal(aj) > isor;
+            const double *xi = m->P + 3 * qi, *xj = m->P + 3 * qj;
+            if (wi) { c_of(xi, poly[np_]); ++np_; }
+            if (wi != wj) {
+                cplx cp[3];
+                if (wi) cs_cut_point(xi, ai, xj, aj, iso, cp); else cs_cut_point(xj, aj, xi, ai, iso, cp);
+                for (int d = 0; d < 3; ++d) poly[np_][d] = cp[d];
+                ++np_;
+                if (wi) {
+                    for (int d = 0; d < 3; ++d) last_exit[d] = cp[d];
+                    pending = 1;
+                } else if (pending) {
+                    if (nseg >= OR_MAXCUT) return -1;
+                    for (int d = 0; d < 3; ++d) { seg_a[nseg][d] = cp[d]; seg_b[nseg][d] = last_exit[d]; }
+                    ++nseg; pending = 0;
+                } else {
+                    first_is_entry = 1;
+                    for (int d = 0; d < 3; ++d) first_entry[d] = cp[d];
+                }
+            }
+        }
+        if (pending && first_is_entry) {
+            if (nseg >= OR_MAXCUT) return -1;
+            for (int d = 0; d < 3; ++d) { seg_a[nseg][d] = first_entry[d]; seg_b[nseg][d] = last_exit[d]; }
+            ++nseg;
+        }
+        if (np_ >= 3) {
+            cplx apex[3];
+            cs_perimeter_centroid(poly, poly, np_, 1, apex);
+            cs_fan(poly, np_, apex, xref, &vol);
+        }
+    }
+    out->n_cut = nseg;
+    for (int d = 0; d < 3; ++d) out->S[d] = out->xS[d] = 0;
+    if (nseg > 0) {
+        cplx o[3];
+        cs_perimeter_centroid(seg_a, seg_b, nseg, 0, o);
+        cplx S[3] = {0, 0, 0};
+        for (int s = 0; s < nseg; ++s) {
+            cplx e0[3], e1[3], St[3], r[3];
+            c_sub3(seg_a[s], o, e0); c_sub3(seg_b[s], o, e1); c_cross3(e0, e1, St);
+            for (int d = 0; d < 3; ++d) { St[d] *= 0.5; r[d] = (o[d] + seg_a[s][d] + seg_b[s][d]) / 3.0 - xref[d]; }
+            vol += c_dot3(St, r) / 3.0;
+            for (int d = 0; d < 3; ++d) S[d] += St[d];
+        }
+        cplx nrm = c_norm3(S);
+        for (int d = 0; d < 3; ++d) out->S[d] = S[d];
+        if (creal(nrm) > 0) {
+            cplx nS[3] = {S[0] / nrm, S[1] / nrm, S[2] / nrm};
+            cplx wsum = 0, xs[3] = {0, 0, 0};
+            for (int s = 0; s < nseg; ++s) {
+                cplx e0[3], e1[3], St[3];
+                c_sub3(seg_a[s], o, e0); c_sub3(seg_b[s], o, e1); c_cross3(e0, e1, St);
+                cplx w = 0.5 * c_dot3(St, nS);
+                for (int d = 0; d < 3; ++d) xs[d] += w * (o[d] + seg_a[s][d] + seg_b[s][d]) / 3.0;
+                wsum += w;
+            }
+            for (int d = 0; d < 3; ++d) out->xS[d] = xs[d] / wsum;
+        }
+    }
+    out->vsub = vol;
+    return 0;
+}
+
+/* R3 with its derivative: the real isovalue of the real data, then the implicit (or jump) tangent */
+static cplx cs_cell_isovalue(const or_mesh *m, int c, const cplx *a_pts, const double *a_re, cplx alpha_c,
+                             int max_iter, int *iters) {
+    int jump = 0;
+    double x = cell_isovalue(m, c, a_re, creal(alpha_c), max_iter, iters, &jump);
+    if (jump) {  /* the isovalue is a vertex value and moves with it */
+        for (int i = m->cpptr[c]; i < m->cpptr[c + 1]; ++i)
+            if (a_re[m->cpts[i]] == x) return a_pts[m->cpts[i]];
+        return x;
+    }
+    cs_cut cut;
+    /* d/dt of G(x; a + t a', alpha + t alpha') at fixed x */
+    cs_cell_cut(m, c, a_pts, x, 0, &cut);
+    double g_dot = cimag(cut.vsub / m->V[c] - alpha_c) / OR_CSTEP;
+    /* dG/dx at the real data */
+    cplx *a_r = (cplx *)xmalloc(sizeof(cplx) * m->n_points);
+    for (int i = m->cpptr[c]; i < m->cpptr[c + 1]; ++i) a_r[m->cpts[i]] = a_re[m->cpts[i]];
+    cs_cell_cut(m, c, a_r, x + OR_CSTEP * _Complex_I, 0, &cut);
+    free(a_r);
+    double g_x = cimag(cut.vsub) / m->V[c] / OR_CSTEP;
+    if (!(g_x != 0.0)) return x;
+    return x + (-g_dot / g_x) * OR_CSTEP * _Complex_I;
+}
+
+/* Time integral over [0, dt] of the wet fraction of a triangle, for the tangent.  The swept
+ * fraction of Eqs. aplus1/aplus2 (reading R8) is the area distribution G of the signed distances
+ * d_k of the triangle's points from the isoface plane, evaluated at the distance u_n tau the plane
+ * has moved (for either sign of u_n; R10); written in the distance, the integral has no division
+ * by u_n except at the breakpoints d_k/u_n, which are clamped to the window, so the derivative
+ * stays well conditioned when u_n is near zero (where arrival times diverge).  Each piece between
+ * breakpoints is a quadratic in tau, integrated exactly (Simpson's rule). */
+static cplx cs_area_cdf(int br, cplx z, cplx e1, cplx e2, cplx e3) {
+    if (br == 0) return 0.0;
+    if (br == 3) return 1.0;
+    if (br == 1) return (z - e1) * (z - e1) / ((e3 - e1) * (e2 - e1));
+    return 1.0 - (e3 - z) * (e3 - z) / ((e3 - e1) * (e3 - e2));
+}
+
+static int cs_area_branch(double z, double e1, double e2, double e3) {
+    return z < e1 ? 0 : (z < e2 ? 1 : (z < e3 ? 2 : 3));
+}
+
+static cplx cs_tri_integral(const double X[3][3], const cplx *xS, const cplx *nS, cplx un, double dt) {
+    cplx d[3];
+    for (int k = 0; k < 3; ++k) { cplx xk[3], e[3]; c_of(X[k], xk); c_sub3(xk, xS, e); d[k] = c_dot3(e, nS); }
+    for (int i = 1; i < 3; ++i)
+        for (int j = i; j > 0 && creal(d[j - 1]) > creal(d[j]); --j) { cplx t = d[j]; d[j] = d[j - 1]; d[j - 1] = t; }
+    const cplx e1 = d[0], e2 = d[1], e3 = d[2];
+    const double r1 = creal(e1), r2 = creal(e2), r3 = creal(e3);
+    if (creal(un) == 0.0) {
+        int br = cs_area_branch(0.0, r1, r2, r3);
+        return dt / 6.0 * (cs_area_cdf(br, 0.0, e1, e2, e3) + 4.0 * cs_area_cdf(br, un * (0.5 * dt), e1, e2, e3) +
+                           cs_area_cdf(br, un * dt, e1, e2, e3));
+    }
+    cplx bk[3] = {e1 / un, e2 / un, e3 / un};
+    if (creal(un) < 0.0) { cplx t = bk[0]; bk[0] = bk[2]; bk[2] = t; }  /* increasing time */
+    cplx acc = 0.0, a0 = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        cplx a1 = dt;
+        if (k < 3) a1 = creal(bk[k]) <= 0.0 ? 0.0 : (creal(bk[k]) >= dt ? dt : bk[k]);
+        if (creal(a1) > creal(a0)) {
+            cplx mid = 0.5 * (a0 + a1);
+            int br = cs_area_branch(creal(un * mid), r1, r2, r3);
+            acc += (a1 - a0) / 6.0 * (cs_area_cdf(br, un * a0, e1, e2, e3) + 4.0 * cs_area_cdf(br, un * mid, e1, e2, e3) +
+                                      cs_area_cdf(br, un * a1, e1, e2, e3));
+            a0 = a1;
+        }
+    }
+    return acc;
+}
+
+static cplx cs_face_integral(const or_mesh *m, int f, int c, const cplx *xS, const cplx *nS, cplx un, double dt) {
+    int fp[OR_MAXFP];
+    int n = face_points_for(m, f, c, fp);
+    const double *ap = m->fapex + 3 * f;
+    double Af = 0;
+    cplx acc = 0;
+    for (int i = 0; i < n; ++i) {
+        const double *p0 = m->P + 3 * fp[i], *p1 = m->P + 3 * fp[(i + 1) % n];
+        double e0[3], e1[3], cr[3];
+        v_sub(p0, ap, e0); v_sub(p1, ap, e1); v_cross(e0, e1, cr);
+        double Ai = 0.5 * v_norm(cr);
+        double X[3][3];
+        for (int d = 0; d < 3; ++d) { X[0][d] = ap[d]; X[1][d] = p0[d]; X[2][d] = p1[d]; }
+        Af += Ai;
+        acc += Ai * cs_tri_integral((const double(*)[3])X, xS, nS, un, dt);
+    }
+    return acc / Af;
+}
+
+static cplx cs_chop(cplx x, double tol) {
+    if (creal(x) < 0.0 && creal(x) >= -tol) return 0.0;
+    if (creal(x) > 1.0 && creal(x) <= 1.0 + tol) return 1.0;
+    return x;
+}
+
+/* The step on complex data (same sequence as or_step; clipped values become constants). */
+static void cs_step(const or_mesh *m, const or_opts *opt, const cplx *alpha, const cplx *phi, const double *U, double dt,
+                    cplx *alpha_new) {
+    int nc = m->n_cells, nf = m->n_faces;
+    cplx *a_pts = (cplx *)xmalloc(sizeof(cplx) * m->n_points);
+    double *a_re = (double *)xmalloc(sizeof(double) * m->n_points);
+    int *kind = (int *)xmalloc(sizeof(int) * nc);
+    cplx *rec = (cplx *)xmalloc(sizeof(cplx) * 7 * nc);
+    cplx *dV = (cplx *)xmalloc(sizeof(cplx) * nf);
+    cs_point_values(m, alpha, a_pts);
+    for (int p = 0; p < m->n_points; ++p) a_re[p] = creal(a_pts[p]);
+    for (int c = 0; c < nc; ++c) {
+        kind[c] = 0;
+        double a = creal(alpha[c]);
+        if (!(a > opt->eps_surf && a < 1.0 - opt->eps_surf)) continue;
+        double lo = 1e300, hi = -1e300;
+        for (int i = m->cpptr[c]; i < m->cpptr[c + 1]; ++i) {
+            double v = a_re[m->cpts[i]];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        if (!(hi - lo > opt->flat_tol)) { kind[c] = 2; continue; }
+        int it = 0;
+        cplx iso = cs_cell_isovalue(m, c, a_pts, a_re, alpha[c], opt->max_bisect, &it);
+        cs_cut cut;
+        cs_cell_cut(m, c, a_pts, iso, 0, &cut);
+        cplx nrm = c_norm3(cut.S);
+        if (!(creal(nrm) > 0)) { kind[c] = 2; continue; }
+        kind[c] = 1;
+        for (int d = 0; d < 3; ++d) { rec[7 * c + d] = cut.xS[d]; rec[7 * c + 3 + d] = cut.S[d] / nrm; }
+        rec[7 * c + 6] = U[c] * rec[7 * c + 3] + U[nc + c] * rec[7 * c + 4] + U[2 * nc + c] * rec[7 * c + 5];
+    }
+    for (int f = 0; f < nf; ++f) dV[f] = 0.0;
+    for (int c = 0; c < nc; ++c)
+        for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) {
+            int fid = m->ce_flux[e], sg = m->ce_sign[e];
+            cplx ph = phi[fid];
+            double out = sg * creal(ph);
+            if (out > 0) {
+                if (kind[c] == 1)
+                    dV[fid] = ph * cs_face_integral(m, m->ce_face[e], c, rec + 7 * c, rec + 7 * c + 3, rec[7 * c + 6], dt);
+                else
+                    dV[fid] = alpha[c] * ph * dt;
+            } else if (out < 0 && m->ce_other[e] < 0) {
+                dV[fid] = m->palpha[m->fpatch[m->ce_face[e]]] * ph * dt;
+            }
+        }
+    cplx *cur = (cplx *)xmalloc(sizeof(cplx) * nc);
+    for (int c = 0; c < nc; ++c) {
+        cplx sum = 0.0;
+        for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) sum += m->ce_sign[e] * dV[m->ce_flux[e]];
+        cur[c] = alpha[c] - sum / m->V[c];
+    }
+    double tol = opt->bound_tol;
+    if (opt->clip) for (int c = 0; c < nc; ++c) cur[c] = cs_chop(cur[c], tol);
+    cplx *delta = (cplx *)xmalloc(sizeof(cplx) * nf);
+    cplx *dVc = (cplx *)xmalloc(sizeof(cplx) * nf);
+    memcpy(dVc, dV, sizeof(cplx) * nf);
+    for (int it = 0; it < opt->n_bound_iter; ++it) {
+        for (int f = 0; f < nf; ++f) delta[f] = 0.0;
+        for (int c = 0; c < nc; ++c) {
+            cplx a = cur[c];
+            int over = creal(a) > 1.0 + tol, under = creal(a) < -tol;
+            if (!over && !under) continue;
+            cplx sumcap = 0.0;
+            for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) {
+                int fid = m->ce_flux[e], sg = m->ce_sign[e];
+                cplx outphi = sg * phi[fid];
+                if (!(creal(outphi) > 0)) continue;
+                cplx outv = sg * dVc[fid];
+                cplx cap = over ? outphi * dt - outv : outv;
+                if (creal(cap) > 0) sumcap += cap;
+            }
+            if (!(creal(sumcap) > 0)) continue;
+            cplx need = over ? (a - 1.0) * m->V[c] : -a * m->V[c];
+            cplx r = need / sumcap;
+            if (creal(r) > 1.0) r = 1.0;
+            for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) {
+                int fid = m->ce_flux[e], sg = m->ce_sign[e];
+                cplx outphi = sg * phi[fid];
+                if (!(creal(outphi) > 0)) continue;
+                cplx outv = sg * dVc[fid];
+                cplx cap = over ? outphi * dt - outv : outv;
+                if (!(creal(cap) > 0)) continue;
+                cplx d = cap * r;
+                delta[fid] = over ? sg * d : -sg * d;
+            }
+        }
+        for (int c = 0; c < nc; ++c) {
+            cplx sum = 0.0;
+            for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) sum += m->ce_sign[e] * delta[m->ce_flux[e]];
+            cur[c] = cur[c] - sum / m->V[c];
+            if (opt->clip) cur[c] = cs_chop(cur[c], tol);
+        }
+        for (int f = 0; f < nf; ++f) dVc[f] += delta[f];
+    }
+    if (opt->clip)
+        for (int c = 0; c < nc; ++c) {
+            if (creal(cur[c]) < 0.0) cur[c] = 0.0;
+            if (creal(cur[c]) > 1.0) cur[c] = 1.0;
+        }
+    for (int c = 0; c < nc; ++c) alpha_new[c] = cur[c];
+    free(a_pts); free(a_re); free(kind); free(rec); free(dV); free(cur); free(delta); free(dVc);
+}
+
+/* alpha_new = step(alpha, phi) and its derivative along (dalpha, dphi): dalpha_new */
+int or_step_tlm(const or_mesh *m, const or_opts *opt, const double *alpha, const double *phi, const double *U, double dt,
+                const double *dalpha, const double *dphi, double *alpha_new, double *dalpha_new) {
+    int nc = m->n_cells, nf = m->n_faces;
+    cplx *a = (cplx *)xmalloc(sizeof(cplx) * nc);
+    cplx *f = (cplx *)xmalloc(sizeof(cplx) * nf);
+    cplx *o = (cplx *)xmalloc(sizeof(cplx) * nc);
+    for (int c = 0; c < nc; ++c) a[c] = alpha[c] + (dalpha ? dalpha[c] : 0.0) * OR_CSTEP * _Complex_I;
+    for (int k = 0; k < nf; ++k) f[k] = phi[k] + (dphi ? dphi[k] : 0.0) * OR_CSTEP * _Complex_I;
+    cs_step(m, opt, a, f, U, dt, o);
+    for (int c = 0; c < nc; ++c) {
+        if (alpha_new) alpha_new[c] = creal(o[c]);
+        dalpha_new[c] = cimag(o[c]) / OR_CSTEP;
+    }
+    free(a); free(f); free(o);
+    return 0;
 }

@@ -85,6 +85,7 @@ def lib():
         L.or_step.argtypes = [C.c_void_p, C.POINTER(Opts), _dp, _dp, _dp, C.c_double, _dp, C.POINTER(Trace),
                               C.POINTER(Stats)]
         L.or_run.argtypes = [C.c_void_p, C.POINTER(Opts), _dp, _dp, _dp, C.c_double, C.c_int]
+        L.or_step_tlm.argtypes = [C.c_void_p, C.POINTER(Opts), _dp, _dp, _dp, C.c_double, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -213,6 +214,38 @@ class OracleMesh:
             arrays["rec"] = arrays["rec"].reshape(-1, 7)
             return out, st.as_dict(), arrays
         return out, st.as_dict()
+
+    def step_tlm(self, alpha, phi, U, dt, dalpha=None, dphi=None, opts=None):
+        """One step and its derivative along (dalpha, dphi) (complex step): (alpha_new, dalpha_new)."""
+        opts = opts or default_opts()
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        da = np.ascontiguousarray(np.zeros(self.n_cells) if dalpha is None else dalpha, dtype=np.float64)
+        dp = np.ascontiguousarray(np.zeros(self.n_faces) if dphi is None else dphi, dtype=np.float64)
+        out = np.zeros(self.n_cells)
+        dout = np.zeros(self.n_cells)
+        lib().or_step_tlm(self.h, C.byref(opts), _d(alpha), _d(phi), _d(U), float(dt), _d(da), _d(dp), _d(out),
+                          _d(dout))
+        return out, dout
+
+    def gradient(self, alpha, phi, U, dt, alpha_new_bar, cells=None, faces=None, opts=None):
+        """Components of the step's vector-Jacobian product (d alpha_new / d input)^T alpha_new_bar,
+        each computed as one tangent along a unit input direction (slow, exact): returns
+        (alpha_bar[cells], phi_bar[faces])."""
+        cells = range(self.n_cells) if cells is None else cells
+        faces = range(self.n_faces) if faces is None else faces
+        ab = np.asarray(alpha_new_bar, dtype=np.float64)
+        ga, gp = [], []
+        for c in cells:
+            e = np.zeros(self.n_cells)
+            e[c] = 1.0
+            ga.append(float(ab @ self.step_tlm(alpha, phi, U, dt, dalpha=e, opts=opts)[1]))
+        for f in faces:
+            e = np.zeros(self.n_faces)
+            e[f] = 1.0
+            gp.append(float(ab @ self.step_tlm(alpha, phi, U, dt, dphi=e, opts=opts)[1]))
+        return np.array(ga), np.array(gp)
 
     def run(self, alpha, phi, U, dt, n_steps, opts=None):
         opts = opts or default_opts()

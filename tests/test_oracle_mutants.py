@@ -35,6 +35,15 @@ MUTANTS = [
      "double Uc[3] = {U[c], U[2 * nc + c], U[nc + c]};"),
 ]
 
+# planted mistakes in the tangent of the step, which its own pins must reject
+TANGENT_MUTANTS = [
+    ("tangent_isovalue_fixed", "return x + (-g_dot / g_x) * OR_CSTEP * _Complex_I;", "return x;"),
+    ("tangent_volume_target_sign", "double g_dot = cimag(cut.vsub / m->V[c] - alpha_c) / OR_CSTEP;",
+     "double g_dot = cimag(cut.vsub / m->V[c] + alpha_c) / OR_CSTEP;"),
+    ("tangent_bounding_need_sign", "cplx need = over ? (a - 1.0) * m->V[c] : -a * m->V[c];",
+     "cplx need = over ? (1.0 - a) * m->V[c] : -a * m->V[c];"),
+]
+
 
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_pins_reject_planted_mistake(tmp_path, name, old, new):
@@ -46,5 +55,19 @@ def test_pins_reject_planted_mistake(tmp_path, name, old, new):
     env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,old,new", TANGENT_MUTANTS, ids=[m[0] for m in TANGENT_MUTANTS])
+def test_tangent_pins_reject_planted_mistake(tmp_path, name, old, new):
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, f"snippet for mutant {name} no longer matches the oracle"
+    mutant_src = tmp_path / "mutant.c"
+    mutant_src.write_text(src.replace(old, new))
+    lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_tlm.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
