@@ -45,12 +45,25 @@ TANGENT_MUTANTS = [
 ]
 
 
+TANGENT_HEADER = "Tangent of the step (directional derivative"
+
+
+def _plant(name, old, new, tangent):
+    """The oracle source with `old` replaced by `new` in the step (before the tangent section) or
+    in the tangent section, where the snippet must occur exactly once."""
+    src = open(O.SRC).read()
+    cut = src.index(TANGENT_HEADER)
+    head, tail = src[:cut], src[cut:]
+    part = tail if tangent else head
+    assert part.count(old) == 1, f"snippet for mutant {name} no longer matches the oracle"
+    part = part.replace(old, new)
+    return head + part if tangent else part + tail
+
+
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_pins_reject_planted_mistake(tmp_path, name, old, new):
-    src = open(O.SRC).read()
-    assert src.count(old) == 1, f"snippet for mutant {name} no longer matches the oracle"
     mutant_src = tmp_path / "mutant.c"
-    mutant_src.write_text(src.replace(old, new))
+    mutant_src.write_text(_plant(name, old, new, tangent=False))
     lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
     env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
@@ -61,10 +74,8 @@ def test_pins_reject_planted_mistake(tmp_path, name, old, new):
 
 @pytest.mark.parametrize("name,old,new", TANGENT_MUTANTS, ids=[m[0] for m in TANGENT_MUTANTS])
 def test_tangent_pins_reject_planted_mistake(tmp_path, name, old, new):
-    src = open(O.SRC).read()
-    assert src.count(old) == 1, f"snippet for mutant {name} no longer matches the oracle"
     mutant_src = tmp_path / "mutant.c"
-    mutant_src.write_text(src.replace(old, new))
+    mutant_src.write_text(_plant(name, old, new, tangent=True))
     lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
     env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
