@@ -144,6 +144,28 @@ iso_status iso_advect_step(iso_plan *plan, const double *alpha, const double *ph
 iso_status iso_advect_step_traced(iso_plan *plan, const double *alpha, const double *phi, const double *U,
                                   double dt, double *alpha_new, iso_step_stats *stats, const iso_trace *trace);
 
+/* Adjoint of one step (vector-Jacobian product; differentiation is not part of the paper's
+ * method).  Given alpha_new_bar = dL/d alpha_new for the step iso_advect_step(alpha, phi, U, dt)
+ * -> alpha_new, writes alpha_bar = dL/d alpha [n_cells] and phi_bar = dL/d phi [n_faces] (zero on
+ * faces that carry no flux and on the partner faces of cyclic pairs).  U and dt are held fixed.
+ * The derivative follows the step exactly: the interface cells' isovalue moves with the volume
+ * constraint of Section 3.2 (implicit function; at a jump of the sub-volume it is the vertex
+ * value), the swept integrals (Eqs. tv .. intaplus) are differentiated through the isoface, and
+ * the bounding sweeps are replayed and reversed; values that chopping or clamping fixes have zero
+ * derivative, and a face with phi = 0 passes no derivative to phi.  Branches (interface cells,
+ * upwind sides, wet vertices, bounding activity) are those of the given state.
+ * fwd (nullable, DEVICE pointers): the intermediates of this same step from
+ * iso_advect_step_traced with the same plan; vert_alpha, kind, iso, dV and alpha_raw are used.
+ * NULL recomputes the forward step internally.  All arrays are DEVICE arrays; alpha_bar and
+ * phi_bar must not overlap the inputs.  Asynchronous on the plan's stream.  The first call
+ * allocates the adjoint workspace (about (50 + 24 S) bytes per cell and 80 bytes per face for S
+ * bounding sweeps).  At most 31 bounding sweeps (ISO_EUNSUPPORTED).  Interface-cell
+ * contributions are accumulated with atomics: results are reproducible to rounding, not bit for
+ * bit. */
+iso_status iso_advect_step_adjoint(iso_plan *plan, const double *alpha, const double *phi, const double *U,
+                                   double dt, const iso_trace *fwd, const double *alpha_new_bar, double *alpha_bar,
+                                   double *phi_bar);
+
 /* Kernel timing (measurement support).  iso_plan_set_timing(plan, n) records HIP events on the
  * plan's stream around each of the step's kernels for the next n steps (0 disables; events are
  * created here, not in the step).  iso_plan_timing syncs the stream and returns, per kernel

@@ -96,6 +96,8 @@ def lib():
         L.iso_advect_step_traced.argtypes = [_vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats),
                                              C.POINTER(IsoTrace)]
         L.iso_advect_step_traced.restype = C.c_int
+        L.iso_advect_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, C.c_double, C.POINTER(IsoTrace), _vp, _vp, _vp]
+        L.iso_advect_step_adjoint.restype = C.c_int
         L.iso_plan_set_timing.argtypes = [_vp, C.c_int32]
         L.iso_plan_set_timing.restype = C.c_int
         L.iso_plan_timing.argtypes = [_vp, _dp, C.POINTER(C.c_int32)]
@@ -270,6 +272,26 @@ class Plan:
             check(lib().iso_advect_step_traced(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt), _ptr(out),
                                                C.byref(st) if st is not None else None, C.byref(tr)))
         return out, (st.as_dict() if st is not None else None)
+
+    TRACE_KEYS = ("vert_alpha", "kind", "iso", "rec", "dV", "alpha_raw", "iters")
+
+    def adjoint(self, alpha, phi, U, dt, alpha_new_bar, trace=None, alpha_bar=None, phi_bar=None):
+        """(alpha_bar, phi_bar) of the step alpha_new = step(alpha, phi, U, dt) for the given alpha_new_bar.
+        ``trace``: the dict of device tensors a traced step of the same inputs wrote (vert_alpha, kind,
+        iso, dV, alpha_raw), or None to recompute the forward step inside."""
+        import torch
+        if alpha_bar is None:
+            alpha_bar = torch.empty_like(alpha)
+        if phi_bar is None:
+            phi_bar = torch.empty_like(phi)
+        self.set_stream(None)
+        tr = None
+        if trace is not None:
+            tr = IsoTrace(*[(_ptr(trace[k]).value if trace.get(k) is not None else None) for k in self.TRACE_KEYS])
+        check(lib().iso_advect_step_adjoint(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt),
+                                            C.byref(tr) if tr is not None else None, _ptr(alpha_new_bar),
+                                            _ptr(alpha_bar), _ptr(phi_bar)))
+        return alpha_bar, phi_bar
 
     KERNELS = ("find_surface", "surface", "update", "bound")
 

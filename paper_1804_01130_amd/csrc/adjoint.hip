@@ -1,0 +1,737 @@
+// Adjoint (vector-Jacobian product) of one isoAdvector step on gfx950, FP64.
+//
+// Given the adjoint of alpha_new, the step's inputs and its intermediates (vertex values, cell
+// kinds, isovalues, face volumes dV and the update before bounding, as the traced forward step
+// writes them), four launches produce the adjoints of alpha and phi:
+//   prep     per cell: the update's round-off chop, the cells the bounding sweeps start from, the
+//            list of reconstructed interface cells; per face buffers cleared
+//   bound    one work-group: the bounding sweeps are replayed with a tape (same arithmetic as the
+//            forward), then reversed (bounding step at the end of Section 3.2)
+//   faces    per cell, a gather over its flux faces: transposes of the flux-form update and of the
+//            bulk fluxes alpha_upwind phi dt; phi's adjoint through dV = phi * (dV/phi)
+//   surface  eight lanes per (interface cell, direction): the derivatives of the swept face
+//            integrals (Eqs. tv .. intaplus) with respect to the cell's 8 vertex values and
+//            alpha_P, by forward-mode dual numbers through the isoface, the isovalue moving with
+//            the volume constraint (implicit function); then the transpose of the vertex
+//            interpolation, scattered to the stencil cells
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace isoadv {
+namespace {
+
+// ------------------------------------------------------------------------------- dual numbers
+struct Dl {
+    double v, d;  // value and derivative along one direction
+};
+__device__ __forceinline__ Dl operator+(Dl a, Dl b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dl operator-(Dl a, Dl b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dl operator-(Dl a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dl operator*(Dl a, Dl b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dl operator*(double s, Dl a) { return {s * a.v, s * a.d}; }
+__device__ __forceinline__ Dl operator/(Dl a, Dl b) {
+    const double q = a.v / b.v;
+    return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Dl dinv(Dl a) {
+    const double q = 1.0 / a.v;
+    return {q, -a.d * q * q};
+}
+__device__ __forceinline__ Dl dsqrt(Dl a) {
+    const double r = sqrt(a.v);
+    return {r, r > 0.0 ? 0.5 * a.d / r : 0.0};
+}
+__device__ __forceinline__ Dl dsel(bool c, Dl a, Dl b) { return {c ? a.v : b.v, c ? a.d : b.d}; }
+__device__ __forceinline__ Dl dmin(Dl a, Dl b) { return a.v <= b.v ? a : b; }
+__device__ __forceinline__ Dl dmax(Dl a, Dl b) { return a.v >= b.v ? a : b; }
+__device__ __forceinline__ Dl dc(double x) { return {x, 0.0}; }
+
+struct DV3 {
+    Dl x, y, z;
+};
+__device__ __forceinline__ DV3 operator+(DV3 a, DV3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ DV3 operator-(DV3 a, DV3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ DV3 operator*(Dl s, DV3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ DV3 operator*(double s, DV3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ DV3 dv(D3 a) { return {dc(a.x), dc(a.y), dc(a.z)}; }
+__device__ __forceinline__ Dl ddot(DV3 a, DV3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ DV3 dcross(DV3 a, DV3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ Dl dnorm(DV3 a) { return dsqrt(ddot(a, a)); }
+__device__ __forceinline__ DV3 dsel3(bool c, DV3 a, DV3 b) { return {dsel(c, a.x, b.x), dsel(c, a.y, b.y), dsel(c, a.z, b.z)}; }
+__device__ __forceinline__ Dl dgrp_sum(Dl a) { return {grp_sum(a.v), grp_sum(a.d)}; }
+__device__ __forceinline__ DV3 dgrp_sum3(DV3 a) { return {dgrp_sum(a.x), dgrp_sum(a.y), dgrp_sum(a.z)}; }
+
+// A lane's face with dual vertex values (geometry is fixed).
+struct DFace {
+    D3 q[4];
+    Dl aq[4];
+    Dl inv[4];
+    int fwd;
+    bool planar, active;
+};
+
+__device__ __forceinline__ DV3 dface_cut(const DFace &f, int i, Dl iso, bool wet_i) {
+    const int j = (i + 1) & 3;
+    const bool fwd = (f.fwd >> i) & 1;
+    const D3 xw = sel3(wet_i, f.q[i], f.q[j]), xd = sel3(wet_i, f.q[j], f.q[i]);
+    const Dl aw = dsel(wet_i, f.aq[i], f.aq[j]);
+    const Dl lam = (wet_i == fwd) ? (iso - aw) * f.inv[i] : (aw - iso) * f.inv[i];
+    return dv(xw) + lam * dv(xd - xw);
+}
+
+struct DPart {
+    Dl v6;
+    DV3 cseg, oacc;
+    Dl oL;
+    DV3 osum;
+    double nseg;
+};
+
+// The face's share of six times the sub-volume and of the isoface sums (the same construction as
+// the forward kernel, in dual numbers; wet iff a > iso).
+__device__ __forceinline__ DPart dface_part(const DFace &f, Dl iso) {
+    const DV3 Z = dv(D3{0, 0, 0});
+    DPart r{dc(0.0), Z, Z, dc(0.0), Z, 0.0};
+    bool w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = f.active && f.aq[i].v > iso.v;
+    DV3 cut[4];
+    bool cuts[4], exits[4], entries[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        cut[i] = dface_cut(f, i, iso, w[i]);
+        cuts[i] = w[i] != w[j];
+        exits[i] = w[i] && !w[j];
+        entries[i] = !w[i] && w[j];
+    }
+    DV3 last = Z;
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        last = dsel3(w[i], dv(f.q[i]), last);
+        last = dsel3(cuts[i], cut[i], last);
+        cnt += (w[i] ? 1 : 0) + (cuts[i] ? 1 : 0);
+    }
+    DV3 C = Z, prev = last;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        C = dsel3(w[i], C + dcross(prev, dv(f.q[i])), C);
+        prev = dsel3(w[i], dv(f.q[i]), prev);
+        C = dsel3(cuts[i], C + dcross(prev, cut[i]), C);
+        prev = dsel3(cuts[i], cut[i], prev);
+    }
+    if (cnt >= 3) {
+        DV3 ap = dv(f.q[0]);
+        if (!f.planar) {
+            DV3 pacc = Z, psum = Z, pv = last;
+            Dl pl = dc(0.0);
+            auto step = [&](bool on, DV3 x) {
+                const Dl l = dnorm(x - pv);
+                pacc = dsel3(on, pacc + (0.5 * l) * (x + pv), pacc);
+                pl = dsel(on, pl + l, pl);
+                psum = dsel3(on, psum + x, psum);
+                pv = dsel3(on, x, pv);
+            };
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                step(w[i], dv(f.q[i]));
+                step(cuts[i], cut[i]);
+            }
+            ap = pl.v > 0.0 ? dinv(pl) * pacc : (1.0 / cnt) * psum;
+        }
+        r.v6 = ddot(ap, C);
+    }
+    DV3 lastexit = Z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lastexit = dsel3(exits[i], cut[i], lastexit);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const DV3 s0 = cut[i], s1 = lastexit;
+        if (entries[i]) {
+            const Dl l = dnorm(s1 - s0);
+            r.cseg = r.cseg + dcross(s0, s1);
+            r.oacc = r.oacc + (0.5 * l) * (s0 + s1);
+            r.oL = r.oL + l;
+            r.osum = r.osum + s0;
+            r.nseg += 1.0;
+        }
+        lastexit = dsel3(exits[i], cut[i], lastexit);
+    }
+    return r;
+}
+
+// Six times the sub-volume (all lanes of the group), and the isoface apex and area vector (x2).
+__device__ __forceinline__ Dl dcell_vsub6(const DFace &f, Dl iso, DV3 *o_out, DV3 *cseg_out) {
+    const DPart p = dface_part(f, iso);
+    const Dl v6 = dgrp_sum(p.v6);
+    const DV3 cseg = dgrp_sum3(p.cseg), oacc = dgrp_sum3(p.oacc), osum = dgrp_sum3(p.osum);
+    const Dl oL = dgrp_sum(p.oL);
+    const double nseg = grp_sum(p.nseg);
+    const DV3 Z = dv(D3{0, 0, 0});
+    const DV3 o = oL.v > 0.0 ? dinv(oL) * oacc : (nseg > 0.0 ? (1.0 / nseg) * osum : Z);
+    if (o_out) *o_out = o;
+    if (cseg_out) *cseg_out = cseg;
+    return v6 + ddot(o, cseg);
+}
+
+__device__ __forceinline__ void dface_centre_part(const DFace &f, Dl iso, DV3 o, DV3 n, DV3 &acc, Dl &ws) {
+    const DV3 Z = dv(D3{0, 0, 0});
+    acc = Z;
+    ws = dc(0.0);
+    bool w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = f.active && f.aq[i].v > iso.v;
+    DV3 cut[4];
+    bool exits[4], entries[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        cut[i] = dface_cut(f, i, iso, w[i]);
+        exits[i] = w[i] && !w[j];
+        entries[i] = !w[i] && w[j];
+    }
+    DV3 lastexit = Z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lastexit = dsel3(exits[i], cut[i], lastexit);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const DV3 s0 = cut[i], s1 = lastexit;
+        if (entries[i]) {
+            const Dl wt = ddot(dcross(s0 - o, s1 - o), n);
+            acc = acc + wt * (o + s0 + s1);
+            ws = ws + wt;
+        }
+        lastexit = dsel3(exits[i], cut[i], lastexit);
+    }
+}
+
+// Swept integral of a triangle (the forward kernel's construction in dual numbers): the wet
+// fraction at time s is the area distribution of the distances at un*s; breakpoints clamped to
+// the window; each piece integrated exactly (Simpson) on the branch of its midpoint.
+__device__ __forceinline__ Dl dtri_piece(int br, Dl z, Dl e1, Dl e2, Dl e3, Dl r31, Dl r21, Dl r32) {
+    if (br == 0) return dc(0.0);
+    if (br == 3) return dc(1.0);
+    if (br == 1) {
+        const Dl u = z - e1;
+        return (u * r31) * (u * r21);
+    }
+    const Dl u = e3 - z;
+    return dc(1.0) - (u * r31) * (u * r32);
+}
+
+__device__ __forceinline__ Dl dtri_sweep(Dl d0, Dl d1, Dl d2, Dl un, double dt) {
+    const Dl e1 = dmin(d0, dmin(d1, d2)), e3 = dmax(d0, dmax(d1, d2));
+    const Dl e2 = dmax(dmin(d0, d1), dmin(dmax(d0, d1), d2));
+    const Dl r31 = e3.v > e1.v ? dinv(e3 - e1) : dc(0.0);
+    const Dl r21 = e2.v > e1.v ? dinv(e2 - e1) : dc(0.0);
+    const Dl r32 = e3.v > e2.v ? dinv(e3 - e2) : dc(0.0);
+    auto branch = [&](double z) { return z < e1.v ? 0 : (z < e2.v ? 1 : (z < e3.v ? 2 : 3)); };
+    if (un.v == 0.0) {
+        const int br = branch(0.0);
+        const Dl m = un * dc(0.5 * dt), b = un * dc(dt);
+        return (dt / 6.0) * (dtri_piece(br, dc(0.0), e1, e2, e3, r31, r21, r32) +
+                             4.0 * dtri_piece(br, m, e1, e2, e3, r31, r21, r32) +
+                             dtri_piece(br, b, e1, e2, e3, r31, r21, r32));
+    }
+    const Dl inv = dinv(un);
+    Dl s1 = e1 * inv, s2 = e2 * inv, s3 = e3 * inv;
+    if (un.v < 0.0) {
+        const Dl t = s1;
+        s1 = s3;
+        s3 = t;
+    }
+    const Dl bk[3] = {s1, s2, s3};
+    Dl acc = dc(0.0), a0 = dc(0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Dl a1 = dc(dt);
+        if (k < 3) a1 = bk[k].v <= 0.0 ? dc(0.0) : (bk[k].v >= dt ? dc(dt) : bk[k]);
+        if (a1.v > a0.v) {
+            const Dl m = 0.5 * (a0 + a1);
+            const int br = branch(un.v * m.v);
+            const Dl fa = dtri_piece(br, un * a0, e1, e2, e3, r31, r21, r32);
+            const Dl fm = dtri_piece(br, un * m, e1, e2, e3, r31, r21, r32);
+            const Dl fb = dtri_piece(br, un * a1, e1, e2, e3, r31, r21, r32);
+            acc = acc + (1.0 / 6.0) * ((a1 - a0) * (fa + 4.0 * fm + fb));
+            a0 = a1;
+        }
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------------------------ kernels
+struct AdjArgs {
+    DevMesh m;
+    const double *alpha, *phi, *U;
+    double dt;
+    const double *dt_dom;
+    double eps, tol;
+    int clip, n_iter;
+    // forward intermediates of this step
+    const double *vert_alpha;  // [8 nc] (interface cells)
+    const int32_t *kind;       // [nc]
+    const double *iso;         // [nc] (reconstructed cells)
+    const double *dV0;         // [nf] dV before bounding, per flux face
+    const double *raw;         // [nc] update before chopping
+    // adjoint in / out
+    const double *abar_new;  // [nc]
+    double *abar;            // [nc]
+    double *phibar;          // [nf]
+    AdjWork w;
+};
+
+// per cell: start state of bounding, lists, per-face buffers cleared
+template <int W>
+__global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
+    const int n = A.m.n_cells;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    bool offend = false, recon = false;
+    if (c < n) {
+        double x = A.raw[c];
+        if (A.clip) {
+            if (x < 0.0 && x >= -A.tol) x = 0.0;
+            else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
+        }
+        A.w.x[c] = x;
+        A.w.xbar[c] = A.abar_new[c];
+        A.w.cflag[c] = 0;
+        offend = x > 1.0 + A.tol || x < -A.tol;
+        recon = A.kind[c] == 1;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int32_t v = A.m.slot_face[(size_t)k * n + c];
+            if (v != kEmpty && v >= 0) {
+                A.w.dVb[v] = 0.0;
+                A.w.phib[v] = 0.0;
+                A.w.dvcurbar[v] = 0.0;
+                A.w.touched[v] = 0;
+            }
+        }
+    }
+    const int bo = wave_append(offend ? 1 : 0, &A.w.counters[kAdjOff]);
+    if (offend) A.w.list[bo] = c;
+    const int br = wave_append(recon ? 1 : 0, &A.w.counters[kAdjRecon]);
+    if (recon) A.w.rlist[br] = c;
+}
+
+// Bounding replayed with a tape, then reversed (one work-group of 1024).  Tape per sweep s and
+// listed cell i (row s*nc + i): a, need, sumcap, r, then cap and dV-now per slot; flags: bit 0 over,
+// bit 1 r capped at 1, bit 2 sumcap > 0, bit 3+k slot k corrected, bit 10+k slot k read the
+// running dV (touched in an earlier sweep).
+template <int W>
+__global__ void __launch_bounds__(1024) k_adj_bound(AdjArgs A) {
+    constexpr int R = 4 + 2 * W;
+    __shared__ int nL[32], nT[32];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n = A.m.n_cells;
+    const DevMesh &m = A.m;
+    AdjWork &w = A.w;
+    if (tid == 0) {
+        nL[0] = w.counters[kAdjOff];
+        for (int s = 0; s < 32; ++s) nT[s] = 0;
+        for (int s = 1; s < 32; ++s) nL[s] = 0;
+    }
+    __syncthreads();
+    const int S = A.n_iter;
+    for (int s = 0; s < S; ++s) {
+        const int32_t *L = w.list + (size_t)s * n;
+        int32_t *T = w.tlist + (size_t)s * n;
+        const int nl = nL[s];
+        // corrections on the outflow faces of the listed cells
+        for (int i = tid; i < nl; i += nt) {
+            const int32_t P = L[i];
+            double *rec = w.tape + ((size_t)s * n + i) * R;
+            const double a = w.x[P];
+            const bool over = a > 1.0 + A.tol;
+            const double dtc = cell_dt(m, A.dt_dom, A.dt, P);
+            int32_t v[W], fid[W];
+            double ph[W], cap[W], dvnow[W];
+            int flags = over ? 1 : 0;
+            double sumcap = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                v[k] = m.slot_face[(size_t)k * n + P];
+                fid[k] = v[k] >= 0 ? v[k] : ~v[k];
+                ph[k] = v[k] != kEmpty ? A.phi[fid[k]] : 0.0;
+                cap[k] = 0.0;
+                dvnow[k] = 0.0;
+                if (v[k] == kEmpty) continue;
+                const double outphi = v[k] >= 0 ? ph[k] : -ph[k];
+                if (!(outphi > 0.0)) continue;
+                const bool tch = w.touched[fid[k]] != 0;
+                if (tch) flags |= 1 << (10 + k);
+                dvnow[k] = tch ? w.dvcur[fid[k]] : A.dV0[fid[k]];
+                const double outv = v[k] >= 0 ? dvnow[k] : -dvnow[k];
+                cap[k] = over ? outphi * dtc - outv : outv;
+                if (cap[k] > 0.0) sumcap += cap[k];
+            }
+            const double need = over ? (a - 1.0) * m.vol[P] : -a * m.vol[P];
+            double r = 0.0;
+            if (sumcap > 0.0) {
+                flags |= 4;
+                const double q = need / sumcap;
+                if (q > 1.0) flags |= 2;
+                r = fmin(q, 1.0);
+            }
+            if (atomicExch(&w.cmark[P], 1) == 0) T[atomicAdd(&nT[s], 1)] = P;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
+                flags |= 1 << (3 + k);
+                const double d = cap[k] * r;
+                const double dd = over ? (v[k] >= 0 ? d : -d) : (v[k] >= 0 ? -d : d);
+                w.delta[fid[k]] = dd;
+                w.dvcur[fid[k]] = dvnow[k] + dd;
+                w.touched[fid[k]] = 1;
+                const int32_t o = m.slot_nbr[(size_t)k * n + P];
+                if (o >= 0 && atomicExch(&w.cmark[o], 1) == 0) T[atomicAdd(&nT[s], 1)] = o;
+            }
+            rec[0] = a; rec[1] = need; rec[2] = sumcap; rec[3] = r;
+#pragma unroll
+            for (int k = 0; k < W; ++k) { rec[4 + k] = cap[k]; rec[4 + W + k] = dvnow[k]; }
+            w.tflag[(size_t)s * n + i] = flags;
+        }
+        __syncthreads();
+        // apply to every touched cell in ascending face order; chop; clamp on the last sweep
+        const bool last = s == S - 1;
+        const int ntc = nT[s];
+        for (int j = tid; j < ntc; j += nt) {
+            const int32_t Q = T[j];
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const int32_t vq = m.slot_face[(size_t)k * n + Q];
+                if (vq == kEmpty) continue;
+                const double d = w.delta[vq >= 0 ? vq : ~vq];
+                sum += vq >= 0 ? d : -d;
+            }
+            const double x0 = w.x[Q] - sum / m.vol[Q];
+            double x = x0;
+            if (A.clip) {
+                if (x < 0.0 && x >= -A.tol) x = 0.0;
+                else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
+                if (last) x = fmin(fmax(x, 0.0), 1.0);
+            }
+            if (x != x0) w.cflag[Q] |= 1 << s;
+            w.x[Q] = x;
+            w.cmark[Q] = 0;
+            if (x > 1.0 + A.tol || x < -A.tol) {
+                if (s + 1 < S) w.list[(size_t)(s + 1) * n + atomicAdd(&nL[s + 1], 1)] = Q;
+            }
+        }
+        __syncthreads();
+        // this sweep's corrections are applied: clear them
+        for (int i = tid; i < nl; i += nt) {
+            const int32_t P = L[i];
+            const int flags = w.tflag[(size_t)s * n + i];
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (flags & (1 << (3 + k))) {
+                    const int32_t vp = m.slot_face[(size_t)k * n + P];
+                    w.delta[vp >= 0 ? vp : ~vp] = 0.0;
+                }
+        }
+        __syncthreads();
+    }
+    if (S == 0 && A.clip) {
+        for (int i = tid; i < nL[0]; i += nt) {
+            const int32_t P = w.list[i];
+            const double x = w.x[P];
+            if (x < 0.0 || x > 1.0) w.cflag[P] |= 1;
+        }
+        __syncthreads();
+        for (int i = tid; i < nL[0]; i += nt) {
+            const int32_t P = w.list[i];
+            if (w.cflag[P] & 1) w.xbar[P] = 0.0;
+        }
+        return;
+    }
+    // ---- reverse
+    for (int s = S - 1; s >= 0; --s) {
+        const int32_t *L = w.list + (size_t)s * n;
+        const int32_t *T = w.tlist + (size_t)s * n;
+        const int nl = nL[s], ntc = nT[s];
+        // adjoint of each correction through the cells it was applied to
+        for (int i = tid; i < nl; i += nt) {
+            const int32_t P = L[i];
+            const int flags = w.tflag[(size_t)s * n + i];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                if (!(flags & (1 << (3 + k)))) continue;
+                const int32_t v = m.slot_face[(size_t)k * n + P];
+                const int32_t o = m.slot_nbr[(size_t)k * n + P];
+                const double sP = v >= 0 ? 1.0 : -1.0;
+                double db = 0.0;
+                if (!(w.cflag[P] & (1 << s))) db -= sP * w.xbar[P] / m.vol[P];
+                if (o >= 0 && !(w.cflag[o] & (1 << s))) db += sP * w.xbar[o] / m.vol[o];
+                w.deltabar[v >= 0 ? v : ~v] = db;
+            }
+        }
+        __syncthreads();
+        // through the apply: chopped or clamped cells are constants
+        for (int j = tid; j < ntc; j += nt) {
+            const int32_t Q = T[j];
+            if (w.cflag[Q] & (1 << s)) w.xbar[Q] = 0.0;
+        }
+        __syncthreads();
+        // through the corrections of each listed cell
+        for (int i = tid; i < nl; i += nt) {
+            const int32_t P = L[i];
+            const int flags = w.tflag[(size_t)s * n + i];
+            const double *rec = w.tape + ((size_t)s * n + i) * R;
+            const bool over = flags & 1;
+            const double need = rec[1], sumcap = rec[2], r = rec[3];
+            const double dtc = cell_dt(m, A.dt_dom, A.dt, P);
+            double capb[W], dvnb[W];
+            double rb = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                capb[k] = 0.0;
+                dvnb[k] = 0.0;
+                if (!(flags & (1 << (3 + k)))) continue;
+                const int32_t v = m.slot_face[(size_t)k * n + P];
+                const int32_t f = v >= 0 ? v : ~v;
+                const double s_ = v >= 0 ? 1.0 : -1.0;
+                const double ddb = w.deltabar[f] + w.dvcurbar[f];
+                const double d_b = over ? s_ * ddb : -s_ * ddb;
+                capb[k] = d_b * r;
+                rb += d_b * rec[4 + k];
+                dvnb[k] = w.dvcurbar[f];  // dvcur_after = dvnow + dd
+            }
+            double needb = 0.0, sumcapb = 0.0;
+            if ((flags & 4) && !(flags & 2)) {
+                needb = rb / sumcap;
+                sumcapb = -rb * r / sumcap;
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const double capk = rec[4 + k];
+                if (!(capk > 0.0) || !(flags & 4)) continue;
+                const int32_t v = m.slot_face[(size_t)k * n + P];
+                const int32_t f = v >= 0 ? v : ~v;
+                const double s_ = v >= 0 ? 1.0 : -1.0;
+                const double cb = capb[k] + sumcapb;
+                const double outvb = over ? -cb : cb;
+                if (over) w.phib[f] += cb * s_ * dtc;
+                dvnb[k] += s_ * outvb;
+                if (flags & (1 << (10 + k))) {
+                    w.dvcurbar[f] = dvnb[k];
+                } else {
+                    w.dVb[f] += dvnb[k];
+                    w.dvcurbar[f] = 0.0;
+                }
+            }
+            w.xbar[P] += needb * (over ? m.vol[P] : -m.vol[P]);
+        }
+        __syncthreads();
+    }
+    // leave the running face state clean for the next call
+    for (int s = 0; s < S; ++s) {
+        const int32_t *L = w.list + (size_t)s * n;
+        for (int i = tid; i < nL[s]; i += nt) {
+            const int32_t P = L[i];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const int32_t v = m.slot_face[(size_t)k * n + P];
+                if (v != kEmpty) w.touched[v >= 0 ? v : ~v] = 0;
+            }
+        }
+    }
+}
+
+// per cell: transposes of the update (through the round-off chop) and of the bulk fluxes
+template <int W>
+__global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
+    const int n = A.m.n_cells;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const DevMesh &m = A.m;
+    auto pre = [&](int q) {  // adjoint of the update before its round-off chop
+        const double x = A.raw[q];
+        const bool chopped = A.clip && ((x < 0.0 && x >= -A.tol) || (x > 1.0 && x <= 1.0 + A.tol));
+        return chopped ? 0.0 : A.w.xbar[q];
+    };
+    const double bc = pre(c);
+    const double Vc = m.vol[c];
+    const bool recon = A.kind[c] == 1;
+    const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
+    double acc = bc;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int32_t v = m.slot_face[(size_t)k * n + c];
+        if (v == kEmpty) continue;
+        const int32_t f = v >= 0 ? v : ~v;
+        const int32_t o = m.slot_nbr[(size_t)k * n + c];
+        const double ph = A.phi[f];
+        // alpha_raw(owner) -= dV/V_owner, alpha_raw(neighbour) += dV/V_neighbour
+        double dvb;
+        if (v >= 0) dvb = -bc / Vc + (o >= 0 ? pre(o) / m.vol[o] : 0.0);
+        else dvb = -(o >= 0 ? pre(o) / m.vol[o] : 0.0) + bc / Vc;
+        dvb += A.w.dVb[f];
+        const double out = v >= 0 ? ph : -ph;
+        if (out > 0.0) {
+            if (recon) A.w.vbar[f] = dvb * ph;  // dV = phi * (swept integral of the interface cell)
+            else acc += dvb * ph * dtc;         // dV = alpha_c phi dt
+        }
+        if (v >= 0) A.phibar[f] = (ph != 0.0 ? dvb * (A.dV0[f] / ph) : 0.0) + A.w.phib[f];
+    }
+    A.abar[c] = acc;
+}
+
+// interface cells: derivatives of the swept integrals along each vertex value and alpha_P
+__global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
+    const DevMesh &m = A.m;
+    const int lv = threadIdx.x & (kLanes - 1);
+    const int ngrp = (gridDim.x * blockDim.x) / kLanes;
+    const int nrec = A.w.counters[kAdjRecon];
+    int fv[4];
+    const int fwd = lane_face_loop(lv, fv);
+    for (int g = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; g < 9 * nrec; g += ngrp) {
+        const int c = A.w.rlist[g / 9];
+        const int dir = g % 9;  // 0..7: vertex value dir, 8: alpha_P
+        const double aP = A.alpha[c];
+        const double V6 = 6.0 * m.vol[c];
+        const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
+        const double *cx = m.cxyz + 24 * (size_t)c + 3 * lv;
+        D3 xv{cx[0], cx[1], cx[2]};
+        const double av = A.vert_alpha[8 * (size_t)c + lv];
+        const D3 xm = 0.125 * grp_sum3(xv);
+        xv = xv - xm;
+        DFace f;
+        f.active = lv < 6;
+        f.planar = (m.cflags[c] >> min(lv, 5)) & 1;
+        f.fwd = fwd;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f.q[i] = D3{grp_get(xv.x, fv[i]), grp_get(xv.y, fv[i]), grp_get(xv.z, fv[i])};
+            f.aq[i] = Dl{grp_get(av, fv[i]), fv[i] == dir ? 1.0 : 0.0};
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const Dl d = ((fwd >> i) & 1) ? f.aq[(i + 1) & 3] - f.aq[i] : f.aq[i] - f.aq[(i + 1) & 3];
+            f.inv[i] = d.v != 0.0 ? dinv(d) : dc(0.0);
+        }
+        const double iso = A.iso[c];
+        // sub-volume at the isovalue and its rate along this direction at fixed isovalue
+        const Dl g0 = dcell_vsub6(f, dc(iso), nullptr, nullptr);
+        // rate with the isovalue (vertex values fixed)
+        DFace f0 = f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f0.aq[i].d = 0.0;
+            f0.inv[i].d = 0.0;
+        }
+        const double gx = dcell_vsub6(f0, Dl{iso, 1.0}, nullptr, nullptr).d;
+        // at a jump of the sub-volume the isovalue is a vertex value and moves with it
+        const bool jump = fabs(g0.v - aP * V6) > 1e-9 * V6;
+        const uint64_t hit = __ballot(jump && lv < 8 && av == iso);
+        const int base = __lane_id() & ~(kLanes - 1);
+        const int mvert = (int)((hit >> base) & 0xFF);
+        const int vjump = mvert ? __ffs(mvert) - 1 : -1;
+        double xdot;
+        if (jump) xdot = (dir < 8 && dir == vjump) ? 1.0 : 0.0;
+        else xdot = gx != 0.0 ? -((dir < 8 ? g0.d : -V6)) / gx : 0.0;
+        // isoface along the direction
+        const Dl isod{iso, xdot};
+        DV3 o, cseg;
+        dcell_vsub6(f, isod, &o, &cseg);
+        const Dl nrm = dnorm(cseg);
+        double contrib = 0.0;
+        if (nrm.v > 0.0) {
+            const DV3 nS = dinv(nrm) * cseg;
+            DV3 acc;
+            Dl ws;
+            dface_centre_part(f, isod, o, nS, acc, ws);
+            acc = dgrp_sum3(acc);
+            ws = dgrp_sum(ws);
+            const DV3 xS = dinv(3.0 * ws) * acc;
+            const Dl un = A.U[c] * nS.x + A.U[m.n_cells + c] * nS.y + A.U[2 * (size_t)m.n_cells + c] * nS.z;
+            if (f.active) {
+                const int32_t v = m.lface[6 * (size_t)c + lv];
+                if (v != kEmpty) {
+                    const int32_t fid = v >= 0 ? v : ~v;
+                    const double ph = A.phi[fid];
+                    const double out = v >= 0 ? ph : -ph;
+                    if (out > 0.0) {
+                        Dl dq[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = ddot(dv(f.q[i]) - xS, nS);
+                        Dl accI = dc(0.0);
+                        double Af = 0.0;
+                        if (f.planar) {
+                            const double A1 = 0.5 * norm3(cross(f.q[1] - f.q[0], f.q[2] - f.q[0]));
+                            const double A2 = 0.5 * norm3(cross(f.q[2] - f.q[0], f.q[3] - f.q[0]));
+                            accI = A1 * dtri_sweep(dq[0], dq[1], dq[2], un, dtc) + A2 * dtri_sweep(dq[0], dq[2], dq[3], un, dtc);
+                            Af = A1 + A2;
+                        } else {
+                            const D3 ap = 0.25 * (f.q[0] + f.q[1] + f.q[2] + f.q[3]);
+                            const Dl dap = ddot(dv(ap) - xS, nS);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const double Ai = 0.5 * norm3(cross(f.q[i] - ap, f.q[(i + 1) & 3] - ap));
+                                accI = accI + Ai * dtri_sweep(dap, dq[i], dq[(i + 1) & 3], un, dtc);
+                                Af += Ai;
+                            }
+                        }
+                        contrib = A.w.vbar[fid] * (accI.d / Af);
+                    }
+                }
+            }
+        }
+        const double gsum = grp_sum(contrib);
+        if (dir == 8) {
+            if (lv == 0) atomicAdd(&A.abar[c], gsum);
+        } else {
+            // transpose of the vertex interpolation: vertex dir's stencil cells
+            const int k = m.cpt[8 * (size_t)c + dir];
+            for (int e = m.st_ptr[k] + lv; e < m.st_ptr[k + 1]; e += kLanes)
+                atomicAdd(&A.abar[m.st_cell[e]], m.st_w[e] * gsum);
+        }
+    }
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <int W>
+hipError_t launch_adj_w(const AdjArgs &a, hipStream_t s) {
+    const int n = a.m.n_cells;
+    const int g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_adj_prep<W>, dim3(g), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adj_bound<W>, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_adj_faces<W>, dim3(g), dim3(256), 0, s, a);
+    const int gs = std::max(1, std::min(2048, (int)((9L * n * kLanes + 255) / 256)));
+    hipLaunchKernelGGL(k_adj_surface, dim3(gs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, const AdjInputs &in, const AdjWork &w,
+                          hipStream_t s) {
+    if (p.n_bound_iter > kAdjMaxSweeps) return hipErrorInvalidValue;
+    const int64_t nf = m.n_faces;
+    const int g = (int)std::min<int64_t>((nf + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_f64, dim3(g), dim3(256), 0, s, in.phibar, nf, 0.0);
+    hipError_t e = launch_offset_copy(nullptr, w.counters, kAdjNum, 0, 0, 0, s);
+    if (e != hipSuccess) return e;
+    AdjArgs A{m, a.alpha, a.phi, a.U, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
+              in.vert_alpha, in.kind, in.iso, in.dV, in.raw, in.abar_new, in.abar, in.phibar, w};
+    switch (m.W) {
+        case 1: return launch_adj_w<1>(A, s);
+        case 2: return launch_adj_w<2>(A, s);
+        case 3: return launch_adj_w<3>(A, s);
+        case 4: return launch_adj_w<4>(A, s);
+        case 5: return launch_adj_w<5>(A, s);
+        default: return launch_adj_w<6>(A, s);
+    }
+}
+
+}  // namespace isoadv

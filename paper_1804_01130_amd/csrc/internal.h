@@ -92,6 +92,39 @@ struct Params {
     int32_t root_max_iter, n_bound_iter, clip;
 };
 
+// Adjoint workspace (device pointers; allocated by a plan on its first adjoint step).  S = number of
+// bounding sweeps (at least 1), nc cells, nf faces.
+enum : int { kAdjOff = 0, kAdjRecon = 1, kAdjNum = 8, kAdjMaxSweeps = 31 };
+struct AdjWork {
+    int32_t *counters = nullptr;  // [kAdjNum]
+    double *x = nullptr;          // [nc] bounding state
+    double *xbar = nullptr;       // [nc] its adjoint
+    int32_t *cflag = nullptr;     // [nc] bit s: chopped or clamped in sweep s
+    int32_t *list = nullptr;      // [S nc] cells listed in each sweep
+    int32_t *tlist = nullptr;     // [S nc] cells touched in each sweep
+    int32_t *rlist = nullptr;     // [nc] reconstructed interface cells
+    int32_t *cmark = nullptr;     // [nc] zero between calls
+    double *tape = nullptr;       // [S nc (4 + 2 W)]
+    int32_t *tflag = nullptr;     // [S nc]
+    double *dvcur = nullptr;      // [nf] running dV of corrected faces
+    int32_t *touched = nullptr;   // [nf]
+    double *delta = nullptr;      // [nf] zero between sweeps
+    double *dVb = nullptr;        // [nf] adjoint of dV before bounding, from bounding
+    double *phib = nullptr;       // [nf] adjoint of phi, from bounding
+    double *dvcurbar = nullptr;   // [nf]
+    double *deltabar = nullptr;   // [nf]
+    double *vbar = nullptr;       // [nf] adjoint of the swept integral of interface-upwind faces, times phi
+};
+struct AdjInputs {
+    const double *vert_alpha;  // forward intermediates of the step
+    const int32_t *kind;
+    const double *iso;
+    const double *dV;
+    const double *raw;
+    const double *abar_new;    // adjoint in
+    double *abar, *phibar;     // adjoints out
+};
+
 // kernels.hip
 // ev: nullptr, or 5 events recorded before each of the 4 kernels and after the last
 hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, const StepArgs &a,
@@ -102,6 +135,9 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
 hipError_t launch_offset_copy(const int32_t *src, int32_t *dst, int64_t n, int mode, int32_t off1, int32_t off2,
                               hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
+// adjoint.hip
+hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, const AdjInputs &in, const AdjWork &w,
+                          hipStream_t s);
 hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha, const double *alpha_new,
                         hipStream_t s);
 
@@ -129,6 +165,11 @@ struct iso_plan {
     double *host_red = nullptr;        // pinned [64]
     std::vector<hipEvent_t> events;    // 5 per recorded step
     int32_t timing_cap = 0, timing_used = 0;
+    // adjoint workspace and forward-trace buffers (allocated on the first adjoint step)
+    isoadv::AdjWork adj;
+    double *adj_vert = nullptr, *adj_iso = nullptr, *adj_dV = nullptr, *adj_raw = nullptr, *adj_new = nullptr;
+    int32_t *adj_kind = nullptr;
+    bool adj_ready = false;
 };
 
 namespace isoadv {

@@ -613,6 +613,74 @@ iso_status iso_advect_step_traced(iso_plan *p, const double *alpha, const double
     return step_impl(p, alpha, phi, U, dt, alpha_new, stats, trace);
 }
 
+static iso_status adj_alloc(iso_plan *p) {
+    if (p->adj_ready) return ISO_OK;
+    const iso_mesh *m = p->mesh;
+    const size_t nc = m->n_cells, nf = m->n_faces;
+    const size_t S = std::max(1, p->opt.n_bound_iter);
+    AdjWork &w = p->adj;
+    auto alloc = [&](void **ptr, size_t bytes) -> bool {
+        if (hipMalloc(ptr, std::max<size_t>(bytes, 256)) != hipSuccess) return false;
+        p->allocations.push_back(*ptr);
+        return hipMemset(*ptr, 0, std::max<size_t>(bytes, 256)) == hipSuccess;
+    };
+    const bool ok =
+        alloc((void **)&w.counters, kAdjNum * 4) && alloc((void **)&w.x, nc * 8) && alloc((void **)&w.xbar, nc * 8) &&
+        alloc((void **)&w.cflag, nc * 4) && alloc((void **)&w.list, S * nc * 4) && alloc((void **)&w.tlist, S * nc * 4) &&
+        alloc((void **)&w.rlist, nc * 4) && alloc((void **)&w.cmark, nc * 4) &&
+        alloc((void **)&w.tape, S * nc * (4 + 2 * (size_t)m->W) * 8) && alloc((void **)&w.tflag, S * nc * 4) &&
+        alloc((void **)&w.dvcur, nf * 8) && alloc((void **)&w.touched, nf * 4) && alloc((void **)&w.delta, nf * 8) &&
+        alloc((void **)&w.dVb, nf * 8) && alloc((void **)&w.phib, nf * 8) && alloc((void **)&w.dvcurbar, nf * 8) &&
+        alloc((void **)&w.deltabar, nf * 8) && alloc((void **)&w.vbar, nf * 8) &&
+        alloc((void **)&p->adj_vert, 8 * nc * 8) && alloc((void **)&p->adj_kind, nc * 4) &&
+        alloc((void **)&p->adj_iso, nc * 8) && alloc((void **)&p->adj_dV, nf * 8) && alloc((void **)&p->adj_raw, nc * 8) &&
+        alloc((void **)&p->adj_new, nc * 8);
+    if (!ok) return fail(ISO_ENOMEM, "adjoint workspace allocation failed");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(ISO_EDEVICE, "device error at adjoint workspace setup");
+    p->adj_ready = true;
+    return ISO_OK;
+}
+
+iso_status iso_advect_step_adjoint(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt,
+                                   const iso_trace *fwd, const double *alpha_new_bar, double *alpha_bar,
+                                   double *phi_bar) {
+    if (!p) return fail(ISO_EINVAL, "null plan");
+    if (!alpha || !phi || !U || !alpha_new_bar || !alpha_bar || !phi_bar) return fail(ISO_EINVAL, "null array");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(ISO_EINVAL, "dt must be positive and finite");
+    if (p->opt.n_bound_iter > kAdjMaxSweeps)
+        return fail(ISO_EUNSUPPORTED, "the adjoint takes at most " + std::to_string(kAdjMaxSweeps) + " bounding sweeps");
+    if (fwd && (!fwd->vert_alpha || !fwd->kind || !fwd->iso || !fwd->dV || !fwd->alpha_raw))
+        return fail(ISO_EINVAL, "forward trace needs vert_alpha, kind, iso, dV and alpha_raw");
+    const iso_mesh *m = p->mesh;
+    const size_t nc = (size_t)m->n_cells * 8, nf = (size_t)m->n_faces * 8;
+    const void *ins[] = {alpha, phi, U, alpha_new_bar};
+    const size_t insz[] = {nc, nf, 3 * nc, nc};
+    for (int i = 0; i < 4; ++i)
+        if (overlaps(alpha_bar, nc, ins[i], insz[i]) || overlaps(phi_bar, nf, ins[i], insz[i]))
+            return fail(ISO_EINVAL, "an adjoint output overlaps an input");
+    if (overlaps(alpha_bar, nc, phi_bar, nf)) return fail(ISO_EINVAL, "alpha_bar overlaps phi_bar");
+    iso_status st = adj_alloc(p);
+    if (st != ISO_OK) return st;
+    (void)hipGetLastError();
+    const Params prm = step_params(p->opt);
+    StepArgs args{alpha, phi, U, p->adj_new, dt, nullptr};
+    iso_trace tr{};
+    if (!fwd) {  // the forward step of these inputs, keeping what the adjoint needs
+        tr.vert_alpha = p->adj_vert;
+        tr.kind = p->adj_kind;
+        tr.iso = p->adj_iso;
+        tr.dV = p->adj_dV;
+        tr.alpha_raw = p->adj_raw;
+        hipError_t e = launch_step(m->dev, p->work, prm, args, &tr, launch_cfg(p->opt), false, p->stream, nullptr);
+        if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("forward launch failed: ") + hipGetErrorString(e));
+        fwd = &tr;
+    }
+    AdjInputs in{fwd->vert_alpha, fwd->kind, fwd->iso, fwd->dV, fwd->alpha_raw, alpha_new_bar, alpha_bar, phi_bar};
+    hipError_t e = launch_adjoint(m->dev, prm, args, in, p->adj, p->stream);
+    if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("adjoint launch failed: ") + hipGetErrorString(e));
+    return ISO_OK;
+}
+
 iso_status iso_plan_set_timing(iso_plan *p, int32_t max_steps) {
     if (!p || max_steps < 0) return fail(ISO_EINVAL, "bad argument");
     if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(ISO_EDEVICE, "stream sync failed");

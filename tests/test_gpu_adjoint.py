@@ -1,0 +1,181 @@
+"""The adjoint step (iso_advect_step_adjoint) and the checkpointed multi-step gradient on the GPU.
+
+One step: every component of alpha_bar and phi_bar against the oracle's gradient, each component
+of which is one exact tangent (complex step) of the oracle's step.  One step of the 256x128 Airy
+case: the dot-product identity <alpha_bar, da> + <phi_bar, dphi> = <alpha_new_bar, tangent(da, dphi)>
+against the oracle tangent.  Fifty steps: the gradient of a misfit loss through checkpoints against
+central differences of the GPU forward along directions that stay clear of topology changes
+(interior-cell alpha, divergence-free fluxes), at 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import wavegen as W
+from tests.gpuutil import gpu_plan, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _adjoint(plan, w, alpha, phi, U, abar_new):
+    import torch
+    ab, pb = plan.adjoint(to_dev(alpha), to_dev(phi), to_dev(U), w.dt, to_dev(abar_new))
+    torch.cuda.synchronize()
+    return ab.cpu().numpy(), pb.cpu().numpy()
+
+
+def _state_after(O, w, steps):
+    om = O.OracleMesh(w.mesh)
+    a = np.array(w.alpha0, copy=True)
+    for n in range(steps):
+        phi, U = w.phi_U(n)
+        a, _ = om.step(a, phi, U, w.dt)
+    return a
+
+
+@pytest.mark.parametrize("name", ["airy_16x8", "cosine_16x8", "violent_6x5x4"])
+def test_one_step_adjoint_matches_oracle_gradient(oracle_lib, name):
+    O = oracle_lib
+    w = {"airy_16x8": lambda: W.airy_slab(16, 8, 8, 0.09, 0.5, 4, name),
+         "cosine_16x8": lambda: W.cosine_uniform(nx=16, ny=8, steps=4, co=0.5),
+         "violent_6x5x4": lambda: W.violent_3d(nx=6, ny=5, nz=4, steps=4)}[name]()
+    say(f"[gpu] one-step adjoint vs oracle gradient: {name} cells={w.mesh.n_cells}")
+    a = _state_after(O, w, 2)  # a state with some history (bounding active in places)
+    phi, U = w.phi_U(2)
+    rng = np.random.default_rng(3)
+    abar_new = rng.standard_normal(w.mesh.n_cells)
+    gm, plan = gpu_plan(w.mesh)
+    ga, gp = _adjoint(plan, w, a, phi, U, abar_new)
+    om = O.OracleMesh(w.mesh)
+    oa, op = om.gradient(a, phi, U, w.dt, abar_new)
+    scale_a = max(np.abs(oa).max(), 1e-300)
+    scale_p = max(np.abs(op).max(), 1e-300)
+    assert np.abs(ga - oa).max() <= 1e-9 * scale_a, (np.argmax(np.abs(ga - oa)), np.abs(ga - oa).max(), scale_a)
+    assert np.abs(gp - op).max() <= 1e-9 * scale_p, (np.argmax(np.abs(gp - op)), np.abs(gp - op).max(), scale_p)
+
+
+def test_adjoint_dot_product_against_oracle_tangent(oracle_lib):
+    O = oracle_lib
+    base, _ = W.adjoint_case()
+    say(f"[gpu] adjoint dot-product test: {base.name} cells={base.mesh.n_cells}")
+    a = _state_after(O, base, 3)
+    phi, U = base.phi_U(3)
+    om = O.OracleMesh(base.mesh)
+    rng = np.random.default_rng(4)
+    abar_new = rng.standard_normal(base.mesh.n_cells)
+    gm, plan = gpu_plan(base.mesh)
+    ga, gp = _adjoint(plan, base, a, phi, U, abar_new)
+    for k in range(6):
+        da = rng.standard_normal(base.mesh.n_cells)
+        dp = rng.standard_normal(base.mesh.n_faces) * np.abs(phi).max()
+        _, t = om.step_tlm(a, phi, U, base.dt, da, dp)
+        lhs, rhs = ga @ da + gp @ dp, abar_new @ t
+        assert abs(lhs - rhs) <= 1e-9 * (np.abs(ga * da).sum() + np.abs(gp * dp).sum()), (k, lhs, rhs)
+
+
+@pytest.fixture(scope="module")
+def misfit():
+    """The adjoint workload: 50 steps, loss sum (alpha_T - alpha_target)^2, target from a run with a
+    perturbed steepness; fields resident on the device."""
+    import torch
+    base, target = W.adjoint_case()
+    S = base.n_steps
+    phis = torch.stack([to_dev(base.phi_U(n)[0]) for n in range(S)]).contiguous()
+    Us = torch.stack([to_dev(base.phi_U(n)[1]) for n in range(S)]).contiguous()
+    gm, plan = gpu_plan(base.mesh)
+    tphis = torch.stack([to_dev(target.phi_U(n)[0]) for n in range(S)]).contiguous()
+    tUs = torch.stack([to_dev(target.phi_U(n)[1]) for n in range(S)]).contiguous()
+    gt, tplan = gpu_plan(target.mesh)
+    a = to_dev(target.alpha0)
+    b = torch.empty_like(a)
+    for n in range(S):
+        tplan.step(a, tphis[n], tUs[n], target.dt, out=b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    return dict(w=base, plan=plan, gm=gm, phis=phis, Us=Us, alpha_target=a.clone(), S=S)
+
+
+def _loss_and_grad(M, alpha0, phis, every=10, grad=True):
+    import torch
+    from paper_1804_01130_amd.autograd import advect
+    a0 = alpha0.clone().requires_grad_(grad)
+    ph = phis.clone().requires_grad_(grad)
+    aT = advect(a0, ph, M["plan"], M["Us"], M["w"].dt, checkpoint_every=every)
+    L = ((aT - M["alpha_target"]) ** 2).sum()
+    if not grad:
+        return L.item(), None, None
+    L.backward()
+    torch.cuda.synchronize()
+    return L.item(), a0.grad.clone(), ph.grad.clone()
+
+
+def _psi_direction(mesh, rng):
+    L = mesh.xs[-1] - mesh.xs[0]
+    H = mesh.ys[-1] - mesh.ys[0]
+    c = rng.standard_normal(3)
+    return lambda x, y, z0, z1: np.sin(np.pi * y / H) * (c[0] * np.cos(2 * np.pi * x / L) + c[1] * np.sin(
+        4 * np.pi * x / L) + c[2] * np.cos(6 * np.pi * x / L)) * (z1 - z0)
+
+
+def test_gradient_of_fifty_steps_against_central_differences(misfit):
+    import torch
+    M = misfit
+    w = M["w"]
+    say(f"[gpu] 50-step gradient vs central differences: {w.name}")
+    alpha0 = to_dev(w.alpha0)
+    L0, ga, gp = _loss_and_grad(M, alpha0, M["phis"])
+    say(f"[gpu]   loss {L0:.12e}")
+    rng = np.random.default_rng(8)
+    inner = (w.alpha0 > 1e-4) & (w.alpha0 < 1 - 1e-4)
+    checked = 0
+    for k in range(6):
+        da = to_dev(rng.standard_normal(w.mesh.n_cells) * inner)
+        dp1 = W.fluxes_from_edge_integral(w.mesh, _psi_direction(w.mesh, rng))
+        dp1 *= np.abs(w.phi_U(0)[0]).max() / np.abs(dp1).max()
+        dp = to_dev(dp1)[None, :].expand_as(M["phis"]).contiguous()
+        pred = float((ga * da).sum() + (gp * dp).sum())
+
+        def L(e):
+            return _loss_and_grad(M, alpha0 + e * da, M["phis"] + e * dp, grad=False)[0]
+        # over 50 steps the loss has many small kinks (cut points crossing vertices, sweep
+        # breakpoints reaching the ends of the step): a direction counts as smooth at this scale when
+        # central differences with two small steps agree to 1e-6, and the adjoint must then agree
+        # with the smaller one to 1e-6
+        fd = [(L(h) - L(-h)) / (2 * h) for h in (2.5e-7, 5e-7, 1e-6)]
+        if abs(fd[0] - fd[1]) > 1e-6 * max(abs(fd[0]), 1e-300):
+            say(f"[gpu]   direction {k}: kink within 5e-7, skipped ({fd} adjoint {pred:.9e})")
+            continue
+        say(f"[gpu]   direction {k}: adjoint {pred:.12e} central differences {fd}")
+        assert abs(pred - fd[0]) <= 1e-6 * max(abs(fd[0]), abs(pred)), (k, pred, fd)
+        checked += 1
+    assert checked >= 3
+
+
+def test_checkpoint_interval_does_not_change_the_gradient(misfit):
+    M = misfit
+    alpha0 = to_dev(M["w"].alpha0)
+    ref = _loss_and_grad(M, alpha0, M["phis"], every=10)
+    for every in (1, 7, 50):
+        say(f"[gpu] checkpoint interval {every}")
+        got = _loss_and_grad(M, alpha0, M["phis"], every=every)
+        assert got[0] == ref[0]
+        for g, r in ((got[1], ref[1]), (got[2], ref[2])):
+            assert float((g - r).abs().max()) <= 1e-12 * max(float(r.abs().max()), 1e-300)
+
+
+def test_adjoint_argument_errors():
+    import torch
+    from paper_1804_01130_amd import IsoError, Plan, default_options
+    w = W.cosine_uniform(nx=8, ny=4, steps=1)
+    gm, plan = gpu_plan(w.mesh)
+    phi, U = w.phi_U(0)
+    a, p, u = to_dev(w.alpha0), to_dev(phi), to_dev(U)
+    with pytest.raises(IsoError):
+        plan.adjoint(a, p, u, -1.0, torch.zeros_like(a))
+    with pytest.raises(IsoError):
+        plan.adjoint(a, p, u, w.dt, torch.zeros_like(a), alpha_bar=a)  # output overlaps an input
+    with pytest.raises(IsoError):
+        plan.adjoint(a, p, u, w.dt, torch.zeros_like(a), trace={"kind": torch.zeros(gm.n_cells, dtype=torch.int32,
+                                                                                       device=a.device)})
+    many = Plan(gm, default_options(n_bound_iter=40))
+    with pytest.raises(IsoError):
+        many.adjoint(a, p, u, w.dt, torch.zeros_like(a))
