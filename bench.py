@@ -30,25 +30,27 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 isoAdvector cell-steps/s + % HBM roofline; batched vs plain; adjoint/fwd ratio"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_01130_amd", "csrc", n) for n in ("kernels.hip", "internal.h")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_01130_amd", "csrc", n) for n in ("kernels.hip", "device_common.h",
+                                                                                "internal.h")]
 PROFILES = os.path.join(ROOT, "profiles")
 # FP64 operations credited per interface cell for vertex interpolation, the isovalue search, the
 # isoface and the swept-face integrals (a fixed per-unit figure, independent of the iteration
 # counts of this implementation)
 FLOP_PER_SURFACE_CELL = 11000.0
 COPY_N = 1 << 27  # doubles moved by the calibration copy (1 GiB read, 1 GiB written)
-KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update", "k_bound": "bound",
+KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update",
+               "k_bound_a": "bound_sweep_corrections", "k_bound_b": "bound_sweep_apply", "k_bound_end": "bound_end",
                "k_stats": "stats"}
 # the commands whose rocprofv3 output --summarize-profiles reads
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
-             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble",
+             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble --no-adjoint",
     "fetch": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
     "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
 }
 
 
@@ -227,7 +229,7 @@ def summarize_profiles(workload):
              f"kernel_source_sha: {shas.pop()}",
              f"scale_fetch: {sf:.6f}",
              f"scale_write: {sw:.6f}"]
-    for k in ("find_surface", "surface", "update", "bound"):
+    for k in ("find_surface", "surface", "update", "bound_sweep_corrections", "bound_sweep_apply", "bound_end"):
         if k not in fetch or k not in write:
             continue
         fk = float(np.mean(fetch[k]))
@@ -325,6 +327,52 @@ def ensemble_bench(steps, warmup, tune_cache=None):
     return out
 
 
+def adjoint_bench(every=10):
+    """The adjoint workload: 256x128 Airy, 50 steps, loss sum (alpha_T - alpha_target)^2; time of the
+    forward pass (plain steps) and of the backward pass (recomputing each segment from its checkpoint
+    with traced steps, then the adjoint steps), both through the same torch autograd Function."""
+    import torch
+    import wavegen as W
+    from paper_1804_01130_amd import Mesh, Plan, default_options
+    from paper_1804_01130_amd.autograd import advect
+    dev = torch.device("cuda:0")
+    base, target = W.adjoint_case()
+    S = base.n_steps
+    T = lambda x: torch.tensor(x, device=dev)
+    phis = torch.stack([T(base.phi_U(n)[0]) for n in range(S)]).contiguous()
+    Us = torch.stack([T(base.phi_U(n)[1]) for n in range(S)]).contiguous()
+    plan = Plan(Mesh.from_arrays(base.mesh), default_options())
+    tplan = Plan(Mesh.from_arrays(target.mesh), default_options())
+    at = T(target.alpha0)
+    tb = torch.empty_like(at)
+    for n in range(S):
+        tplan.step(at, T(target.phi_U(n)[0]), T(target.phi_U(n)[1]), target.dt, out=tb)
+        at, tb = tb, at
+    a0 = T(base.alpha0)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    best = None
+    for rep in range(4):  # the first repetition warms up (adjoint workspace, allocator)
+        x0 = a0.clone().requires_grad_(True)
+        ph = phis.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        e0.record()
+        aT = advect(x0, ph, plan, Us, base.dt, checkpoint_every=every)
+        L = ((aT - at) ** 2).sum()
+        e1.record()
+        L.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        f, b = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        if rep > 0 and (best is None or f + b < best[0] + best[1]):
+            best = (f, b, L.item())
+    f, b, Lv = best
+    out = {"workload": "airy_2d_256x128 (32768 cells), 50 steps, loss sum (alpha_T - alpha_target)^2",
+           "checkpoint_every": every, "forward_ms": f, "backward_ms": b, "adjoint_fwd_ratio": b / f,
+           "loss": Lv, "note": "backward = recomputation of each segment from its checkpoint + adjoint steps"}
+    log(f"[bench] adjoint: forward {f:.2f} ms, backward {b:.2f} ms, ratio {b / f:.2f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +385,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain copy kernel of known size (scale of the HBM counters)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-vs-plain ensemble measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
@@ -426,6 +475,7 @@ def main():
         del phis, Us, a, b, plan, gm
         torch.cuda.empty_cache()
         ens = ensemble_bench(args.steps, args.warmup)
+    adj = None if args.no_adjoint else adjoint_bench()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -445,6 +495,7 @@ def main():
         "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
         "ensemble": ens,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 
