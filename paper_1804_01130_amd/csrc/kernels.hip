@@ -1,19 +1,21 @@
 // HIP kernels of the isoAdvector step for gfx950 (wave64), FP64.
 //
-// One step (Section 3.2 of the paper) is four launches on one stream:
+// One step (Section 3.2 of the paper) runs on one stream with no host synchronisation:
 //   find_surface   interface cells (eps < alpha < 1-eps), compacted with wave ballots and one
 //                  atomic per 4096-cell work-group
 //   surface        eight lanes per interface cell: lane v gathers vertex v's value (inverse
-//                  distance stencil); the lanes then search the isovalue together, evaluating
-//                  the sub-volume at eight isovalues per round (sorted vertex values, then
-//                  points around a cubic model of the sub-volume), build the isoface, and lane k
-//                  integrates the submerged fraction of face k over the step (Eqs. tv .. intaplus)
-//                  when it is an outflow face -> dV (each face has one upwind cell: no atomics)
+//                  distance stencil); lane k < 6 then owns canonical face k.  The group brackets
+//                  the isovalue between two consecutive sorted vertex values, then solves the
+//                  volume constraint: Newton on the interval's functional form for planar cells,
+//                  Illinois otherwise.  It builds the isoface, and lane k integrates the submerged
+//                  fraction of face k over the step when it is an outflow face (Eqs. tv ..
+//                  intaplus) -> dV (each face has one upwind cell: no atomics)
 //   update         per cell, gather over its flux faces in ascending face id: dV from the
 //                  interface kernel or alpha_upwind*phi*dt; alpha - sum/V; round-off chopping;
 //                  cells outside the bounds are appended to a list
-//   bound          one work-group: Jacobi redistribution over outflow faces of the listed
-//                  cells, then chopping (bounding step at the end of Section 3.2)
+//   bound          per Jacobi sweep, corrections over the outflow faces of the listed cells, then
+//                  their application in face order with chopping (bounding step at the end of
+//                  Section 3.2); a one-group kernel leaves the workspace clean
 // Nothing in the step is a dense contraction, so no matrix instructions are used.
 #include <hip/hip_runtime.h>
 
