@@ -381,7 +381,8 @@ def main():
     ap.add_argument("--workload", default="violent_3d", choices=["violent_3d", "airy_2d", "cosine_2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--surface-waves", type=int, default=0, help="register budget of the interface kernel (2-4)")
+    ap.add_argument("--surface-waves", type=int, default=0, help="register budget of the interface kernel (1-4)")
+    ap.add_argument("--surface-blocks", type=int, default=0, help="work-groups of the interface kernel (0: default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain copy kernel of known size (scale of the HBM counters)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-vs-plain ensemble measurement")
@@ -407,7 +408,7 @@ def main():
     gm = Mesh.from_arrays(w.mesh)
     info = gm.info()
     from paper_1804_01130_amd import default_options
-    plan = Plan(gm, default_options(surface_waves=args.surface_waves))
+    plan = Plan(gm, default_options(surface_waves=args.surface_waves, surface_blocks=args.surface_blocks))
     n_steps_total = args.warmup + args.steps
     if w.steady:
         phi, U = w.phi_U(0)

@@ -472,6 +472,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
         const bool planar_cell = (m.cflags[c] & 63) == 63;
         double iso = 0.0;
         int rounds = 0;
+        bool face_done = false;
         D3 nS{0, 0, 0}, xS{0, 0, 0};
         double un = 0.0;
         if (recon) {
@@ -552,6 +553,31 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                     }
                     if (!conv) ++nonconv;
                     iso = xr + u;
+                    // the isoface at the isovalue, from the face segments: apex (perimeter
+                    // centroid), area vector (x2) = sum of s x e, centre = area-weighted fan centroid
+                    const Perim pr = seg_eval(fq, u);
+                    const D3 oacc = grp_sum3(pr.oacc);
+                    const double oL = grp_sum(pr.oL);
+                    const D3 cs = grp_sum3(pr.Bu);
+                    const double nrm = norm3(cs);
+                    if (oL > 0.0 && nrm > 0.0) {
+                        const D3 o = (1.0 / oL) * oacc;
+                        nS = (1.0 / nrm) * cs;
+                        D3 acc{0, 0, 0};
+                        double ws = 0.0;
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) {
+                            const D3 sp = fq.s0[k] + u * fq.s1[k], ep = fq.e0[k] + u * fq.e1[k];
+                            const double wt = dot(cross(sp - o, ep - o), nS);
+                            acc = sel3(fq.on[k], acc + wt * (o + sp + ep), acc);
+                            ws += fq.on[k] ? wt : 0.0;
+                        }
+                        acc = grp_sum3(acc);
+                        ws = grp_sum(ws);
+                        xS = (1.0 / (3.0 * ws)) * acc;
+                        un = A.U[c] * nS.x + A.U[m.n_cells + c] * nS.y + A.U[2 * (size_t)m.n_cells + c] * nS.z;
+                        face_done = true;
+                    }
                 }
             } else if (!exact) {
                 double x0 = sorted_at(il), x1 = sorted_at(ih), f0 = fl;
@@ -590,11 +616,12 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                     iso = fabs(f0) <= fabs(f1) ? x0 : x1;
                 }
             }
-            // isoface at the isovalue
-            D3 o, cseg;
-            cell_vsub6(f, iso, false, &o, &cseg);
+            // isoface at the isovalue (unless the interval solve already built it)
+            D3 o, cseg{0, 0, 0};
+            if (!face_done) cell_vsub6(f, iso, false, &o, &cseg);
             const double nrm = norm3(cseg);
-            if (nrm > 0.0) {
+            if (face_done) {
+            } else if (nrm > 0.0) {
                 nS = (1.0 / nrm) * cseg;
                 D3 acc;
                 double ws;
