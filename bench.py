@@ -383,6 +383,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--surface-waves", type=int, default=0, help="register budget of the interface kernel (1-4)")
     ap.add_argument("--surface-blocks", type=int, default=0, help="work-groups of the interface kernel (0: default)")
+    ap.add_argument("--bound-blocks", type=int, default=0, help="work-groups of the bounding sweeps (0: default)")
+    ap.add_argument("--block-cells", type=int, default=0, help="threads per block of the per-cell kernels (0: default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain copy kernel of known size (scale of the HBM counters)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-vs-plain ensemble measurement")
@@ -408,7 +410,8 @@ def main():
     gm = Mesh.from_arrays(w.mesh)
     info = gm.info()
     from paper_1804_01130_amd import default_options
-    plan = Plan(gm, default_options(surface_waves=args.surface_waves, surface_blocks=args.surface_blocks))
+    plan = Plan(gm, default_options(surface_waves=args.surface_waves, surface_blocks=args.surface_blocks,
+                                    bound_blocks=args.bound_blocks, block_cells=args.block_cells))
     n_steps_total = args.warmup + args.steps
     if w.steady:
         phi, U = w.phi_U(0)

@@ -56,6 +56,17 @@ constexpr bool face_edges_consistent() {
 static_assert(face_edges_consistent(), "face/edge tables disagree");
 
 
+// Work-groups are dispatched to the 8 XCDs round-robin (group b on XCD b mod 8), and each XCD has
+// its own L2.  This bijection renumbers groups so that each XCD works through one contiguous
+// range (consecutive logical groups, hence neighbouring cells and the faces and stencils they
+// share, stay behind one L2).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % kXcds, k = b / kXcds;
+    const int q = nb / kXcds, r = nb % kXcds;
+    return x * q + min(x, r) + k;
+}
+
 // Vertex loop of face lv (lanes 6 and 7 take face 0's) and, as bit i, whether loop position i runs
 // along the canonical edge direction.
 __device__ __forceinline__ int lane_face_loop(int lv, int *fv) {

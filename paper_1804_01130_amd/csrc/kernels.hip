@@ -32,8 +32,6 @@ struct Part {
     D3 cseg;    // sum of s0 x s1 over isoface edges on the face
     D3 oacc;    // sum of length x midpoint over those edges
     double oL;  // their total length
-    D3 osum;    // sum of their entry points
-    double nseg;
 };
 
 // Divergence-theorem share of face k for isovalue iso (vertex wet iff a > iso; a >= iso with
@@ -47,7 +45,7 @@ struct Part {
 // are all computed and masked, so the lanes of a wave (different faces, different cells) never
 // diverge.
 __device__ __forceinline__ Part face_part(const FaceLane &f, double iso, bool tie_wet) {
-    Part r{0.0, {0, 0, 0}, {0, 0, 0}, 0.0, {0, 0, 0}, 0.0};
+    Part r{0.0, {0, 0, 0}, {0, 0, 0}, 0.0};
     bool w[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) w[i] = f.active && (tie_wet ? f.aq[i] >= iso : f.aq[i] > iso);
@@ -115,8 +113,6 @@ __device__ __forceinline__ Part face_part(const FaceLane &f, double iso, bool ti
             r.cseg = r.cseg + cr;
             r.oacc = r.oacc + (0.5 * l) * (s0 + s1);
             r.oL += l;
-            r.osum = r.osum + s0;
-            r.nseg += 1.0;
         }
         lastexit = sel3(exits[i], cut[i], lastexit);
     }
@@ -338,12 +334,14 @@ __device__ __forceinline__ double tri_sweep(double d0, double d1, double d2, dou
 }
 
 // Six times the wet sub-volume of the cell (all lanes of the group take part and get the result).
+// The isoface's fan apex is the perimeter centroid of its edges; when they all have zero length
+// every s0 x s1 is exactly zero, so the apex does not enter and is left at the origin.
 __device__ __forceinline__ double cell_vsub6(const FaceLane &f, double iso, bool tie_wet, D3 *o_out, D3 *cseg_out) {
     const Part p = face_part(f, iso, tie_wet);
     const double v6 = grp_sum(p.v6);
-    const D3 cseg = grp_sum3(p.cseg), oacc = grp_sum3(p.oacc), osum = grp_sum3(p.osum);
-    const double oL = grp_sum(p.oL), nseg = grp_sum(p.nseg);
-    const D3 o = oL > 0.0 ? (1.0 / oL) * oacc : (nseg > 0.0 ? (1.0 / nseg) * osum : D3{0, 0, 0});
+    const D3 cseg = grp_sum3(p.cseg), oacc = grp_sum3(p.oacc);
+    const double oL = grp_sum(p.oL);
+    const D3 o = oL > 0.0 ? (1.0 / oL) * oacc : D3{0, 0, 0};
     if (o_out) *o_out = o;
     if (cseg_out) *cseg_out = cseg;
     return v6 + dot(o, cseg);
@@ -422,6 +420,8 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
     int fv[4];
     const int fwd = lane_face_loop(lv, fv);
     int rounds_max = 0, flat = 0, nonconv = 0;
+    // groups take list entries round-robin over the XCDs: interface cells are clustered, and
+    // contiguous ranges per XCD would leave the XCDs with unequal work
     for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; idx < n; idx += ngrp) {
         const int c = A.list[idx];
         const double aP = A.alpha[c];
@@ -722,7 +722,7 @@ struct UpdArgs {
 template <int W>
 __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     const int n = A.m.n_cells;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     bool offend = false;
     if (c < n) {
         int32_t v[W], o[W];
