@@ -151,8 +151,9 @@ iso_status iso_advect_step_traced(iso_plan *plan, const double *alpha, const dou
  * The derivative follows the step exactly: the interface cells' isovalue moves with the volume
  * constraint of Section 3.2 (implicit function; at a jump of the sub-volume it is the vertex
  * value), the swept integrals (Eqs. tv .. intaplus) are differentiated through the isoface, and
- * the bounding sweeps are replayed and reversed; values that chopping or clamping fixes have zero
- * derivative, and a face with phi = 0 passes no derivative to phi.  Branches (interface cells,
+ * the bounding sweeps are replayed and reversed; values that chopping or clamping moves by more
+ * than 1e-14 have zero derivative (a smaller move only removes round-off and passes the
+ * derivative), and a face with phi = 0 passes no derivative to phi.  Branches (interface cells,
  * upwind sides, wet vertices, bounding activity) are those of the given state.
  * fwd (nullable, DEVICE pointers): the intermediates of this same step from
  * iso_advect_step_traced with the same plan; vert_alpha, kind, iso, dV and alpha_raw are used.

@@ -1234,9 +1234,17 @@ static cplx cs_face_integral(const or_mesh *m, int f, int c, const cplx *xS, con
     return acc / Af;
 }
 
+/* A chop or clip that moves a value by at most OR_ROUND only removes round-off (whether such a
+ * value lies just inside or just outside a bound is decided by rounding order), so its tangent is
+ * kept; a larger one makes the value a constant. */
+#define OR_ROUND 1e-14
+static cplx cs_to_bound(cplx x, double b) {
+    return fabs(creal(x) - b) <= OR_ROUND ? b + cimag(x) * _Complex_I : b;
+}
+
 static cplx cs_chop(cplx x, double tol) {
-    if (creal(x) < 0.0 && creal(x) >= -tol) return 0.0;
-    if (creal(x) > 1.0 && creal(x) <= 1.0 + tol) return 1.0;
+    if (creal(x) < 0.0 && creal(x) >= -tol) return cs_to_bound(x, 0.0);
+    if (creal(x) > 1.0 && creal(x) <= 1.0 + tol) return cs_to_bound(x, 1.0);
     return x;
 }
 
@@ -1338,8 +1346,8 @@ static void cs_step(const or_mesh *m, const or_opts *opt, const cplx *alpha, con
     }
     if (opt->clip)
         for (int c = 0; c < nc; ++c) {
-            if (creal(cur[c]) < 0.0) cur[c] = 0.0;
-            if (creal(cur[c]) > 1.0) cur[c] = 1.0;
+            if (creal(cur[c]) < 0.0) cur[c] = cs_to_bound(cur[c], 0.0);
+            if (creal(cur[c]) > 1.0) cur[c] = cs_to_bound(cur[c], 1.0);
         }
     for (int c = 0; c < nc; ++c) alpha_new[c] = cur[c];
     free(a_pts); free(a_re); free(kind); free(rec); free(dV); free(cur); free(delta); free(dVc);

@@ -266,6 +266,11 @@ __device__ __forceinline__ Dl dtri_sweep(Dl d0, Dl d1, Dl d2, Dl un, double dt) 
 }
 
 // ------------------------------------------------------------------------------------ kernels
+// A chop or clamp that moves a value by at most this much only removes round-off (which side of a
+// bound such a value lands on is decided by rounding order): its derivative passes through.  A
+// larger one makes the value a constant.
+constexpr double kRound = 1e-14;
+
 struct AdjArgs {
     DevMesh m;
     const double *alpha, *phi, *U;
@@ -418,7 +423,7 @@ __global__ void __launch_bounds__(1024) k_adj_bound(AdjArgs A) {
                 else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
                 if (last) x = fmin(fmax(x, 0.0), 1.0);
             }
-            if (x != x0) w.cflag[Q] |= 1 << s;
+            if (fabs(x - x0) > kRound) w.cflag[Q] |= 1 << s;
             w.x[Q] = x;
             w.cmark[Q] = 0;
             if (x > 1.0 + A.tol || x < -A.tol) {
@@ -443,7 +448,7 @@ __global__ void __launch_bounds__(1024) k_adj_bound(AdjArgs A) {
         for (int i = tid; i < nL[0]; i += nt) {
             const int32_t P = w.list[i];
             const double x = w.x[P];
-            if (x < 0.0 || x > 1.0) w.cflag[P] |= 1;
+            if (x < -kRound || x > 1.0 + kRound) w.cflag[P] |= 1;
         }
         __syncthreads();
         for (int i = tid; i < nL[0]; i += nt) {
@@ -554,7 +559,7 @@ __global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
     const DevMesh &m = A.m;
     auto pre = [&](int q) {  // adjoint of the update before its round-off chop
         const double x = A.raw[q];
-        const bool chopped = A.clip && ((x < 0.0 && x >= -A.tol) || (x > 1.0 && x <= 1.0 + A.tol));
+        const bool chopped = A.clip && ((x < -kRound && x >= -A.tol) || (x > 1.0 + kRound && x <= 1.0 + A.tol));
         return chopped ? 0.0 : A.w.xbar[q];
     };
     const double bc = pre(c);

@@ -32,12 +32,13 @@ def _state_after(O, w, steps):
     return a
 
 
-@pytest.mark.parametrize("name", ["airy_16x8", "cosine_16x8", "violent_6x5x4"])
+@pytest.mark.parametrize("name", ["airy_16x8", "cosine_16x8", "violent_6x5x4", "perturbed_5x4x4"])
 def test_one_step_adjoint_matches_oracle_gradient(oracle_lib, name):
     O = oracle_lib
     w = {"airy_16x8": lambda: W.airy_slab(16, 8, 8, 0.09, 0.5, 4, name),
          "cosine_16x8": lambda: W.cosine_uniform(nx=16, ny=8, steps=4, co=0.5),
-         "violent_6x5x4": lambda: W.violent_3d(nx=6, ny=5, nz=4, steps=4)}[name]()
+         "violent_6x5x4": lambda: W.violent_3d(nx=6, ny=5, nz=4, steps=4),
+         "perturbed_5x4x4": lambda: W.perturbed_box(nx=5, ny=4, nz=4, steps=4)}[name]()
     say(f"[gpu] one-step adjoint vs oracle gradient: {name} cells={w.mesh.n_cells}")
     a = _state_after(O, w, 2)  # a state with some history (bounding active in places)
     phi, U = w.phi_U(2)

@@ -28,6 +28,8 @@ def small_cases():
         "airy_128x64": W.airy_slab(128, 64, 32, 0.07, 0.5, 30, "airy_128x64"),
         "violent_32x16x16": W.violent_3d(nx=32, ny=16, nz=16, steps=10),
         "band_periodic": band,
+        # non-planar faces (randomly displaced interior points), in/out patches with inflow alpha
+        "perturbed_10x7x6": W.perturbed_box(),
     }
 
 

@@ -127,3 +127,22 @@ def test_gradient_is_transpose_of_tangent(O):
         _, t = om.step_tlm(w.alpha0, phi, U, w.dt, da, dp)
         lhs, rhs = ga @ da + gp @ dp, abar @ t
         assert abs(lhs - rhs) <= 1e-11 * (np.abs(ga * da).sum() + np.abs(gp * dp).sum() + 1e-300)
+
+
+def test_tangent_on_nonplanar_faces_matches_central_differences(O):
+    """Randomly displaced interior points (non-planar faces, in/out patches): alpha directions in
+    cells strictly inside (0, 1), central differences of the real oracle step."""
+    w = W.perturbed_box(nx=8, ny=7, nz=6, steps=2)
+    om = O.OracleMesh(w.mesh)
+    phi, U = w.phi_U(0)
+    rng = np.random.default_rng(21)
+    inner = (w.alpha0 > 1e-4) & (w.alpha0 < 1 - 1e-4)
+    for trial in range(3):
+        da = rng.standard_normal(w.mesh.n_cells) * inner
+        _, t = om.step_tlm(w.alpha0, phi, U, w.dt, da, None)
+        eps = 1e-7
+        ap, _ = om.step(w.alpha0 + eps * da, phi, U, w.dt)
+        am, _ = om.step(w.alpha0 - eps * da, phi, U, w.dt)
+        fd = (ap - am) / (2 * eps)
+        assert np.abs(t).max() > 0
+        assert np.abs(fd - t).max() <= 1e-6 * np.abs(t).max(), (trial, np.abs(fd - t).max(), np.abs(t).max())

@@ -7,7 +7,7 @@ from .mesh import (PATCH_CYCLIC, PATCH_EMPTY, PATCH_INOUT, PATCH_WALL, Mesh, Pat
                    hex_block)
 from .fields import (AiryWave, UniformPlusTaylorGreen, alpha_column_plus_wave_3d, alpha_cosine_2d,
                      cell_fraction_below_cosine, courant_dt, fluxes_from_edge_integral)
-from .configs import (Workload, adjoint_case, airy_1024x256, airy_ensemble, airy_slab, cosine_uniform,
+from .configs import (Workload, adjoint_case, airy_1024x256, airy_ensemble, airy_slab, cosine_uniform, perturbed_box,
                       slab_mesh, violent_3d)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

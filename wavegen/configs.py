@@ -18,7 +18,7 @@ import numpy as np
 
 from .fields import AiryWave, UniformPlusTaylorGreen, alpha_column_plus_wave_3d, alpha_cosine_2d, \
     courant_dt, fluxes_from_edge_integral
-from .mesh import PATCH_EMPTY, PATCH_WALL, Mesh, graded_halves, hex_block
+from .mesh import PATCH_EMPTY, PATCH_INOUT, PATCH_WALL, Mesh, graded_halves, hex_block
 
 
 @dataclass
@@ -131,3 +131,30 @@ def adjoint_case(seed=2, steps=50):
 def tiny_slab(nx=4, ny=4, steps=3):
     """Small cosine case for quick parity checks."""
     return cosine_uniform(nx=nx, ny=ny, steps=steps)
+
+
+def perturbed_box(nx=10, ny=7, nz=6, amp=0.15, seed=3, steps=8, co=0.4) -> Workload:
+    """A hexahedral box [0,1]^3 whose interior points are displaced at random by up to ``amp``
+    times the spacing (seeded), so that its faces are not planar; in/out patches at x = 0
+    (inflow with alpha = 1) and x = 1, walls elsewhere.  alpha, fluxes and velocities are those of
+    the undisplaced box (a column plus a wave, a uniform stream plus a Taylor-Green vortex): they
+    are inputs of the step here, not a flow of the displaced geometry."""
+    rng = np.random.default_rng(seed)
+    xs = np.linspace(0.0, 1.0, nx + 1)
+    ys = np.linspace(0.0, 1.0, ny + 1)
+    zs = np.linspace(0.0, 1.0, nz + 1)
+    box = hex_block(xs, ys, zs, kinds={"xmin": PATCH_INOUT, "xmax": PATCH_INOUT}, periodic_x=False,
+                    alpha_in={"xmin": 1.0})
+    alpha0 = alpha_column_plus_wave_3d(box, 0.3, 0.6, 0.45, 0.08, 2.0 * np.pi)
+    flow = UniformPlusTaylorGreen(0.5, 0.8, 0.5)
+    phi = flow.fluxes(box)
+    U = flow.cell_velocity(box)
+    P = box.points.copy()
+    h = np.array([xs[1] - xs[0], ys[1] - ys[0], zs[1] - zs[0]])
+    inner = np.all((P > 1e-12) & (P < 1.0 - 1e-12), axis=1)
+    P[inner] += amp * h * rng.uniform(-1.0, 1.0, size=(int(inner.sum()), 3))
+    mesh = Mesh(P, box.face_ptr, box.face_pts, box.owner, box.neighbour, box.n_cells, box.patches, box.shape,
+                box.xs, box.ys, box.zs)
+    dt = courant_dt(box, phi, co)
+    return Workload(f"perturbed_box_{nx}x{ny}x{nz}", mesh, alpha0, dt, steps, lambda n: (phi, U), steady=True,
+                    meta={"amp": amp})
