@@ -45,8 +45,6 @@ __device__ __forceinline__ Dl dsqrt(Dl a) {
     return {r, r > 0.0 ? 0.5 * a.d / r : 0.0};
 }
 __device__ __forceinline__ Dl dsel(bool c, Dl a, Dl b) { return {c ? a.v : b.v, c ? a.d : b.d}; }
-__device__ __forceinline__ Dl dmin(Dl a, Dl b) { return a.v <= b.v ? a : b; }
-__device__ __forceinline__ Dl dmax(Dl a, Dl b) { return a.v >= b.v ? a : b; }
 __device__ __forceinline__ Dl dc(double x) { return {x, 0.0}; }
 
 struct DV3 {
@@ -226,8 +224,19 @@ __device__ __forceinline__ Dl dtri_piece(int br, Dl z, Dl e1, Dl e2, Dl e3, Dl r
 }
 
 __device__ __forceinline__ Dl dtri_sweep(Dl d0, Dl d1, Dl d2, Dl un, double dt) {
-    const Dl e1 = dmin(d0, dmin(d1, d2)), e3 = dmax(d0, dmax(d1, d2));
-    const Dl e2 = dmax(dmin(d0, d1), dmin(dmax(d0, d1), d2));
+    // sorted by compare-and-swap: a permutation, so at a tie each distance keeps its own rate
+    // (a min and a max that both return the same member would count one vertex twice)
+    Dl e1 = d0, e2 = d1, e3 = d2;
+    auto order = [](Dl &x, Dl &y) {
+        if (y.v < x.v) {
+            const Dl t = x;
+            x = y;
+            y = t;
+        }
+    };
+    order(e1, e2);
+    order(e2, e3);
+    order(e1, e2);
     const Dl r31 = e3.v > e1.v ? dinv(e3 - e1) : dc(0.0);
     const Dl r21 = e2.v > e1.v ? dinv(e2 - e1) : dc(0.0);
     const Dl r32 = e3.v > e2.v ? dinv(e3 - e2) : dc(0.0);

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import wavegen as W
-from tests.gpuutil import gpu_plan, say, to_dev
+from tests.gpuutil import gpu_plan, gpu_traced_step, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -52,6 +52,36 @@ def test_one_step_adjoint_matches_oracle_gradient(oracle_lib, name):
     scale_p = max(np.abs(op).max(), 1e-300)
     assert np.abs(ga - oa).max() <= 1e-9 * scale_a, (np.argmax(np.abs(ga - oa)), np.abs(ga - oa).max(), scale_a)
     assert np.abs(gp - op).max() <= 1e-9 * scale_p, (np.argmax(np.abs(gp - op)), np.abs(gp - op).max(), scale_p)
+
+
+def test_adjoint_keeps_each_rate_at_exact_ties(oracle_lib):
+    """On a mesh extruded along z the two vertices of every z-edge carry the same value, so the
+    distances of a face's vertices from the isoface come in pairs that tie exactly or differ by
+    round-off, depending on the last bit of the isovalue.  Each vertex's rate must survive either
+    way: the gradient with every traced isovalue moved one ulp up, or one ulp down, is the oracle's."""
+    import torch
+    O = oracle_lib
+    w = W.violent_3d(nx=6, ny=5, nz=4, steps=4)
+    say(f"[gpu] adjoint with the isovalues moved by one ulp: {w.name} cells={w.mesh.n_cells}")
+    a = _state_after(O, w, 2)
+    phi, U = w.phi_U(2)
+    abar_new = np.random.default_rng(3).standard_normal(w.mesh.n_cells)
+    gm, plan = gpu_plan(w.mesh)
+    _, _, tr = gpu_traced_step(plan, gm, a, phi, U, w.dt)
+    oa, op = O.OracleMesh(w.mesh).gradient(a, phi, U, w.dt, abar_new)
+    rec = tr["kind"] == 1
+    assert rec.sum() > 10
+    for towards in (np.inf, -np.inf):
+        iso = tr["iso"].copy()
+        iso[rec] = np.nextafter(iso[rec], towards)
+        dev_tr = {"vert_alpha": to_dev(tr["vert_alpha"].reshape(-1)), "iso": to_dev(iso), "dV": to_dev(tr["dV"]),
+                  "alpha_raw": to_dev(tr["alpha_raw"]),
+                  "kind": torch.tensor(tr["kind"], dtype=torch.int32, device="cuda:0")}
+        ab, pb = plan.adjoint(to_dev(a), to_dev(phi), to_dev(U), w.dt, to_dev(abar_new), trace=dev_tr)
+        torch.cuda.synchronize()
+        ab, pb = ab.cpu().numpy(), pb.cpu().numpy()
+        assert np.abs(ab - oa).max() <= 1e-9 * np.abs(oa).max(), (towards, np.argmax(np.abs(ab - oa)))
+        assert np.abs(pb - op).max() <= 1e-9 * np.abs(op).max(), (towards, np.argmax(np.abs(pb - op)))
 
 
 def test_adjoint_dot_product_against_oracle_tangent(oracle_lib):
