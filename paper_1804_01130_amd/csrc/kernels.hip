@@ -434,7 +434,20 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
         {
             const int k = m.cpt[8 * (size_t)c + lv];
             const int e0 = m.st_ptr[k], e1 = m.st_ptr[k + 1];
-            for (int e = e0; e < e1; ++e) av += m.st_w[e] * A.alpha[m.st_cell[e]];
+            // stencil entries eight at a time: the loads of a chunk are all in flight together
+            for (int e = e0; e < e1; e += 8) {
+                int32_t sc[8];
+                double sw[8], sa[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    sc[j] = e + j < e1 ? m.st_cell[e + j] : -1;
+                    sw[j] = e + j < e1 ? m.st_w[e + j] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) sa[j] = sc[j] >= 0 ? A.alpha[sc[j]] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) av += sw[j] * sa[j];
+            }
         }
         if (A.tr.vert_alpha) A.tr.vert_alpha[8 * (size_t)c + lv] = av;
         const D3 xm = 0.125 * grp_sum3(xv);
@@ -533,17 +546,37 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 if (gleft > 0.0) {
                     iso = hi;  // the sub-volume jumps across alpha_P at this vertex value
                 } else {
-                    // Newton on G, safeguarded by the bracket [ulo, uhi] (G(ulo) > 0 >= G(uhi))
-                    double ua = ulo, ub = uhi;
-                    double u = ulo + (uhi - ulo) * (fl / (fl - gleft / V6));
+                    // Newton on G, safeguarded by the bracket [ua, ub] (G(ua) > 0 >= G(ub)).  Where the
+                    // root sits next to a bracket end at which the isoface shrinks to a vertex or an
+                    // edge, G behaves like a power of the distance to that end and G' vanishes there:
+                    // an unusable Newton step is replaced by the root of a cubic power law anchored at
+                    // the end with the smaller residual (bisection if that leaves the bracket).
+                    double ua = ulo, ub = uhi, ga = fl * V6, gb = gleft;
+                    double u = ulo + (uhi - ulo) * (ga / (ga - gb));  // secant start
+                    double up = uhi, dGp = dG;  // previous point, for the curvature estimate
                     bool conv = false;
                     for (; rounds < A.max_rounds; ++rounds) {
                         const double g = G(u, dG);
                         if (g == 0.0) { conv = true; ++rounds; break; }
-                        if (g > 0.0) ua = u; else ub = u;
-                        double nu = dG < 0.0 ? u - g / dG : 0.5 * (ua + ub);
-                        if (!(nu > ua && nu < ub)) nu = 0.5 * (ua + ub);
-                        const bool done = fabs(nu - u) <= 2.0 * __DBL_EPSILON__ * fmax(fabs(xr + nu), 1e-300);
+                        if (g > 0.0) { ua = u; ga = g; } else { ub = u; gb = g; }
+                        double nu = dG < 0.0 ? u - g / dG : ua;
+                        const bool newton = nu > ua && nu < ub;
+                        if (!newton) {
+                            const bool left = ga <= -gb;
+                            const double w = (ub - ua) * cbrt((left ? ga : -gb) / (ga - gb));
+                            nu = left ? ua + w : ub - w;
+                            if (!(nu > ua && nu < ub)) nu = 0.5 * (ua + ub);
+                        }
+                        // converged when the step is at round-off of the isovalue, or when a short Newton
+                        // step leaves an error |G''| s^2 / (2 |G'|), with G'' from the last two slopes,
+                        // below an eighth of that
+                        const double tolu = 2.0 * __DBL_EPSILON__ * fmax(fabs(xr + nu), 1e-300);
+                        const double s = nu - u;
+                        bool done = fabs(s) <= tolu;
+                        if (newton && !done && fabs(s) <= 1e-3 * (uhi - ulo))
+                            done = fabs(dG - dGp) * s * s <= 0.25 * tolu * fabs(dG) * fabs(u - up);
+                        up = u;
+                        dGp = dG;
                         u = nu;
                         if (done || !(ub - ua > 2.0 * __DBL_EPSILON__ * fmax(fabs(xr + ua), fabs(xr + ub)))) {
                             conv = true;
@@ -728,11 +761,11 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
         int32_t v[W], o[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            v[k] = A.m.slot_face[(size_t)k * n + c];
-            o[k] = A.m.slot_nbr[(size_t)k * n + c];
+            v[k] = __builtin_nontemporal_load(A.m.slot_face + (size_t)k * n + c);
+            o[k] = __builtin_nontemporal_load(A.m.slot_nbr + (size_t)k * n + c);
         }
         const double aP = A.alpha[c];
-        const double V = A.m.vol[c];
+        const double V = __builtin_nontemporal_load(A.m.vol + c);
         double ph[W], ao[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -764,7 +797,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
         }
         offend = x > 1.0 + A.tol || x < -A.tol;
-        A.alpha_new[c] = x;
+        __builtin_nontemporal_store(x, A.alpha_new + c);
     }
     const uint64_t mask = __ballot(offend);
     if (mask == 0) return;
