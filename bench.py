@@ -8,8 +8,9 @@ plus a 3D wave, advected by a uniform stream plus a Taylor-Green vortex at Coura
 Prints ONE JSON line.  Fields beyond the basic contract:
   roofline      dominant kernel: algorithmic bytes (or flops) per launch / mean launch time,
                 measured with HIP events recorded around each kernel on the step's stream
-                during the timed steps; traffic from committed rocprofv3 counters when they
-                belong to the current kernel source, else null
+                over a second pass of the same K steps (the throughput pass has no event
+                between kernels: each event adds a dispatch gap); traffic from committed
+                rocprofv3 counters when they belong to the current kernel source, else null
   cpu_baseline  the CPU oracle (single thread) on a bounded sample of the same workload
   step_roofline the whole step's algorithmic bytes per cell-step x cell-steps/s / 8 TB/s
 """
@@ -431,8 +432,9 @@ def main():
         a, b = b, a
     _, st = plan.step(a, phis[sel(args.warmup)], Us[sel(args.warmup)], w.dt, out=b, stats=True)
     n_surface = st["n_surface"]
-    plan.set_timing(args.steps)
+    a_start = a.clone()
     torch.cuda.synchronize()
+    # throughput: the K steps back to back, with no event between the kernels of a step
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for n in range(args.warmup, n_steps_total):
@@ -441,7 +443,16 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    # per-kernel durations: the same K steps again from the same state, with HIP events on the
+    # plan's stream around each kernel group (each event adds a dispatch gap, hence the second pass)
+    a.copy_(a_start)
+    plan.set_timing(args.steps)
+    for n in range(args.warmup, n_steps_total):
+        plan.step(a, phis[sel(n)], Us[sel(n)], w.dt, out=b)
+        a, b = b, a
+    torch.cuda.synchronize()
     kms, nrec = plan.timing()
+    del a_start
     ms_per_step = ms / args.steps
     cells = w.mesh.n_cells
     value = cells * args.steps / (ms * 1e-3)

@@ -55,10 +55,11 @@ def test_one_step_adjoint_matches_oracle_gradient(oracle_lib, name):
 
 
 def test_adjoint_keeps_each_rate_at_exact_ties(oracle_lib):
-    """On a mesh extruded along z the two vertices of every z-edge carry the same value, so the
-    distances of a face's vertices from the isoface come in pairs that tie exactly or differ by
-    round-off, depending on the last bit of the isovalue.  Each vertex's rate must survive either
-    way: the gradient with every traced isovalue moved one ulp up, or one ulp down, is the oracle's."""
+    """The small violent case is mirror-symmetric about y = 1/2: in the middle row of cells both
+    ends of every y-edge carry the same value, so the distances of a face's vertices from the
+    isoface come in pairs that tie exactly or differ by round-off, depending on the last bit of the
+    isovalue.  Each vertex's rate must survive either way: the gradient with every traced isovalue
+    moved one ulp up, or one ulp down, is the oracle's."""
     import torch
     O = oracle_lib
     w = W.violent_3d(nx=6, ny=5, nz=4, steps=4)
