@@ -139,19 +139,22 @@ __device__ __forceinline__ D3 grp_sum3(D3 v) { return D3{grp_sum(v.x), grp_sum(v
 __device__ __forceinline__ double grp_get(double v, int src) { return __shfl(v, src, 8); }
 
 // Append `count` entries per lane to a device-wide list: one atomic per wave.  Returns the index of
-// this lane's first entry.  Every lane of the wave must call it (count may be 0).
+// this lane's first entry.  Every active lane of the wave must call it (count may be 0).
 __device__ __forceinline__ int wave_append(int count, int32_t *counter) {
+    // the active lanes are a prefix of the wave (a whole wave, or the last wave of a work-group
+    // whose size is not a multiple of 64): the highest of them holds the total and takes the slots
     const int lane = __lane_id();
+    const int top = 63 - __clzll((unsigned long long)__ballot(1));
     int incl = count;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const int y = __shfl_up(incl, o, 64);
         if (lane >= o) incl += y;
     }
-    const int total = __shfl(incl, 63, 64);
+    const int total = __shfl(incl, top, 64);
     int base = 0;
-    if (lane == 63 && total > 0) base = atomicAdd(counter, total);
-    base = __shfl(base, 63, 64);
+    if (lane == top && total > 0) base = atomicAdd(counter, total);
+    base = __shfl(base, top, 64);
     return base + incl - count;
 }
 

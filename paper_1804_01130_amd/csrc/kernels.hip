@@ -748,25 +748,42 @@ struct UpdArgs {
     int32_t *olist;
     int32_t *counters;
     double *trace_dV, *trace_raw;
+    int n_iter;  // redistribution sweeps; with one or more the update runs the first sweep's phase A
+    DevWork w;
 };
 
+// Bounding counters of sweep `it` live in one of three rotating slots: a slot is read by the two
+// kernels of its sweep and by phase A of the next sweep, and cleared by phase B of the sweep after.
+__device__ __forceinline__ int32_t *bound_slot(int32_t *counters, int it) { return counters + kCntBound + 3 * (it % 3); }
+enum : int { kSlotTouched = 0, kSlotNext = 1, kSlotDelta = 2 };
+
 // W flux slots per cell, all loads of one kind issued together (independent gathers in flight).
-// Any block size up to 1024 (the block_cells option) is valid.
+// Any block size up to 1024 (the block_cells option) is valid.  A cell left out of bounds also
+// runs phase A of the first redistribution sweep (k_bound_a) here: no face is marked yet, so the
+// current dV of each of its outflow faces is the one just computed.
 template <int W>
 __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     const int n = A.m.n_cells;
     const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     bool offend = false;
+    int32_t v[W], o[W];
+    double ph[W], dvo[W];  // face fluxes; dV of the outflow faces (0 elsewhere)
+    double x = 0.0, V = 0.0, dtc = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        v[k] = kEmpty;
+        o[k] = -1;
+        ph[k] = dvo[k] = 0.0;
+    }
     if (c < n) {
-        int32_t v[W], o[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             v[k] = __builtin_nontemporal_load(A.m.slot_face + (size_t)k * n + c);
             o[k] = __builtin_nontemporal_load(A.m.slot_nbr + (size_t)k * n + c);
         }
         const double aP = A.alpha[c];
-        const double V = __builtin_nontemporal_load(A.m.vol + c);
-        double ph[W], ao[W];
+        V = __builtin_nontemporal_load(A.m.vol + c);
+        double ao[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const int32_t fid = v[k] >= 0 ? v[k] : ~v[k];
@@ -774,7 +791,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             ao[k] = o[k] >= 0 ? A.alpha[o[k]] : (v[k] != kEmpty ? A.m.patch_alpha[-1 - o[k]] : 0.0);
         }
         const bool sP = interface_cell(aP, A.eps);
-        const double dtc = cell_dt(A.m, A.dt_dom, A.dt, c);
+        dtc = cell_dt(A.m, A.dt_dom, A.dt, c);
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -784,13 +801,14 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             double dv = 0.0;
             if (out > 0.0) {
                 dv = sP ? A.dvs[fid] : aP * ph[k] * dtc;
+                dvo[k] = dv;
             } else if (out < 0.0) {
                 dv = (o[k] >= 0 && interface_cell(ao[k], A.eps)) ? A.dvs[fid] : ao[k] * ph[k] * dtc;
             }
             sum += v[k] >= 0 ? dv : -dv;
             if (A.trace_dV && v[k] >= 0) A.trace_dV[fid] = dv;
         }
-        double x = aP - sum / V;
+        x = aP - sum / V;
         if (A.trace_raw) A.trace_raw[c] = x;
         if (A.clip) {
             if (x < 0.0 && x >= -A.tol) x = 0.0;
@@ -809,6 +827,64 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     if (offend)
         A.olist[base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] = c;
+    if (A.n_iter < 1) return;
+    // phase A of sweep 0 (as in k_bound_a, with every face unmarked)
+    const int nf = A.m.n_faces;
+    int32_t *slot = bound_slot(A.counters, 0);
+    int ndl = 0, ntl = 0;
+    int32_t fsel[W], tsel[W + 1];
+#pragma unroll
+    for (int k = 0; k <= W; ++k) tsel[k] = -1;
+#pragma unroll
+    for (int k = 0; k < W; ++k) fsel[k] = -1;
+    if (offend) {
+        const bool over = x > 1.0 + A.tol;
+        double cap[W];
+        double sumcap = 0.0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            cap[k] = 0.0;
+            if (v[k] == kEmpty) continue;
+            const double outphi = v[k] >= 0 ? ph[k] : -ph[k];
+            if (!(outphi > 0.0)) continue;
+            const double outv = v[k] >= 0 ? dvo[k] : -dvo[k];
+            cap[k] = over ? outphi * dtc - outv : outv;
+            if (cap[k] > 0.0) sumcap += cap[k];
+        }
+        if (atomicExch(&A.w.cmark[c], 1) == 0) tsel[W] = c;
+        const double need = over ? (x - 1.0) * V : -x * V;
+        const double r = sumcap > 0.0 ? fmin(need / sumcap, 1.0) : 0.0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
+            const double d = cap[k] * r;
+            const double dd = over ? (v[k] >= 0 ? d : -d) : (v[k] >= 0 ? -d : d);
+            const int32_t f = v[k] >= 0 ? v[k] : ~v[k];
+            A.w.delta[f] = dd;
+            A.w.dvcur[f] = dvo[k] + dd;
+            A.w.fmark[f] = 1;
+            fsel[k] = f;
+            if (o[k] >= 0 && atomicExch(&A.w.cmark[o[k]], 1) == 0) tsel[k] = o[k];
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) ndl += fsel[k] >= 0 ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k <= W; ++k) ntl += tsel[k] >= 0 ? 1 : 0;
+    }
+    // every marked face is new at sweep 0: it enters both the sweep's correction list and flist
+    int bd = wave_append(ndl, &slot[kSlotDelta]);
+    int bf = wave_append(ndl, &A.counters[kCntFaces]);
+    int bt = wave_append(ntl, &slot[kSlotTouched]);
+    int32_t *dlist = A.w.flist + (size_t)nf;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        if (fsel[k] >= 0) {
+            dlist[bd++] = fsel[k];
+            A.w.flist[bf++] = fsel[k];
+        }
+#pragma unroll
+    for (int k = 0; k <= W; ++k)
+        if (tsel[k] >= 0) A.w.tlist[bt++] = tsel[k];
 }
 
 struct BoundArgs {
@@ -843,17 +919,14 @@ __device__ __forceinline__ void load_slots(const BoundArgs &A, int32_t c, Slots<
     }
 }
 
-// Bounding counters of sweep `it` live in one of three rotating slots: a slot is read by the two
-// kernels of its sweep and by phase A of the next sweep, and cleared by phase B of the sweep after.
-__device__ __forceinline__ int32_t *bound_slot(int32_t *counters, int it) { return counters + kCntBound + 3 * (it % 3); }
-enum : int { kSlotTouched = 0, kSlotNext = 1, kSlotDelta = 2 };
 
-// Redistribution sweeps (Jacobi), two grid-wide kernels per sweep.  (A) every listed cell computes
+// Redistribution sweeps (Jacobi), two grid-wide phases per sweep.  (A) every listed cell computes
 // the change of the heavy-fluid outflow of each of its outflow faces (each face has one upwind
 // cell, so it alone writes that face's correction and its running dV); (B) every touched cell
 // applies the corrections of its faces in ascending face order and is listed for the next sweep
 // if still out of bounds.  Corrections alternate between two buffers; phase A of a sweep clears
-// the buffer read by the previous sweep.  List order never affects a result.
+// the buffer read by the previous sweep.  List order never affects a result.  Phase A of sweep 0
+// runs inside the update kernel; k_bound_a serves the sweeps from 1 on.
 template <int W>
 __global__ void __launch_bounds__(256) k_bound_a(BoundArgs A, int it) {
     const int n = A.m.n_cells, nf = A.m.n_faces;
@@ -863,10 +936,10 @@ __global__ void __launch_bounds__(256) k_bound_a(BoundArgs A, int it) {
     const int32_t *cur = A.w.olist + (par ? n : 0);
     double *delta = A.w.delta + (size_t)par * nf;
     int32_t *dlist = A.w.flist + (size_t)(1 + par) * nf;
-    const int n_old = it == 0 ? counters[kCntOff] : bound_slot(counters, it - 1)[kSlotNext];
+    const int n_old = bound_slot(counters, it - 1)[kSlotNext];
     const int stride = gridDim.x * blockDim.x;
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (it > 0) {  // the other buffer was read by the previous sweep: clear it
+    {  // the other buffer was read by the previous sweep: clear it
         const int n_stale = bound_slot(counters, it - 1)[kSlotDelta];
         double *stale = A.w.delta + (size_t)(par ^ 1) * nf;
         const int32_t *slist = A.w.flist + (size_t)(2 - par) * nf;
@@ -1057,10 +1130,10 @@ template <int W>
 void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, const LaunchCfg &cfg, hipStream_t s,
                  hipEvent_t *ev) {
     const int gc = (m.n_cells + cfg.block_cells - 1) / cfg.block_cells;
-    hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(cfg.block_cells), 0, s, ua);
+    hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(cfg.block_cells), 0, s, ua);  // and sweep 0's phase A
     if (ev) (void)hipEventRecord(ev[3], s);
     for (int it = 0; it < ba.n_iter; ++it) {
-        hipLaunchKernelGGL(k_bound_a<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
+        if (it > 0) hipLaunchKernelGGL(k_bound_a<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
         hipLaunchKernelGGL(k_bound_b<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it, it == ba.n_iter - 1 ? 1 : 0);
     }
     hipLaunchKernelGGL(k_bound_end, dim3(1), dim3(1024), 0, s, ba);
@@ -1115,7 +1188,7 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     }
     if (ev) (void)hipEventRecord(ev[2], s);
     UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist,
-               w.counters, tr.dV, tr.alpha_raw};
+               w.counters, tr.dV, tr.alpha_raw, p.n_bound_iter, w};
     BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
                  a.alpha_new, w};
     switch (m.W) {

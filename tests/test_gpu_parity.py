@@ -115,7 +115,8 @@ def test_determinism_across_launch_shapes():
     w = CASES["violent_32x16x16"]
     say("[gpu] determinism across block sizes")
     outs = []
-    for bc, sw in ((256, 2), (64, 3), (128, 4), (32, 1)):
+    # 32 and 100 threads per work-group leave the update kernel's waves partly filled
+    for bc, sw in ((256, 2), (64, 3), (128, 4), (32, 1), (100, 2)):
         gm, plan = gpu_plan(w.mesh, block_cells=bc, surface_waves=sw)
         outs.append(gpu_trajectory(plan, w, 5))
     for o in outs[1:]:
