@@ -76,7 +76,7 @@ typedef struct {
     int32_t check_inputs;   /* validate inputs on the host before each step (syncs; default 0) */
     int32_t block_cells;    /* threads per block of the per-cell kernels, up to 1024 (0 = 256) */
     int32_t surface_blocks; /* work-groups of the interface-cell kernel, which loops over the list
-                               (0 = up to 1024, from the list capacity); at most 65535 */
+                               (0 = up to 2048, from the list capacity); at most 65535 */
     int32_t max_surface;    /* capacity of the interface-cell list (0 = n_cells) */
     int32_t surface_waves;  /* register budget of the interface-cell kernel in waves per SIMD:
                                1, 2, 3 or 4 (0 = 2) */

@@ -35,70 +35,29 @@ struct Part {
 };
 
 // Divergence-theorem share of face k for isovalue iso (vertex wet iff a > iso; a >= iso with
-// tie_wet, the limit from below).  The wet part of the face is its loop emitting wet vertices and
-// cut points; fanned about any apex q its share is q . sum(p_i x p_i+1), linear in q.  Planar
-// faces use a face vertex (the value does not depend on the apex), others the perimeter centroid
-// of the wet part.  Isoface edges on the face run from an entry cut back to the preceding exit cut
+// tie_wet, the limit from below).  The wet part of the face is its loop of wet vertices and cut
+// points; fanned about any apex q its share is q . sum(p_i x p_i+1), linear in q.  Planar faces
+// use a face vertex (the value does not depend on the apex), others the perimeter centroid of the
+// wet part.  Isoface edges on the face run from an entry cut back to the preceding exit cut
 // (closing the wet part); they are summed for the isoface's own fan, whose apex is the perimeter
 // centroid of all isoface edges.
-// Straight-line code: the eight candidate points of the loop (vertex k, cut on edge k, k = 0..3)
-// are all computed and masked, so the lanes of a wave (different faces, different cells) never
-// diverge.
+// The loop sum is taken edge by edge: face edge i contributes a x b with a, b its wet end or its
+// cut point (nothing when both ends are dry), and each isoface edge, walked from exit to entry,
+// closes the loop with the opposite of its own term.  Masked sums are 0/1-weighted (exact for
+// finite terms) and the lanes of a wave (different faces, different cells) never diverge.
 __device__ __forceinline__ Part face_part(const FaceLane &f, double iso, bool tie_wet) {
     Part r{0.0, {0, 0, 0}, {0, 0, 0}, 0.0};
     bool w[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) w[i] = f.active && (tie_wet ? f.aq[i] >= iso : f.aq[i] > iso);
     D3 cut[4];
-    bool cuts[4], exits[4], entries[4];
+    bool exits[4], entries[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int j = (i + 1) & 3;
         cut[i] = face_cut(f, i, iso, w[i]);
-        cuts[i] = w[i] != w[j];
         exits[i] = w[i] && !w[j];
         entries[i] = !w[i] && w[j];
-    }
-    // the wet loop: vertex i (if wet), then the cut on edge i (if cut), i = 0..3
-    D3 last{0, 0, 0};
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        last = sel3(w[i], f.q[i], last);
-        last = sel3(cuts[i], cut[i], last);
-        cnt += (w[i] ? 1 : 0) + (cuts[i] ? 1 : 0);
-    }
-    D3 C{0, 0, 0}, prev = last;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const D3 kv = cross(prev, f.q[i]);
-        C = sel3(w[i], C + kv, C);
-        prev = sel3(w[i], f.q[i], prev);
-        const D3 kc = cross(prev, cut[i]);
-        C = sel3(cuts[i], C + kc, C);
-        prev = sel3(cuts[i], cut[i], prev);
-    }
-    if (cnt >= 3) {
-        D3 ap = f.q[0];
-        if (!f.planar) {
-            D3 pacc{0, 0, 0}, psum{0, 0, 0};
-            double pl = 0.0;
-            D3 pv = last;
-            auto step = [&](bool on, D3 x) {
-                const double l = norm3(x - pv);
-                pacc = sel3(on, pacc + (0.5 * l) * (x + pv), pacc);
-                pl += on ? l : 0.0;
-                psum = sel3(on, psum + x, psum);
-                pv = sel3(on, x, pv);
-            };
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                step(w[i], f.q[i]);
-                step(cuts[i], cut[i]);
-            }
-            ap = pl > 0.0 ? (1.0 / pl) * pacc : (1.0 / cnt) * psum;
-        }
-        r.v6 = dot(ap, C);
     }
     // isoface edges: each entry pairs with the exit before it, cyclically
     D3 lastexit{0, 0, 0};
@@ -107,14 +66,43 @@ __device__ __forceinline__ Part face_part(const FaceLane &f, double iso, bool ti
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const D3 s0 = cut[i], s1 = lastexit;
-        const D3 cr = cross(s0, s1);
+        const double m = entries[i] ? 1.0 : 0.0;
         const double l = norm3(s1 - s0);
-        if (entries[i]) {
-            r.cseg = r.cseg + cr;
-            r.oacc = r.oacc + (0.5 * l) * (s0 + s1);
-            r.oL += l;
-        }
+        r.cseg = r.cseg + m * cross(s0, s1);
+        r.oacc = r.oacc + (m * 0.5 * l) * (s0 + s1);
+        r.oL += m * l;
         lastexit = sel3(exits[i], cut[i], lastexit);
+    }
+    // the wet loop's sum: the face edges' terms, and the isoface edges walked exit to entry
+    D3 C = r.cseg;
+    C = D3{-C.x, -C.y, -C.z};
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        const D3 a = sel3(w[i], f.q[i], cut[i]), b = sel3(w[j], f.q[j], cut[i]);
+        C = C + ((w[i] || w[j]) ? 1.0 : 0.0) * cross(a, b);
+        cnt += (w[i] ? 1 : 0) + (w[i] != w[j] ? 1 : 0);
+    }
+    if (cnt >= 3) {
+        D3 ap = f.q[0];
+        if (!f.planar) {
+            // perimeter centroid of the wet loop: its face-edge pieces and its isoface edges
+            D3 pacc = r.oacc, psum{0, 0, 0};
+            double pl = r.oL;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = (i + 1) & 3;
+                const D3 a = sel3(w[i], f.q[i], cut[i]), b = sel3(w[j], f.q[j], cut[i]);
+                const double m = (w[i] || w[j]) ? 1.0 : 0.0;
+                const double l = norm3(b - a);
+                pacc = pacc + (m * 0.5 * l) * (a + b);
+                pl += m * l;
+                psum = psum + (w[i] ? 1.0 : 0.0) * f.q[i] + (w[i] != w[j] ? 1.0 : 0.0) * cut[i];
+            }
+            ap = pl > 0.0 ? (1.0 / pl) * pacc : (1.0 / cnt) * psum;
+        }
+        r.v6 = dot(ap, C);
     }
     return r;
 }
@@ -253,33 +241,56 @@ __device__ __forceinline__ FaceQuad face_quad_segs(const FaceLane &f, const bool
     return r;
 }
 
-// Per face at u: perimeter sums of its isoface edges and their rates of change with u, and the
-// edge sum B(u) = sum s x e with its derivative.
+// One isoface edge of the interval, held by one lane: entry point s0 + u s1 to exit point
+// e0 + u e1.  A lane without an edge holds zeros, which contribute exact zeros below.
+struct Seg {
+    D3 s0, s1, e0, e1;
+    bool on;
+};
+
+// Per edge at u: its perimeter sums and their rates of change with u, and B(u) = s x e with its
+// derivative.
 struct Perim {
-    D3 oacc, doacc;  // sum of length x midpoint, and its derivative
-    double oL, doL;  // total length, and its derivative
+    D3 oacc, doacc;  // length x midpoint, and its derivative
+    double oL, doL;  // length, and its derivative
     D3 Bu, Bd;       // B(u), B'(u)
 };
 
-__device__ __forceinline__ Perim seg_eval(const FaceQuad &fq, double u) {
-    const D3 Z{0, 0, 0};
-    Perim r{Z, Z, 0.0, 0.0, Z, Z};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const D3 sp = fq.s0[k] + u * fq.s1[k], ep = fq.e0[k] + u * fq.e1[k];
-        const D3 d = ep - sp, dd = fq.e1[k] - fq.s1[k];
-        const double l = norm3(d);
-        const double dl = l > 0.0 ? dot(d, dd) / l : 0.0;
-        const D3 ao = (0.5 * l) * (sp + ep), dao = (0.5 * dl) * (sp + ep) + (0.5 * l) * (fq.s1[k] + fq.e1[k]);
-        const bool on = fq.on[k];
-        r.oacc = sel3(on, r.oacc + ao, r.oacc);
-        r.doacc = sel3(on, r.doacc + dao, r.doacc);
-        r.oL += on ? l : 0.0;
-        r.doL += on ? dl : 0.0;
-        r.Bu = sel3(on, r.Bu + cross(sp, ep), r.Bu);
-        r.Bd = sel3(on, r.Bd + cross(fq.s1[k], ep) + cross(sp, fq.e1[k]), r.Bd);
-    }
+__device__ __forceinline__ Perim seg_eval(const Seg &sg, double u) {
+    Perim r;
+    const D3 sp = sg.s0 + u * sg.s1, ep = sg.e0 + u * sg.e1;
+    const D3 d = ep - sp, dd = sg.e1 - sg.s1;
+    const double l = norm3(d);
+    const double dl = l > 0.0 ? dot(d, dd) / l : 0.0;
+    r.oacc = (0.5 * l) * (sp + ep);
+    r.doacc = (0.5 * dl) * (sp + ep) + (0.5 * l) * (sg.s1 + sg.e1);
+    r.oL = l;
+    r.doL = dl;
+    r.Bu = cross(sp, ep);
+    r.Bd = cross(sg.s1, ep) + cross(sp, sg.e1);
     return r;
+}
+
+// Gives every lane of the group one isoface edge: lane k < 6 keeps the first edge of face k; the
+// second edges of saddle faces (all four edges cut) go to lanes 6 and 7, which own no face.
+// Returns false when more than two faces of the cell are saddles (the caller then solves with the
+// generic sub-volume instead).
+__device__ __forceinline__ bool spread_edges(const FaceQuad &fq, int lv, Seg &sg) {
+    const uint64_t bal = __ballot(fq.on[1]);
+    const uint32_t gm = (uint32_t)(bal >> (__lane_id() & ~(kLanes - 1))) & 0xFFu;
+    const uint32_t gm2 = gm & (gm - 1u);
+    const int src = lv == 6 ? (gm ? __ffs(gm) - 1 : 0) : (lv == 7 ? (gm2 ? __ffs(gm2) - 1 : 0) : lv);
+    const bool take = (lv == 6 && gm != 0u) || (lv == 7 && gm2 != 0u);
+    const D3 Z{0, 0, 0};
+    auto pull = [&](const D3 &x) { return D3{grp_get(x.x, src), grp_get(x.y, src), grp_get(x.z, src)}; };
+    const D3 s0 = pull(fq.s0[1]), s1 = pull(fq.s1[1]), e0 = pull(fq.e0[1]), e1 = pull(fq.e1[1]);
+    const bool face = lv < 6;
+    sg.s0 = face ? fq.s0[0] : (take ? s0 : Z);
+    sg.s1 = face ? fq.s1[0] : (take ? s1 : Z);
+    sg.e0 = face ? fq.e0[0] : (take ? e0 : Z);
+    sg.e1 = face ? fq.e1[0] : (take ? e1 : Z);
+    sg.on = face ? fq.on[0] : take;
+    return __popc(gm) <= 2;
 }
 
 // ------------------------------------------------------------------------------------------ sweep
@@ -509,16 +520,21 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 else if (fm < 0.0) { ih = im; }
                 else { iso = sm; exact = true; break; }
             }
+            // planar cells: the interval solve on the face quadratics and isoface edges
+            const double lo = sorted_at(il), hi = sorted_at(ih);
+            const double xr = 0.5 * (lo + hi);
+            double ac[3] = {0.0, 0.0, 0.0};
+            Seg sg;
+            bool quad = false;
             if (!exact && planar_cell) {
-                const double lo = sorted_at(il), hi = sorted_at(ih);
                 // wet/dry pattern of the open interval (lo, hi) and the quadratic coefficients
-                const double xr = 0.5 * (lo + hi);
                 bool w[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) w[i] = f.aq[i] > xr;
-                double ac[3];
                 face_quad_share(f, w, xr, ac);
-                const FaceQuad fq = face_quad_segs(f, w, xr);
+                quad = spread_edges(face_quad_segs(f, w, xr), lv, sg);
+            }
+            if (quad) {
                 ++rounds;
 
                 // G(u) = six times the sub-volume minus its target, and G'(u): each face adds its
@@ -526,7 +542,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 // edges (with no isoface length B vanishes and o does not enter)
                 const double target = aP * V6;
                 auto G = [&](double u, double &dG) {
-                    const Perim pr = seg_eval(fq, u);
+                    const Perim pr = seg_eval(sg, u);
                     const D3 oacc = grp_sum3(pr.oacc), doacc = grp_sum3(pr.doacc);
                     const double oL = grp_sum(pr.oL), doL = grp_sum(pr.doL);
                     D3 o{0, 0, 0}, od{0, 0, 0};
@@ -588,7 +604,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                     iso = xr + u;
                     // the isoface at the isovalue, from the face segments: apex (perimeter
                     // centroid), area vector (x2) = sum of s x e, centre = area-weighted fan centroid
-                    const Perim pr = seg_eval(fq, u);
+                    const Perim pr = seg_eval(sg, u);
                     const D3 oacc = grp_sum3(pr.oacc);
                     const double oL = grp_sum(pr.oL);
                     const D3 cs = grp_sum3(pr.Bu);
@@ -596,15 +612,10 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                     if (oL > 0.0 && nrm > 0.0) {
                         const D3 o = (1.0 / oL) * oacc;
                         nS = (1.0 / nrm) * cs;
-                        D3 acc{0, 0, 0};
-                        double ws = 0.0;
-#pragma unroll
-                        for (int k = 0; k < 2; ++k) {
-                            const D3 sp = fq.s0[k] + u * fq.s1[k], ep = fq.e0[k] + u * fq.e1[k];
-                            const double wt = dot(cross(sp - o, ep - o), nS);
-                            acc = sel3(fq.on[k], acc + wt * (o + sp + ep), acc);
-                            ws += fq.on[k] ? wt : 0.0;
-                        }
+                        const D3 sp = sg.s0 + u * sg.s1, ep = sg.e0 + u * sg.e1;
+                        const double wt = sg.on ? dot(cross(sp - o, ep - o), nS) : 0.0;
+                        D3 acc = wt * (o + sp + ep);
+                        double ws = wt;
                         acc = grp_sum3(acc);
                         ws = grp_sum(ws);
                         xS = (1.0 / (3.0 * ws)) * acc;
@@ -1179,7 +1190,7 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     const long groups_per_block = bs / kLanes;
     long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
     // persistent: groups loop over the list, which is only known on the device
-    gs = std::max(1L, std::min(gs, cfg.surface_blocks > 0 ? (long)cfg.surface_blocks : 1024L));
+    gs = std::max(1L, std::min(gs, cfg.surface_blocks > 0 ? (long)cfg.surface_blocks : 2048L));
     switch (cfg.surface_waves) {
         case 1: hipLaunchKernelGGL(k_surface<1>, dim3((int)gs), dim3(bs), 0, s, sa); break;
         case 3: hipLaunchKernelGGL(k_surface<3>, dim3((int)gs), dim3(bs), 0, s, sa); break;
