@@ -100,6 +100,34 @@ def test_trajectory(O, name):
     assert err <= TOL_TRAJ
 
 
+@pytest.mark.parametrize("n_iter,clip", [(0, 1), (0, 0), (1, 1), (2, 0), (5, 1)])
+def test_bounding_sweep_counts(O, n_iter, clip):
+    """Every bounding schedule against the oracle with the same options: no sweep (chop only, or
+    nothing), one sweep (its phase A runs inside the update), and more sweeps than the three
+    rotating counter slots; with and without the final chop."""
+    import torch
+    w = CASES["violent_32x16x16"]
+    say(f"[gpu] bounding sweeps={n_iter} clip={clip}: {w.name}")
+    gm, plan = gpu_plan(w.mesh, n_bound_iter=n_iter, clip=clip)
+    om = O.OracleMesh(w.mesh)
+    steps = 12
+    phi, U = w.phi_U(0)
+    tphi, tU = to_dev(phi), to_dev(U)
+    a = to_dev(w.alpha0)
+    b = torch.empty_like(a)
+    active = 0
+    for _ in range(steps):
+        _, st = plan.step(a, tphi, tU, w.dt, out=b, stats=True)
+        active += st["n_bound_active"]
+        a, b = b, a
+    g = a.cpu().numpy()
+    o = oracle_trajectory(om, w, steps, opts=O.default_opts(n_bound_iter=n_iter, clip=clip))
+    err = np.abs(g - o).max()
+    say(f"[gpu]   cells flagged for bounding over the run: {active}; max |gpu - oracle| = {err:.3e}")
+    assert active > 0
+    assert err <= TOL_TRAJ
+
+
 def test_planar_transport_exact_on_gpu(O):
     """The exactness pin of the oracle holds for the GPU path too (clip off)."""
     w = CASES["band_periodic"]
