@@ -45,13 +45,13 @@ struct DevWork {
     int32_t *counters = nullptr;   // [kCntNum] see kCnt* below
     int32_t *surf = nullptr;       // [cap] interface cells
     double *dvs = nullptr;         // [n_faces] dV written by interface upwind cells
-    int32_t *olist = nullptr;      // [n_cells] cells needing redistribution (two halves ping-pong)
-    int32_t *tlist = nullptr;      // [n_cells] cells touched by a sweep
-    int32_t *flist = nullptr;      // [3*n_faces] faces whose dV changed during bounding; then the faces
-                                   // holding a correction in each of the two correction buffers
-    int32_t *cmark = nullptr;      // [n_cells] zero between steps
+    int32_t *olist = nullptr;      // [n_cells] cells out of bounds after the update
+    int32_t *tlist = nullptr;      // [2*n_cells] cells touched by a sweep (two banks by sweep parity)
+    int32_t *flist = nullptr;      // [4*n_faces] faces whose dV changed during bounding; then the faces
+                                   // holding a correction in each of the three correction buffers
+    int32_t *cmark = nullptr;      // [2*n_cells] touched marks (two banks by sweep parity), zero between steps
     int32_t *fmark = nullptr;      // [n_faces] zero between steps
-    double *delta = nullptr;       // [2*n_faces] correction buffers, zero between steps
+    double *delta = nullptr;       // [3*n_faces] correction buffers (sweep mod 3), zero between steps
     double *dvcur = nullptr;       // [n_faces] current dV of faces in flist
     double *red = nullptr;         // [64] reductions for stats
     int32_t cap = 0;
@@ -66,7 +66,7 @@ enum : int {
     kCntMaxIter = 5,
     kCntActive0 = 6,    // n_bound_active of the last step
     kCntFaces = 7,      // flist length
-    kCntBound = 16,     // [16, 25): three rotating slots of per-sweep bounding counters
+    kCntBound = 16,     // [16, 24): four rotating slots of per-sweep bounding counters
     kCntNum = 32
 };
 

@@ -763,15 +763,23 @@ struct UpdArgs {
     DevWork w;
 };
 
-// Bounding counters of sweep `it` live in one of three rotating slots: a slot is read by the two
-// kernels of its sweep and by phase A of the next sweep, and cleared by phase B of the sweep after.
-__device__ __forceinline__ int32_t *bound_slot(int32_t *counters, int it) { return counters + kCntBound + 3 * (it % 3); }
-enum : int { kSlotTouched = 0, kSlotNext = 1, kSlotDelta = 2 };
+// Bounding counters of sweep `it` live in one of four rotating slots: a slot is filled by the
+// kernel before its sweep's (phase A), read by its sweep's kernel and the next one, and cleared by
+// the one after that.
+__device__ __forceinline__ int32_t *bound_slot(int32_t *counters, int it) { return counters + kCntBound + 2 * (it % 4); }
+enum : int { kSlotTouched = 0, kSlotDelta = 1 };
+
+// Sweep s's corrections and their face list: three rotating buffers, so that a kernel can apply
+// sweep s, compute sweep s+1 and clear what sweep s-1 left, all on different buffers.
+__device__ __forceinline__ double *delta_buf(const DevWork &w, int s, int nf) { return w.delta + (size_t)(s % 3) * nf; }
+__device__ __forceinline__ int32_t *dlist_buf(const DevWork &w, int s, int nf) {
+    return w.flist + (size_t)(1 + s % 3) * nf;
+}
 
 // W flux slots per cell, all loads of one kind issued together (independent gathers in flight).
 // Any block size up to 1024 (the block_cells option) is valid.  A cell left out of bounds also
-// runs phase A of the first redistribution sweep (k_bound_a) here: no face is marked yet, so the
-// current dV of each of its outflow faces is the one just computed.
+// runs phase A of the first redistribution sweep (see k_bound_sweep) here: no face is marked yet,
+// so the current dV of each of its outflow faces is the one just computed.
 template <int W>
 __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     const int n = A.m.n_cells;
@@ -839,7 +847,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
         A.olist[base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] = c;
     if (A.n_iter < 1) return;
-    // phase A of sweep 0 (as in k_bound_a, with every face unmarked)
+    // phase A of sweep 0 (as in k_bound_sweep, with every face unmarked)
     const int nf = A.m.n_faces;
     int32_t *slot = bound_slot(A.counters, 0);
     int ndl = 0, ntl = 0;
@@ -871,7 +879,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             const double d = cap[k] * r;
             const double dd = over ? (v[k] >= 0 ? d : -d) : (v[k] >= 0 ? -d : d);
             const int32_t f = v[k] >= 0 ? v[k] : ~v[k];
-            A.w.delta[f] = dd;
+            delta_buf(A.w, 0, nf)[f] = dd;
             A.w.dvcur[f] = dvo[k] + dd;
             A.w.fmark[f] = 1;
             fsel[k] = f;
@@ -886,7 +894,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     int bd = wave_append(ndl, &slot[kSlotDelta]);
     int bf = wave_append(ndl, &A.counters[kCntFaces]);
     int bt = wave_append(ntl, &slot[kSlotTouched]);
-    int32_t *dlist = A.w.flist + (size_t)nf;
+    int32_t *dlist = dlist_buf(A.w, 0, nf);
 #pragma unroll
     for (int k = 0; k < W; ++k)
         if (fsel[k] >= 0) {
@@ -909,155 +917,49 @@ struct BoundArgs {
     DevWork w;
 };
 
+// Redistribution sweeps (Jacobi), two phases per sweep.  (A) every cell out of bounds computes the
+// change of the heavy-fluid outflow of each of its outflow faces (each face has one upwind cell,
+// so it alone writes that face's correction and its running dV) and marks the cells it touches;
+// (B) every touched cell applies the corrections of its faces in ascending face order.  Phase A
+// of a cell needs only its own new alpha and its own outflow faces, so a cell still out of bounds
+// after phase B of sweep s runs phase A of sweep s+1 at once: one kernel per sweep (phase A of
+// sweep 0 runs inside the update).  Touched lists and marks alternate between two banks, counter
+// slots rotate over four.  List order never affects a result.
 template <int W>
-struct Slots {
-    int32_t v[W], fid[W], nbr[W];
-    double ph[W];
-};
-
-template <int W>
-__device__ __forceinline__ void load_slots(const BoundArgs &A, int32_t c, Slots<W> &s) {
-    const int n = A.m.n_cells;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        s.v[k] = A.m.slot_face[(size_t)k * n + c];
-        s.nbr[k] = A.m.slot_nbr[(size_t)k * n + c];
-    }
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        s.fid[k] = s.v[k] >= 0 ? s.v[k] : ~s.v[k];
-        s.ph[k] = s.v[k] != kEmpty ? A.phi[s.fid[k]] : 0.0;
-    }
-}
-
-
-// Redistribution sweeps (Jacobi), two grid-wide phases per sweep.  (A) every listed cell computes
-// the change of the heavy-fluid outflow of each of its outflow faces (each face has one upwind
-// cell, so it alone writes that face's correction and its running dV); (B) every touched cell
-// applies the corrections of its faces in ascending face order and is listed for the next sweep
-// if still out of bounds.  Corrections alternate between two buffers; phase A of a sweep clears
-// the buffer read by the previous sweep.  List order never affects a result.  Phase A of sweep 0
-// runs inside the update kernel; k_bound_a serves the sweeps from 1 on.
-template <int W>
-__global__ void __launch_bounds__(256) k_bound_a(BoundArgs A, int it) {
+__global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
     const int n = A.m.n_cells, nf = A.m.n_faces;
     int32_t *counters = A.w.counters;
-    int32_t *slot = bound_slot(counters, it);
-    const int par = it & 1;
-    const int32_t *cur = A.w.olist + (par ? n : 0);
-    double *delta = A.w.delta + (size_t)par * nf;
-    int32_t *dlist = A.w.flist + (size_t)(1 + par) * nf;
-    const int n_old = bound_slot(counters, it - 1)[kSlotNext];
     const int stride = gridDim.x * blockDim.x;
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
-    {  // the other buffer was read by the previous sweep: clear it
+    const bool last = it == A.n_iter - 1;
+    if (it >= 1) {  // sweep it-1's corrections were read by the previous kernel: clear them
         const int n_stale = bound_slot(counters, it - 1)[kSlotDelta];
-        double *stale = A.w.delta + (size_t)(par ^ 1) * nf;
-        const int32_t *slist = A.w.flist + (size_t)(2 - par) * nf;
+        double *stale = delta_buf(A.w, it - 1, nf);
+        const int32_t *slist = dlist_buf(A.w, it - 1, nf);
         for (int i = t0; i < n_stale; i += stride) stale[slist[i]] = 0.0;
     }
-    const int nloop = (n_old + 255) & ~255;  // whole work-groups iterate together
-    for (int i0 = blockIdx.x * blockDim.x; i0 < nloop; i0 += stride) {
-        const int i = i0 + threadIdx.x;
-        const bool valid = i < n_old;
-        int ndl = 0, nfl = 0, ntl = 0;
-        int32_t fsel[W], tsel[W + 1];
-        bool newf[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) { fsel[k] = -1; newf[k] = false; tsel[k] = -1; }
-        tsel[W] = -1;
-        if (valid) {
-            const int32_t P = cur[i];
-            Slots<W> sl;
-            load_slots<W>(A, P, sl);
-            const double a = A.alpha_new[P];
-            const bool over = a > 1.0 + A.tol;
-            const double aold = A.alpha[P];
-            const bool sP = interface_cell(aold, A.eps);
-            const double dtc = cell_dt(A.m, A.dt_dom, A.dt, P);
-            int32_t mk[W];
-            double dvs_v[W], dvc_v[W];
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const bool outflow = sl.v[k] != kEmpty && (sl.v[k] >= 0 ? sl.ph[k] : -sl.ph[k]) > 0.0;
-                mk[k] = outflow ? A.w.fmark[sl.fid[k]] : 0;
-                dvs_v[k] = (outflow && sP) ? A.dvs[sl.fid[k]] : 0.0;
-                dvc_v[k] = outflow ? A.w.dvcur[sl.fid[k]] : 0.0;
-            }
-            double cap[W], dvnow[W];
-            double sumcap = 0.0;
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                cap[k] = 0.0;
-                dvnow[k] = 0.0;
-                if (sl.v[k] == kEmpty) continue;
-                const double outphi = sl.v[k] >= 0 ? sl.ph[k] : -sl.ph[k];
-                if (!(outphi > 0.0)) continue;
-                // current dV of the face: running value once touched, else this step's
-                dvnow[k] = mk[k] ? dvc_v[k] : (sP ? dvs_v[k] : aold * sl.ph[k] * dtc);
-                const double outv = sl.v[k] >= 0 ? dvnow[k] : -dvnow[k];
-                cap[k] = over ? outphi * dtc - outv : outv;
-                if (cap[k] > 0.0) sumcap += cap[k];
-            }
-            if (atomicExch(&A.w.cmark[P], 1) == 0) tsel[W] = P;
-            const double need = over ? (a - 1.0) * A.m.vol[P] : -a * A.m.vol[P];
-            const double r = sumcap > 0.0 ? fmin(need / sumcap, 1.0) : 0.0;
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
-                const double d = cap[k] * r;
-                const double dd = over ? (sl.v[k] >= 0 ? d : -d) : (sl.v[k] >= 0 ? -d : d);
-                const int32_t f = sl.fid[k];
-                delta[f] = dd;
-                A.w.dvcur[f] = dvnow[k] + dd;
-                fsel[k] = f;
-                if (!mk[k]) {
-                    A.w.fmark[f] = 1;
-                    newf[k] = true;
-                }
-                if (sl.nbr[k] >= 0 && atomicExch(&A.w.cmark[sl.nbr[k]], 1) == 0) tsel[k] = sl.nbr[k];
-            }
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                ndl += fsel[k] >= 0 ? 1 : 0;
-                nfl += newf[k] ? 1 : 0;
-            }
-#pragma unroll
-            for (int k = 0; k <= W; ++k) ntl += tsel[k] >= 0 ? 1 : 0;
-        }
-        int bd = wave_append(ndl, &slot[kSlotDelta]);
-        int bf = wave_append(nfl, &counters[kCntFaces]);
-        int bt = wave_append(ntl, &slot[kSlotTouched]);
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            if (fsel[k] >= 0) dlist[bd++] = fsel[k];
-            if (newf[k]) A.w.flist[bf++] = fsel[k];
-        }
-#pragma unroll
-        for (int k = 0; k <= W; ++k)
-            if (tsel[k] >= 0) A.w.tlist[bt++] = tsel[k];
-    }
-}
-
-template <int W>
-__global__ void __launch_bounds__(256) k_bound_b(BoundArgs A, int it, int last) {
-    const int n = A.m.n_cells, nf = A.m.n_faces;
-    int32_t *counters = A.w.counters;
-    int32_t *slot = bound_slot(counters, it);
-    const int par = it & 1;
-    int32_t *nxt = A.w.olist + (par ? 0 : n);
-    const double *delta = A.w.delta + (size_t)par * nf;
+    // nothing reads sweep it-2's counters any more (its slot returns for sweep it+2)
+    if (it >= 2 && blockIdx.x == 0 && threadIdx.x < 2) bound_slot(counters, it - 2)[threadIdx.x] = 0;
+    const int32_t *slot = bound_slot(counters, it);
+    int32_t *slot_next = bound_slot(counters, it + 1);
+    const double *delta = delta_buf(A.w, it, nf);
+    double *delta_next = delta_buf(A.w, it + 1, nf);
+    int32_t *dlist_next = dlist_buf(A.w, it + 1, nf);
+    const int32_t *touched = A.w.tlist + (size_t)(it & 1) * n;
+    int32_t *touched_next = A.w.tlist + (size_t)((it + 1) & 1) * n;
+    int32_t *mark = A.w.cmark + (size_t)(it & 1) * n;
+    int32_t *mark_next = A.w.cmark + (size_t)((it + 1) & 1) * n;
     const int nT = slot[kSlotTouched];
-    const int stride = gridDim.x * blockDim.x;
-    if (it > 0 && blockIdx.x == 0 && threadIdx.x < 3) bound_slot(counters, it - 1)[threadIdx.x] = 0;
-    const int nloop = (nT + 255) & ~255;
+    const int nloop = (nT + 255) & ~255;  // whole work-groups iterate together
     for (int i0 = blockIdx.x * blockDim.x; i0 < nloop; i0 += stride) {
         const int i = i0 + threadIdx.x;
         bool again = false;
         int32_t Q = 0;
+        double x = 0.0;
+        int32_t v[W];
+        // phase B of sweep it
         if (i < nT) {
-            Q = A.w.tlist[i];
-            int32_t v[W];
+            Q = touched[i];
 #pragma unroll
             for (int k = 0; k < W; ++k) v[k] = A.m.slot_face[(size_t)k * n + Q];
             const double aq = A.alpha_new[Q], vq = A.m.vol[Q];
@@ -1068,18 +970,98 @@ __global__ void __launch_bounds__(256) k_bound_b(BoundArgs A, int it, int last) 
 #pragma unroll
             for (int k = 0; k < W; ++k)
                 if (v[k] != kEmpty) sum += v[k] >= 0 ? d[k] : -d[k];
-            double x = aq - sum / vq;
+            x = aq - sum / vq;
             if (A.clip) {
                 if (x < 0.0 && x >= -A.tol) x = 0.0;
                 else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
                 if (last) x = fmin(fmax(x, 0.0), 1.0);
             }
             A.alpha_new[Q] = x;
-            A.w.cmark[Q] = 0;
+            mark[Q] = 0;
             again = x > 1.0 + A.tol || x < -A.tol;
         }
-        const int b = wave_append(again ? 1 : 0, &slot[kSlotNext]);
-        if (again) nxt[b] = Q;
+        if (last) continue;  // uniform
+        // phase A of sweep it+1 for a cell still out of bounds
+        int ndl = 0, nfl = 0, ntl = 0;
+        int32_t fsel[W], tsel[W + 1];
+        bool newf[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) { fsel[k] = -1; newf[k] = false; tsel[k] = -1; }
+        tsel[W] = -1;
+        if (again) {
+            int32_t nbr[W], fid[W];
+            double ph[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                nbr[k] = A.m.slot_nbr[(size_t)k * n + Q];
+                fid[k] = v[k] >= 0 ? v[k] : ~v[k];
+                ph[k] = v[k] != kEmpty ? A.phi[fid[k]] : 0.0;
+            }
+            const bool over = x > 1.0 + A.tol;
+            const double aold = A.alpha[Q];
+            const bool sP = interface_cell(aold, A.eps);
+            const double dtc = cell_dt(A.m, A.dt_dom, A.dt, Q);
+            int32_t mk[W];
+            double dvs_v[W], dvc_v[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const bool outflow = v[k] != kEmpty && (v[k] >= 0 ? ph[k] : -ph[k]) > 0.0;
+                mk[k] = outflow ? A.w.fmark[fid[k]] : 0;
+                dvs_v[k] = (outflow && sP) ? A.dvs[fid[k]] : 0.0;
+                dvc_v[k] = outflow ? A.w.dvcur[fid[k]] : 0.0;
+            }
+            double cap[W], dvnow[W];
+            double sumcap = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                cap[k] = 0.0;
+                dvnow[k] = 0.0;
+                if (v[k] == kEmpty) continue;
+                const double outphi = v[k] >= 0 ? ph[k] : -ph[k];
+                if (!(outphi > 0.0)) continue;
+                // current dV of the face: running value once touched, else this step's
+                dvnow[k] = mk[k] ? dvc_v[k] : (sP ? dvs_v[k] : aold * ph[k] * dtc);
+                const double outv = v[k] >= 0 ? dvnow[k] : -dvnow[k];
+                cap[k] = over ? outphi * dtc - outv : outv;
+                if (cap[k] > 0.0) sumcap += cap[k];
+            }
+            if (atomicExch(&mark_next[Q], 1) == 0) tsel[W] = Q;
+            const double need = over ? (x - 1.0) * A.m.vol[Q] : -x * A.m.vol[Q];
+            const double r = sumcap > 0.0 ? fmin(need / sumcap, 1.0) : 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
+                const double dk = cap[k] * r;
+                const double dd = over ? (v[k] >= 0 ? dk : -dk) : (v[k] >= 0 ? -dk : dk);
+                const int32_t f = fid[k];
+                delta_next[f] = dd;
+                A.w.dvcur[f] = dvnow[k] + dd;
+                fsel[k] = f;
+                if (!mk[k]) {
+                    A.w.fmark[f] = 1;
+                    newf[k] = true;
+                }
+                if (nbr[k] >= 0 && atomicExch(&mark_next[nbr[k]], 1) == 0) tsel[k] = nbr[k];
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                ndl += fsel[k] >= 0 ? 1 : 0;
+                nfl += newf[k] ? 1 : 0;
+            }
+#pragma unroll
+            for (int k = 0; k <= W; ++k) ntl += tsel[k] >= 0 ? 1 : 0;
+        }
+        int bd = wave_append(ndl, &slot_next[kSlotDelta]);
+        int bf = wave_append(nfl, &counters[kCntFaces]);
+        int bt = wave_append(ntl, &slot_next[kSlotTouched]);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (fsel[k] >= 0) dlist_next[bd++] = fsel[k];
+            if (newf[k]) A.w.flist[bf++] = fsel[k];
+        }
+#pragma unroll
+        for (int k = 0; k <= W; ++k)
+            if (tsel[k] >= 0) touched_next[bt++] = tsel[k];
     }
 }
 
@@ -1099,10 +1081,10 @@ __global__ void __launch_bounds__(1024) k_bound_end(BoundArgs A) {
             }
         }
     } else {
-        const int it = A.n_iter - 1, par = it & 1;
+        const int it = A.n_iter - 1;
         const int nd = bound_slot(counters, it)[kSlotDelta];
-        const int32_t *dl = A.w.flist + (size_t)(1 + par) * nf;
-        double *delta = A.w.delta + (size_t)par * nf;
+        const int32_t *dl = dlist_buf(A.w, it, nf);
+        double *delta = delta_buf(A.w, it, nf);
         for (int i = tid; i < nd; i += nt) delta[dl[i]] = 0.0;
     }
     const int nF = counters[kCntFaces];
@@ -1111,7 +1093,7 @@ __global__ void __launch_bounds__(1024) k_bound_end(BoundArgs A) {
     if (tid < 8) counters[8 + tid] = tid == kCntActive0 ? counters[kCntOff] : counters[tid];
     __syncthreads();
     if (tid < 8) counters[tid] = 0;
-    if (tid >= kCntBound && tid < kCntBound + 9) counters[tid] = 0;
+    if (tid >= kCntBound && tid < kCntBound + 8) counters[tid] = 0;
 }
 
 __global__ void __launch_bounds__(1024) k_stats(const double *alpha, const double *alpha_new, const double *vol, int n,
@@ -1143,10 +1125,8 @@ void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, const
     const int gc = (m.n_cells + cfg.block_cells - 1) / cfg.block_cells;
     hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(cfg.block_cells), 0, s, ua);  // and sweep 0's phase A
     if (ev) (void)hipEventRecord(ev[3], s);
-    for (int it = 0; it < ba.n_iter; ++it) {
-        if (it > 0) hipLaunchKernelGGL(k_bound_a<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
-        hipLaunchKernelGGL(k_bound_b<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it, it == ba.n_iter - 1 ? 1 : 0);
-    }
+    for (int it = 0; it < ba.n_iter; ++it)
+        hipLaunchKernelGGL(k_bound_sweep<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
     hipLaunchKernelGGL(k_bound_end, dim3(1), dim3(1024), 0, s, ba);
 }
 

@@ -494,10 +494,10 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
         return hipMemset(*ptr, 0, std::max<size_t>(bytes, 256)) == hipSuccess;
     };
     bool ok = alloc((void **)&w.counters, kCntNum * sizeof(int32_t)) && alloc((void **)&w.surf, sizeof(int32_t) * w.cap) &&
-              alloc((void **)&w.dvs, sizeof(double) * nf) && alloc((void **)&w.olist, sizeof(int32_t) * 2 * (size_t)nc) &&
-              alloc((void **)&w.tlist, sizeof(int32_t) * nc) && alloc((void **)&w.flist, sizeof(int32_t) * 3 * (size_t)nf) &&
-              alloc((void **)&w.cmark, sizeof(int32_t) * nc) && alloc((void **)&w.fmark, sizeof(int32_t) * nf) &&
-              alloc((void **)&w.delta, sizeof(double) * 2 * (size_t)nf) && alloc((void **)&w.dvcur, sizeof(double) * nf) &&
+              alloc((void **)&w.dvs, sizeof(double) * nf) && alloc((void **)&w.olist, sizeof(int32_t) * (size_t)nc) &&
+              alloc((void **)&w.tlist, sizeof(int32_t) * 2 * (size_t)nc) && alloc((void **)&w.flist, sizeof(int32_t) * 4 * (size_t)nf) &&
+              alloc((void **)&w.cmark, sizeof(int32_t) * 2 * (size_t)nc) && alloc((void **)&w.fmark, sizeof(int32_t) * nf) &&
+              alloc((void **)&w.delta, sizeof(double) * 3 * (size_t)nf) && alloc((void **)&w.dvcur, sizeof(double) * nf) &&
               alloc((void **)&w.red, sizeof(double) * 64);
     if (!ok || hipHostMalloc((void **)&p->host_counters, kCntNum * sizeof(int32_t)) != hipSuccess ||
         hipHostMalloc((void **)&p->host_red, 64 * sizeof(double)) != hipSuccess) {
