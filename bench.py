@@ -40,7 +40,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 FLOP_PER_SURFACE_CELL = 11000.0
 COPY_N = 1 << 27  # doubles moved by the calibration copy (1 GiB read, 1 GiB written)
 KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update",
-               "k_bound_a": "bound_sweep_corrections", "k_bound_b": "bound_sweep_apply", "k_bound_end": "bound_end",
+               "k_bound_sweep": "bound_sweep", "k_bound_end": "bound_end",
                "k_stats": "stats"}
 # the commands whose rocprofv3 output --summarize-profiles reads
 PROFILE_COMMANDS = {
@@ -106,7 +106,8 @@ def committed_traffic(kernel, workload):
 
 
 def algorithmic(kernel, mesh_info, n_surface, n_flux, n_cells):
-    """(quantity per launch, unit, bound) of each kernel's compulsory work; see the design doc."""
+    """(quantity per launch, unit, bound) of each kernel's compulsory work: bytes that must cross
+    HBM for the memory-bound kernels, FP64 operations of the method for the interface kernel."""
     if kernel == "update":
         # alpha, V read + alpha_new written (8 B each) per cell; per flux face phi (8 B) and the
         # owner/neighbour pair (2 x 4 B); dV of interface-upwind faces (8 B, <= 6 per interface cell)
