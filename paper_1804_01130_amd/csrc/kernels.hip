@@ -6,16 +6,18 @@
 //   surface        eight lanes per interface cell: lane v gathers vertex v's value (inverse
 //                  distance stencil); lane k < 6 then owns canonical face k.  The group brackets
 //                  the isovalue between two consecutive sorted vertex values, then solves the
-//                  volume constraint: Newton on the interval's functional form for planar cells,
-//                  Illinois otherwise.  It builds the isoface, and lane k integrates the submerged
-//                  fraction of face k over the step when it is an outflow face (Eqs. tv ..
-//                  intaplus) -> dV (each face has one upwind cell: no atomics)
+//                  volume constraint: Newton on the interval's functional form for planar cells
+//                  (one isoface edge per lane), Illinois otherwise.  It builds the isoface, and
+//                  lane k integrates the submerged fraction of face k over the step when it is an
+//                  outflow face (Eqs. tv .. intaplus) -> dV (each face has one upwind cell: no
+//                  atomics)
 //   update         per cell, gather over its flux faces in ascending face id: dV from the
 //                  interface kernel or alpha_upwind*phi*dt; alpha - sum/V; round-off chopping;
-//                  cells outside the bounds are appended to a list
-//   bound          per Jacobi sweep, corrections over the outflow faces of the listed cells, then
-//                  their application in face order with chopping (bounding step at the end of
-//                  Section 3.2); a one-group kernel leaves the workspace clean
+//                  cells outside the bounds are listed and compute the first sweep's corrections
+//   bound          one kernel per Jacobi sweep: the touched cells apply the sweep's corrections in
+//                  face order with chopping, and those still outside the bounds compute the next
+//                  sweep's (bounding step at the end of Section 3.2); a one-group kernel leaves
+//                  the workspace clean
 // Nothing in the step is a dense contraction, so no matrix instructions are used.
 #include <hip/hip_runtime.h>
 
