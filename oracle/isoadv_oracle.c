@@ -49,6 +49,16 @@
  *       inflow boundary uses the patch value.
  *   R12 update sums in ascending flux-face id, owner side negative.
  *   R13 bounding: Jacobi redistribution over outflow faces, then chopping.
+ *   R14 outer iterations (Crank-Nicolson, end of Section 3.2): the step takes the
+ *       time-averaged fields phi = (phi(t) + phi(t+dt))/2 and U = (U(t) + U(t+dt))/2;
+ *       the caller forms them, this file sees one phi and one U.
+ *   R15 (us_mode 1) U_S by cell-point interpolation to x_S (the paper names no
+ *       scheme): point velocities by R1's weights; the cell split into tetrahedra
+ *       (cell centre, vertex mean of a face, two consecutive points of that face)
+ *       carrying U_P, the mean of the face's point velocities and the point
+ *       velocities; the linear interpolant in the tetrahedron with the largest
+ *       smallest barycentric coordinate of x_S (the one containing it).  us_mode 0
+ *       keeps U_S = U_P (R6).
  */
 #include <math.h>
 #include <stdint.h>
@@ -68,6 +78,7 @@ typedef struct {
     int n_bound_iter;  /* Jacobi sweeps, default 3 */
     int clip;          /* chop to [0,1], default 1 */
     int max_bisect;    /* default 200 */
+    int us_mode;       /* 0: U_S = U_P (R6); 1: cell-point interpolation to x_S (R15) */
 } or_opts;
 
 typedef struct {
@@ -795,7 +806,68 @@ double or_face_integral(const or_mesh *m, int f, int c, const double *xS, const 
 /* ------------------------------------------------------------------ the step */
 void or_default_opts(or_opts *o) {
     o->eps_surf = 1e-8; o->flat_tol = 1e-12; o->bound_tol = 1e-12;
-    o->n_bound_iter = 3; o->clip = 1; o->max_bisect = 200;
+    o->n_bound_iter = 3; o->clip = 1; o->max_bisect = 200; o->us_mode = 0;
+}
+
+/* R15: the velocity at x in cell c by cell-point interpolation.  U_pts holds the point velocities
+ * (R1), component-major.  Each face of the cell, fanned about its vertex mean, gives tetrahedra
+ * (cell centre, vertex mean, p_i, p_i+1) carrying U_P, the mean of the face's point velocities,
+ * U(p_i) and U(p_i+1); the barycentric coordinates of x come from Cramer's rule, and the
+ * tetrahedron whose smallest coordinate is largest (the first one met on a tie) gives the value. */
+static void cell_point_velocity(const or_mesh *m, int c, const double *U, const double *U_pts, const double *x,
+                                double *out) {
+    const int nc = m->n_cells, np = m->n_points;
+    const double *xc = m->xc + 3 * c;
+    const double Up[3] = {U[c], U[nc + c], U[2 * nc + c]};
+    double best = -INFINITY;
+    for (int d = 0; d < 3; ++d) out[d] = Up[d];
+    int fp[OR_MAXFP];
+    double r[3];
+    v_sub(x, xc, r);
+    for (int k = m->cfptr[c]; k < m->cfptr[c + 1]; ++k) {
+        int f = m->cfaces[k];
+        int n = face_points_for(m, f, c, fp);
+        const double *fc = m->fapex + 3 * f;
+        double Uf[3] = {0, 0, 0};
+        for (int i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) Uf[d] += U_pts[d * np + fp[i]];
+        for (int d = 0; d < 3; ++d) Uf[d] /= n;
+        for (int i = 0; i < n; ++i) {
+            int pa = fp[i], pb = fp[(i + 1) % n];
+            double e1[3], e2[3], e3[3], k23[3], kr3[3], k2r[3];
+            v_sub(fc, xc, e1);
+            v_sub(m->P + 3 * pa, xc, e2);
+            v_sub(m->P + 3 * pb, xc, e3);
+            v_cross(e2, e3, k23);
+            double det = v_dot(e1, k23);
+            if (det == 0.0) continue;
+            v_cross(r, e3, kr3);
+            v_cross(e2, r, k2r);
+            double l1 = v_dot(r, k23) / det, l2 = v_dot(e1, kr3) / det, l3 = v_dot(e1, k2r) / det;
+            double l0 = 1.0 - l1 - l2 - l3;
+            double mn = fmin(fmin(l0, l1), fmin(l2, l3));
+            if (mn > best) {
+                best = mn;
+                for (int d = 0; d < 3; ++d)
+                    out[d] = l0 * Up[d] + l1 * Uf[d] + l2 * U_pts[d * np + pa] + l3 * U_pts[d * np + pb];
+            }
+        }
+    }
+}
+
+/* Point velocities (R1 weights per component), component-major [3 * n_points]. */
+static double *point_velocities(const or_mesh *m, const double *U) {
+    const int nc = m->n_cells, np = m->n_points;
+    double *U_pts = (double *)xmalloc(sizeof(double) * 3 * np);
+    for (int d = 0; d < 3; ++d) or_point_values(m, U + (size_t)d * nc, U_pts + (size_t)d * np);
+    return U_pts;
+}
+
+/* R15 for one cell and point (tests): computes the point velocities itself. */
+void or_cell_point_velocity(const or_mesh *m, int c, const double *U, const double *x, double *out) {
+    double *U_pts = point_velocities(m, U);
+    cell_point_velocity(m, c, U, U_pts, x, out);
+    free(U_pts);
 }
 
 static double chop_roundoff(double x, double tol, double V, double *clipped) {
@@ -816,6 +888,7 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
 
     /* R1 */
     or_point_values(m, alpha, a_pts);
+    double *U_pts = opt->us_mode == 1 ? point_velocities(m, U) : NULL;
 
     /* R2, R3, R6: interface cells, their isovalue and isoface */
     for (int c = 0; c < nc; ++c) {
@@ -839,8 +912,9 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
         if (!(nrm > 0)) { kind[c] = 2; ++s.n_flat; continue; }
         kind[c] = 1;
         double nS[3] = {cut.S[0] / nrm, cut.S[1] / nrm, cut.S[2] / nrm};
-        double Uc[3] = {U[c], U[nc + c], U[2 * nc + c]};
-        double un = v_dot(Uc, nS);  /* U_S = U_P (reading R6) */
+        double Uc[3] = {U[c], U[nc + c], U[2 * nc + c]};  /* U_S = U_P (R6) */
+        if (U_pts) cell_point_velocity(m, c, U, U_pts, cut.xS, Uc);  /* R15 */
+        double un = v_dot(Uc, nS);
         for (int d = 0; d < 3; ++d) { rec[7 * c + d] = cut.xS[d]; rec[7 * c + 3 + d] = nS[d]; }
         rec[7 * c + 6] = un;
         if (tr && tr->iso) tr->iso[c] = iso;
@@ -953,7 +1027,7 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
         if (tr->rec) memcpy(tr->rec, rec, sizeof(double) * 7 * nc);
     }
     if (st) *st = s;
-    free(a_pts); free(kind); free(rec); free(dV); free(cur); free(delta); free(dVc);
+    free(a_pts); free(kind); free(rec); free(dV); free(cur); free(delta); free(dVc); free(U_pts);
     return 0;
 }
 
@@ -1357,6 +1431,7 @@ static void cs_step(const or_mesh *m, const or_opts *opt, const cplx *alpha, con
 int or_step_tlm(const or_mesh *m, const or_opts *opt, const double *alpha, const double *phi, const double *U, double dt,
                 const double *dalpha, const double *dphi, double *alpha_new, double *dalpha_new) {
     int nc = m->n_cells, nf = m->n_faces;
+    if (opt->us_mode != 0) return -1;  /* the tangent follows U_S = U_P (R6) only */
     cplx *a = (cplx *)xmalloc(sizeof(cplx) * nc);
     cplx *f = (cplx *)xmalloc(sizeof(cplx) * nf);
     cplx *o = (cplx *)xmalloc(sizeof(cplx) * nc);

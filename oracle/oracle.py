@@ -23,7 +23,7 @@ _ip = C.POINTER(C.c_int)
 
 class Opts(C.Structure):
     _fields_ = [("eps_surf", C.c_double), ("flat_tol", C.c_double), ("bound_tol", C.c_double),
-                ("n_bound_iter", C.c_int), ("clip", C.c_int), ("max_bisect", C.c_int)]
+                ("n_bound_iter", C.c_int), ("clip", C.c_int), ("max_bisect", C.c_int), ("us_mode", C.c_int)]
 
 
 class Trace(C.Structure):
@@ -86,6 +86,8 @@ def lib():
                               C.POINTER(Stats)]
         L.or_run.argtypes = [C.c_void_p, C.POINTER(Opts), _dp, _dp, _dp, C.c_double, C.c_int]
         L.or_step_tlm.argtypes = [C.c_void_p, C.POINTER(Opts), _dp, _dp, _dp, C.c_double, _dp, _dp, _dp, _dp]
+        L.or_step_tlm.restype = C.c_int
+        L.or_cell_point_velocity.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -186,6 +188,14 @@ class OracleMesh:
         return {"vsub": out[0], "S": out[1:4].copy(), "xS": out[4:7].copy(), "Swet": out[7:10].copy(),
                 "n_cut": int(out[10])}
 
+    def cell_point_velocity(self, c, U, x):
+        """Velocity at x in cell c by cell-point interpolation (reading R15), U as [3 n_cells] SoA."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(3)
+        lib().or_cell_point_velocity(self.h, int(c), _d(U), _d(x), _d(out))
+        return out
+
     def face_integral(self, f, c, xS, nS, un, dt):
         xS = np.ascontiguousarray(xS, dtype=np.float64)
         nS = np.ascontiguousarray(nS, dtype=np.float64)
@@ -225,8 +235,9 @@ class OracleMesh:
         dp = np.ascontiguousarray(np.zeros(self.n_faces) if dphi is None else dphi, dtype=np.float64)
         out = np.zeros(self.n_cells)
         dout = np.zeros(self.n_cells)
-        lib().or_step_tlm(self.h, C.byref(opts), _d(alpha), _d(phi), _d(U), float(dt), _d(da), _d(dp), _d(out),
-                          _d(dout))
+        if lib().or_step_tlm(self.h, C.byref(opts), _d(alpha), _d(phi), _d(U), float(dt), _d(da), _d(dp), _d(out),
+                             _d(dout)) != 0:
+            raise ValueError("the tangent follows U_S = U_P only (us_mode 0)")
         return out, dout
 
     def gradient(self, alpha, phi, U, dt, alpha_new_bar, cells=None, faces=None, opts=None):

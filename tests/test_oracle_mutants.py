@@ -33,6 +33,10 @@ MUTANTS = [
      "perimeter_centroid(seg_a, seg_a, nseg, 0, o);"),
     ("velocity_components_swapped", "double Uc[3] = {U[c], U[nc + c], U[2 * nc + c]};",
      "double Uc[3] = {U[c], U[2 * nc + c], U[nc + c]};"),
+    ("cell_point_face_value_not_mean", "for (int d = 0; d < 3; ++d) Uf[d] /= n;",
+     "for (int d = 0; d < 3; ++d) Uf[d] /= n + 1;"),
+    ("cell_point_centre_carries_face_value", "out[d] = l0 * Up[d] + l1 * Uf[d]", "out[d] = l0 * Uf[d] + l1 * Uf[d]"),
+    ("cell_point_tet_least_inside", "if (mn > best) {", "if (-mn > best) {"),
 ]
 
 # planted mistakes in the tangent of the step, which its own pins must reject

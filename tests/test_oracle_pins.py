@@ -502,3 +502,121 @@ def test_isovalue_is_root_or_jump(oracle_lib):
             assert np.any(a_pts == iso)
             assert f < 0 and om.cut(0, a_pts, np.nextafter(iso, -1))["vsub"] / V[0] - alpha > 0
     assert jumps > 0
+
+
+# ---------------------------------------------------------------------- R15: isoface velocity
+def _uniform_box(n=(6, 5, 5)):
+    xs, ys, zs = (np.linspace(0.0, 1.0, k + 1) for k in n)
+    return W.hex_block(xs, ys, zs, periodic_x=False), n
+
+
+def _box_cell(n, c):
+    nx, ny, _ = n
+    return c % nx, (c // nx) % ny, c // (nx * ny)
+
+
+def _interior(n, c):
+    i, j, k = _box_cell(n, c)
+    return all(1 <= q <= m - 2 for q, m in zip((i, j, k), n))
+
+
+def test_cell_point_velocity_constant_field(oracle_lib):
+    """A uniform velocity is reproduced anywhere in any cell (weights sum to one at every stage)."""
+    m, n = _uniform_box()
+    om = oracle_lib.OracleMesh(m)
+    xc, _ = om.geometry()
+    u0 = np.array([0.3, -0.2, 0.7])
+    U = np.repeat(u0, m.n_cells)
+    rng = np.random.default_rng(5)
+    for c in rng.choice(m.n_cells, 40, replace=False):
+        x = xc[c] + rng.uniform(-0.45, 0.45, 3) * 0.2
+        assert np.abs(om.cell_point_velocity(c, U, x) - u0).max() <= 1e-15
+
+
+def test_cell_point_velocity_linear_field_interior(oracle_lib):
+    """U = a + G x sampled at the cell centres: in cells whose points are all interior to a uniform
+    box (where the inverse-distance point values of a linear field are exact by symmetry) the
+    interpolant is exact at every point of the cell."""
+    m, n = _uniform_box()
+    om = oracle_lib.OracleMesh(m)
+    xc, _ = om.geometry()
+    rng = np.random.default_rng(6)
+    a = rng.normal(size=3)
+    G = rng.normal(size=(3, 3))
+    Uc = a + xc @ G.T
+    U = np.ascontiguousarray(Uc.T.ravel())
+    cells = [c for c in range(m.n_cells) if _interior(n, c)]
+    assert len(cells) >= 20
+    h = np.array([1.0 / q for q in n])
+    for c in cells:
+        for _ in range(5):
+            x = xc[c] + rng.uniform(-0.5, 0.5, 3) * h
+            assert np.abs(om.cell_point_velocity(c, U, x) - (a + G @ x)).max() <= 1e-13
+
+
+def test_cell_point_velocity_centre_and_points(oracle_lib):
+    """At the cell centre the interpolant is U_P; at a point of the cell it is that point's
+    inverse-distance value (R1), whatever the field."""
+    m, n = _uniform_box()
+    om = oracle_lib.OracleMesh(m)
+    xc, _ = om.geometry()
+    rng = np.random.default_rng(7)
+    U = rng.normal(size=3 * m.n_cells)
+    pts = np.stack([om.point_values(U[d * m.n_cells:(d + 1) * m.n_cells]) for d in range(3)], axis=1)
+    nx, ny, _ = n
+    for c in rng.choice(m.n_cells, 25, replace=False):
+        Up = U[[c, m.n_cells + c, 2 * m.n_cells + c]]
+        assert np.abs(om.cell_point_velocity(c, U, xc[c]) - Up).max() <= 1e-14
+        i, j, k = _box_cell(n, c)
+        for di, dj, dk in ((0, 0, 0), (1, 0, 1), (1, 1, 1), (0, 1, 0)):
+            p = (i + di) + (nx + 1) * ((j + dj) + (ny + 1) * (k + dk))
+            assert np.abs(om.cell_point_velocity(c, U, m.points[p]) - pts[p]).max() <= 1e-14
+
+
+def test_step_isoface_velocity_modes(oracle_lib):
+    """The step's U_S . n_S (trace) with us_mode 1 is the linear field at the isoface centre in the
+    interior cells of a uniform box; with us_mode 0 it is U_P . n_S."""
+    m, n = _uniform_box()
+    om = oracle_lib.OracleMesh(m)
+    xc, _ = om.geometry()
+    rng = np.random.default_rng(8)
+    a = rng.normal(size=3)
+    G = 0.3 * rng.normal(size=(3, 3))
+    U = np.ascontiguousarray((a + xc @ G.T).T.ravel())
+    alpha = np.clip(0.5 + 0.9 * (xc[:, 2] - 0.5) + 0.4 * (xc[:, 0] - 0.5) + 0.2 * (xc[:, 1] - 0.5), 0.02, 0.98)
+    phi = np.zeros(m.n_faces)
+    dt = 1e-3
+    checked = 0
+    for mode in (0, 1):
+        _, _, tr = om.step(alpha, phi, U, dt, oracle_lib.default_opts(us_mode=mode), trace=True)
+        for c in np.nonzero(tr["kind"] == 1)[0]:
+            xS, nS, un = tr["rec"][c, :3], tr["rec"][c, 3:6], tr["rec"][c, 6]
+            if mode == 0:
+                assert abs(un - U[[c, m.n_cells + c, 2 * m.n_cells + c]] @ nS) <= 1e-15
+            elif _interior(n, c):
+                assert abs(un - (a + G @ xS) @ nS) <= 1e-13
+                checked += 1
+    assert checked >= 10
+
+
+def test_cell_point_velocity_stays_within_nodal_values(oracle_lib):
+    """Inside a (convex) cell the interpolant is a convex combination of U_P, the face means and the
+    point values, so each component lies within their range: picking a tetrahedron that does not
+    contain x would extrapolate."""
+    m, n = _uniform_box()
+    om = oracle_lib.OracleMesh(m)
+    xc, _ = om.geometry()
+    rng = np.random.default_rng(9)
+    U = rng.normal(size=3 * m.n_cells)
+    pts = np.stack([om.point_values(U[d * m.n_cells:(d + 1) * m.n_cells]) for d in range(3)], axis=1)
+    nx, ny, _ = n
+    h = np.array([1.0 / q for q in n])
+    for c in rng.choice(m.n_cells, 30, replace=False):
+        i, j, k = _box_cell(n, c)
+        ids = [(i + di) + (nx + 1) * ((j + dj) + (ny + 1) * (k + dk)) for di in (0, 1) for dj in (0, 1) for dk in (0, 1)]
+        nodal = np.vstack([pts[ids], U[[c, m.n_cells + c, 2 * m.n_cells + c]][None, :]])
+        lo, hi = nodal.min(axis=0) - 1e-14, nodal.max(axis=0) + 1e-14
+        for _ in range(10):
+            x = xc[c] + rng.uniform(-0.49, 0.49, 3) * h
+            u = om.cell_point_velocity(c, U, x)
+            assert np.all(u >= lo) and np.all(u <= hi), (c, x, u, lo, hi)
