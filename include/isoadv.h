@@ -83,6 +83,15 @@ typedef struct {
     int32_t bound_blocks;   /* work-groups of the bounding sweeps (0 = 512); at most 65535.
                                Results are bitwise the same for every choice of the launch shapes
                                block_cells, surface_blocks, surface_waves and bound_blocks. */
+    int32_t us_mode;        /* isoface velocity U_S (Section 3.2 interpolates the cell velocity to
+                               the isoface centre x_S and names no scheme): 0 = U_P, the cell value
+                               (default); 1 = cell-point interpolation: point velocities with the
+                               inverse-distance weights of the vertex values, the cell split into
+                               tetrahedra (cell centre, vertex mean of a face, two consecutive face
+                               points) carrying U_P, the face's mean point velocity and the point
+                               velocities, and the linear interpolant at x_S in the tetrahedron
+                               with the largest smallest barycentric coordinate.  The adjoint
+                               takes us_mode 0 only (ISO_EUNSUPPORTED). */
 } iso_options;
 
 typedef struct {
@@ -143,6 +152,16 @@ iso_status iso_advect_step(iso_plan *plan, const double *alpha, const double *ph
 /* Same step, also writing the intermediates named in trace (device pointers). */
 iso_status iso_advect_step_traced(iso_plan *plan, const double *alpha, const double *phi, const double *U,
                                   double dt, double *alpha_new, iso_step_stats *stats, const iso_trace *trace);
+/* The step of an outer (nonlinear) iteration, second order in time (Crank-Nicolson, end of
+ * Section 3.2): the fluxes and velocities are the time averages (phi0 + phi1)/2 and (U0 + U1)/2
+ * of the fields at t (phi0, U0) and the current estimates at t + dt (phi1, U1), formed as the
+ * kernels read them (no averaged copy is written).  Layouts as iso_advect_step; all DEVICE arrays;
+ * alpha_new must not overlap any input.  The result is bit for bit iso_advect_step with the
+ * averaged fields.  For its adjoint, call iso_advect_step_adjoint with the averaged fields: each
+ * level's phi_bar is then half the returned one. */
+iso_status iso_advect_step_avg(iso_plan *plan, const double *alpha, const double *phi0, const double *phi1,
+                               const double *U0, const double *U1, double dt, double *alpha_new,
+                               iso_step_stats *stats);
 
 /* Adjoint of one step (vector-Jacobian product; differentiation is not part of the paper's
  * method).  Given alpha_new_bar = dL/d alpha_new for the step iso_advect_step(alpha, phi, U, dt)

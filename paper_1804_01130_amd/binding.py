@@ -30,7 +30,7 @@ class IsoOptions(C.Structure):
                 ("max_courant", C.c_double), ("root_max_iter", C.c_int32), ("n_bound_iter", C.c_int32),
                 ("clip", C.c_int32), ("check_inputs", C.c_int32), ("block_cells", C.c_int32),
                 ("surface_blocks", C.c_int32), ("max_surface", C.c_int32), ("surface_waves", C.c_int32),
-                ("bound_blocks", C.c_int32)]
+                ("bound_blocks", C.c_int32), ("us_mode", C.c_int32)]
 
 
 class IsoStepStats(C.Structure):
@@ -96,6 +96,8 @@ def lib():
         L.iso_advect_step_traced.argtypes = [_vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats),
                                              C.POINTER(IsoTrace)]
         L.iso_advect_step_traced.restype = C.c_int
+        L.iso_advect_step_avg.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats)]
+        L.iso_advect_step_avg.restype = C.c_int
         L.iso_advect_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, C.c_double, C.POINTER(IsoTrace), _vp, _vp, _vp]
         L.iso_advect_step_adjoint.restype = C.c_int
         L.iso_plan_set_timing.argtypes = [_vp, C.c_int32]
@@ -256,14 +258,23 @@ class Plan:
     def set_stream(self, stream):
         check(lib().iso_plan_set_stream(self.h, _stream_handle(stream)))
 
-    def step(self, alpha, phi, U, dt, out=None, stats=False, trace=None):
-        """alpha_new = isoAdvector step (device tensors, float64).  Returns (alpha_new, stats dict or None)."""
+    def step(self, alpha, phi, U, dt, out=None, stats=False, trace=None, phi1=None, U1=None):
+        """alpha_new = isoAdvector step (device tensors, float64).  Returns (alpha_new, stats dict or None).
+        phi1, U1: the fields' estimates at t + dt of an outer iteration; the step then uses the
+        averages (phi + phi1)/2 and (U + U1)/2 (iso_advect_step_avg; no trace)."""
         import torch
         if out is None:
             out = torch.empty_like(alpha)
         st = IsoStepStats() if stats else None
         self.set_stream(None)
-        if trace is None:
+        if (phi1 is None) != (U1 is None):
+            raise ValueError("phi1 and U1 go together")
+        if phi1 is not None:
+            if trace is not None:
+                raise ValueError("the averaged-field step takes no trace")
+            check(lib().iso_advect_step_avg(self.h, _ptr(alpha), _ptr(phi), _ptr(phi1), _ptr(U), _ptr(U1), float(dt),
+                                            _ptr(out), C.byref(st) if st is not None else None))
+        elif trace is None:
             check(lib().iso_advect_step(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt), _ptr(out),
                                         C.byref(st) if st is not None else None))
         else:

@@ -160,9 +160,9 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     b->u = u;
     u->device = dev;
     DevMesh &d = u->dev;
-    double *cxyz, *vol, *st_w, *palpha;
+    double *cxyz, *vol, *st_w, *palpha, *ccen;
     int32_t *cpt, *sface, *snbr, *lface, *cflags, *st_ptr, *st_cell, *dom_off;
-    if (!dev_alloc(u, &cxyz, 24 * N) || !dev_alloc(u, &vol, N) || !dev_alloc(u, &st_w, S) ||
+    if (!dev_alloc(u, &cxyz, 24 * N) || !dev_alloc(u, &vol, N) || !dev_alloc(u, &st_w, S) || !dev_alloc(u, &ccen, 3 * N) ||
         !dev_alloc(u, &palpha, std::max<int64_t>(P, 1)) || !dev_alloc(u, &cpt, 8 * N) ||
         !dev_alloc(u, &sface, (int64_t)W * N) || !dev_alloc(u, &snbr, (int64_t)W * N) || !dev_alloc(u, &lface, 6 * N) ||
         !dev_alloc(u, &cflags, N) || !dev_alloc(u, &st_ptr, K + 1) || !dev_alloc(u, &st_cell, S) ||
@@ -184,6 +184,7 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         const int64_t nc = m->n_cells;
         ok(hipMemcpyAsync(cxyz + 24 * co, md.cxyz, 24 * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
         ok(hipMemcpyAsync(vol + co, md.vol, nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+        ok(hipMemcpyAsync(ccen + 3 * co, md.ccen, 3 * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
         ok(hipMemcpyAsync(cflags + co, md.cflags, nc * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         ok(launch_offset_copy(md.cpt, cpt + 8 * co, 8 * nc, 0, (int32_t)ko, 0, s));
         for (int k = 0; k < W; ++k) {
@@ -218,6 +219,7 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     d.n_cells = (int32_t)N; d.n_faces = (int32_t)F; d.n_classes = (int32_t)K; d.W = W; d.n_patches = (int32_t)P;
     d.cxyz = cxyz; d.cpt = cpt; d.vol = vol; d.slot_face = sface; d.slot_nbr = snbr; d.lface = lface;
     d.cflags = cflags; d.st_ptr = st_ptr; d.st_cell = st_cell; d.st_w = st_w; d.patch_alpha = palpha;
+    d.ccen = ccen;
     d.n_dom = n; d.dom_off = dom_off;
     u->n_cells = (int32_t)N; u->n_faces = (int32_t)F; u->n_classes = (int32_t)K; u->W = W;
     u->n_flux = (int32_t)NF; u->st_nnz = S;

@@ -34,6 +34,7 @@ struct DevMesh {
     const int32_t *st_cell = nullptr;
     const double *st_w = nullptr;        // normalised inverse-distance weights
     const double *patch_alpha = nullptr; // [n_patches]
+    const double *ccen = nullptr;        // [3*n_cells] cell centroids (same frame as cxyz), AoS
     // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;
@@ -77,6 +78,10 @@ struct StepArgs {
     double *alpha_new;
     double dt;
     const double *dt_dom;  // [n_dom] per-member time steps of an ensemble, or nullptr
+    // second time level of an outer iteration (or nullptr): the kernels read (phi + phi1)/2 and
+    // (U + U1)/2
+    const double *phi1 = nullptr;
+    const double *U1 = nullptr;
 };
 
 // Launch shapes of a step (none of them changes a result).
@@ -90,6 +95,7 @@ struct LaunchCfg {
 struct Params {
     double eps_surf, flat_tol, bound_tol;
     int32_t root_max_iter, n_bound_iter, clip;
+    int32_t us_mode;  // 0: U_S = U_P; 1: cell-point interpolation to x_S
 };
 
 // Adjoint workspace (device pointers; allocated by a plan on its first adjoint step).  S = number of

@@ -406,6 +406,18 @@ __global__ void __launch_bounds__(kFindBlock) k_find_surface(const double *__res
     }
 }
 
+// The flux of face f and the velocity of cell c; with a second time level (outer iterations,
+// Crank-Nicolson) their averages, formed as they are read.
+template <bool kAvg>
+__device__ __forceinline__ double flux_at(const double *phi, const double *phi1, int32_t f) {
+    if constexpr (kAvg) return 0.5 * (phi[f] + phi1[f]);
+    else return phi[f];
+}
+__device__ __forceinline__ D3 vel_at(const double *U, const double *U1, int32_t c, size_t n) {
+    if (U1) return D3{0.5 * (U[c] + U1[c]), 0.5 * (U[n + c] + U1[n + c]), 0.5 * (U[2 * n + c] + U1[2 * n + c])};
+    return D3{U[c], U[n + c], U[2 * n + c]};
+}
+
 struct SurfArgs {
     DevMesh m;
     const double *alpha, *phi, *U;
@@ -419,11 +431,70 @@ struct SurfArgs {
     double *dvs;
     int want_stats;
     iso_trace tr;
+    const double *phi1, *U1;  // second time level, or nullptr
 };
+
+// U_S . n_S of interface cell c (all lanes of its group).  U_S = U_P, or with us_mode 1 the
+// cell-point interpolation of the velocity to x_S: lane v takes vertex v's velocity with the
+// inverse-distance weights of the vertex values; face lane k splits its face about the vertex
+// mean into four tetrahedra with the cell centre, carrying U_P, the face's mean vertex velocity
+// and the two vertex velocities; each lane keeps the tetrahedron whose smallest barycentric
+// coordinate of x_S (Cramer's rule) is largest, and the group takes the best (lowest lane on a
+// tie).  Coordinates relative to the vertex mean xm.
+template <bool kInterp>
+__device__ __forceinline__ double isoface_speed(const SurfArgs &A, int32_t c, int lv, const FaceLane &f,
+                                                const int *fv, D3 xm, D3 xS, D3 nS) {
+    const DevMesh &m = A.m;
+    const size_t n = m.n_cells;
+    const D3 Up = vel_at(A.U, A.U1, c, n);
+    D3 Us = Up;
+    if constexpr (kInterp) {
+        D3 uv{0, 0, 0};
+        {
+            const int k = m.cpt[8 * (size_t)c + lv];
+            for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e) uv = uv + m.st_w[e] * vel_at(A.U, A.U1, m.st_cell[e], n);
+        }
+        D3 uq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) uq[i] = D3{grp_get(uv.x, fv[i]), grp_get(uv.y, fv[i]), grp_get(uv.z, fv[i])};
+        const D3 cc = D3{m.ccen[3 * (size_t)c], m.ccen[3 * (size_t)c + 1], m.ccen[3 * (size_t)c + 2]} - xm;
+        double best = -INFINITY;
+        D3 val = Up;
+        if (f.active) {
+            const D3 fc = 0.25 * (f.q[0] + f.q[1] + f.q[2] + f.q[3]);
+            const D3 uf = 0.25 * (uq[0] + uq[1] + uq[2] + uq[3]);
+            const D3 e1 = fc - cc, r = xS - cc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = (i + 1) & 3;
+                const D3 e2 = f.q[i] - cc, e3 = f.q[j] - cc;
+                const D3 k23 = cross(e2, e3);
+                const double det = dot(e1, k23);
+                if (det == 0.0) continue;
+                const double l1 = dot(r, k23) / det, l2 = dot(e1, cross(r, e3)) / det, l3 = dot(e1, cross(e2, r)) / det;
+                const double l0 = 1.0 - l1 - l2 - l3;
+                const double mn = fmin(fmin(l0, l1), fmin(l2, l3));
+                if (mn > best) {
+                    best = mn;
+                    val = l0 * Up + l1 * uf + l2 * uq[i] + l3 * uq[j];
+                }
+            }
+        }
+        double gb = best;
+#pragma unroll
+        for (int o = 1; o < kLanes; o <<= 1) gb = fmax(gb, __shfl_xor(gb, o, kLanes));
+        const uint64_t bal = __ballot(best == gb);
+        const uint32_t gm = (uint32_t)(bal >> (__lane_id() & ~(kLanes - 1))) & 0xFFu;
+        const int win = __ffs(gm) - 1;
+        Us = D3{grp_get(val.x, win), grp_get(val.y, win), grp_get(val.z, win)};
+    }
+    return Us.x * nS.x + Us.y * nS.y + Us.z * nS.z;
+}
 
 
 // kMinBlocks: work-groups of 256 per CU the register allocation must allow (waves per SIMD)
-template <int kMinBlocks>
+// kInterp: U_S by cell-point interpolation (us_mode 1) instead of U_P
+template <int kMinBlocks, bool kInterp>
 __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
     const DevMesh &m = A.m;
     const int lv = threadIdx.x & (kLanes - 1);
@@ -621,7 +692,6 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                         acc = grp_sum3(acc);
                         ws = grp_sum(ws);
                         xS = (1.0 / (3.0 * ws)) * acc;
-                        un = A.U[c] * nS.x + A.U[m.n_cells + c] * nS.y + A.U[2 * (size_t)m.n_cells + c] * nS.z;
                         face_done = true;
                     }
                 }
@@ -675,11 +745,11 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 acc = grp_sum3(acc);
                 ws = grp_sum(ws);
                 xS = (1.0 / (3.0 * ws)) * acc;
-                un = A.U[c] * nS.x + A.U[m.n_cells + c] * nS.y + A.U[2 * (size_t)m.n_cells + c] * nS.z;
             } else {
                 recon = false;
             }
         }
+        if (recon) un = isoface_speed<kInterp>(A, c, lv, f, fv, xm, xS, nS);
         if (lv == 0) {
             if (!recon) ++flat;
             rounds_max = max(rounds_max, rounds);
@@ -700,7 +770,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
             const int32_t v = m.lface[6 * (size_t)c + lv];
             if (v != kEmpty) {
                 const int32_t fid = v >= 0 ? v : ~v;
-                const double ph = A.phi[fid];
+                const double ph = A.phi1 ? flux_at<true>(A.phi, A.phi1, fid) : flux_at<false>(A.phi, A.phi1, fid);
                 const double out = v >= 0 ? ph : -ph;
                 if (out > 0.0) {
                     double dv;
@@ -763,6 +833,7 @@ struct UpdArgs {
     double *trace_dV, *trace_raw;
     int n_iter;  // redistribution sweeps; with one or more the update runs the first sweep's phase A
     DevWork w;
+    const double *phi1;  // second time level of the fluxes, or nullptr
 };
 
 // Bounding counters of sweep `it` live in one of four rotating slots: a slot is filled by the
@@ -782,7 +853,7 @@ __device__ __forceinline__ int32_t *dlist_buf(const DevWork &w, int s, int nf) {
 // Any block size up to 1024 (the block_cells option) is valid.  A cell left out of bounds also
 // runs phase A of the first redistribution sweep (see k_bound_sweep) here: no face is marked yet,
 // so the current dV of each of its outflow faces is the one just computed.
-template <int W>
+template <int W, bool kAvg>
 __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     const int n = A.m.n_cells;
     const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -808,7 +879,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const int32_t fid = v[k] >= 0 ? v[k] : ~v[k];
-            ph[k] = v[k] != kEmpty ? A.phi[fid] : 0.0;
+            ph[k] = v[k] != kEmpty ? flux_at<kAvg>(A.phi, A.phi1, fid) : 0.0;
             ao[k] = o[k] >= 0 ? A.alpha[o[k]] : (v[k] != kEmpty ? A.m.patch_alpha[-1 - o[k]] : 0.0);
         }
         const bool sP = interface_cell(aP, A.eps);
@@ -917,6 +988,7 @@ struct BoundArgs {
     int clip, n_iter;
     double *alpha_new;
     DevWork w;
+    const double *phi1;  // second time level of the fluxes, or nullptr
 };
 
 // Redistribution sweeps (Jacobi), two phases per sweep.  (A) every cell out of bounds computes the
@@ -927,7 +999,7 @@ struct BoundArgs {
 // after phase B of sweep s runs phase A of sweep s+1 at once: one kernel per sweep (phase A of
 // sweep 0 runs inside the update).  Touched lists and marks alternate between two banks, counter
 // slots rotate over four.  List order never affects a result.
-template <int W>
+template <int W, bool kAvg>
 __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
     const int n = A.m.n_cells, nf = A.m.n_faces;
     int32_t *counters = A.w.counters;
@@ -997,7 +1069,7 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
             for (int k = 0; k < W; ++k) {
                 nbr[k] = A.m.slot_nbr[(size_t)k * n + Q];
                 fid[k] = v[k] >= 0 ? v[k] : ~v[k];
-                ph[k] = v[k] != kEmpty ? A.phi[fid[k]] : 0.0;
+                ph[k] = v[k] != kEmpty ? flux_at<kAvg>(A.phi, A.phi1, fid[k]) : 0.0;
             }
             const bool over = x > 1.0 + A.tol;
             const double aold = A.alpha[Q];
@@ -1121,14 +1193,14 @@ __global__ void __launch_bounds__(1024) k_stats(const double *alpha, const doubl
     if (t == 0) { red[0] = sb[0]; red[1] = sa[0]; red[2] = smin[0]; red[3] = smax[0]; red[4] = 0.0; }
 }
 
-template <int W>
+template <int W, bool kAvg>
 void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, const LaunchCfg &cfg, hipStream_t s,
                  hipEvent_t *ev) {
     const int gc = (m.n_cells + cfg.block_cells - 1) / cfg.block_cells;
-    hipLaunchKernelGGL(k_update<W>, dim3(gc), dim3(cfg.block_cells), 0, s, ua);  // and sweep 0's phase A
+    hipLaunchKernelGGL((k_update<W, kAvg>), dim3(gc), dim3(cfg.block_cells), 0, s, ua);  // and sweep 0's phase A
     if (ev) (void)hipEventRecord(ev[3], s);
     for (int it = 0; it < ba.n_iter; ++it)
-        hipLaunchKernelGGL(k_bound_sweep<W>, dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
+        hipLaunchKernelGGL((k_bound_sweep<W, kAvg>), dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
     hipLaunchKernelGGL(k_bound_end, dim3(1), dim3(1024), 0, s, ba);
 }
 
@@ -1167,30 +1239,46 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
                        w.counters, tr.kind);
     if (ev) (void)hipEventRecord(ev[1], s);
     SurfArgs sa{m, a.alpha, a.phi, a.U, a.dt, a.dt_dom, p.eps_surf, p.flat_tol, p.root_max_iter, w.surf, w.counters,
-                w.cap, w.dvs, want_stats ? 1 : 0, tr};
+                w.cap, w.dvs, want_stats ? 1 : 0, tr, a.phi1, a.U1};
     const int bs = 256;  // the interface kernel's register budget assumes 256-thread work-groups
     const long groups_per_block = bs / kLanes;
     long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
     // persistent: groups loop over the list, which is only known on the device
     gs = std::max(1L, std::min(gs, cfg.surface_blocks > 0 ? (long)cfg.surface_blocks : 2048L));
-    switch (cfg.surface_waves) {
-        case 1: hipLaunchKernelGGL(k_surface<1>, dim3((int)gs), dim3(bs), 0, s, sa); break;
-        case 3: hipLaunchKernelGGL(k_surface<3>, dim3((int)gs), dim3(bs), 0, s, sa); break;
-        case 4: hipLaunchKernelGGL(k_surface<4>, dim3((int)gs), dim3(bs), 0, s, sa); break;
-        default: hipLaunchKernelGGL(k_surface<2>, dim3((int)gs), dim3(bs), 0, s, sa); break;
+    if (p.us_mode == 1) {
+        switch (cfg.surface_waves) {
+            case 1: hipLaunchKernelGGL((k_surface<1, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 3: hipLaunchKernelGGL((k_surface<3, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 4: hipLaunchKernelGGL((k_surface<4, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            default: hipLaunchKernelGGL((k_surface<2, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+        }
+    } else {
+        switch (cfg.surface_waves) {
+            case 1: hipLaunchKernelGGL((k_surface<1, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 3: hipLaunchKernelGGL((k_surface<3, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 4: hipLaunchKernelGGL((k_surface<4, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            default: hipLaunchKernelGGL((k_surface<2, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+        }
     }
     if (ev) (void)hipEventRecord(ev[2], s);
     UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist,
-               w.counters, tr.dV, tr.alpha_raw, p.n_bound_iter, w};
+               w.counters, tr.dV, tr.alpha_raw, p.n_bound_iter, w, a.phi1};
     BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
-                 a.alpha_new, w};
-    switch (m.W) {
-        case 1: launch_wide<1>(m, ua, ba, cfg, s, ev); break;
-        case 2: launch_wide<2>(m, ua, ba, cfg, s, ev); break;
-        case 3: launch_wide<3>(m, ua, ba, cfg, s, ev); break;
-        case 4: launch_wide<4>(m, ua, ba, cfg, s, ev); break;
-        case 5: launch_wide<5>(m, ua, ba, cfg, s, ev); break;
-        default: launch_wide<6>(m, ua, ba, cfg, s, ev); break;
+                 a.alpha_new, w, a.phi1};
+    const bool avg = a.phi1 != nullptr;
+    switch (m.W * 2 + (avg ? 1 : 0)) {
+        case 2: launch_wide<1, false>(m, ua, ba, cfg, s, ev); break;
+        case 3: launch_wide<1, true>(m, ua, ba, cfg, s, ev); break;
+        case 4: launch_wide<2, false>(m, ua, ba, cfg, s, ev); break;
+        case 5: launch_wide<2, true>(m, ua, ba, cfg, s, ev); break;
+        case 6: launch_wide<3, false>(m, ua, ba, cfg, s, ev); break;
+        case 7: launch_wide<3, true>(m, ua, ba, cfg, s, ev); break;
+        case 8: launch_wide<4, false>(m, ua, ba, cfg, s, ev); break;
+        case 9: launch_wide<4, true>(m, ua, ba, cfg, s, ev); break;
+        case 10: launch_wide<5, false>(m, ua, ba, cfg, s, ev); break;
+        case 11: launch_wide<5, true>(m, ua, ba, cfg, s, ev); break;
+        case 13: launch_wide<6, true>(m, ua, ba, cfg, s, ev); break;
+        default: launch_wide<6, false>(m, ua, ba, cfg, s, ev); break;
     }
     if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();

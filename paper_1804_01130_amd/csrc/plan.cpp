@@ -97,7 +97,7 @@ LaunchCfg launch_cfg(const iso_options &o) {
     return c;
 }
 Params step_params(const iso_options &o) {
-    return Params{o.eps_surf, o.flat_tol, o.bound_tol, o.root_max_iter, o.n_bound_iter, o.clip};
+    return Params{o.eps_surf, o.flat_tol, o.bound_tol, o.root_max_iter, o.n_bound_iter, o.clip, o.us_mode};
 }
 }  // namespace isoadv
 
@@ -432,7 +432,8 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||
         (st = upload(m, slot_face, &d.slot_face)) || (st = upload(m, slot_nbr, &d.slot_nbr)) ||
         (st = upload(m, lface, &d.lface)) || (st = upload(m, cflags, &d.cflags)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
-        (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha))) {
+        (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha)) ||
+        (st = upload(m, m->xc, &d.ccen))) {
         iso_mesh_destroy(m);
         return st;
     }
@@ -480,7 +481,7 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
     if (!(o.eps_surf >= 0 && o.eps_surf < 0.5) || !(o.flat_tol >= 0) || !(o.bound_tol >= 0) || o.root_max_iter < 1 ||
         o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 ||
         o.surface_blocks < 0 || o.surface_blocks > 65535 || o.bound_blocks < 0 || o.bound_blocks > 65535 ||
-        o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4) {
+        o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1) {
         delete p;
         return fail(ISO_EINVAL, "bad options");
     }
@@ -550,22 +551,26 @@ static iso_status check_inputs_host(iso_plan *p, const double *alpha, const doub
     return ISO_OK;
 }
 
+// phi1/U1: the second time level of an outer iteration (both or neither), averaged in the kernels
 static iso_status step_impl(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt,
-                            double *alpha_new, iso_step_stats *stats, const iso_trace *trace) {
+                            double *alpha_new, iso_step_stats *stats, const iso_trace *trace,
+                            const double *phi1 = nullptr, const double *U1 = nullptr) {
     if (!p) return fail(ISO_EINVAL, "null plan");
     if (!alpha || !phi || !U || !alpha_new) return fail(ISO_EINVAL, "null array");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(ISO_EINVAL, "dt must be positive and finite");
     const iso_mesh *m = p->mesh;
     size_t nc = (size_t)m->n_cells * 8, nf = (size_t)m->n_faces * 8;
-    if (overlaps(alpha_new, nc, alpha, nc) || overlaps(alpha_new, nc, phi, nf) || overlaps(alpha_new, nc, U, 3 * nc))
+    if (overlaps(alpha_new, nc, alpha, nc) || overlaps(alpha_new, nc, phi, nf) || overlaps(alpha_new, nc, U, 3 * nc) ||
+        (phi1 && overlaps(alpha_new, nc, phi1, nf)) || (U1 && overlaps(alpha_new, nc, U1, 3 * nc)))
         return fail(ISO_EINVAL, "alpha_new overlaps an input");
-    if (p->opt.check_inputs) {
+    if (p->opt.check_inputs) {  // each level within the limits: so is their average
         iso_status s = check_inputs_host(p, alpha, phi, U, dt);
+        if (s == ISO_OK && phi1) s = check_inputs_host(p, alpha, phi1, U1, dt);
         if (s != ISO_OK) return s;
     }
     (void)hipGetLastError();
     const Params prm = step_params(p->opt);
-    StepArgs args{alpha, phi, U, alpha_new, dt, nullptr};
+    StepArgs args{alpha, phi, U, alpha_new, dt, nullptr, phi1, U1};
     hipEvent_t *ev = nullptr;
     if (p->timing_used < p->timing_cap) ev = &p->events[5 * (size_t)p->timing_used++];
     hipError_t e = launch_step(m->dev, p->work, prm, args, trace, launch_cfg(p->opt), stats != nullptr, p->stream, ev);
@@ -613,6 +618,13 @@ iso_status iso_advect_step_traced(iso_plan *p, const double *alpha, const double
     return step_impl(p, alpha, phi, U, dt, alpha_new, stats, trace);
 }
 
+iso_status iso_advect_step_avg(iso_plan *p, const double *alpha, const double *phi0, const double *phi1,
+                               const double *U0, const double *U1, double dt, double *alpha_new,
+                               iso_step_stats *stats) {
+    if (!phi1 || !U1) return fail(ISO_EINVAL, "null array");
+    return step_impl(p, alpha, phi0, U0, dt, alpha_new, stats, nullptr, phi1, U1);
+}
+
 static iso_status adj_alloc(iso_plan *p) {
     if (p->adj_ready) return ISO_OK;
     const iso_mesh *m = p->mesh;
@@ -649,6 +661,7 @@ iso_status iso_advect_step_adjoint(iso_plan *p, const double *alpha, const doubl
     if (!(dt > 0) || !std::isfinite(dt)) return fail(ISO_EINVAL, "dt must be positive and finite");
     if (p->opt.n_bound_iter > kAdjMaxSweeps)
         return fail(ISO_EUNSUPPORTED, "the adjoint takes at most " + std::to_string(kAdjMaxSweeps) + " bounding sweeps");
+    if (p->opt.us_mode != 0) return fail(ISO_EUNSUPPORTED, "the adjoint takes U_S = U_P (us_mode 0) only");
     if (fwd && (!fwd->vert_alpha || !fwd->kind || !fwd->iso || !fwd->dV || !fwd->alpha_raw))
         return fail(ISO_EINVAL, "forward trace needs vert_alpha, kind, iso, dV and alpha_raw");
     const iso_mesh *m = p->mesh;

@@ -23,6 +23,7 @@ def test_status_strings_and_defaults():
         assert L.iso_status_string(s)
     o = B.default_options()
     assert o.eps_surf == 1e-8 and o.n_bound_iter == 3 and o.clip == 1 and o.root_max_iter == 100
+    assert o.us_mode == 0  # U_S = U_P unless cell-point interpolation is asked for
 
 
 def _create(m, **over):
