@@ -45,13 +45,13 @@ KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_upda
 # the commands whose rocprofv3 output --summarize-profiles reads
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
-             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble --no-adjoint",
+             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble --no-adjoint --no-variants",
     "fetch": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
     "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
 }
 
 
@@ -231,7 +231,7 @@ def summarize_profiles(workload):
              f"kernel_source_sha: {shas.pop()}",
              f"scale_fetch: {sf:.6f}",
              f"scale_write: {sw:.6f}"]
-    for k in ("find_surface", "surface", "update", "bound_sweep_corrections", "bound_sweep_apply", "bound_end"):
+    for k in ("find_surface", "surface", "update", "bound_sweep", "bound_end"):
         if k not in fetch or k not in write:
             continue
         fk = float(np.mean(fetch[k]))
@@ -329,6 +329,39 @@ def ensemble_bench(steps, warmup, tune_cache=None):
     return out
 
 
+def variants_bench(gm, w, phis, Us, sel, a_start, args):
+    """The same K steps from the same state with the step's variants: the isoface velocity by
+    cell-point interpolation (us_mode 1), and the averaged fields of an outer iteration (the
+    fields of the step and of the next one, averaged as the kernels read them)."""
+    import torch
+    from paper_1804_01130_amd import Plan, default_options
+    out = {}
+    for name, us_mode, avg in (("us_mode_1", 1, False), ("averaged_fields", 0, True)):
+        plan = Plan(gm, default_options(us_mode=us_mode))
+        a = a_start.clone()
+        b = torch.empty_like(a)
+        nxt = (lambda n: 0) if w.steady else (lambda n: min(n + 1, len(phis) - 1))
+        kw = lambda n: dict(phi1=phis[nxt(n)], U1=Us[nxt(n)]) if avg else {}
+        for n in range(args.warmup):  # warm-up from the same state, then restart
+            plan.step(a, phis[sel(n)], Us[sel(n)], w.dt, out=b, **kw(n))
+            a, b = b, a
+        a.copy_(a_start)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for n in range(args.warmup, args.warmup + args.steps):
+            plan.step(a, phis[sel(n)], Us[sel(n)], w.dt, out=b, **kw(n))
+            a, b = b, a
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out[name] = {"ms_per_step": ms, "cell_steps_per_s": w.mesh.n_cells / (ms * 1e-3)}
+        log(f"[bench] variant {name}: {ms * 1e3:.1f} us/step")
+        plan.close()
+        del a, b
+    return out
+
+
 def adjoint_bench(every=10):
     """The adjoint workload: 256x128 Airy, 50 steps, loss sum (alpha_T - alpha_target)^2; time of the
     forward pass (plain steps) and of the backward pass (recomputing each segment from its checkpoint
@@ -391,6 +424,8 @@ def main():
                     help="after timing, run a plain copy kernel of known size (scale of the HBM counters)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-vs-plain ensemble measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the interpolated isoface velocity and averaged-field step timings")
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
@@ -453,6 +488,7 @@ def main():
         a, b = b, a
     torch.cuda.synchronize()
     kms, nrec = plan.timing()
+    variants = None if args.no_variants else variants_bench(gm, w, phis, Us, sel, a_start, args)
     del a_start
     ms_per_step = ms / args.steps
     cells = w.mesh.n_cells
@@ -510,6 +546,7 @@ def main():
         "kernel_ms_per_step": {k: v / max(nrec, 1) for k, v in kms.items()},
         "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
+        "variants": variants,
         "ensemble": ens,
         "adjoint": adj,
     }
