@@ -59,6 +59,13 @@
  *       velocities; the linear interpolant in the tetrahedron with the largest
  *       smallest barycentric coordinate of x_S (the one containing it).  us_mode 0
  *       keeps U_S = U_P (R6).
+ *   R16 ghost-fluid faces after advection (Eqs. 12-20): the jump H = p_d^- - p_d^+
+ *       at x_Gamma is (rho^+ - rho^-) g . x_Gamma, which Eq. 3 (p_d = p - rho g . x) with
+ *       a continuous pressure and Eq. 7 give; Eq. 15 as printed has the opposite sign.
+ *       A cell is wet iff alpha > 1/2; lambda (Eq. 13) is measured from the face's owner,
+ *       beta_w (Eq. 18) from its heavy cell; the ghost values are the heavy fluid's p_d
+ *       extended to the dry cell (Eq. 20) and the light fluid's extended to the wet cell
+ *       (the mirror of Eqs. 17-20).
  */
 #include <math.h>
 #include <stdint.h>
@@ -1050,6 +1057,51 @@ int or_cell_cut_flat(const or_mesh *m, int c, const double *a_pts, double iso, d
     for (int d = 0; d < 3; ++d) { out[1 + d] = cut.S[d]; out[4 + d] = cut.xS[d]; out[7 + d] = cut.Swet[d]; }
     out[10] = cut.n_cut;
     return r;
+}
+
+/* ------------------------------------------------------------------ R16 ghost-fluid faces
+ * For every flux-carrying face with a cell on each side (internal faces and the flux face of a
+ * cyclic pair, the far cell's centre translated into the owner's frame), lambda (Eq. 13) when the
+ * two cells lie on opposite sides of alpha = 1/2, else -1; the interface point x_Gamma (Eq. 12),
+ * the jump H = p_d^- - p_d^+ there (R16), beta_w (Eq. 18, lambda measured from the heavy cell),
+ * and the ghost values: ghost_nbr = p_d at the neighbour's centre seen from the owner's fluid,
+ * ghost_own = p_d at the owner's centre seen from the neighbour's fluid (Eq. 20 for the heavy
+ * fluid's side, its mirror for the light fluid's).  Away from the interface (and on faces with
+ * one cell) the ghost values are the plain cell values (p_d of the owner where there is no
+ * neighbour), jump and beta_w are 0. */
+void or_gfm_faces(const or_mesh *m, const double *alpha, const double *p_d, double rho_heavy, double rho_light,
+                  const double *g, double *lambda, double *jump, double *beta_w, double *ghost_own,
+                  double *ghost_nbr) {
+    const double bp = 1.0 / rho_heavy, bm = 1.0 / rho_light;  /* Eq. 14 */
+    for (int f = 0; f < m->n_faces; ++f) {
+        int P = m->owner[f];
+        lambda[f] = -1.0; jump[f] = 0.0; beta_w[f] = 0.0;
+        ghost_own[f] = p_d[P]; ghost_nbr[f] = p_d[P];
+        if (m->flux_id[f] != f || m->flux_other[f] < 0) continue;
+        int N = m->flux_other[f];
+        double xN[3];
+        for (int d = 0; d < 3; ++d) xN[d] = m->xc[3 * N + d];
+        if (f >= m->n_internal) {  /* cyclic: the far cell's centre in the owner's frame */
+            int p = m->fpatch[f];
+            for (int d = 0; d < 3; ++d) xN[d] -= m->ptrans[3 * p + d];
+        }
+        ghost_nbr[f] = p_d[N];
+        double aP = alpha[P], aN = alpha[N];
+        int wetP = aP > 0.5, wetN = aN > 0.5;
+        if (wetP == wetN) continue;
+        double lam = (aP - 0.5) / (aP - aN);  /* Eq. 13 */
+        double xG[3];
+        for (int d = 0; d < 3; ++d) xG[d] = m->xc[3 * P + d] + lam * (xN[d] - m->xc[3 * P + d]);  /* Eq. 12 */
+        double H = (rho_heavy - rho_light) * v_dot(g, xG);  /* R16 */
+        double lw = wetP ? lam : 1.0 - lam;                  /* distance fraction from the heavy cell */
+        double bw = lw * bm + (1.0 - lw) * bp;               /* Eq. 18 */
+        double pW = wetP ? p_d[P] : p_d[N], pD = wetP ? p_d[N] : p_d[P];
+        double to_dry = (bm / bw) * pD + (1.0 - bm / bw) * pW - (bm / bw) * H;  /* Eq. 20 */
+        double to_wet = (bp / bw) * pW + (1.0 - bp / bw) * pD + (bp / bw) * H;  /* its mirror */
+        lambda[f] = lam; jump[f] = H; beta_w[f] = bw;
+        ghost_nbr[f] = wetP ? to_dry : to_wet;
+        ghost_own[f] = wetP ? to_wet : to_dry;
+    }
 }
 
 /* ==================================================================================================

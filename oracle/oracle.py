@@ -88,6 +88,7 @@ def lib():
         L.or_step_tlm.argtypes = [C.c_void_p, C.POINTER(Opts), _dp, _dp, _dp, C.c_double, _dp, _dp, _dp, _dp]
         L.or_step_tlm.restype = C.c_int
         L.or_cell_point_velocity.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.or_gfm_faces.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -194,6 +195,17 @@ class OracleMesh:
         x = np.ascontiguousarray(x, dtype=np.float64)
         out = np.zeros(3)
         lib().or_cell_point_velocity(self.h, int(c), _d(U), _d(x), _d(out))
+        return out
+
+    def gfm_faces(self, alpha, p_d, rho_heavy, rho_light, g):
+        """Ghost-fluid face data (Eqs. 12-20, reading R16) per face: dict of lambda, jump, beta_w,
+        ghost_own and ghost_nbr, each [n_faces]."""
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        p_d = np.ascontiguousarray(p_d, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        out = {k: np.zeros(self.n_faces) for k in ("lambda", "jump", "beta_w", "ghost_own", "ghost_nbr")}
+        lib().or_gfm_faces(self.h, _d(alpha), _d(p_d), float(rho_heavy), float(rho_light), _d(g),
+                           *(_d(out[k]) for k in ("lambda", "jump", "beta_w", "ghost_own", "ghost_nbr")))
         return out
 
     def face_integral(self, f, c, xS, nS, un, dt):

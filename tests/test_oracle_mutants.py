@@ -48,6 +48,19 @@ TANGENT_MUTANTS = [
      "cplx need = over ? (1.0 - a) * m->V[c] : -a * m->V[c];"),
 ]
 
+# planted mistakes in the ghost-fluid face data (Eqs. 12-20), which its own pins must reject
+GFM_MUTANTS = [
+    ("gfm_jump_sign_as_printed", "double H = (rho_heavy - rho_light) * v_dot(g, xG);",
+     "double H = (rho_light - rho_heavy) * v_dot(g, xG);"),
+    ("gfm_lambda_from_neighbour", "double lam = (aP - 0.5) / (aP - aN);", "double lam = (aN - 0.5) / (aN - aP);"),
+    ("gfm_weight_from_owner", "double lw = wetP ? lam : 1.0 - lam;", "double lw = lam;"),
+    ("gfm_beta_weights_swapped", "double bw = lw * bm + (1.0 - lw) * bp;", "double bw = lw * bp + (1.0 - lw) * bm;"),
+    ("gfm_cyclic_translation_sign", "for (int d = 0; d < 3; ++d) xN[d] -= m->ptrans[3 * p + d];",
+     "for (int d = 0; d < 3; ++d) xN[d] += m->ptrans[3 * p + d];"),
+    ("gfm_ghosts_on_wrong_cells", "ghost_nbr[f] = wetP ? to_dry : to_wet;", "ghost_nbr[f] = wetP ? to_wet : to_dry;"),
+    ("gfm_mirror_jump_sign", "+ (bp / bw) * H;  /* its mirror */", "- (bp / bw) * H;  /* its mirror */"),
+]
+
 
 TANGENT_HEADER = "Tangent of the step (directional derivative"
 
@@ -84,5 +97,17 @@ def test_tangent_pins_reject_planted_mistake(tmp_path, name, old, new):
     env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_tlm.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,old,new", GFM_MUTANTS, ids=[m[0] for m in GFM_MUTANTS])
+def test_gfm_pins_reject_planted_mistake(tmp_path, name, old, new):
+    mutant_src = tmp_path / "mutant.c"
+    mutant_src.write_text(_plant(name, old, new, tangent=False))
+    lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_gfm.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
