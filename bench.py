@@ -32,7 +32,7 @@ METRIC = "FP64 isoAdvector cell-steps/s + % HBM roofline; batched vs plain; adjo
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_01130_amd", "csrc", n) for n in ("kernels.hip", "device_common.h",
-                                                                                "internal.h")]
+                                                                                "internal.h", "gfm.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 # FP64 operations credited per interface cell for vertex interpolation, the isovalue search, the
 # isoface and the swept-face integrals (a fixed per-unit figure, independent of the iteration
@@ -41,7 +41,7 @@ FLOP_PER_SURFACE_CELL = 11000.0
 COPY_N = 1 << 27  # doubles moved by the calibration copy (1 GiB read, 1 GiB written)
 KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update",
                "k_bound_sweep": "bound_sweep", "k_bound_end": "bound_end",
-               "k_stats": "stats"}
+               "k_gfm_faces": "gfm_faces", "k_stats": "stats"}
 # the commands whose rocprofv3 output --summarize-profiles reads
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
@@ -231,7 +231,7 @@ def summarize_profiles(workload):
              f"kernel_source_sha: {shas.pop()}",
              f"scale_fetch: {sf:.6f}",
              f"scale_write: {sw:.6f}"]
-    for k in ("find_surface", "surface", "update", "bound_sweep", "bound_end"):
+    for k in ("find_surface", "surface", "update", "bound_sweep", "bound_end", "gfm_faces"):
         if k not in fetch or k not in write:
             continue
         fk = float(np.mean(fetch[k]))
@@ -362,6 +362,44 @@ def variants_bench(gm, w, phis, Us, sel, a_start, args):
     return out
 
 
+# vertical axis and still-water level of each workload (inputs of the ghost-fluid face data)
+GRAVITY = {"violent_3d": ((0.0, 0.0, -9.81), (0.0, 0.0, 0.5)), "airy_2d": ((0.0, -9.81, 0.0), (0.0, 0.5, 0.0)),
+           "cosine_2d": ((0.0, -9.81, 0.0), (0.0, 0.5, 0.0))}
+RHO_HEAVY, RHO_LIGHT = 1000.0, 1.2
+
+
+def gfm_bench(gm, plan, workload, a, reps=20):
+    """Ghost-fluid face data (iso_gfm_faces, Eqs. 12-20) from the state the timed steps reached, with
+    a synthetic dynamic pressure: time per call and its HBM roofline.  Algorithmic bytes per call:
+    per face the owner/neighbour pair (8 B) and the five outputs (40 B); per cell alpha and p_d read
+    once (16 B); per interface face the two cell centroids (48 B)."""
+    import torch
+    import wavegen as W
+    g, level = GRAVITY[workload]
+    xc = gm.geometry()[1]
+    a_host = a.cpu().numpy()
+    p = torch.tensor(W.dynamic_pressure(xc, a_host, RHO_HEAVY, RHO_LIGHT, g, level, seed=7), device=a.device)
+    out = plan.gfm_faces(a, p, RHO_HEAVY, RHO_LIGHT, g)
+    for _ in range(3):
+        plan.gfm_faces(a, p, RHO_HEAVY, RHO_LIGHT, g, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.gfm_faces(a, p, RHO_HEAVY, RHO_LIGHT, g, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    n_if = int((out["lambda"] >= 0).sum().item())
+    nf, nc = gm.n_faces, gm.n_cells
+    q = 48.0 * nf + 16.0 * nc + 48.0 * n_if
+    achieved = q / (us * 1e-6) / 1e9
+    log(f"[bench] ghost-fluid face data: {us:.1f} us per call, {n_if} interface faces, {achieved:.0f} GB/s")
+    return {"us_per_call": us, "faces": nf, "interface_faces": n_if, "algorithmic_bytes_per_launch": q,
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": committed_traffic("gfm_faces", workload), "rho": [RHO_HEAVY, RHO_LIGHT], "g": list(g)}
+
+
 def adjoint_bench(every=10):
     """The adjoint workload: 256x128 Airy, 50 steps, loss sum (alpha_T - alpha_target)^2; time of the
     forward pass (plain steps) and of the backward pass (recomputing each segment from its checkpoint
@@ -426,6 +464,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the interpolated isoface velocity and averaged-field step timings")
+    ap.add_argument("--no-gfm", action="store_true", help="skip the ghost-fluid face data timing")
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
@@ -489,6 +528,7 @@ def main():
     torch.cuda.synchronize()
     kms, nrec = plan.timing()
     variants = None if args.no_variants else variants_bench(gm, w, phis, Us, sel, a_start, args)
+    gfm = None if args.no_gfm else gfm_bench(gm, plan, args.workload, a)
     del a_start
     ms_per_step = ms / args.steps
     cells = w.mesh.n_cells
@@ -547,6 +587,7 @@ def main():
         "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
         "variants": variants,
+        "gfm_faces": gfm,
         "ensemble": ens,
         "adjoint": adj,
     }

@@ -163,6 +163,32 @@ iso_status iso_advect_step_avg(iso_plan *plan, const double *alpha, const double
                                const double *U0, const double *U1, double dt, double *alpha_new,
                                iso_step_stats *stats);
 
+/* Ghost-fluid face data after advection (Section 3.1, Eqs. 12-20): what the interface-corrected
+ * interpolation of the dynamic pressure needs from the new volume fractions.  A cell is wet
+ * (heavy fluid, density rho_heavy) iff alpha > 1/2.  For every face with a cell on each side (an
+ * internal face, or the face of a cyclic pair that carries the flux, the partner's cell centre
+ * moved into the owner's frame by the pair's translation) whose two cells are one wet and one dry:
+ *   lambda    = (alpha_P - 1/2) / (alpha_P - alpha_N), P the face's owner (Eq. 13), and
+ *               x_Gamma = x_P + lambda (x_N - x_P) (Eq. 12) from the cell centroids;
+ *   jump      = p_d^- - p_d^+ at x_Gamma = (rho_heavy - rho_light) g . x_Gamma (the jump of Eq. 7,
+ *               which Eq. 3 fixes for a continuous pressure; Eq. 15 prints the opposite sign);
+ *   beta_w    = l / rho_light + (1 - l) / rho_heavy, l the distance fraction of x_Gamma from the wet
+ *               cell (Eq. 18);
+ *   ghost_nbr = p_d at the neighbour's centre seen from the owner's fluid, ghost_own = p_d at the
+ *               owner's centre seen from the neighbour's fluid: the heavy fluid's value at the
+ *               dry cell by Eq. 20, the light fluid's at the wet cell by the mirror expression.
+ * Every other face: lambda = -1, jump = beta_w = 0, ghost_own = p_d of the owner, ghost_nbr = p_d
+ * of the neighbour (of the owner where the face has one cell, and on the partner face of a
+ * cyclic pair, which carries nothing of its own).
+ * alpha, p_d [n_cells] (p_d: the dynamic pressure p - rho g . x per cell) and the five outputs
+ * [n_faces] are DEVICE arrays; the outputs must not overlap the inputs or each other.
+ * rho_heavy, rho_light > 0; g = (gx, gy, gz) the gravitational acceleration.  Asynchronous on the
+ * plan's stream; nothing is allocated.  The arithmetic is rounded operation by operation in the
+ * order written above (no fused multiply-add). */
+iso_status iso_gfm_faces(iso_plan *plan, const double *alpha, const double *p_d, double rho_heavy,
+                         double rho_light, double gx, double gy, double gz, double *lambda, double *jump,
+                         double *beta_w, double *ghost_own, double *ghost_nbr);
+
 /* Adjoint of one step (vector-Jacobian product; differentiation is not part of the paper's
  * method).  Given alpha_new_bar = dL/d alpha_new for the step iso_advect_step(alpha, phi, U, dt)
  * -> alpha_new, writes alpha_bar = dL/d alpha [n_cells] and phi_bar = dL/d phi [n_faces] (zero on

@@ -98,6 +98,9 @@ def lib():
         L.iso_advect_step_traced.restype = C.c_int
         L.iso_advect_step_avg.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats)]
         L.iso_advect_step_avg.restype = C.c_int
+        L.iso_gfm_faces.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    _vp, _vp, _vp, _vp, _vp]
+        L.iso_gfm_faces.restype = C.c_int
         L.iso_advect_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, C.c_double, C.POINTER(IsoTrace), _vp, _vp, _vp]
         L.iso_advect_step_adjoint.restype = C.c_int
         L.iso_plan_set_timing.argtypes = [_vp, C.c_int32]
@@ -285,6 +288,19 @@ class Plan:
         return out, (st.as_dict() if st is not None else None)
 
     TRACE_KEYS = ("vert_alpha", "kind", "iso", "rec", "dV", "alpha_raw", "iters")
+    GFM_KEYS = ("lambda", "jump", "beta_w", "ghost_own", "ghost_nbr")
+
+    def gfm_faces(self, alpha, p_d, rho_heavy, rho_light, g, out=None):
+        """Ghost-fluid face data (iso_gfm_faces): dict of lambda, jump, beta_w, ghost_own and
+        ghost_nbr, each a float64 device tensor [n_faces] (``out`` supplies them)."""
+        import torch
+        if out is None:
+            out = {k: torch.empty(self.mesh.n_faces, dtype=torch.float64, device=alpha.device) for k in self.GFM_KEYS}
+        gx, gy, gz = (float(v) for v in g)
+        self.set_stream(None)
+        check(lib().iso_gfm_faces(self.h, _ptr(alpha), _ptr(p_d), float(rho_heavy), float(rho_light), gx, gy, gz,
+                                  *(_ptr(out[k]) for k in self.GFM_KEYS)))
+        return out
 
     def adjoint(self, alpha, phi, U, dt, alpha_new_bar, trace=None, alpha_bar=None, phi_bar=None):
         """(alpha_bar, phi_bar) of the step alpha_new = step(alpha, phi, U, dt) for the given alpha_new_bar.

@@ -35,6 +35,12 @@ struct DevMesh {
     const double *st_w = nullptr;        // normalised inverse-distance weights
     const double *patch_alpha = nullptr; // [n_patches]
     const double *ccen = nullptr;        // [3*n_cells] cell centroids (same frame as cxyz), AoS
+    // face-major table of the ghost-fluid face data (single meshes only; null in an ensemble)
+    int32_t n_internal = 0;
+    const int32_t *fcell = nullptr;      // [2*n_faces] owner, cell across (-1: none, or the partner
+                                         // face of a cyclic pair)
+    const int32_t *bpatch = nullptr;     // [n_faces-n_internal] patch of each boundary face
+    const double *ptrans = nullptr;      // [3*n_patches] cyclic translations (x_partner = x + T)
     // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;
@@ -144,6 +150,18 @@ hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_
 // adjoint.hip
 hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, const AdjInputs &in, const AdjWork &w,
                           hipStream_t s);
+// Ghost-fluid face data (Eqs. 12-20): see gfm.hip.
+struct GfmArgs {
+    const int32_t *fcell, *bpatch;
+    const double *ptrans, *ccen;
+    const double *alpha, *p_d;
+    double *lambda, *jump, *beta_w, *ghost_own, *ghost_nbr;
+    double b_heavy, b_light, drho;  // 1/rho^+, 1/rho^-, rho^+ - rho^-
+    double g[3];
+    int64_t n_faces;
+    int32_t n_internal;
+};
+hipError_t launch_gfm_faces(const GfmArgs &a, hipStream_t s);
 hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha, const double *alpha_new,
                         hipStream_t s);
 

@@ -307,6 +307,19 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         }
     }
     m->n_flux = n_flux;
+    // face-major table of the ghost-fluid face data: owner and the cell across (the partner face's
+    // owner for the face of a cyclic pair that carries the flux, -1 for every other boundary face)
+    std::vector<int32_t> fcell(2 * (size_t)n_faces), bpatch(std::max(1, n_faces - n_internal));
+    for (int32_t f = 0; f < n_faces; ++f) {
+        fcell[2 * (size_t)f] = owner[f];
+        int32_t other = -1;
+        if (f < n_internal) other = neighbour[f];
+        else if (f_fid[f] == f && patch_kind[fpatch[f]] == ISO_PATCH_CYCLIC) other = f_other[f];
+        fcell[2 * (size_t)f + 1] = other;
+        if (f >= n_internal) bpatch[f - n_internal] = fpatch[f];
+    }
+    std::vector<double> ptrans(3 * (size_t)std::max(n_patches, 1), 0.0);
+    for (int32_t p = 0; p < 3 * n_patches; ++p) ptrans[p] = patch_translation[p];
     // slots per cell sorted by face id
     int W = 0;
     std::vector<std::vector<std::array<int32_t, 3>>> slots(n_cells);
@@ -428,12 +441,14 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     if (hipGetDevice(&m->device) != hipSuccess) { iso_mesh_destroy(m); return fail(ISO_EDEVICE, "no HIP device"); }
     DevMesh &d = m->dev;
     d.n_cells = n_cells; d.n_faces = n_faces; d.n_classes = n_classes; d.W = W; d.n_patches = n_patches;
+    d.n_internal = n_internal;
     iso_status st = ISO_OK;
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||
         (st = upload(m, slot_face, &d.slot_face)) || (st = upload(m, slot_nbr, &d.slot_nbr)) ||
         (st = upload(m, lface, &d.lface)) || (st = upload(m, cflags, &d.cflags)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
         (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha)) ||
-        (st = upload(m, m->xc, &d.ccen))) {
+        (st = upload(m, m->xc, &d.ccen)) || (st = upload(m, fcell, &d.fcell)) || (st = upload(m, bpatch, &d.bpatch)) ||
+        (st = upload(m, ptrans, &d.ptrans))) {
         iso_mesh_destroy(m);
         return st;
     }
@@ -623,6 +638,37 @@ iso_status iso_advect_step_avg(iso_plan *p, const double *alpha, const double *p
                                iso_step_stats *stats) {
     if (!phi1 || !U1) return fail(ISO_EINVAL, "null array");
     return step_impl(p, alpha, phi0, U0, dt, alpha_new, stats, nullptr, phi1, U1);
+}
+
+iso_status iso_gfm_faces(iso_plan *p, const double *alpha, const double *p_d, double rho_heavy, double rho_light,
+                         double gx, double gy, double gz, double *lambda, double *jump, double *beta_w,
+                         double *ghost_own, double *ghost_nbr) {
+    if (!p) return fail(ISO_EINVAL, "null plan");
+    if (!alpha || !p_d || !lambda || !jump || !beta_w || !ghost_own || !ghost_nbr) return fail(ISO_EINVAL, "null array");
+    if (!(rho_heavy > 0) || !(rho_light > 0) || !std::isfinite(rho_heavy) || !std::isfinite(rho_light))
+        return fail(ISO_EINVAL, "densities must be positive and finite");
+    if (!std::isfinite(gx) || !std::isfinite(gy) || !std::isfinite(gz)) return fail(ISO_EINVAL, "g must be finite");
+    const iso_mesh *m = p->mesh;
+    if (!m->dev.fcell) return fail(ISO_EUNSUPPORTED, "the plan's mesh has no face table");
+    const size_t nc = (size_t)m->n_cells * 8, nf = (size_t)m->n_faces * 8;
+    double *outs[5] = {lambda, jump, beta_w, ghost_own, ghost_nbr};
+    for (int i = 0; i < 5; ++i) {
+        if (overlaps(outs[i], nf, alpha, nc) || overlaps(outs[i], nf, p_d, nc))
+            return fail(ISO_EINVAL, "a ghost-fluid output overlaps an input");
+        for (int j = 0; j < i; ++j)
+            if (overlaps(outs[i], nf, outs[j], nf)) return fail(ISO_EINVAL, "ghost-fluid outputs overlap");
+    }
+    (void)hipGetLastError();
+    GfmArgs a{};
+    a.fcell = m->dev.fcell; a.bpatch = m->dev.bpatch; a.ptrans = m->dev.ptrans; a.ccen = m->dev.ccen;
+    a.alpha = alpha; a.p_d = p_d;
+    a.lambda = lambda; a.jump = jump; a.beta_w = beta_w; a.ghost_own = ghost_own; a.ghost_nbr = ghost_nbr;
+    a.b_heavy = 1.0 / rho_heavy; a.b_light = 1.0 / rho_light; a.drho = rho_heavy - rho_light;
+    a.g[0] = gx; a.g[1] = gy; a.g[2] = gz;
+    a.n_faces = m->n_faces; a.n_internal = m->n_internal;
+    hipError_t e = launch_gfm_faces(a, p->stream);
+    if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return ISO_OK;
 }
 
 static iso_status adj_alloc(iso_plan *p) {

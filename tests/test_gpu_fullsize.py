@@ -25,8 +25,8 @@ def test_airy_1024x256_full_trajectory(oracle_lib):
 
 
 def test_violent_3d_full_size_steps(oracle_lib):
-    """4.19M-cell graded 3D box: the first step from the initial field and a later step from the GPU's
-    own state (identical inputs to both sides) agree per cell within 1e-10."""
+    """4.19M-cell graded 3D box: six steps from the initial field on each side; every cell within
+    1e-10 of the oracle after the first step and after the sixth."""
     import torch
     w = W.violent_3d()
     say(f"[gpu] {w.name}: {w.mesh.n_cells} cells")
@@ -36,14 +36,12 @@ def test_violent_3d_full_size_steps(oracle_lib):
     tphi, tU = to_dev(phi), to_dev(U)
     a = to_dev(w.alpha0)
     b = torch.empty_like(a)
-    states = [w.alpha0]
+    o = np.array(w.alpha0, copy=True)
     for n in range(6):
         plan.step(a, tphi, tU, w.dt, out=b)
         a, b = b, a
-        states.append(a.cpu().numpy())
-    for n in (0, 5):
-        say(f"[gpu]   oracle step from state {n}")
-        o, _ = om.step(states[n], phi, U, w.dt)
-        err = np.abs(states[n + 1] - o).max()
-        say(f"[gpu]   step {n}: max |gpu - oracle| = {err:.3e}")
-        assert err <= 1e-10
+        o, _ = om.step(o, phi, U, w.dt)
+        if n in (0, 5):
+            err = np.abs(a.cpu().numpy() - o).max()
+            say(f"[gpu]   step {n + 1}: max |gpu - oracle| = {err:.3e}")
+            assert err <= 1e-10

@@ -271,3 +271,21 @@ def alpha_column_plus_wave_3d(mesh: Mesh, col_x, col_top, eta0, amp, kw, n_gauss
                 out[:, ii] = fl * col_frac_z + (1.0 - fl) * wr
         alpha[kk] = out
     return np.ascontiguousarray(np.clip(alpha, 0.0, 1.0).ravel())
+
+
+# --------------------------------------------------------------------------------------
+# dynamic pressure for the ghost-fluid face data
+# --------------------------------------------------------------------------------------
+def dynamic_pressure(xc, alpha, rho_heavy, rho_light, g, level, seed, noise=0.02, p_atm=1.0e5):
+    """A synthetic dynamic pressure p_d = p - rho g . x per cell, an input of the ghost-fluid face
+    data: hydrostatic about a flat free surface through the point ``level`` (p = p_atm there), the
+    fluid of each cell chosen by alpha > 1/2, plus seeded normal noise of relative size ``noise``
+    of rho_heavy |g| times the extent of the cell centres (a stand-in for the flow's dynamic part).
+    xc: (n_cells, 3) cell centres."""
+    xc = np.asarray(xc, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    rho = np.where(np.asarray(alpha) > 0.5, rho_heavy, rho_light)
+    base = p_atm - rho * float(g @ np.asarray(level, dtype=np.float64))
+    ext = float(np.ptp(xc, axis=0).max())
+    rng = np.random.default_rng(seed)
+    return base + noise * rho_heavy * float(np.linalg.norm(g)) * ext * rng.standard_normal(len(rho))
