@@ -66,6 +66,13 @@
  *       beta_w (Eq. 18) from its heavy cell; the ghost values are the heavy fluid's p_d
  *       extended to the dry cell (Eq. 20) and the light fluid's extended to the wet cell
  *       (the mirror of Eqs. 17-20).
+ *   R17 relaxation zones (Section 3, the paragraph on wave generation and absorption): the
+ *       paper blends alpha explicitly towards a target after the advection step with the
+ *       exponential weight of Jacobsen, Fuhrman & Fredsoe (2012), which it cites without
+ *       printing: alpha <- w alpha + (1 - w) alpha_target, w(chi) = 1 - (exp(chi^3.5) - 1)/(e - 1),
+ *       chi in [0, 1] the cell centre's distance from the zone's inner edge (w = 1, the computed
+ *       solution kept) towards its outer edge (w = 0, the target imposed), over the zone's
+ *       length.  A zone is a slab: an inner-edge point, a direction and a length.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1058,6 +1065,41 @@ int or_cell_cut_flat(const or_mesh *m, int c, const double *a_pts, double iso, d
     out[10] = cut.n_cut;
     return r;
 }
+
+/* ------------------------------------------------------------------ R17 relaxation zones
+ * zones: 7 numbers per zone, the inner-edge point (3), the direction into the zone (3) and the
+ * length.  A cell whose centre projects to chi = ((x - origin) . e) / length in [0, 1] (e the unit
+ * direction) is blended; every other cell keeps alpha.  Returns 0, or -1 for a zone with a zero
+ * direction or a length that is not positive, or a cell inside two zones. */
+static double relax_weight(double chi) { return 1.0 - (exp(pow(chi, 3.5)) - 1.0) / (exp(1.0) - 1.0); }
+
+int or_relax_blend(const or_mesh *m, int n_zones, const double *zones, const double *alpha, const double *target,
+                   double *out) {
+    for (int z = 0; z < n_zones; ++z) {
+        const double *d = zones + 7 * z + 3;
+        if (!(v_norm(d) > 0.0) || !(zones[7 * z + 6] > 0.0)) return -1;
+    }
+    for (int c = 0; c < m->n_cells; ++c) {
+        int hit = -1;
+        double chi = 0.0;
+        for (int z = 0; z < n_zones; ++z) {
+            const double *o = zones + 7 * z, *d = zones + 7 * z + 3;
+            double n = v_norm(d), e[3] = {d[0] / n, d[1] / n, d[2] / n}, r[3];
+            v_sub(m->xc + 3 * c, o, r);
+            double q = v_dot(r, e) / zones[7 * z + 6];
+            if (q >= 0.0 && q <= 1.0) {
+                if (hit >= 0) return -1;
+                hit = z; chi = q;
+            }
+        }
+        if (hit < 0) { out[c] = alpha[c]; continue; }
+        double w = relax_weight(chi);
+        out[c] = w * alpha[c] + (1.0 - w) * target[c];
+    }
+    return 0;
+}
+
+double or_relax_weight(double chi) { return relax_weight(chi); }
 
 /* ------------------------------------------------------------------ R16 ghost-fluid faces
  * For every flux-carrying face with a cell on each side (internal faces and the flux face of a

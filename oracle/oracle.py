@@ -88,6 +88,10 @@ def lib():
         L.or_step_tlm.argtypes = [C.c_void_p, C.POINTER(Opts), _dp, _dp, _dp, C.c_double, _dp, _dp, _dp, _dp]
         L.or_step_tlm.restype = C.c_int
         L.or_cell_point_velocity.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.or_relax_blend.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp, _dp]
+        L.or_relax_blend.restype = C.c_int
+        L.or_relax_weight.argtypes = [C.c_double]
+        L.or_relax_weight.restype = C.c_double
         L.or_gfm_faces.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
@@ -107,6 +111,11 @@ def default_opts(**kw) -> Opts:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def relax_weight(chi) -> float:
+    """Blending weight of a relaxation zone at the zone coordinate chi (reading R17)."""
+    return lib().or_relax_weight(float(chi))
 
 
 def tri_integral(x9, xS, nS, un, dt) -> float:
@@ -195,6 +204,19 @@ class OracleMesh:
         x = np.ascontiguousarray(x, dtype=np.float64)
         out = np.zeros(3)
         lib().or_cell_point_velocity(self.h, int(c), _d(U), _d(x), _d(out))
+        return out
+
+    def relax_blend(self, zones, alpha, target):
+        """alpha blended towards target in relaxation zones (reading R17).  zones: list of
+        (origin[3], direction[3], length).  Raises ValueError for invalid or overlapping zones."""
+        z = np.ascontiguousarray([list(o) + list(d) + [ln] for o, d, ln in zones], dtype=np.float64).ravel()
+        if z.size == 0:
+            z = np.zeros(1)
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        target = np.ascontiguousarray(target, dtype=np.float64)
+        out = np.zeros(self.n_cells)
+        if lib().or_relax_blend(self.h, len(zones), _d(z), _d(alpha), _d(target), _d(out)) != 0:
+            raise ValueError("invalid or overlapping relaxation zones")
         return out
 
     def gfm_faces(self, alpha, p_d, rho_heavy, rho_light, g):

@@ -61,6 +61,18 @@ GFM_MUTANTS = [
     ("gfm_mirror_jump_sign", "+ (bp / bw) * H;  /* its mirror */", "- (bp / bw) * H;  /* its mirror */"),
 ]
 
+# planted mistakes in the relaxation-zone blending, which its own pins must reject
+RELAX_MUTANTS = [
+    ("relax_exponent_three", "return 1.0 - (exp(pow(chi, 3.5)) - 1.0) / (exp(1.0) - 1.0);",
+     "return 1.0 - (exp(pow(chi, 3.0)) - 1.0) / (exp(1.0) - 1.0);"),
+    ("relax_normalised_by_e", "return 1.0 - (exp(pow(chi, 3.5)) - 1.0) / (exp(1.0) - 1.0);",
+     "return 1.0 - (exp(pow(chi, 3.5)) - 1.0) / exp(1.0);"),
+    ("relax_blend_reversed", "out[c] = w * alpha[c] + (1.0 - w) * target[c];",
+     "out[c] = w * target[c] + (1.0 - w) * alpha[c];"),
+    ("relax_direction_not_normalised", "e[3] = {d[0] / n, d[1] / n, d[2] / n}", "e[3] = {d[0], d[1], d[2]}"),
+    ("relax_overlap_accepted", "if (hit >= 0) return -1;", "if (hit >= 0) continue;"),
+]
+
 
 TANGENT_HEADER = "Tangent of the step (directional derivative"
 
@@ -109,5 +121,17 @@ def test_gfm_pins_reject_planted_mistake(tmp_path, name, old, new):
     env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_gfm.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,old,new", RELAX_MUTANTS, ids=[m[0] for m in RELAX_MUTANTS])
+def test_relax_pins_reject_planted_mistake(tmp_path, name, old, new):
+    mutant_src = tmp_path / "mutant.c"
+    mutant_src.write_text(_plant(name, old, new, tangent=False))
+    lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_relax.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
