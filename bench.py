@@ -32,7 +32,7 @@ METRIC = "FP64 isoAdvector cell-steps/s + % HBM roofline; batched vs plain; adjo
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_01130_amd", "csrc", n) for n in ("kernels.hip", "device_common.h",
-                                                                                "internal.h", "gfm.hip")]
+                                                                                "internal.h", "gfm.hip", "relax.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 # FP64 operations credited per interface cell for vertex interpolation, the isovalue search, the
 # isoface and the swept-face integrals (a fixed per-unit figure, independent of the iteration
@@ -41,7 +41,7 @@ FLOP_PER_SURFACE_CELL = 11000.0
 COPY_N = 1 << 27  # doubles moved by the calibration copy (1 GiB read, 1 GiB written)
 KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update",
                "k_bound_sweep": "bound_sweep", "k_bound_end": "bound_end",
-               "k_gfm_faces": "gfm_faces", "k_stats": "stats"}
+               "k_gfm_faces": "gfm_faces", "k_relax_blend": "relax_blend", "k_stats": "stats"}
 # the commands whose rocprofv3 output --summarize-profiles reads
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
@@ -231,7 +231,7 @@ def summarize_profiles(workload):
              f"kernel_source_sha: {shas.pop()}",
              f"scale_fetch: {sf:.6f}",
              f"scale_write: {sw:.6f}"]
-    for k in ("find_surface", "surface", "update", "bound_sweep", "bound_end", "gfm_faces"):
+    for k in ("find_surface", "surface", "update", "bound_sweep", "bound_end", "gfm_faces", "relax_blend"):
         if k not in fetch or k not in write:
             continue
         fk = float(np.mean(fetch[k]))
@@ -400,6 +400,41 @@ def gfm_bench(gm, plan, workload, a, reps=20):
             "traffic": committed_traffic("gfm_faces", workload), "rho": [RHO_HEAVY, RHO_LIGHT], "g": list(g)}
 
 
+# relaxation zones at both ends of each workload's periodic direction (inner edge, outward direction,
+# length), about 15 % of the domain each
+RELAX_ZONES = {
+    "violent_3d": [((0.3003, 0.0, 0.0), (-1.0, 0.0, 0.0), 0.3), ((1.6997, 0.0, 0.0), (1.0, 0.0, 0.0), 0.3)],
+    "airy_2d": [((0.6003, 0.0, 0.0), (-1.0, 0.0, 0.0), 0.6), ((3.3997, 0.0, 0.0), (1.0, 0.0, 0.0), 0.6)],
+    "cosine_2d": [((0.3003, 0.0, 0.0), (-1.0, 0.0, 0.0), 0.3), ((1.6997, 0.0, 0.0), (1.0, 0.0, 0.0), 0.3)],
+}
+
+
+def relax_bench(plan, workload, a, target, reps=50):
+    """Relaxation-zone blending (iso_relax_blend) of the state the timed steps reached towards the
+    initial field: time per call and its HBM roofline.  Algorithmic bytes per call: 36 B per zone
+    cell (index 4, weight 8, alpha read and written 16, target 8)."""
+    import torch
+    n = plan.set_relaxation(RELAX_ZONES[workload])
+    x = a.clone()
+    for _ in range(3):
+        plan.relax_blend(x, target)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.relax_blend(x, target)
+    e1.record()
+    torch.cuda.synchronize()
+    plan.set_relaxation([])
+    us = e0.elapsed_time(e1) / reps * 1e3
+    q = 36.0 * n
+    achieved = q / (us * 1e-6) / 1e9
+    log(f"[bench] relaxation blend: {us:.1f} us per call, {n} zone cells, {achieved:.0f} GB/s")
+    return {"us_per_call": us, "zone_cells": n, "algorithmic_bytes_per_launch": q, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": committed_traffic("relax_blend", workload)}
+
+
 def adjoint_bench(every=10):
     """The adjoint workload: 256x128 Airy, 50 steps, loss sum (alpha_T - alpha_target)^2; time of the
     forward pass (plain steps) and of the backward pass (recomputing each segment from its checkpoint
@@ -465,6 +500,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the interpolated isoface velocity and averaged-field step timings")
     ap.add_argument("--no-gfm", action="store_true", help="skip the ghost-fluid face data timing")
+    ap.add_argument("--no-relax", action="store_true", help="skip the relaxation-zone blending timing")
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
@@ -529,6 +565,7 @@ def main():
     kms, nrec = plan.timing()
     variants = None if args.no_variants else variants_bench(gm, w, phis, Us, sel, a_start, args)
     gfm = None if args.no_gfm else gfm_bench(gm, plan, args.workload, a)
+    relax = None if args.no_relax else relax_bench(plan, args.workload, a, torch.tensor(w.alpha0, device=dev))
     del a_start
     ms_per_step = ms / args.steps
     cells = w.mesh.n_cells
@@ -588,6 +625,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "gfm_faces": gfm,
+        "relax_blend": relax,
         "ensemble": ens,
         "adjoint": adj,
     }

@@ -189,6 +189,32 @@ iso_status iso_gfm_faces(iso_plan *plan, const double *alpha, const double *p_d,
                          double rho_light, double gx, double gy, double gz, double *lambda, double *jump,
                          double *beta_w, double *ghost_own, double *ghost_nbr);
 
+/* Relaxation zones (Section 3, wave generation and absorption): after the advection step alpha
+ * is blended explicitly towards a target solution (e.g. an incident wave's) with the exponential
+ * weight of Jacobsen, Fuhrman & Fredsoe (2012), which the paper cites:
+ *     alpha <- w alpha + (1 - w) alpha_target,   w(chi) = 1 - (exp(chi^3.5) - 1) / (e - 1),
+ * chi = ((x_P - origin) . e) / length in [0, 1] for the cell centroid x_P, e = direction/|direction|:
+ * w = 1 at the zone's inner edge (origin; the computed solution is kept), w = 0 at its outer edge
+ * (the target is imposed).  A zone is the slab 0 <= chi <= 1; cells outside every zone are left
+ * alone. */
+typedef struct {
+    double origin[3];     /* a point of the zone's inner edge */
+    double direction[3];  /* into the zone, towards its outer edge (any non-zero length) */
+    double length;        /* extent of the zone along direction (> 0) */
+} iso_relax_zone;
+/* Sets the plan's zones (host array, copied; n_zones = 0 clears them).  Finds the cells whose
+ * centroids lie in a zone and their weights once, on the host, and keeps them on the device (12
+ * bytes per zone cell; this call allocates, iso_relax_blend does not).  n_zone_cells (nullable)
+ * receives their number.  ISO_EINVAL for a zero or non-finite direction, a length that is not
+ * positive, or a cell inside two zones.  Synchronises the plan's stream. */
+iso_status iso_plan_set_relaxation(iso_plan *plan, int32_t n_zones, const iso_relax_zone *zones,
+                                   int64_t *n_zone_cells);
+/* Blends alpha [n_cells] in place towards alpha_target [n_cells] in the plan's zones (DEVICE arrays,
+ * not overlapping; only the zone cells are read or written).  Asynchronous on the plan's stream; a
+ * plan without zones does nothing.  Rounded operation by operation as written (no fused
+ * multiply-add). */
+iso_status iso_relax_blend(iso_plan *plan, double *alpha, const double *alpha_target);
+
 /* Adjoint of one step (vector-Jacobian product; differentiation is not part of the paper's
  * method).  Given alpha_new_bar = dL/d alpha_new for the step iso_advect_step(alpha, phi, U, dt)
  * -> alpha_new, writes alpha_bar = dL/d alpha [n_cells] and phi_bar = dL/d phi [n_faces] (zero on

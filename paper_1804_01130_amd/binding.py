@@ -43,6 +43,10 @@ class IsoStepStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class IsoRelaxZone(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("direction", C.c_double * 3), ("length", C.c_double)]
+
+
 class IsoTrace(C.Structure):
     _fields_ = [("vert_alpha", _vp), ("kind", _vp), ("iso", _vp), ("rec", _vp), ("dV", _vp),
                 ("alpha_raw", _vp), ("iters", _vp)]
@@ -101,6 +105,10 @@ def lib():
         L.iso_gfm_faces.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                     _vp, _vp, _vp, _vp, _vp]
         L.iso_gfm_faces.restype = C.c_int
+        L.iso_plan_set_relaxation.argtypes = [_vp, C.c_int32, C.POINTER(IsoRelaxZone), C.POINTER(C.c_int64)]
+        L.iso_plan_set_relaxation.restype = C.c_int
+        L.iso_relax_blend.argtypes = [_vp, _vp, _vp]
+        L.iso_relax_blend.restype = C.c_int
         L.iso_advect_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, C.c_double, C.POINTER(IsoTrace), _vp, _vp, _vp]
         L.iso_advect_step_adjoint.restype = C.c_int
         L.iso_plan_set_timing.argtypes = [_vp, C.c_int32]
@@ -288,6 +296,24 @@ class Plan:
         return out, (st.as_dict() if st is not None else None)
 
     TRACE_KEYS = ("vert_alpha", "kind", "iso", "rec", "dV", "alpha_raw", "iters")
+
+    def set_relaxation(self, zones):
+        """Relaxation zones (iso_plan_set_relaxation): a list of (origin[3], direction[3], length).
+        Returns the number of zone cells."""
+        arr = (IsoRelaxZone * max(len(zones), 1))()
+        for i, (o, d, ln) in enumerate(zones):
+            arr[i].origin[:] = [float(v) for v in o]
+            arr[i].direction[:] = [float(v) for v in d]
+            arr[i].length = float(ln)
+        n = C.c_int64(0)
+        check(lib().iso_plan_set_relaxation(self.h, len(zones), arr, C.byref(n)))
+        return n.value
+
+    def relax_blend(self, alpha, alpha_target):
+        """alpha (device tensor) blended in place towards alpha_target in the plan's zones."""
+        self.set_stream(None)
+        check(lib().iso_relax_blend(self.h, _ptr(alpha), _ptr(alpha_target)))
+        return alpha
     GFM_KEYS = ("lambda", "jump", "beta_w", "ghost_own", "ghost_nbr")
 
     def gfm_faces(self, alpha, p_d, rho_heavy, rho_light, g, out=None):

@@ -11,7 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libisoadv.so")
 SOURCES = [os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "batch.cpp"), os.path.join(CSRC, "kernels.hip"),
-           os.path.join(CSRC, "adjoint.hip"), os.path.join(CSRC, "gfm.hip")]
+           os.path.join(CSRC, "adjoint.hip"), os.path.join(CSRC, "gfm.hip"),
+           os.path.join(CSRC, "relax.hip")]
 HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "device_common.h"), os.path.join(INCLUDE, "isoadv.h")]
 ARCH = os.environ.get("ISOADV_ARCH", "gfx950")
 

@@ -162,6 +162,9 @@ struct GfmArgs {
     int32_t n_internal;
 };
 hipError_t launch_gfm_faces(const GfmArgs &a, hipStream_t s);
+// Relaxation-zone blend (relax.hip): alpha[cells[i]] = w[i] alpha + (1 - w[i]) target, in place.
+hipError_t launch_relax_blend(const int32_t *cells, const double *w, int64_t n, double *alpha, const double *target,
+                              hipStream_t s);
 hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha, const double *alpha_new,
                         hipStream_t s);
 
@@ -194,6 +197,10 @@ struct iso_plan {
     double *adj_vert = nullptr, *adj_iso = nullptr, *adj_dV = nullptr, *adj_raw = nullptr, *adj_new = nullptr;
     int32_t *adj_kind = nullptr;
     bool adj_ready = false;
+    // relaxation zones (iso_plan_set_relaxation): zone cells and their weights
+    int32_t *rz_cell = nullptr;
+    double *rz_w = nullptr;
+    int64_t rz_n = 0;
 };
 
 namespace isoadv {

@@ -481,6 +481,8 @@ void iso_plan_destroy(iso_plan *p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     for (void *a : p->allocations) (void)hipFree(a);
+    if (p->rz_cell) (void)hipFree(p->rz_cell);
+    if (p->rz_w) (void)hipFree(p->rz_w);
     if (p->host_counters) (void)hipHostFree(p->host_counters);
     if (p->host_red) (void)hipHostFree(p->host_red);
     delete p;
@@ -667,6 +669,70 @@ iso_status iso_gfm_faces(iso_plan *p, const double *alpha, const double *p_d, do
     a.g[0] = gx; a.g[1] = gy; a.g[2] = gz;
     a.n_faces = m->n_faces; a.n_internal = m->n_internal;
     hipError_t e = launch_gfm_faces(a, p->stream);
+    if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return ISO_OK;
+}
+
+iso_status iso_plan_set_relaxation(iso_plan *p, int32_t n_zones, const iso_relax_zone *zones, int64_t *n_zone_cells) {
+    if (!p) return fail(ISO_EINVAL, "null plan");
+    if (n_zones < 0 || (n_zones > 0 && !zones)) return fail(ISO_EINVAL, "bad zone list");
+    for (int32_t z = 0; z < n_zones; ++z) {
+        const double *d = zones[z].direction;
+        const double n = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        bool finite = std::isfinite(zones[z].length);
+        for (int k = 0; k < 3; ++k) finite = finite && std::isfinite(zones[z].origin[k]) && std::isfinite(d[k]);
+        if (!finite || !(n > 0) || !std::isfinite(n) || !(zones[z].length > 0))
+            return fail(ISO_EINVAL, "zone " + std::to_string(z) + ": direction and length must be finite and non-zero");
+    }
+    // zone coordinate of each cell centre: chi = ((x - origin) . e) / length, e the unit direction;
+    // a cell is in a zone iff 0 <= chi <= 1, and in at most one
+    const iso_mesh *m = p->mesh;
+    std::vector<int32_t> cells;
+    std::vector<double> w;
+    const double norm = std::exp(1.0) - 1.0;
+    for (int32_t c = 0; c < m->n_cells; ++c) {
+        int32_t hit = -1;
+        double chi = 0;
+        for (int32_t z = 0; z < n_zones; ++z) {
+            const double *o = zones[z].origin, *d = zones[z].direction;
+            const double n = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double e0 = d[0] / n, e1 = d[1] / n, e2 = d[2] / n;
+            const double *x = &m->xc[3 * (size_t)c];
+            const double q = ((x[0] - o[0]) * e0 + (x[1] - o[1]) * e1 + (x[2] - o[2]) * e2) / zones[z].length;
+            if (q >= 0.0 && q <= 1.0) {
+                if (hit >= 0) return fail(ISO_EINVAL, "cell " + std::to_string(c) + " lies in two relaxation zones");
+                hit = z;
+                chi = q;
+            }
+        }
+        if (hit < 0) continue;
+        cells.push_back(c);
+        w.push_back(1.0 - (std::exp(std::pow(chi, 3.5)) - 1.0) / norm);
+    }
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->rz_cell) (void)hipFree(p->rz_cell);
+    if (p->rz_w) (void)hipFree(p->rz_w);
+    p->rz_cell = nullptr; p->rz_w = nullptr; p->rz_n = 0;
+    if (!cells.empty()) {
+        if (hipMalloc((void **)&p->rz_cell, cells.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void **)&p->rz_w, w.size() * sizeof(double)) != hipSuccess)
+            return fail(ISO_ENOMEM, "relaxation zone allocation failed");
+        if (hipMemcpy(p->rz_cell, cells.data(), cells.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p->rz_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(ISO_EDEVICE, "relaxation zone upload failed");
+        p->rz_n = (int64_t)cells.size();
+    }
+    if (n_zone_cells) *n_zone_cells = p->rz_n;
+    return ISO_OK;
+}
+
+iso_status iso_relax_blend(iso_plan *p, double *alpha, const double *alpha_target) {
+    if (!p) return fail(ISO_EINVAL, "null plan");
+    if (!alpha || !alpha_target) return fail(ISO_EINVAL, "null array");
+    const size_t nc = (size_t)p->mesh->n_cells * 8;
+    if (overlaps(alpha, nc, alpha_target, nc)) return fail(ISO_EINVAL, "alpha overlaps alpha_target");
+    (void)hipGetLastError();
+    hipError_t e = launch_relax_blend(p->rz_cell, p->rz_w, p->rz_n, alpha, alpha_target, p->stream);
     if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return ISO_OK;
 }
