@@ -200,6 +200,18 @@ class UniformPlusTaylorGreen:
     def fluxes(self, mesh: Mesh):
         return fluxes_from_edge_integral(mesh, self.edge_integral)
 
+    def psi(self, x, y, z):
+        k, A = self.k, self.A
+        return self.u0 * y + (A / k) * np.sin(k * x) * np.sin(k * y) * np.cos(k * z)
+
+    def velocity_at(self, c):
+        """Cell velocities (SoA) at the points c (n, 3)."""
+        k, A = self.k, self.A
+        x, y, z = c[:, 0], c[:, 1], c[:, 2]
+        u = self.u0 + A * np.sin(k * x) * np.cos(k * y) * np.cos(k * z)
+        v = -A * np.cos(k * x) * np.sin(k * y) * np.cos(k * z)
+        return np.ascontiguousarray(np.concatenate([u, v, np.zeros_like(u)]))
+
     def cell_velocity(self, mesh: Mesh):
         c = mesh.cell_centres_structured()
         k, A = self.k, self.A

@@ -1,0 +1,331 @@
+"""Meshes of tetrahedra and triangular prisms in face-based (owner/neighbour) form, and face fluxes
+on meshes whose edges need not be vertical.
+
+Like the rest of the package this only produces inputs of the advection method (its polyhedral
+control volumes, Section 3): a block of hexahedra cut into prisms (each hexahedron split along one
+diagonal of its xy projection, a 2D triangle mesh when the block is one cell thick) or into six
+tetrahedra (the Kuhn split along the main diagonal, conforming between neighbours and identical
+on opposite periodic sides).
+
+Conventions are those of wavegen.mesh: interior faces first in upper-triangular order, boundary
+faces patch after patch (xmin, xmax, ymin, ymax, zmin, zmax), the points of a face counter-clockwise
+seen from outside its owner, face n of a cyclic patch matching face n of its partner.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+from .mesh import PATCH_CYCLIC, PATCH_WALL, Mesh, Patch
+
+
+def _grid_points(xs, ys, zs):
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def mesh_from_cells(points, cells, xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False, alpha_in=None):
+    """Face-based mesh from cells given as lists of faces, each face a tuple of point ids
+    counter-clockwise seen from outside the cell.  Boundary faces go to the patch of the block side
+    they lie on (xs, ys, zs: the block's node coordinates)."""
+    kinds = dict(kinds or {})
+    if periodic_x:
+        kinds["xmin"] = kinds["xmax"] = PATCH_CYCLIC
+    if periodic_y:
+        kinds["ymin"] = kinds["ymax"] = PATCH_CYCLIC
+    for key in ("xmin", "xmax", "ymin", "ymax", "zmin", "zmax"):
+        kinds.setdefault(key, PATCH_WALL)
+    alpha_in = dict(alpha_in or {})
+    seen = {}
+    internal = []
+    for c, faces in enumerate(cells):
+        for fp in faces:
+            key = tuple(sorted(fp))
+            if key in seen:
+                own, pts = seen.pop(key)
+                internal.append((own, c, pts))
+            else:
+                seen[key] = (c, tuple(fp))
+    internal.sort(key=lambda t: (t[0], t[1]))
+    P = np.asarray(points, dtype=np.float64)
+    lo = np.array([xs[0], ys[0], zs[0]])
+    hi = np.array([xs[-1], ys[-1], zs[-1]])
+    span = hi - lo
+    sides = {"xmin": (0, 0), "xmax": (0, 1), "ymin": (1, 0), "ymax": (1, 1), "zmin": (2, 0), "zmax": (2, 1)}
+    groups = {k: [] for k in sides}
+    for own, pts in seen.values():
+        cen = P[list(pts)].mean(axis=0)
+        name = None
+        for k, (ax, end) in sides.items():
+            ref = hi[ax] if end else lo[ax]
+            if np.all(np.abs(P[list(pts), ax] - ref) <= 1e-12 * max(1.0, span[ax])):
+                name = k
+                break
+        if name is None:
+            raise ValueError(f"boundary face {pts} lies on no side of the block")
+        groups[name].append((own, pts, cen))
+    # order each side by the transverse coordinates of the face centroids, so that the faces of
+    # opposite sides match one to one
+    for k, (ax, _) in sides.items():
+        tr = [a for a in range(3) if a != ax]
+        groups[k].sort(key=lambda t: (round(t[2][tr[1]], 9), round(t[2][tr[0]], 9)))
+    owner = [t[0] for t in internal]
+    neighbour = [t[1] for t in internal]
+    fpts = [t[2] for t in internal]
+    patches = []
+    start = len(internal)
+    for k in ("xmin", "xmax", "ymin", "ymax", "zmin", "zmax"):
+        g = groups[k]
+        patches.append(Patch(k, kinds[k], start, len(g), alpha_in=float(alpha_in.get(k, 0.0))))
+        owner += [t[0] for t in g]
+        fpts += [t[1] for t in g]
+        start += len(g)
+    if periodic_x:
+        L = float(xs[-1] - xs[0])
+        patches[0].partner, patches[0].translation = 1, (L, 0.0, 0.0)
+        patches[1].partner, patches[1].translation = 0, (-L, 0.0, 0.0)
+    if periodic_y:
+        L = float(ys[-1] - ys[0])
+        patches[2].partner, patches[2].translation = 3, (0.0, L, 0.0)
+        patches[3].partner, patches[3].translation = 2, (0.0, -L, 0.0)
+    face_ptr = np.concatenate([[0], np.cumsum([len(f) for f in fpts])]).astype(np.int32)
+    face_pts = np.array([p for f in fpts for p in f], dtype=np.int32)
+    return Mesh(points=P, face_ptr=face_ptr, face_pts=face_pts, owner=np.array(owner, dtype=np.int32),
+                neighbour=np.array(neighbour, dtype=np.int32), n_cells=len(cells), patches=patches,
+                shape=(len(xs) - 1, len(ys) - 1, len(zs) - 1))
+
+
+def prism_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False):
+    """Each hexahedron (i, j, k) of the block cut into two triangular prisms along the diagonal from
+    (x_i, y_j) to (x_i+1, y_j+1): cell 2 c (the lower-right triangle) and 2 c + 1, c the hexahedron's
+    number in wavegen.mesh.hex_block."""
+    xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+
+    def P(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    cells = []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                for tri in (((i, j), (i + 1, j), (i + 1, j + 1)), ((i, j), (i + 1, j + 1), (i, j + 1))):
+                    bot = [P(a, b, k) for a, b in tri]
+                    top = [P(a, b, k + 1) for a, b in tri]
+                    faces = [tuple(reversed(bot)), tuple(top)]
+                    for e in range(3):
+                        a, b = e, (e + 1) % 3
+                        faces.append((bot[a], bot[b], top[b], top[a]))
+                    cells.append(faces)
+    return mesh_from_cells(_grid_points(xs, ys, zs), cells, xs, ys, zs, kinds, periodic_x, periodic_y)
+
+
+def pyramid_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False):
+    """Each hexahedron of the block cut into six square pyramids with their apex at its centre (one
+    extra point per hexahedron, numbered after the grid points): cells 6 c .. 6 c + 5, bases on the
+    -x, +x, -y, +y, -z, +z sides."""
+    xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    pts = [_grid_points(xs, ys, zs)]
+    n0 = len(pts[0])
+
+    def P(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    cells, centres = [], []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                apex = n0 + len(centres)
+                centres.append([0.5 * (xs[i] + xs[i + 1]), 0.5 * (ys[j] + ys[j + 1]), 0.5 * (zs[k] + zs[k + 1])])
+                # the hexahedron's faces counter-clockwise from outside (as in hex_block)
+                quads = [(P(i, j + 1, k), P(i, j, k), P(i, j, k + 1), P(i, j + 1, k + 1)),
+                         (P(i + 1, j, k), P(i + 1, j + 1, k), P(i + 1, j + 1, k + 1), P(i + 1, j, k + 1)),
+                         (P(i, j, k), P(i + 1, j, k), P(i + 1, j, k + 1), P(i, j, k + 1)),
+                         (P(i + 1, j + 1, k), P(i, j + 1, k), P(i, j + 1, k + 1), P(i + 1, j + 1, k + 1)),
+                         (P(i, j, k), P(i, j + 1, k), P(i + 1, j + 1, k), P(i + 1, j, k)),
+                         (P(i, j, k + 1), P(i + 1, j, k + 1), P(i + 1, j + 1, k + 1), P(i, j + 1, k + 1))]
+                for q in quads:
+                    # base outward as on the hexahedron; each side triangle outward from the pyramid
+                    cells.append([q] + [(q[(a + 1) % 4], q[a], apex) for a in range(4)])
+    pts = np.concatenate([pts[0], np.array(centres, dtype=np.float64)])
+    return mesh_from_cells(pts, cells, xs, ys, zs, kinds, periodic_x, periodic_y)
+
+
+def tet_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False):
+    """Each hexahedron of the block cut into six tetrahedra along its main diagonal (Kuhn): cells
+    6 c .. 6 c + 5, one per ordering of the axes."""
+    xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    pts = _grid_points(xs, ys, zs)
+
+    def P(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    cells = []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                for perm in itertools.permutations(range(3)):
+                    v = [0, 0, 0]
+                    path = [P(i, j, k)]
+                    for ax in perm:
+                        v[ax] += 1
+                        path.append(P(i + v[0], j + v[1], k + v[2]))
+                    a, b, c, d = path
+                    vol = np.dot(pts[b] - pts[a], np.cross(pts[c] - pts[a], pts[d] - pts[a]))
+                    if vol < 0:
+                        b, c = c, b
+                    cells.append([(a, c, b), (a, b, d), (a, d, c), (b, c, d)])
+    return mesh_from_cells(pts, cells, xs, ys, zs, kinds, periodic_x, periodic_y)
+
+
+def cell_geometry(mesh):
+    """Cell volumes and centroids of any mesh with planar faces (faces fanned about their vertex
+    mean, cells about the mean of their faces' vertex means)."""
+    P = mesh.points
+    nf = mesh.n_faces
+    vol = np.zeros(mesh.n_cells)
+    mom = np.zeros((mesh.n_cells, 3))
+    ref = np.zeros((mesh.n_cells, 3))
+    cnt = np.zeros(mesh.n_cells)
+    ni = mesh.n_internal
+    for f in range(nf):
+        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
+        m = P[fp].mean(axis=0)
+        for c in ([mesh.owner[f], mesh.neighbour[f]] if f < ni else [mesh.owner[f]]):
+            ref[c] += m
+            cnt[c] += 1
+    ref /= cnt[:, None]
+    for f in range(nf):
+        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
+        q = P[fp]
+        ap = q.mean(axis=0)
+        sides = [(mesh.owner[f], 1.0)] + ([(mesh.neighbour[f], -1.0)] if f < ni else [])
+        for c, sgn in sides:
+            for a in range(len(fp)):
+                b = (a + 1) % len(fp)
+                tv = sgn * np.dot(ap - ref[c], np.cross(q[a] - ref[c], q[b] - ref[c])) / 6.0
+                vol[c] += tv
+                mom[c] += tv * 0.25 * (ref[c] + ap + q[a] + q[b])
+    return vol, mom / vol[:, None]
+
+
+def fluxes_from_potential(mesh, psi, n_gauss=8):
+    """phi_f = circulation of the vector potential (0, 0, psi) around face f (Stokes), each edge's
+    line integral of psi dz computed once (Gauss-Legendre with n_gauss points along the straight
+    edge) and shared with opposite sign, so that every cell's fluxes sum to zero up to round-off.
+    Wall and empty patches carry exactly zero flux."""
+    P = mesh.points
+    gx, gw = np.polynomial.legendre.leggauss(n_gauss)
+    s = 0.5 * (gx + 1.0)
+    w = 0.5 * gw
+    cache = {}
+    phi = np.zeros(mesh.n_faces)
+    for f in range(mesh.n_faces):
+        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
+        tot = 0.0
+        for a in range(len(fp)):
+            pa, pb = int(fp[a]), int(fp[(a + 1) % len(fp)])
+            if P[pa, 2] == P[pb, 2]:
+                continue
+            key = (min(pa, pb), max(pa, pb))
+            if key not in cache:
+                xa, xb = P[key[0]], P[key[1]]
+                x = xa[None, :] + s[:, None] * (xb - xa)[None, :]
+                cache[key] = float(np.dot(w, psi(x[:, 0], x[:, 1], x[:, 2]))) * (xb[2] - xa[2])
+            tot += cache[key] if pa == key[0] else -cache[key]
+        phi[f] = tot
+    for p in mesh.patches:
+        if p.kind in (0, 1):
+            phi[p.start:p.start + p.size] = 0.0
+    return phi
+
+
+def _lattice(order):
+    """Barycentric points (4 weights) of the interior of a tetrahedral lattice of the given order:
+    equal-weight sample points of a tetrahedron."""
+    pts = []
+    for i in range(order):
+        for j in range(order - i):
+            for k in range(order - i - j):
+                l = order - 1 - i - j - k
+                pts.append((i + 0.25, j + 0.25, k + 0.25, l + 0.25))
+    b = np.array(pts, dtype=np.float64)
+    return b / b.sum(axis=1, keepdims=True)
+
+
+def alpha_sampled(mesh, wet, order=6):
+    """Volume fractions of the region wet(x, y, z) > 0 per cell, by equal-weight sampling of the
+    tetrahedra that fan each cell about its centroid over its face triangles (an input generator:
+    a sharp field with fractional values near the surface, not an exact integral)."""
+    vol, cen = cell_geometry(mesh)
+    bary = _lattice(order)
+    P = mesh.points
+    acc = np.zeros(mesh.n_cells)
+    ni = mesh.n_internal
+    for f in range(mesh.n_faces):
+        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
+        q = P[fp]
+        ap = q.mean(axis=0)
+        for c in ([mesh.owner[f], mesh.neighbour[f]] if f < ni else [mesh.owner[f]]):
+            for a in range(len(fp)):
+                t = np.array([cen[c], ap, q[a], q[(a + 1) % len(fp)]])
+                tv = abs(np.dot(t[1] - t[0], np.cross(t[2] - t[0], t[3] - t[0]))) / 6.0
+                x = bary @ t
+                acc[c] += tv * np.mean(wet(x[:, 0], x[:, 1], x[:, 2]) > 0)
+    return np.clip(acc / vol, 0.0, 1.0)
+
+
+class PolyWorkload:
+    """A steady flow on a tetrahedral or prismatic mesh: mesh, alpha0, phi_U(n), dt, n_steps."""
+
+    def __init__(self, name, mesh, alpha0, phi, U, dt, n_steps):
+        self.name, self.mesh, self.alpha0, self.dt, self.n_steps = name, mesh, alpha0, dt, n_steps
+        self._phi, self._U = phi, U
+        self.steady = True
+
+    def phi_U(self, n):
+        return self._phi, self._U
+
+
+def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5):
+    """The violent 3D workload's ingredients on tetrahedra or prisms: the box [0,2]x[0,1]x[0,1],
+    periodic in x, a water column {x < 0.3, z < 0.6} joined to a wavy layer
+    {z < 0.45 + 0.02 cos 4 pi x cos 4 pi y}, and the uniform + Taylor-Green flow (its fluxes from the
+    vector potential along the straight edges)."""
+    from .fields import UniformPlusTaylorGreen
+    xs, ys, zs = np.linspace(0, 2, nx + 1), np.linspace(0, 1, ny + 1), np.linspace(0, 1, nz + 1)
+    build = tet_block if kind == "tet" else prism_block
+    mesh = build(xs, ys, zs, periodic_x=True)
+    flow = UniformPlusTaylorGreen(0.5, 1.0, 0.25)
+    wet = lambda x, y, z: np.maximum(0.45 + 0.02 * np.cos(4 * np.pi * x) * np.cos(4 * np.pi * y) - z,
+                                     np.minimum(0.3 - x, 0.6 - z))
+    a0 = alpha_sampled(mesh, wet)
+    phi = fluxes_from_potential(mesh, flow.psi)
+    vol, cen = cell_geometry(mesh)
+    U = flow.velocity_at(cen)
+    from .fields import courant_dt
+    dt = courant_dt(mesh, phi, co, volumes=vol)
+    return PolyWorkload(f"violent_{kind}_{nx}x{ny}x{nz}", mesh, a0, phi, U, dt, steps)
+
+
+def poly_airy(kind="prism", nx=64, ny=32, steps=8, co=0.5, steepness=0.07):
+    """A linear Airy wave (as wavegen.configs.airy_slab) on a one-cell-thick slab of triangular
+    prisms (kind "prism") or tetrahedra, [0, 2] x [0, 1], periodic in x, wavelength 1."""
+    from .fields import AiryWave, courant_dt
+    from .mesh import PATCH_EMPTY
+    h = 1.0 / ny
+    xs, ys, zs = np.linspace(0, 2, nx + 1), np.linspace(0, 1, ny + 1), np.array([0.0, h])
+    build = prism_block if kind == "prism" else tet_block
+    mesh = build(xs, ys, zs, kinds={"zmin": PATCH_EMPTY, "zmax": PATCH_EMPTY}, periodic_x=True)
+    wave = AiryWave(1.0, steepness, 0.5, 1.0)
+    wet = lambda x, y, z: 0.5 + 0.5 * steepness * np.cos(2 * np.pi * x) - y
+    a0 = alpha_sampled(mesh, wet)
+    vol, cen = cell_geometry(mesh)
+    phi = fluxes_from_potential(mesh, lambda x, y, z: wave.psi(x, y, 0.0))
+    u, v = wave.velocity(cen[:, 0], cen[:, 1], 0.0)
+    U = np.ascontiguousarray(np.concatenate([u, v, np.zeros_like(u)]))
+    dt = courant_dt(mesh, phi, co, volumes=vol)
+    return PolyWorkload(f"airy_{kind}_{nx}x{ny}", mesh, a0, phi, U, dt, steps)
