@@ -21,8 +21,11 @@
  *    neighbour of every interior face), interior faces first, boundary faces
  *    grouped into patches.  The points of a face run counter-clockwise seen
  *    from outside its owner, so phi_f > 0 is flow from owner to neighbour (or
- *    out of the domain).  This kernel path takes hexahedral cells (6
- *    quadrilateral faces, 8 points); other cells give ISO_EUNSUPPORTED.
+ *    out of the domain).  Cells: hexahedra (6 quadrilateral faces, 8 points),
+ *    and cells of 4 to 6 faces of 3 or 4 points over at most 8 points
+ *    (tetrahedra, square pyramids, triangular prisms), mixed freely; other
+ *    cells give ISO_EUNSUPPORTED.  Meshes with cells other than hexahedra take
+ *    us_mode 0 only, and neither the adjoint nor ensembles.
  *  - Patch kinds: WALL and EMPTY faces carry no flux (their phi is ignored);
  *    INOUT faces carry flux, inflow carrying the patch's alpha_in; CYCLIC
  *    patches come in pairs (face n of a patch matches face n of its partner,
@@ -55,7 +58,7 @@ typedef enum {
     ISO_ENOSPACE = 4,      /* interface cells exceed the plan's capacity */
     ISO_ECOURANT = 5,      /* input check: a cell Courant number exceeds max_courant */
     ISO_EMESH = 6,         /* inconsistent mesh (indices, orientation, cyclic matching, volume) */
-    ISO_EUNSUPPORTED = 7   /* valid mesh the kernels do not take (non-hexahedral cells) */
+    ISO_EUNSUPPORTED = 7   /* valid input the kernels do not take (e.g. a cell of more than 8 points) */
 } iso_status;
 
 enum { ISO_PATCH_WALL = 0, ISO_PATCH_EMPTY = 1, ISO_PATCH_INOUT = 2, ISO_PATCH_CYCLIC = 3 };
@@ -133,7 +136,9 @@ void iso_mesh_destroy(iso_mesh *mesh);
 /* info[0..7] = n_cells, n_points, n_faces, n_flux_faces, n_point_classes, slots per cell,
  *              device bytes held, reserved */
 iso_status iso_mesh_info(const iso_mesh *mesh, int64_t *info);
-/* host out[8*n_cells]: user point id of each canonical vertex of each cell */
+/* host out[8*n_cells]: user point id of each canonical vertex of each cell (hexahedra: the
+ * canonical order; other cells: their distinct points in order of first appearance over their
+ * faces, then the first point repeated) */
 iso_status iso_mesh_cell_points(const iso_mesh *mesh, int32_t *out);
 /* host out[n_cells]: cell volumes; xc (nullable) [3*n_cells]: cell centres */
 iso_status iso_mesh_geometry(const iso_mesh *mesh, double *vol, double *xc);

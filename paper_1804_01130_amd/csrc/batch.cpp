@@ -139,6 +139,7 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         const iso_mesh *m = meshes[i];
         if (!m) return fail(ISO_EINVAL, "null mesh in the ensemble");
         if (m->device != dev) return fail(ISO_EINVAL, "ensemble members must live on the current device");
+        if (m->generic) return fail(ISO_EUNSUPPORTED, "ensemble members must be meshes of hexahedra");
         N += m->n_cells; F += m->n_faces; K += m->n_classes; S += m->st_nnz; P += m->dev.n_patches;
         NF += m->n_flux;
         W = std::max(W, m->W);

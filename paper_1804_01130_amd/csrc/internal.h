@@ -41,6 +41,8 @@ struct DevMesh {
                                          // face of a cyclic pair)
     const int32_t *bpatch = nullptr;     // [n_faces-n_internal] patch of each boundary face
     const double *ptrans = nullptr;      // [3*n_patches] cyclic translations (x_partner = x + T)
+    // local face loops of every cell (see plan.cpp), or null when every cell is a hexahedron
+    const int32_t *cloop = nullptr;      // [6*n_cells]
     // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;
@@ -173,7 +175,10 @@ hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha,
 struct iso_mesh {
     isoadv::DevMesh dev;
     int32_t n_points = 0, n_faces = 0, n_internal = 0, n_cells = 0, n_flux = 0, n_classes = 0, W = 0;
-    std::vector<int32_t> cell_pts;   // [8*n_cells] user point ids, canonical order
+    std::vector<int32_t> cell_pts;   // [8*n_cells] user point ids, canonical order (a cell with fewer
+                                     // points repeats its first one after them)
+    std::vector<int32_t> nvtx;       // [n_cells] distinct points of each cell
+    bool generic = false;            // some cell is not a hexahedron
     std::vector<double> vol, xc;
     std::vector<double> patch_alpha;
     int64_t st_nnz = 0;              // entries of the vertex stencils

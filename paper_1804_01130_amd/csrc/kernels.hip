@@ -494,20 +494,33 @@ __device__ __forceinline__ double isoface_speed(const SurfArgs &A, int32_t c, in
 
 // kMinBlocks: work-groups of 256 per CU the register allocation must allow (waves per SIMD)
 // kInterp: U_S by cell-point interpolation (us_mode 1) instead of U_P
-template <int kMinBlocks, bool kInterp>
+// kGeneric: the mesh has cells other than hexahedra (tetrahedra, pyramids, prisms), and every
+// cell takes its faces' vertex loops from m.cloop: up to six faces of three or four points (a
+// triangle repeats its first point, which gives a zero-length edge that is never cut and adds
+// nothing) over up to eight points (lanes past the cell's points repeat its first point).  Such
+// cells use the generic isovalue search; hexahedra keep the interval solve.
+template <int kMinBlocks, bool kInterp, bool kGeneric>
 __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
     const DevMesh &m = A.m;
     const int lv = threadIdx.x & (kLanes - 1);
     const int ngrp = (gridDim.x * blockDim.x) / kLanes;
     const int n = min(A.counters[kCntSurf], A.cap);
-    // face lv's vertex loop and edge directions (constant per lane)
+    // face lv's vertex loop and edge directions (constant per lane on a mesh of hexahedra)
     int fv[4];
-    const int fwd = lane_face_loop(lv, fv);
+    int fwd = lane_face_loop(lv, fv);
+    bool face_on = lv < 6;
     int rounds_max = 0, flat = 0, nonconv = 0;
     // groups take list entries round-robin over the XCDs: interface cells are clustered, and
     // contiguous ranges per XCD would leave the XCDs with unequal work
     for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; idx < n; idx += ngrp) {
         const int c = A.list[idx];
+        if constexpr (kGeneric) {
+            const int32_t L = lv < 6 ? m.cloop[6 * (size_t)c + lv] : 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fv[i] = (L >> (3 * i)) & 7;
+            fwd = (L >> 16) & 15;
+            face_on = (L >> 12) & 1;
+        }
         const double aP = A.alpha[c];
         const double V6 = 6.0 * m.vol[c];
         const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
@@ -540,7 +553,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = grp_get(av, i);
         FaceLane f;
-        f.active = lv < 6;
+        f.active = face_on;
         f.planar = (m.cflags[c] >> min(lv, 5)) & 1;
         f.fwd = fwd;
 #pragma unroll
@@ -566,7 +579,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 s[i + 1] = y;
             }
         bool recon = s[7] - s[0] > A.flat_tol;
-        const bool planar_cell = (m.cflags[c] & 63) == 63;
+        const bool planar_cell = (m.cflags[c] & 0x13f) == 63;  // a hexahedron with six planar faces
         double iso = 0.0;
         int rounds = 0;
         bool face_done = false;
@@ -1245,19 +1258,26 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
     // persistent: groups loop over the list, which is only known on the device
     gs = std::max(1L, std::min(gs, cfg.surface_blocks > 0 ? (long)cfg.surface_blocks : 2048L));
-    if (p.us_mode == 1) {
+    if (m.cloop) {
         switch (cfg.surface_waves) {
-            case 1: hipLaunchKernelGGL((k_surface<1, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
-            case 3: hipLaunchKernelGGL((k_surface<3, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
-            case 4: hipLaunchKernelGGL((k_surface<4, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
-            default: hipLaunchKernelGGL((k_surface<2, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 1: hipLaunchKernelGGL((k_surface<1, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 3: hipLaunchKernelGGL((k_surface<3, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 4: hipLaunchKernelGGL((k_surface<4, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            default: hipLaunchKernelGGL((k_surface<2, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+        }
+    } else if (p.us_mode == 1) {
+        switch (cfg.surface_waves) {
+            case 1: hipLaunchKernelGGL((k_surface<1, true, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 3: hipLaunchKernelGGL((k_surface<3, true, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 4: hipLaunchKernelGGL((k_surface<4, true, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            default: hipLaunchKernelGGL((k_surface<2, true, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
         }
     } else {
         switch (cfg.surface_waves) {
-            case 1: hipLaunchKernelGGL((k_surface<1, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
-            case 3: hipLaunchKernelGGL((k_surface<3, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
-            case 4: hipLaunchKernelGGL((k_surface<4, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
-            default: hipLaunchKernelGGL((k_surface<2, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 1: hipLaunchKernelGGL((k_surface<1, false, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 3: hipLaunchKernelGGL((k_surface<3, false, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 4: hipLaunchKernelGGL((k_surface<4, false, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            default: hipLaunchKernelGGL((k_surface<2, false, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
         }
     }
     if (ev) (void)hipEventRecord(ev[2], s);

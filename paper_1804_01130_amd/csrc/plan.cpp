@@ -185,34 +185,102 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
 
     auto P = [&](int32_t i) { return V3{px[i], py[i], pz[i]}; };
 
-    // ---- cells: six quadrilateral faces each
+    // ---- cells: hexahedra (six quadrilaterals, the canonical vertex order below), or other cells
+    // of at most six faces of three or four points and at most eight distinct points
+    // (tetrahedra, pyramids, prisms), whose faces are listed with their own vertex loops
     std::vector<int32_t> ncf(n_cells, 0);
     for (int32_t f = 0; f < n_faces; ++f) {
         ncf[owner[f]]++;
         if (f < n_internal) ncf[neighbour[f]]++;
     }
     for (int32_t c = 0; c < n_cells; ++c)
-        if (ncf[c] != 6) return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " is not a hexahedron");
-    for (int32_t f = 0; f < n_faces; ++f)
-        if (face_ptr[f + 1] - face_ptr[f] != 4) return fail(ISO_EUNSUPPORTED, "face " + std::to_string(f) + " is not a quadrilateral");
-    std::vector<int32_t> cfaces(6 * (size_t)n_cells);
+        if (ncf[c] < 4 || ncf[c] > 6)
+            return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has " + std::to_string(ncf[c]) +
+                                              " faces (4 to 6 are taken)");
+    for (int32_t f = 0; f < n_faces; ++f) {
+        const int32_t np = face_ptr[f + 1] - face_ptr[f];
+        if (np < 3 || np > 4)
+            return fail(ISO_EUNSUPPORTED, "face " + std::to_string(f) + " has " + std::to_string(np) +
+                                              " points (3 or 4 are taken)");
+    }
+    std::vector<int32_t> cfaces(6 * (size_t)n_cells, -1);
     std::fill(ncf.begin(), ncf.end(), 0);
     for (int32_t f = 0; f < n_faces; ++f) {  // ascending face id per cell
         cfaces[6 * (size_t)owner[f] + ncf[owner[f]]++] = f;
         if (f < n_internal) cfaces[6 * (size_t)neighbour[f] + ncf[neighbour[f]]++] = f;
     }
+    // a face's points counter-clockwise seen from outside cell c (a triangle repeats its first point)
     auto outward = [&](int32_t f, int32_t c, std::array<int32_t, 4> &q) {
         const int32_t *fp = face_pts + face_ptr[f];
-        if (owner[f] == c) for (int i = 0; i < 4; ++i) q[i] = fp[i];
-        else for (int i = 0; i < 4; ++i) q[i] = fp[3 - i];
+        const int np = face_ptr[f + 1] - face_ptr[f];
+        if (owner[f] == c) for (int i = 0; i < np; ++i) q[i] = fp[i];
+        else for (int i = 0; i < np; ++i) q[i] = fp[np - 1 - i];
+        if (np == 3) q[3] = q[0];
     };
+    auto npts = [&](int32_t f) { return face_ptr[f + 1] - face_ptr[f]; };
 
     iso_mesh *m = new iso_mesh();
     m->n_points = n_points; m->n_faces = n_faces; m->n_internal = n_internal; m->n_cells = n_cells;
     m->cell_pts.resize(8 * (size_t)n_cells);
-    std::vector<int32_t> lface_actual(6 * (size_t)n_cells);
+    m->nvtx.assign(n_cells, 8);
+    std::vector<int32_t> lface_actual(6 * (size_t)n_cells, -1);
+    // other cells: local vertex loop of each face (local indices 0-7, a triangle's fourth entry
+    // repeating its first) and the number of points of the face (0: no face)
+    std::vector<std::array<int8_t, 4>> gloop(6 * (size_t)n_cells, std::array<int8_t, 4>{0, 0, 0, 0});
+    std::vector<int8_t> gnp(6 * (size_t)n_cells, 0);
+
+    bool closed_ok = true;
+    auto make_generic = [&](int32_t c) -> bool {
+        // generic cell: distinct points in order of first appearance
+        int32_t v[8];
+        int nv = 0;
+        bool ok = true;
+        for (int k = 0; k < ncf[c] && ok; ++k) {
+            std::array<int32_t, 4> q;
+            const int32_t f = cfaces[6 * (size_t)c + k];
+            outward(f, c, q);
+            for (int i = 0; i < npts(f) && ok; ++i) {
+                int j = 0;
+                while (j < nv && v[j] != q[i]) ++j;
+                if (j == nv) {
+                    if (nv == 8) ok = false;
+                    else v[nv++] = q[i];
+                }
+                gloop[6 * (size_t)c + k][i] = (int8_t)j;
+            }
+            if (npts(f) == 3) gloop[6 * (size_t)c + k][3] = gloop[6 * (size_t)c + k][0];
+            gnp[6 * (size_t)c + k] = (int8_t)npts(f);
+            lface_actual[6 * (size_t)c + k] = f;
+        }
+        if (!ok || nv < 4) return false;  // more than eight points (or a degenerate cell)
+        for (int i = 0; i < 8; ++i) m->cell_pts[8 * (size_t)c + i] = v[i < nv ? i : 0];
+        // closed: the outward area vectors of the faces sum to zero
+        V3 sum{0, 0, 0};
+        double mag = 0;
+        for (int k = 0; k < ncf[c]; ++k) {
+            std::array<int32_t, 4> q;
+            const int32_t f = cfaces[6 * (size_t)c + k];
+            outward(f, c, q);
+            const V3 a = 0.5 * cross(P(q[2]) - P(q[0]), P(q[3]) - P(q[1]));
+            sum = sum + a;
+            mag += norm(a);
+        }
+        if (!(norm(sum) <= 1e-9 * mag)) closed_ok = false;
+        m->nvtx[c] = nv;
+        m->generic = true;
+        return true;
+    };
 
     for (int32_t c = 0; c < n_cells; ++c) {
+        bool hex = ncf[c] == 6;
+        for (int k = 0; k < ncf[c] && hex; ++k) hex = npts(cfaces[6 * (size_t)c + k]) == 4;
+        if (!hex) {
+            if (!make_generic(c)) {
+                iso_mesh_destroy(m);
+                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points");
+            }
+            continue;
+        }
         std::array<std::array<int32_t, 4>, 6> fq;
         for (int k = 0; k < 6; ++k) outward(cfaces[6 * (size_t)c + k], c, fq[k]);
         // bottom = first face; its outward loop is canonical (0,3,2,1)
@@ -241,7 +309,13 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
             std::sort(s, s + 8);
             ok = std::adjacent_find(s, s + 8) == s + 8;
         }
-        if (!ok) { iso_mesh_destroy(m); return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " is not a hexahedron"); }
+        if (!ok) {  // six quadrilaterals that do not make a hexahedron
+            if (!make_generic(c)) {
+                iso_mesh_destroy(m);
+                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points");
+            }
+            continue;
+        }
         // match canonical faces to actual faces, with orientation
         for (int k = 0; k < 6; ++k) {
             int found = -1;
@@ -261,25 +335,35 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         for (int i = 0; i < 8; ++i) m->cell_pts[8 * (size_t)c + i] = v[i];
     }
 
+    if (!closed_ok) { iso_mesh_destroy(m); return fail(ISO_EMESH, "a cell's faces do not close it"); }
+
     // ---- volumes and centroids: tetrahedra (vertex mean, face vertex mean, edge) over outward faces
     m->vol.resize(n_cells);
     m->xc.resize(3 * (size_t)n_cells);
     for (int32_t c = 0; c < n_cells; ++c) {
         const int32_t *v = &m->cell_pts[8 * (size_t)c];
+        const int nv = m->nvtx[c];
         V3 xm{0, 0, 0};
-        for (int i = 0; i < 8; ++i) xm = xm + P(v[i]);
-        xm = 0.125 * xm;
+        for (int i = 0; i < nv; ++i) xm = xm + P(v[i]);
+        xm = (nv == 8 ? 0.125 : 1.0 / nv) * xm;
         double vol = 0;
         V3 mom{0, 0, 0};
         for (int k = 0; k < 6; ++k) {
             V3 q[4];
-            for (int i = 0; i < 4; ++i) q[i] = P(v[kHexFace[k][i]]);
-            V3 ap = 0.25 * (q[0] + q[1] + q[2] + q[3]);
-            for (int i = 0; i < 4; ++i) {
-                V3 a = ap - xm, b = q[i] - xm, cc = q[(i + 1) % 4] - xm;
+            int np = 4;
+            if (gnp[6 * (size_t)c] == 0) {
+                for (int i = 0; i < 4; ++i) q[i] = P(v[kHexFace[k][i]]);
+            } else {
+                np = gnp[6 * (size_t)c + k];
+                if (np == 0) continue;
+                for (int i = 0; i < np; ++i) q[i] = P(v[gloop[6 * (size_t)c + k][i]]);
+            }
+            V3 ap = np == 4 ? 0.25 * (q[0] + q[1] + q[2] + q[3]) : (1.0 / 3.0) * (q[0] + q[1] + q[2]);
+            for (int i = 0; i < np; ++i) {
+                V3 a = ap - xm, b = q[i] - xm, cc = q[(i + 1) % np] - xm;
                 double tv = dot(a, cross(b, cc)) / 6.0;
                 vol += tv;
-                mom = mom + (tv * 0.25) * (xm + ap + q[i] + q[(i + 1) % 4]);
+                mom = mom + (tv * 0.25) * (xm + ap + q[i] + q[(i + 1) % np]);
             }
         }
         if (!(vol > 0)) { iso_mesh_destroy(m); return fail(ISO_EMESH, "cell " + std::to_string(c) + " has non-positive volume"); }
@@ -326,7 +410,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     for (int32_t c = 0; c < n_cells; ++c) {
         for (int k = 0; k < 6; ++k) {
             int32_t f = cfaces[6 * (size_t)c + k];
-            if (f_fid[f] < 0) continue;
+            if (f < 0 || f_fid[f] < 0) continue;
             int s; int32_t other;
             if (f < n_internal) { s = owner[f] == c ? 1 : -1; other = owner[f] == c ? neighbour[f] : owner[f]; }
             else { s = f_sign[f]; other = f_other[f]; }
@@ -347,7 +431,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     for (int32_t c = 0; c < n_cells; ++c)
         for (int k = 0; k < 6; ++k) {
             int32_t f = lface_actual[6 * (size_t)c + k];
-            if (f_fid[f] < 0) continue;
+            if (f < 0 || f_fid[f] < 0) continue;
             int s = f < n_internal ? (owner[f] == c ? 1 : -1) : f_sign[f];
             lface[6 * (size_t)c + k] = pack_face(f_fid[f], s);
         }
@@ -361,13 +445,20 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         for (int32_t i = 0; i < patch_size[p]; ++i) {
             int32_t f = patch_start[p] + i, g = patch_start[q] + i;
             const int32_t *fa = face_pts + face_ptr[f], *gb = face_pts + face_ptr[g];
-            V3 ctr = 0.25 * (P(fa[0]) + P(fa[1]) + P(fa[2]) + P(fa[3]));
+            const int na = npts(f);
+            if (npts(g) != na) {
+                iso_mesh_destroy(m);
+                return fail(ISO_EMESH, "cyclic face " + std::to_string(f) + " does not match its partner");
+            }
+            V3 ctr{0, 0, 0};
+            for (int a = 0; a < na; ++a) ctr = ctr + P(fa[a]);
+            ctr = (1.0 / na) * ctr;
             double h = 0;
-            for (int a = 0; a < 4; ++a) h = std::max(h, norm(P(fa[a]) - ctr));
-            for (int a = 0; a < 4; ++a) {
+            for (int a = 0; a < na; ++a) h = std::max(h, norm(P(fa[a]) - ctr));
+            for (int a = 0; a < na; ++a) {
                 V3 tgt = P(fa[a]) + T;
                 int32_t hit = -1;
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < na; ++b)
                     if (norm(P(gb[b]) - tgt) <= 1e-8 * h) hit = gb[b];
                 if (hit < 0) {
                     iso_mesh_destroy(m);
@@ -390,14 +481,14 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     // stencil of each class: every (cell, vertex) whose point is in the class, centre in the root frame
     std::vector<int32_t> cnt(n_classes + 1, 0);
     for (int32_t c = 0; c < n_cells; ++c)
-        for (int i = 0; i < 8; ++i) cnt[cls[m->cell_pts[8 * (size_t)c + i]] + 1]++;
+        for (int i = 0; i < m->nvtx[c]; ++i) cnt[cls[m->cell_pts[8 * (size_t)c + i]] + 1]++;
     for (int32_t k = 0; k < n_classes; ++k) cnt[k + 1] += cnt[k];
     m->st_nnz = cnt[n_classes];
     std::vector<int32_t> st_cell(cnt[n_classes]);
     std::vector<double> st_w(cnt[n_classes]);
     std::vector<int32_t> fillc(n_classes, 0);
     for (int32_t c = 0; c < n_cells; ++c)  // ascending cell id within each stencil
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < m->nvtx[c]; ++i) {
             int32_t p = m->cell_pts[8 * (size_t)c + i];
             int32_t k = cls[p];
             int32_t e = cnt[k] + fillc[k]++;
@@ -412,11 +503,20 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         for (int32_t e = cnt[k]; e < cnt[k + 1]; ++e) st_w[e] /= s;
     }
     // planar faces: the four points within 1e-12 (relative) of their mean plane
+    // (bit k: local face k is planar; a triangle always is); bit 8: not a hexahedron
     std::vector<int32_t> cflags(n_cells, 0);
     for (int32_t c = 0; c < n_cells; ++c)
         for (int k = 0; k < 6; ++k) {
             V3 q[4];
-            for (int i = 0; i < 4; ++i) q[i] = P(m->cell_pts[8 * (size_t)c + kHexFace[k][i]]);
+            if (gnp[6 * (size_t)c] != 0) {
+                cflags[c] |= 1 << 8;
+                const int np = gnp[6 * (size_t)c + k];
+                if (np == 3) cflags[c] |= 1 << k;
+                if (np != 4) continue;
+                for (int i = 0; i < 4; ++i) q[i] = P(m->cell_pts[8 * (size_t)c + gloop[6 * (size_t)c + k][i]]);
+            } else {
+                for (int i = 0; i < 4; ++i) q[i] = P(m->cell_pts[8 * (size_t)c + kHexFace[k][i]]);
+            }
             V3 nrm = cross(q[2] - q[0], q[3] - q[1]);
             double ln = norm(nrm), size = norm(q[2] - q[0]) + norm(q[3] - q[1]);
             V3 mean = 0.25 * (q[0] + q[1] + q[2] + q[3]);
@@ -434,6 +534,29 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
             cxyz[24 * (size_t)c + 3 * i + 1] = x.y;
             cxyz[24 * (size_t)c + 3 * i + 2] = x.z;
         }
+    // local face loops of every cell when the mesh has cells other than hexahedra (hexahedra take
+    // the canonical loops): bits 3i..3i+2 the local vertex at loop position i, bit 12 a face,
+    // bits 16+i whether loop position i runs from the lower to the higher local index
+    std::vector<int32_t> cloop;
+    if (m->generic) {
+        cloop.assign(6 * (size_t)n_cells, 0);
+        for (int32_t c = 0; c < n_cells; ++c)
+            for (int k = 0; k < 6; ++k) {
+                int lv[4];
+                if (gnp[6 * (size_t)c] == 0) {
+                    for (int i = 0; i < 4; ++i) lv[i] = kHexFace[k][i];
+                } else {
+                    if (gnp[6 * (size_t)c + k] == 0) continue;
+                    for (int i = 0; i < 4; ++i) lv[i] = gloop[6 * (size_t)c + k][i];
+                }
+                int32_t word = 1 << 12;
+                for (int i = 0; i < 4; ++i) {
+                    word |= lv[i] << (3 * i);
+                    if (lv[i] < lv[(i + 1) & 3]) word |= 1 << (16 + i);
+                }
+                cloop[6 * (size_t)c + k] = word;
+            }
+    }
     m->patch_alpha.assign(std::max(n_patches, 1), 0.0);
     for (int32_t p = 0; p < n_patches; ++p) m->patch_alpha[p] = patch_alpha_in[p];
 
@@ -448,7 +571,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         (st = upload(m, lface, &d.lface)) || (st = upload(m, cflags, &d.cflags)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
         (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha)) ||
         (st = upload(m, m->xc, &d.ccen)) || (st = upload(m, fcell, &d.fcell)) || (st = upload(m, bpatch, &d.bpatch)) ||
-        (st = upload(m, ptrans, &d.ptrans))) {
+        (st = upload(m, ptrans, &d.ptrans)) || (m->generic && (st = upload(m, cloop, &d.cloop)))) {
         iso_mesh_destroy(m);
         return st;
     }
@@ -501,6 +624,10 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
         o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1) {
         delete p;
         return fail(ISO_EINVAL, "bad options");
+    }
+    if (mesh->generic && o.us_mode != 0) {
+        delete p;
+        return fail(ISO_EUNSUPPORTED, "the interpolated isoface velocity (us_mode 1) takes meshes of hexahedra only");
     }
     p->stream = static_cast<hipStream_t>(stream);
     const int32_t nc = mesh->n_cells, nf = mesh->n_faces;
@@ -774,6 +901,7 @@ iso_status iso_advect_step_adjoint(iso_plan *p, const double *alpha, const doubl
     if (p->opt.n_bound_iter > kAdjMaxSweeps)
         return fail(ISO_EUNSUPPORTED, "the adjoint takes at most " + std::to_string(kAdjMaxSweeps) + " bounding sweeps");
     if (p->opt.us_mode != 0) return fail(ISO_EUNSUPPORTED, "the adjoint takes U_S = U_P (us_mode 0) only");
+    if (p->mesh->generic) return fail(ISO_EUNSUPPORTED, "the adjoint takes meshes of hexahedra only");
     if (fwd && (!fwd->vert_alpha || !fwd->kind || !fwd->iso || !fwd->dV || !fwd->alpha_raw))
         return fail(ISO_EINVAL, "forward trace needs vert_alpha, kind, iso, dV and alpha_raw");
     const iso_mesh *m = p->mesh;

@@ -48,14 +48,28 @@ def test_mesh_validation_errors_before_device():
     with pytest.raises(B.IsoError) as e:
         _create(m, pp=pp2)
     assert e.value.status == B.ISO_EMESH
-    tri_ptr = m.face_ptr.copy()
-    with pytest.raises(B.IsoError) as e:  # a cell with a face of three points
+    with pytest.raises(B.IsoError) as e:  # a face of five points
+        fp = m.face_pts.copy()
+        fptr = np.concatenate([[0], np.cumsum([5] + [4] * (m.n_faces - 1))]).astype(np.int32)
+        fp = np.concatenate([fp[:4], fp[:1], fp[4:]])
+        _create(m, face_ptr=fptr, face_pts=fp)
+    assert e.value.status == B.ISO_EUNSUPPORTED
+    with pytest.raises(B.IsoError) as e:  # a cell whose faces do not close it
         fp = m.face_pts.copy()
         fptr = np.concatenate([[0], np.cumsum([3] + [4] * (m.n_faces - 1))]).astype(np.int32)
         fp = np.concatenate([fp[:3], fp[4:]])
         _create(m, face_ptr=fptr, face_pts=fp)
-    assert e.value.status == B.ISO_EUNSUPPORTED
-    del tri_ptr
+    assert e.value.status == B.ISO_EMESH
+
+
+@pytest.mark.parametrize("build", [W.tet_block, W.prism_block, W.pyramid_block])
+def test_cells_with_triangular_faces_pass_the_host_checks(build):
+    """Tetrahedra, prisms and pyramids are taken: without a GPU the only failure left is the
+    device one, after every host-side check."""
+    m = build(np.linspace(0, 2, 5), np.linspace(0, 1, 3), np.linspace(0, 1, 3), periodic_x=True)
+    with pytest.raises(B.IsoError) as e:
+        _create(m)
+    assert e.value.status == B.ISO_EDEVICE, e.value
 
 
 def test_cyclic_mismatch_detected():

@@ -139,18 +139,49 @@ def pyramid_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False):
             for i in range(nx):
                 apex = n0 + len(centres)
                 centres.append([0.5 * (xs[i] + xs[i + 1]), 0.5 * (ys[j] + ys[j + 1]), 0.5 * (zs[k] + zs[k + 1])])
-                # the hexahedron's faces counter-clockwise from outside (as in hex_block)
-                quads = [(P(i, j + 1, k), P(i, j, k), P(i, j, k + 1), P(i, j + 1, k + 1)),
-                         (P(i + 1, j, k), P(i + 1, j + 1, k), P(i + 1, j + 1, k + 1), P(i + 1, j, k + 1)),
-                         (P(i, j, k), P(i + 1, j, k), P(i + 1, j, k + 1), P(i, j, k + 1)),
-                         (P(i + 1, j + 1, k), P(i, j + 1, k), P(i, j + 1, k + 1), P(i + 1, j + 1, k + 1)),
-                         (P(i, j, k), P(i, j + 1, k), P(i + 1, j + 1, k), P(i + 1, j, k)),
-                         (P(i, j, k + 1), P(i + 1, j, k + 1), P(i + 1, j + 1, k + 1), P(i, j + 1, k + 1))]
-                for q in quads:
+                for q in _hex_quads(P, i, j, k):
                     # base outward as on the hexahedron; each side triangle outward from the pyramid
                     cells.append([q] + [(q[(a + 1) % 4], q[a], apex) for a in range(4)])
     pts = np.concatenate([pts[0], np.array(centres, dtype=np.float64)])
     return mesh_from_cells(pts, cells, xs, ys, zs, kinds, periodic_x, periodic_y)
+
+
+def _hex_quads(P, i, j, k):
+    """The six faces of hexahedron (i, j, k) counter-clockwise from outside (as in hex_block):
+    -x, +x, -y, +y, -z, +z."""
+    return [(P(i, j + 1, k), P(i, j, k), P(i, j, k + 1), P(i, j + 1, k + 1)),
+            (P(i + 1, j, k), P(i + 1, j + 1, k), P(i + 1, j + 1, k + 1), P(i + 1, j, k + 1)),
+            (P(i, j, k), P(i + 1, j, k), P(i + 1, j, k + 1), P(i, j, k + 1)),
+            (P(i + 1, j + 1, k), P(i, j + 1, k), P(i, j + 1, k + 1), P(i + 1, j + 1, k + 1)),
+            (P(i, j, k), P(i, j + 1, k), P(i + 1, j + 1, k), P(i + 1, j, k)),
+            (P(i, j, k + 1), P(i + 1, j, k + 1), P(i + 1, j + 1, k + 1), P(i, j + 1, k + 1))]
+
+
+def mixed_block(xs, ys, zs, split_from, kinds=None, periodic_x=False, periodic_y=False):
+    """Hexahedra in the columns i < split_from, and each hexahedron of the columns i >= split_from
+    cut into two prisms as in prism_block (they meet the hexahedra on whole quadrilaterals)."""
+    xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+
+    def P(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    cells = []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                if i < split_from:
+                    cells.append(_hex_quads(P, i, j, k))
+                    continue
+                for tri in (((i, j), (i + 1, j), (i + 1, j + 1)), ((i, j), (i + 1, j + 1), (i, j + 1))):
+                    bot = [P(a, b, k) for a, b in tri]
+                    top = [P(a, b, k + 1) for a, b in tri]
+                    faces = [tuple(reversed(bot)), tuple(top)]
+                    for e in range(3):
+                        a, b = e, (e + 1) % 3
+                        faces.append((bot[a], bot[b], top[b], top[a]))
+                    cells.append(faces)
+    return mesh_from_cells(_grid_points(xs, ys, zs), cells, xs, ys, zs, kinds, periodic_x, periodic_y)
 
 
 def tet_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False):
@@ -163,52 +194,70 @@ def tet_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False):
     def P(i, j, k):
         return i + (nx + 1) * (j + (ny + 1) * k)
 
+    # corner offsets of each tetrahedron's path, ordered for a positive volume (the coordinates
+    # increase along every axis, so one orientation test per ordering of the axes holds for all)
+    paths = []
+    for perm in itertools.permutations(range(3)):
+        v = [0, 0, 0]
+        path = [(0, 0, 0)]
+        for ax in perm:
+            v[ax] += 1
+            path.append(tuple(v))
+        o = np.array(path, dtype=np.float64)
+        if np.dot(o[1] - o[0], np.cross(o[2] - o[0], o[3] - o[0])) < 0:
+            path[1], path[2] = path[2], path[1]
+        paths.append(path)
     cells = []
     for k in range(nz):
         for j in range(ny):
             for i in range(nx):
-                for perm in itertools.permutations(range(3)):
-                    v = [0, 0, 0]
-                    path = [P(i, j, k)]
-                    for ax in perm:
-                        v[ax] += 1
-                        path.append(P(i + v[0], j + v[1], k + v[2]))
-                    a, b, c, d = path
-                    vol = np.dot(pts[b] - pts[a], np.cross(pts[c] - pts[a], pts[d] - pts[a]))
-                    if vol < 0:
-                        b, c = c, b
+                for path in paths:
+                    a, b, c, d = (P(i + di, j + dj, k + dk) for di, dj, dk in path)
                     cells.append([(a, c, b), (a, b, d), (a, d, c), (b, c, d)])
     return mesh_from_cells(pts, cells, xs, ys, zs, kinds, periodic_x, periodic_y)
+
+
+def _face_groups(mesh):
+    """Faces grouped by their number of points: {n: (face ids, (len, n) point ids)}."""
+    cnt = np.diff(mesh.face_ptr)
+    out = {}
+    for n in np.unique(cnt):
+        f = np.nonzero(cnt == n)[0]
+        idx = mesh.face_ptr[f][:, None] + np.arange(n)[None, :]
+        out[int(n)] = (f, mesh.face_pts[idx])
+    return out
 
 
 def cell_geometry(mesh):
     """Cell volumes and centroids of any mesh with planar faces (faces fanned about their vertex
     mean, cells about the mean of their faces' vertex means)."""
     P = mesh.points
-    nf = mesh.n_faces
-    vol = np.zeros(mesh.n_cells)
-    mom = np.zeros((mesh.n_cells, 3))
+    groups = _face_groups(mesh)
     ref = np.zeros((mesh.n_cells, 3))
     cnt = np.zeros(mesh.n_cells)
-    ni = mesh.n_internal
-    for f in range(nf):
-        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
-        m = P[fp].mean(axis=0)
-        for c in ([mesh.owner[f], mesh.neighbour[f]] if f < ni else [mesh.owner[f]]):
-            ref[c] += m
-            cnt[c] += 1
+    for n, (f, pts) in groups.items():
+        m = P[pts].mean(axis=1)
+        inner = f < mesh.n_internal
+        cells = np.concatenate([mesh.owner[f], mesh.neighbour[f[inner]]])
+        np.add.at(ref, cells, np.concatenate([m, m[inner]]))
+        np.add.at(cnt, cells, 1.0)
     ref /= cnt[:, None]
-    for f in range(nf):
-        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
-        q = P[fp]
-        ap = q.mean(axis=0)
-        sides = [(mesh.owner[f], 1.0)] + ([(mesh.neighbour[f], -1.0)] if f < ni else [])
-        for c, sgn in sides:
-            for a in range(len(fp)):
-                b = (a + 1) % len(fp)
-                tv = sgn * np.dot(ap - ref[c], np.cross(q[a] - ref[c], q[b] - ref[c])) / 6.0
-                vol[c] += tv
-                mom[c] += tv * 0.25 * (ref[c] + ap + q[a] + q[b])
+    vol = np.zeros(mesh.n_cells)
+    mom = np.zeros((mesh.n_cells, 3))
+    for n, (f, pts) in groups.items():
+        q = P[pts]
+        ap = q.mean(axis=1)
+        inner = f < mesh.n_internal
+        cells = np.concatenate([mesh.owner[f], mesh.neighbour[f[inner]]])
+        sgn = np.concatenate([np.ones(len(f)), -np.ones(int(inner.sum()))])
+        qq = np.concatenate([q, q[inner]])
+        aa = np.concatenate([ap, ap[inner]])
+        r = ref[cells]
+        for a in range(n):
+            qa, qb = qq[:, a], qq[:, (a + 1) % n]
+            tv = sgn * np.einsum("ij,ij->i", aa - r, np.cross(qa - r, qb - r)) / 6.0
+            np.add.at(vol, cells, tv)
+            np.add.at(mom, cells, (tv * 0.25)[:, None] * (r + aa + qa + qb))
     return vol, mom / vol[:, None]
 
 
@@ -221,22 +270,27 @@ def fluxes_from_potential(mesh, psi, n_gauss=8):
     gx, gw = np.polynomial.legendre.leggauss(n_gauss)
     s = 0.5 * (gx + 1.0)
     w = 0.5 * gw
-    cache = {}
+    fa, pa, pb = [], [], []
+    for n, (f, pts) in _face_groups(mesh).items():
+        for a in range(n):
+            fa.append(f)
+            pa.append(pts[:, a])
+            pb.append(pts[:, (a + 1) % n])
+    fa, pa, pb = np.concatenate(fa), np.concatenate(pa), np.concatenate(pb)
+    lo, hi = np.minimum(pa, pb), np.maximum(pa, pb)
+    keys, inv = np.unique(lo.astype(np.int64) * (len(P) + 1) + hi, return_inverse=True)
+    ka, kb = keys // (len(P) + 1), keys % (len(P) + 1)
+    xa, xb = P[ka], P[kb]
+    val = np.zeros(len(keys))
+    for q in range(n_gauss):
+        x = xa + s[q] * (xb - xa)
+        val += w[q] * psi(x[:, 0], x[:, 1], x[:, 2])
+    val *= xb[:, 2] - xa[:, 2]
+    val[xb[:, 2] == xa[:, 2]] = 0.0
+    e = val[inv]
+    e = np.where(pa == lo, e, -e)
     phi = np.zeros(mesh.n_faces)
-    for f in range(mesh.n_faces):
-        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
-        tot = 0.0
-        for a in range(len(fp)):
-            pa, pb = int(fp[a]), int(fp[(a + 1) % len(fp)])
-            if P[pa, 2] == P[pb, 2]:
-                continue
-            key = (min(pa, pb), max(pa, pb))
-            if key not in cache:
-                xa, xb = P[key[0]], P[key[1]]
-                x = xa[None, :] + s[:, None] * (xb - xa)[None, :]
-                cache[key] = float(np.dot(w, psi(x[:, 0], x[:, 1], x[:, 2]))) * (xb[2] - xa[2])
-            tot += cache[key] if pa == key[0] else -cache[key]
-        phi[f] = tot
+    np.add.at(phi, fa, e)
     for p in mesh.patches:
         if p.kind in (0, 1):
             phi[p.start:p.start + p.size] = 0.0
@@ -256,7 +310,7 @@ def _lattice(order):
     return b / b.sum(axis=1, keepdims=True)
 
 
-def alpha_sampled(mesh, wet, order=6):
+def alpha_sampled(mesh, wet, order=6, chunk=20000):
     """Volume fractions of the region wet(x, y, z) > 0 per cell, by equal-weight sampling of the
     tetrahedra that fan each cell about its centroid over its face triangles (an input generator:
     a sharp field with fractional values near the surface, not an exact integral)."""
@@ -264,17 +318,22 @@ def alpha_sampled(mesh, wet, order=6):
     bary = _lattice(order)
     P = mesh.points
     acc = np.zeros(mesh.n_cells)
-    ni = mesh.n_internal
-    for f in range(mesh.n_faces):
-        fp = mesh.face_pts[mesh.face_ptr[f]:mesh.face_ptr[f + 1]]
-        q = P[fp]
-        ap = q.mean(axis=0)
-        for c in ([mesh.owner[f], mesh.neighbour[f]] if f < ni else [mesh.owner[f]]):
-            for a in range(len(fp)):
-                t = np.array([cen[c], ap, q[a], q[(a + 1) % len(fp)]])
-                tv = abs(np.dot(t[1] - t[0], np.cross(t[2] - t[0], t[3] - t[0]))) / 6.0
-                x = bary @ t
-                acc[c] += tv * np.mean(wet(x[:, 0], x[:, 1], x[:, 2]) > 0)
+    for n, (f, pts) in _face_groups(mesh).items():
+        q = P[pts]
+        ap = q.mean(axis=1)
+        inner = f < mesh.n_internal
+        cells = np.concatenate([mesh.owner[f], mesh.neighbour[f[inner]]])
+        qq = np.concatenate([q, q[inner]])
+        aa = np.concatenate([ap, ap[inner]])
+        for a in range(n):
+            for lo in range(0, len(cells), chunk):
+                sl = slice(lo, lo + chunk)
+                t = np.stack([cen[cells[sl]], aa[sl], qq[sl, a], qq[sl, (a + 1) % n]], axis=1)
+                tv = np.abs(np.einsum("ij,ij->i", t[:, 1] - t[:, 0],
+                                      np.cross(t[:, 2] - t[:, 0], t[:, 3] - t[:, 0]))) / 6.0
+                x = np.matmul(bary[None, :, :], t)
+                fr = (wet(x[..., 0], x[..., 1], x[..., 2]) > 0).mean(axis=1)
+                np.add.at(acc, cells[sl], tv * fr)
     return np.clip(acc / vol, 0.0, 1.0)
 
 
@@ -291,14 +350,18 @@ class PolyWorkload:
 
 
 def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5):
-    """The violent 3D workload's ingredients on tetrahedra or prisms: the box [0,2]x[0,1]x[0,1],
+    """The violent 3D workload's ingredients on tetrahedra, prisms, pyramids, or hexahedra and prisms
+    side by side ("mixed"): the box [0,2]x[0,1]x[0,1],
     periodic in x, a water column {x < 0.3, z < 0.6} joined to a wavy layer
     {z < 0.45 + 0.02 cos 4 pi x cos 4 pi y}, and the uniform + Taylor-Green flow (its fluxes from the
     vector potential along the straight edges)."""
     from .fields import UniformPlusTaylorGreen
     xs, ys, zs = np.linspace(0, 2, nx + 1), np.linspace(0, 1, ny + 1), np.linspace(0, 1, nz + 1)
-    build = tet_block if kind == "tet" else prism_block
-    mesh = build(xs, ys, zs, periodic_x=True)
+    if kind == "mixed":
+        mesh = mixed_block(xs, ys, zs, nx // 2, periodic_x=True)
+    else:
+        build = {"tet": tet_block, "prism": prism_block, "pyramid": pyramid_block}[kind]
+        mesh = build(xs, ys, zs, periodic_x=True)
     flow = UniformPlusTaylorGreen(0.5, 1.0, 0.25)
     wet = lambda x, y, z: np.maximum(0.45 + 0.02 * np.cos(4 * np.pi * x) * np.cos(4 * np.pi * y) - z,
                                      np.minimum(0.3 - x, 0.6 - z))
