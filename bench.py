@@ -45,13 +45,13 @@ KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_upda
 # the commands whose rocprofv3 output --summarize-profiles reads
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
-             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble --no-adjoint --no-variants",
+             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble --no-adjoint --no-variants --no-poly",
     "fetch": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-poly --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
     "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
+             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-poly --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
 }
 
 
@@ -435,6 +435,46 @@ def relax_bench(plan, workload, a, target, reps=50):
             "traffic": committed_traffic("relax_blend", workload)}
 
 
+def poly_bench(steps, warmup):
+    """The step on cells other than hexahedra: the violent 3D case's ingredients on 48x24x24
+    hexahedra each cut into six tetrahedra (165,888 cells, steady flow), and on the same block cut
+    into prisms; K steps from the sampled initial field, timed like the main line."""
+    import torch
+    import wavegen as W
+    from paper_1804_01130_amd import Mesh, Plan, default_options
+    out = {}
+    for kind, n in (("tet", (48, 24, 24)), ("prism", (64, 32, 32))):
+        t0 = time.time()
+        w = W.poly_violent(kind, nx=n[0], ny=n[1], nz=n[2], steps=steps)
+        gm = Mesh.from_arrays(w.mesh)
+        plan = Plan(gm, default_options())
+        phi, U = (torch.tensor(v, device="cuda:0") for v in w.phi_U(0))
+        a = torch.tensor(w.alpha0, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(warmup):
+            plan.step(a, phi, U, w.dt, out=b)
+            a, b = b, a
+        _, st = plan.step(a, phi, U, w.dt, out=b, stats=True)
+        a, b = b, a
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.step(a, phi, U, w.dt, out=b)
+            a, b = b, a
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[kind] = {"workload": w.name, "cells": w.mesh.n_cells, "interface_cells": st["n_surface"],
+                     "ms_per_step": ms, "cell_steps_per_s": w.mesh.n_cells / (ms * 1e-3),
+                     "interface_cells_per_s": st["n_surface"] / (ms * 1e-3)}
+        log(f"[bench] {w.name}: {w.mesh.n_cells} cells, {st['n_surface']} interface cells, {ms * 1e3:.1f} us/step "
+            f"(set up in {time.time() - t0:.1f} s)")
+        plan.close()
+        gm.close()
+    return out
+
+
 def adjoint_bench(every=10):
     """The adjoint workload: 256x128 Airy, 50 steps, loss sum (alpha_T - alpha_target)^2; time of the
     forward pass (plain steps) and of the backward pass (recomputing each segment from its checkpoint
@@ -501,6 +541,7 @@ def main():
                     help="skip the interpolated isoface velocity and averaged-field step timings")
     ap.add_argument("--no-gfm", action="store_true", help="skip the ghost-fluid face data timing")
     ap.add_argument("--no-relax", action="store_true", help="skip the relaxation-zone blending timing")
+    ap.add_argument("--no-poly", action="store_true", help="skip the tetrahedral and prismatic meshes")
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
@@ -605,6 +646,7 @@ def main():
         torch.cuda.empty_cache()
         ens = ensemble_bench(args.steps, args.warmup)
     adj = None if args.no_adjoint else adjoint_bench()
+    poly = None if args.no_poly else poly_bench(min(args.steps, 50), args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -628,6 +670,7 @@ def main():
         "relax_blend": relax,
         "ensemble": ens,
         "adjoint": adj,
+        "cells_other_than_hexahedra": poly,
     }
     print(json.dumps(out), flush=True)
 

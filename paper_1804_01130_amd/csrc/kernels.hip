@@ -497,8 +497,9 @@ __device__ __forceinline__ double isoface_speed(const SurfArgs &A, int32_t c, in
 // kGeneric: the mesh has cells other than hexahedra (tetrahedra, pyramids, prisms), and every
 // cell takes its faces' vertex loops from m.cloop: up to six faces of three or four points (a
 // triangle repeats its first point, which gives a zero-length edge that is never cut and adds
-// nothing) over up to eight points (lanes past the cell's points repeat its first point).  Such
-// cells use the generic isovalue search; hexahedra keep the interval solve.
+// nothing) over up to eight points (lanes past the cell's points repeat its first point).  Cells
+// whose faces are all planar take the interval solve like hexahedra (a repeated point adds zero
+// terms to the face quadratics and never starts an isoface edge); the others the generic search.
 template <int kMinBlocks, bool kInterp, bool kGeneric>
 __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
     const DevMesh &m = A.m;
@@ -579,7 +580,8 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 s[i + 1] = y;
             }
         bool recon = s[7] - s[0] > A.flat_tol;
-        const bool planar_cell = (m.cflags[c] & 0x13f) == 63;  // a hexahedron with six planar faces
+        // a hexahedron with six planar faces, or another cell whose faces are all planar
+        const bool planar_cell = (m.cflags[c] & 0x13f) == 63 || (kGeneric && (m.cflags[c] & 0x200));
         double iso = 0.0;
         int rounds = 0;
         bool face_done = false;

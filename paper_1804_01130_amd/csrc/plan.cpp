@@ -503,7 +503,8 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         for (int32_t e = cnt[k]; e < cnt[k + 1]; ++e) st_w[e] /= s;
     }
     // planar faces: the four points within 1e-12 (relative) of their mean plane
-    // (bit k: local face k is planar; a triangle always is); bit 8: not a hexahedron
+    // (bit k: local face k is planar; a triangle always is); bit 8: not a hexahedron; bit 9: not a
+    // hexahedron, and every face planar
     std::vector<int32_t> cflags(n_cells, 0);
     for (int32_t c = 0; c < n_cells; ++c)
         for (int k = 0; k < 6; ++k) {
@@ -524,6 +525,13 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
             for (int i = 0; i < 4 && planar; ++i) planar = std::fabs(dot(q[i] - mean, nrm)) <= 1e-12 * size * ln;
             if (planar) cflags[c] |= 1 << k;
         }
+    for (int32_t c = 0; c < n_cells; ++c) {
+        if (gnp[6 * (size_t)c] == 0) continue;
+        bool all = true;
+        for (int k = 0; k < 6; ++k)
+            if (gnp[6 * (size_t)c + k] != 0 && !((cflags[c] >> k) & 1)) all = false;
+        if (all) cflags[c] |= 1 << 9;
+    }
     std::vector<int32_t> cpt(8 * (size_t)n_cells);
     for (size_t i = 0; i < cpt.size(); ++i) cpt[i] = cls[m->cell_pts[i]];
     std::vector<double> cxyz(24 * (size_t)n_cells);

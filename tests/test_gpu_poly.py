@@ -21,6 +21,9 @@ def _cases():
         "pyramid_8x4x4": W.poly_violent("pyramid", nx=8, ny=4, nz=4, steps=8),
         "mixed_16x8x8": W.poly_violent("mixed", nx=16, ny=8, nz=8, steps=8),
         "airy_prism_64x32": W.poly_airy("prism", 64, 32, steps=12),
+        # bent quadrilaterals: those prisms and hexahedra take the generic search
+        "prism_perturbed_12x6x6": W.poly_violent("prism", nx=12, ny=6, nz=6, steps=8, perturb=0.15),
+        "mixed_perturbed_12x6x6": W.poly_violent("mixed", nx=12, ny=6, nz=6, steps=8, perturb=0.15),
     }
 
 

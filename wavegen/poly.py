@@ -349,9 +349,9 @@ class PolyWorkload:
         return self._phi, self._U
 
 
-def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5):
+def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5, perturb=0.0, seed=4):
     """The violent 3D workload's ingredients on tetrahedra, prisms, pyramids, or hexahedra and prisms
-    side by side ("mixed"): the box [0,2]x[0,1]x[0,1],
+    side by side ("mixed"), with the interior points optionally moved at random: the box [0,2]x[0,1]x[0,1],
     periodic in x, a water column {x < 0.3, z < 0.6} joined to a wavy layer
     {z < 0.45 + 0.02 cos 4 pi x cos 4 pi y}, and the uniform + Taylor-Green flow (its fluxes from the
     vector potential along the straight edges)."""
@@ -362,6 +362,14 @@ def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5):
     else:
         build = {"tet": tet_block, "prism": prism_block, "pyramid": pyramid_block}[kind]
         mesh = build(xs, ys, zs, periodic_x=True)
+    if perturb > 0.0:
+        # move the interior grid points by up to perturb cell sizes (seeded), which bends the
+        # quadrilaterals out of plane; the boundary stays flat, so the periodic sides still match
+        P = mesh.points
+        h = np.array([2.0 / nx, 1.0 / ny, 1.0 / nz])
+        inner = np.all((P > 1e-12) & (P < np.array([2.0, 1.0, 1.0]) - 1e-12), axis=1)
+        rng = np.random.default_rng(seed)
+        P[inner] += rng.uniform(-perturb, perturb, (int(inner.sum()), 3)) * h
     flow = UniformPlusTaylorGreen(0.5, 1.0, 0.25)
     wet = lambda x, y, z: np.maximum(0.45 + 0.02 * np.cos(4 * np.pi * x) * np.cos(4 * np.pi * y) - z,
                                      np.minimum(0.3 - x, 0.6 - z))
