@@ -730,7 +730,10 @@ static void sweep_setup(const double X[3][3], const double *t, const double *nS,
     if (sw->step) return;
     double x21[3], x31[3], x41[3], x4[3], x43[3], x23[3], cr[3];
     v_sub(x2, x1, x21); v_sub(x3, x1, x31);
-    double r = v_dot(x21, nS) / v_dot(x31, nS);       /* Eq. x_41 */
+    /* Eq. x_41: the ratio of the projections of x_21 and x_31 on the normal is the ratio of the
+     * arrival-time differences, which the sort keeps in [0, 1]; projecting the point differences
+     * again can round a face nearly parallel to the isoface to a zero denominator */
+    double r = (sw->t2 - sw->t1) / (sw->t3 - sw->t1);
     for (int d = 0; d < 3; ++d) { x41[d] = r * x31[d]; x4[d] = x1[d] + x41[d]; }
     v_sub(x4, x3, x43); v_sub(x2, x3, x23);
     v_cross(x31, x21, cr); double A = 0.5 * v_norm(cr);

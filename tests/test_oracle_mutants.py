@@ -21,8 +21,8 @@ MUTANTS = [
     ("no_dry_fraction_for_receding_plane", "return un > 0 ? I : dt - I;", "return I;"),
     ("update_sign", "sum += m->ce_sign[e] * dV[m->ce_flux[e]];", "sum -= m->ce_sign[e] * dV[m->ce_flux[e]];"),
     ("bulk_flux_ignores_alpha", "dV[fid] = alpha[c] * ph * dt;", "dV[fid] = ph * dt;"),
-    ("x41_ratio_inverted", "double r = v_dot(x21, nS) / v_dot(x31, nS);",
-     "double r = v_dot(x31, nS) / v_dot(x21, nS);"),
+    ("x41_ratio_inverted", "double r = (sw->t2 - sw->t1) / (sw->t3 - sw->t1);",
+     "double r = (sw->t3 - sw->t1) / (sw->t2 - sw->t1);"),
     ("equal_triangle_weights", "double Ai = 0.5 * v_norm(cr);", "double Ai = 0.5;"),
     ("isoface_centre_is_vertex_mean", "for (int d = 0; d < 3; ++d) out->xS[d] = xs[d] / wsum;",
      "for (int d = 0; d < 3; ++d) out->xS[d] = o[d] + 0.0 * xs[d] / wsum;"),

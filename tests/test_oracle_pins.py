@@ -97,6 +97,26 @@ def test_triangle_area_fraction_pieces(oracle_lib):
         assert oracle_lib.tri_wet_fraction(tri, xS, n, un, t[2]) == pytest.approx(1.0, abs=1e-14)
 
 
+def test_triangle_parallel_to_the_plane_up_to_rounding(oracle_lib):
+    """A triangle whose plane is parallel to the isoface only up to rounding (its vertex distances
+    agree to a few ulps): all of it arrives at once, so the integral is the step's closed form
+    dt - t (or t for a receding plane), never a 0/0 from Eq. x_41's ratio of projections."""
+    rng = np.random.default_rng(12)
+    n = np.array([-1.0, 1.0, 0.0]) / np.sqrt(2.0)
+    for _ in range(200):
+        c = rng.uniform(-1, 1)
+        p = rng.uniform(-1, 1, (3, 2))
+        tri = np.array([[x, x + c, z] for x, z in p])  # on the plane y - x = c
+        d0 = rng.uniform(-0.3, 0.3)
+        xS = tri.mean(axis=0) - d0 * n
+        for un in (0.7, -0.7):
+            dt = 0.5
+            got = oracle_lib.tri_integral(tri, xS, n, un, dt)
+            t = ((tri - xS) @ n).mean() / un
+            ref = (dt - min(max(t, 0.0), dt)) if un > 0 else min(max(t, 0.0), dt)
+            assert np.isfinite(got) and abs(got - ref) <= 1e-12, (got, ref, t)
+
+
 def test_printed_aplus2_would_jump():
     """Documents the reading of Eq. aplus2: the printed bracket [1-(1-(tau-t3)/(t2-t3))^2]
     equals 1 at tau=t2, so alpha+ would jump by A234/A there and return to alpha+(t2) at t3."""
