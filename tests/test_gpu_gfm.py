@@ -188,3 +188,18 @@ def test_gfm_faces_argument_errors():
     with pytest.raises(IsoError):  # two outputs in one buffer
         plan.gfm_faces(a, p, 1000.0, 1.0, (0, 0, -9.81), out={k: buf for k in KEYS})
     plan.close()
+
+
+@pytest.mark.parametrize("fill", [0.0, 0.5, 1.0])
+def test_gfm_faces_without_interface(fill):
+    """A uniform field (all dry, exactly 1/2 everywhere, all wet): no face lies on the surface, so
+    every face carries lambda = -1, no jump, and the plain cell values, bit for bit."""
+    w = W.violent_3d(nx=12, ny=8, nz=6, steps=1)
+    a = np.full(w.mesh.n_cells, fill)
+    p = np.random.default_rng(81).normal(1.0e5, 50.0, w.mesh.n_cells)
+    got = _gpu(w.mesh, a, p, (0.0, 0.0, -9.81))
+    ni = w.mesh.n_internal
+    own, nbr = w.mesh.owner, w.mesh.neighbour
+    assert np.all(got["lambda"] == -1.0) and np.all(got["jump"] == 0.0) and np.all(got["beta_w"] == 0.0)
+    assert np.array_equal(got["ghost_own"], p[own])
+    assert np.array_equal(got["ghost_nbr"][:ni], p[nbr])
