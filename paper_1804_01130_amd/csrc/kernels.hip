@@ -553,20 +553,27 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
         double a[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = grp_get(av, i);
-        FaceLane f;
-        f.active = face_on;
-        f.planar = (m.cflags[c] >> min(lv, 5)) & 1;
-        f.fwd = fwd;
+        const bool f_planar = (m.cflags[c] >> min(lv, 5)) & 1;
+        // face lv's lane state, built from the group's vertex data; built again after the interval
+        // solve rather than held in registers through it
+        auto build_face = [&](D3 x, double a) {
+            FaceLane r;
+            r.active = face_on;
+            r.planar = f_planar;
+            r.fwd = fwd;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            f.q[i] = D3{grp_get(xv.x, fv[i]), grp_get(xv.y, fv[i]), grp_get(xv.z, fv[i])};
-            f.aq[i] = grp_get(av, fv[i]);
-        }
+            for (int i = 0; i < 4; ++i) {
+                r.q[i] = D3{grp_get(x.x, fv[i]), grp_get(x.y, fv[i]), grp_get(x.z, fv[i])};
+                r.aq[i] = grp_get(a, fv[i]);
+            }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double d = ((fwd >> i) & 1) ? f.aq[(i + 1) & 3] - f.aq[i] : f.aq[i] - f.aq[(i + 1) & 3];
-            f.inv[i] = d != 0.0 ? 1.0 / d : 0.0;
-        }
+            for (int i = 0; i < 4; ++i) {
+                const double d = ((fwd >> i) & 1) ? r.aq[(i + 1) & 3] - r.aq[i] : r.aq[i] - r.aq[(i + 1) & 3];
+                r.inv[i] = d != 0.0 ? 1.0 / d : 0.0;
+            }
+            return r;
+        };
+        FaceLane f = build_face(xv, av);
         // sorted vertex values (odd-even transposition, 8 elements)
         double s[8];
 #pragma unroll
@@ -746,6 +753,14 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                     if (!conv) ++nonconv;
                     iso = fabs(f0) <= fabs(f1) ? x0 : x1;
                 }
+            }
+            if (quad) {
+                // the same values again: the empty asm hides that, so that the first copy need not
+                // stay live through the solve
+                D3 x2 = xv;
+                double a2 = av;
+                asm volatile("" : "+v"(x2.x), "+v"(x2.y), "+v"(x2.z), "+v"(a2));
+                f = build_face(x2, a2);
             }
             // isoface at the isovalue (unless the interval solve already built it)
             D3 o, cseg{0, 0, 0};
