@@ -277,7 +277,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         if (!hex) {
             if (!make_generic(c)) {
                 iso_mesh_destroy(m);
-                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points");
+                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points or fewer than 4");
             }
             continue;
         }
@@ -312,7 +312,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         if (!ok) {  // six quadrilaterals that do not make a hexahedron
             if (!make_generic(c)) {
                 iso_mesh_destroy(m);
-                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points");
+                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points or fewer than 4");
             }
             continue;
         }
