@@ -35,6 +35,8 @@
  *   R7  face triangles: fan about the vertex mean; A_f = sum of triangle areas.
  *   R8  Eq. aplus2 as printed is not continuous; the reading used is
  *       alpha+(tau) = alpha+(t2) + (A234/A) [1 - ((t3 - tau)/(t3 - t2))^2].
+ *   R8a Eq. x_41's ratio of projections is taken from the sorted arrival times,
+ *       (t2 - t1)/(t3 - t1), equal in exact arithmetic and free of a zero denominator.
  *   R9  Eq. intaplus: polynomial pieces integrated over their overlap with the
  *       step window, time measured from the start of the step, each piece's
  *       polynomial written about its own end point (t1 for the first piece,
