@@ -1,5 +1,6 @@
-"""Pins of the oracle on tetrahedra, triangular prisms and square pyramids (cells with triangular
-faces), against what elementary geometry and the method's invariants fix:
+"""Pins of the oracle on tetrahedra, triangular prisms, square pyramids and polyhedra made of merged
+hexahedra (split faces, up to 18 points and 16 faces), against what elementary geometry and the
+method's invariants fix:
 
 * linear vertex data cut at an isovalue is exactly a plane clip of the cell (convex hull of the
   clipped vertices), and the isoface is the plane section (normal, area, centroid);
@@ -15,7 +16,30 @@ import pytest
 import wavegen as W
 from tests import geomref as R
 
-BUILDERS = {"tet": W.tet_block, "prism": W.prism_block, "pyramid": W.pyramid_block}
+
+def _refined(v):
+    v = list(v)
+    return [v[0], 0.5 * (v[0] + v[1]), v[1]] if len(v) == 2 else v
+
+
+def merged_x(xs, ys, zs, **kw):
+    """Hexahedra (i, j, k), i even, joined with (i+1, j, k): 12 points, 10 faces."""
+    xs = _refined(xs)
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    return W.merged_block(xs, ys, zs, merge_x=[(i, j, k) for k in range(nz) for j in range(ny)
+                                              for i in range(0, nx - 1, 2)], **kw)
+
+
+def merged_xy(xs, ys, zs, **kw):
+    """2 x 2 hexahedra joined from every (i, j, k) with i, j even: 18 points, 16 faces."""
+    xs, ys = _refined(xs), _refined(ys)
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    return W.merged_block(xs, ys, zs, merge_xy=[(i, j, k) for k in range(nz) for j in range(0, ny - 1, 2)
+                                                for i in range(0, nx - 1, 2)], **kw)
+
+
+BUILDERS = {"tet": W.tet_block, "prism": W.prism_block, "pyramid": W.pyramid_block, "merged_x": merged_x,
+            "merged_xy": merged_xy}
 
 
 def _cell_faces(mesh, c):
@@ -90,6 +114,7 @@ def test_isoface_of_linear_data(oracle_lib, kind):
 
 def _workloads():
     return [W.poly_violent("tet", nx=8, ny=4, nz=4, steps=6), W.poly_violent("prism", nx=8, ny=4, nz=4, steps=6),
+            W.poly_violent("merged", nx=16, ny=8, nz=8, steps=6),
             W.poly_airy("prism", 32, 16, steps=6), W.poly_airy("tet", 24, 12, steps=6)]
 
 
@@ -122,7 +147,7 @@ def test_conservation_and_bounds(oracle_lib):
             assert a.min() >= 0.0 and a.max() <= 1.0
 
 
-@pytest.mark.parametrize("kind", ["tet", "prism", "pyramid"])
+@pytest.mark.parametrize("kind", ["tet", "prism", "pyramid", "merged_x"])
 def test_surface_face_fluxes_brute_force(oracle_lib, kind):
     """A smooth field on a 3x3x3 block of cells of one kind: every flux of an interface cell equals
     phi times the exact space-time integral of the submerged part of the face (each face fanned

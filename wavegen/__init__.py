@@ -8,7 +8,7 @@ from .mesh import (PATCH_CYCLIC, PATCH_EMPTY, PATCH_INOUT, PATCH_WALL, Mesh, Pat
 from .fields import (AiryWave, UniformPlusTaylorGreen, alpha_column_plus_wave_3d, alpha_cosine_2d, dynamic_pressure,
                      cell_fraction_below_cosine, courant_dt, fluxes_from_edge_integral)
 from .poly import (PolyWorkload, alpha_sampled, cell_geometry, fluxes_from_potential, mesh_from_cells, poly_airy,
-                   mixed_block, poly_violent, prism_block, pyramid_block, tet_block)
+                   merged_block, mixed_block, poly_violent, prism_block, pyramid_block, tet_block)
 from .configs import (Workload, adjoint_case, airy_1024x256, airy_ensemble, airy_slab, cosine_uniform, perturbed_box,
                       slab_mesh, violent_3d)
 

@@ -184,6 +184,54 @@ def mixed_block(xs, ys, zs, split_from, kinds=None, periodic_x=False, periodic_y
     return mesh_from_cells(_grid_points(xs, ys, zs), cells, xs, ys, zs, kinds, periodic_x, periodic_y)
 
 
+def merged_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False, merge_x=(), merge_xy=()):
+    """Hexahedra, some of them merged into polyhedra whose sides are split faces: each (i, j, k) in
+    merge_x joins hexahedra (i, j, k) and (i+1, j, k) into one cell of 12 points and 10
+    quadrilateral faces; each (i, j, k) in merge_xy joins the 2 x 2 hexahedra from (i, j, k) into
+    one cell of 18 points and 16 faces.  The neighbours keep their faces, so the mesh conforms."""
+    xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+
+    def P(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    owner_of = {}
+    groups = []
+    for (i, j, k) in merge_xy:
+        g = [(i, j, k), (i + 1, j, k), (i, j + 1, k), (i + 1, j + 1, k)]
+        groups.append(g)
+    for (i, j, k) in merge_x:
+        groups.append([(i, j, k), (i + 1, j, k)])
+    for gi, g in enumerate(groups):
+        for h in g:
+            if h in owner_of:
+                raise ValueError(f"hexahedron {h} merged twice")
+            owner_of[h] = gi
+    cells = []
+    done = set()
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                h = (i, j, k)
+                if h in owner_of:
+                    gi = owner_of[h]
+                    if gi in done:
+                        continue
+                    done.add(gi)
+                    faces = {}
+                    for hh in groups[gi]:
+                        for q in _hex_quads(P, *hh):
+                            key = tuple(sorted(q))
+                            if key in faces:
+                                del faces[key]  # shared inside the merged cell
+                            else:
+                                faces[key] = q
+                    cells.append(list(faces.values()))
+                else:
+                    cells.append(_hex_quads(P, i, j, k))
+    return mesh_from_cells(_grid_points(xs, ys, zs), cells, xs, ys, zs, kinds, periodic_x, periodic_y)
+
+
 def tet_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False):
     """Each hexahedron of the block cut into six tetrahedra along its main diagonal (Kuhn): cells
     6 c .. 6 c + 5, one per ordering of the axes."""
@@ -359,6 +407,11 @@ def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5, perturb=0.0, se
     xs, ys, zs = np.linspace(0, 2, nx + 1), np.linspace(0, 1, ny + 1), np.linspace(0, 1, nz + 1)
     if kind == "mixed":
         mesh = mixed_block(xs, ys, zs, nx // 2, periodic_x=True)
+    elif kind == "merged":
+        # polyhedra: pairs along x in every fourth column, 2 x 2 blocks in another
+        mx = [(i, j, k) for k in range(nz) for j in range(ny) for i in range(1, nx - 1, 4)]
+        mxy = [(i, j, k) for k in range(nz) for j in range(0, ny - 1, 2) for i in range(3, nx - 1, 4)]
+        mesh = merged_block(xs, ys, zs, periodic_x=True, merge_x=mx, merge_xy=mxy)
     else:
         build = {"tet": tet_block, "prism": prism_block, "pyramid": pyramid_block}[kind]
         mesh = build(xs, ys, zs, periodic_x=True)
