@@ -21,11 +21,13 @@
  *    neighbour of every interior face), interior faces first, boundary faces
  *    grouped into patches.  The points of a face run counter-clockwise seen
  *    from outside its owner, so phi_f > 0 is flow from owner to neighbour (or
- *    out of the domain).  Cells: hexahedra (6 quadrilateral faces, 8 points),
- *    and cells of 4 to 6 faces of 3 or 4 points over at most 8 points
- *    (tetrahedra, square pyramids, triangular prisms), mixed freely; other
- *    cells give ISO_EUNSUPPORTED.  Meshes with cells other than hexahedra take
- *    us_mode 0 only, and neither the adjoint nor ensembles.
+ *    out of the domain).  Cells (Section 3: arbitrary polyhedra), mixed
+ *    freely: hexahedra (6 quadrilateral faces, 8 points); cells of 4 to 6
+ *    faces of 3 or 4 points over at most 8 points (tetrahedra, square
+ *    pyramids, triangular prisms); and general polyhedra of 4 to 16 faces of 3
+ *    to 16 points over at most 32 points (e.g. hexahedra merged across split
+ *    faces).  Larger cells give ISO_EUNSUPPORTED.  Meshes with cells other
+ *    than hexahedra take us_mode 0 only, and neither the adjoint nor ensembles.
  *  - Patch kinds: WALL and EMPTY faces carry no flux (their phi is ignored);
  *    INOUT faces carry flux, inflow carrying the patch's alpha_in; CYCLIC
  *    patches come in pairs (face n of a patch matches face n of its partner,
@@ -58,7 +60,7 @@ typedef enum {
     ISO_ENOSPACE = 4,      /* interface cells exceed the plan's capacity */
     ISO_ECOURANT = 5,      /* input check: a cell Courant number exceeds max_courant */
     ISO_EMESH = 6,         /* inconsistent mesh (indices, orientation, cyclic matching, volume) */
-    ISO_EUNSUPPORTED = 7   /* valid input the kernels do not take (e.g. a cell of more than 8 points) */
+    ISO_EUNSUPPORTED = 7   /* valid input the kernels do not take (e.g. a cell of more than 32 points) */
 } iso_status;
 
 enum { ISO_PATCH_WALL = 0, ISO_PATCH_EMPTY = 1, ISO_PATCH_INOUT = 2, ISO_PATCH_CYCLIC = 3 };

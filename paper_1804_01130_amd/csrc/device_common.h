@@ -159,4 +159,55 @@ __device__ __forceinline__ int wave_append(int count, int32_t *counter) {
 }
 
 }  // namespace
+// ------------------------------------------------------------------------------------------ sweep
+// Integral over s in [0, dt] of the submerged fraction of a triangle with signed distances
+// d0..d2 from the isoface plane moving with normal speed un: the fraction at time s is
+// G(un*s), G the area distribution of d over the triangle (a triangular distribution).
+// [0, dt] is split where un*s crosses a vertex distance; on each piece G(un*s) is a quadratic
+// in s, integrated exactly by Simpson's rule on the branch picked at the piece's midpoint.
+__device__ __forceinline__ double tri_piece(int br, double z, double e1, double e2, double e3, double r31,
+                                            double r21, double r32) {
+    if (br == 0) return 0.0;
+    if (br == 3) return 1.0;
+    if (br == 1) {
+        const double u = z - e1;
+        return (u * r31) * (u * r21);
+    }
+    const double u = e3 - z;
+    return 1.0 - (u * r31) * (u * r32);
+}
+
+__device__ __forceinline__ double tri_sweep(double d0, double d1, double d2, double un, double dt) {
+    const double e1 = fmin(d0, fmin(d1, d2)), e3 = fmax(d0, fmax(d1, d2));
+    const double e2 = fmax(fmin(d0, d1), fmin(fmax(d0, d1), d2));
+    const double r31 = e3 > e1 ? 1.0 / (e3 - e1) : 0.0;
+    const double r21 = e2 > e1 ? 1.0 / (e2 - e1) : 0.0;
+    const double r32 = e3 > e2 ? 1.0 / (e3 - e2) : 0.0;
+    auto branch = [&](double z) { return z < e1 ? 0 : (z < e2 ? 1 : (z < e3 ? 2 : 3)); };
+    if (un == 0.0) return dt * tri_piece(branch(0.0), 0.0, e1, e2, e3, r31, r21, r32);
+    const double inv = 1.0 / un;
+    double s1 = e1 * inv, s2 = e2 * inv, s3 = e3 * inv;
+    if (un < 0.0) {  // breakpoints in increasing time
+        const double t = s1;
+        s1 = s3;
+        s3 = t;
+    }
+    const double bk[3] = {s1, s2, s3};
+    double I = 0.0, a0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double a1 = k < 3 ? fmin(fmax(bk[k], 0.0), dt) : dt;
+        if (a1 > a0) {
+            const double m = 0.5 * (a0 + a1);
+            const int br = branch(un * m);
+            const double fa = tri_piece(br, un * a0, e1, e2, e3, r31, r21, r32);
+            const double fm = tri_piece(br, un * m, e1, e2, e3, r31, r21, r32);
+            const double fb = tri_piece(br, un * a1, e1, e2, e3, r31, r21, r32);
+            I += (a1 - a0) * (fa + 4.0 * fm + fb) * (1.0 / 6.0);
+            a0 = a1;
+        }
+    }
+    return I;
+}
+
 }  // namespace isoadv

@@ -43,6 +43,16 @@ struct DevMesh {
     const double *ptrans = nullptr;      // [3*n_patches] cyclic translations (x_partner = x + T)
     // local face loops of every cell (see plan.cpp), or null when every cell is a hexahedron
     const int32_t *cloop = nullptr;      // [6*n_cells]
+    // general polyhedra (beyond 6 faces, 8 points or 4 points per face): null when there are none
+    const int32_t *cbig = nullptr;       // [n_cells] index among them, or -1
+    const int32_t *bv_ptr = nullptr;     // [n_big+1] points of each
+    const int32_t *bv_cls = nullptr;     //   point class of each point
+    const double *bv_xyz = nullptr;      //   its coordinates in the cell's frame
+    const int32_t *bf_ptr = nullptr;     // [n_big+1] faces of each
+    const int32_t *bf_face = nullptr;    //   packed flux face (kEmpty: none)
+    const int32_t *bf_planar = nullptr;  //   1 if planar
+    const int32_t *bl_ptr = nullptr;     // [faces+1] loop positions of each face
+    const int32_t *bl_vtx = nullptr;     //   local point at each loop position, outward
     // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;
@@ -152,6 +162,23 @@ hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_
 // adjoint.hip
 hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, const AdjInputs &in, const AdjWork &w,
                           hipStream_t s);
+// General polyhedra: limits of the one-thread-per-cell interface kernel (big.hip).
+constexpr int kBigPts = 32, kBigFaces = 16, kBigFacePts = 16;
+struct BigArgs {
+    DevMesh m;
+    const double *alpha, *phi, *U;
+    const double *phi1, *U1;  // second time level of an outer iteration, or nullptr
+    double dt, flat_tol;
+    int max_rounds;
+    const int32_t *list;
+    int32_t *counters;
+    int cap;
+    double *dvs;
+    int want_stats;
+    iso_trace tr;
+};
+hipError_t launch_surface_big(const BigArgs &a, hipStream_t s);
+
 // Ghost-fluid face data (Eqs. 12-20): see gfm.hip.
 struct GfmArgs {
     const int32_t *fcell, *bpatch;

@@ -295,57 +295,6 @@ __device__ __forceinline__ bool spread_edges(const FaceQuad &fq, int lv, Seg &sg
     return __popc(gm) <= 2;
 }
 
-// ------------------------------------------------------------------------------------------ sweep
-// Integral over s in [0, dt] of the submerged fraction of a triangle with signed distances
-// d0..d2 from the isoface plane moving with normal speed un: the fraction at time s is
-// G(un*s), G the area distribution of d over the triangle (a triangular distribution).
-// [0, dt] is split where un*s crosses a vertex distance; on each piece G(un*s) is a quadratic
-// in s, integrated exactly by Simpson's rule on the branch picked at the piece's midpoint.
-__device__ __forceinline__ double tri_piece(int br, double z, double e1, double e2, double e3, double r31,
-                                            double r21, double r32) {
-    if (br == 0) return 0.0;
-    if (br == 3) return 1.0;
-    if (br == 1) {
-        const double u = z - e1;
-        return (u * r31) * (u * r21);
-    }
-    const double u = e3 - z;
-    return 1.0 - (u * r31) * (u * r32);
-}
-
-__device__ __forceinline__ double tri_sweep(double d0, double d1, double d2, double un, double dt) {
-    const double e1 = fmin(d0, fmin(d1, d2)), e3 = fmax(d0, fmax(d1, d2));
-    const double e2 = fmax(fmin(d0, d1), fmin(fmax(d0, d1), d2));
-    const double r31 = e3 > e1 ? 1.0 / (e3 - e1) : 0.0;
-    const double r21 = e2 > e1 ? 1.0 / (e2 - e1) : 0.0;
-    const double r32 = e3 > e2 ? 1.0 / (e3 - e2) : 0.0;
-    auto branch = [&](double z) { return z < e1 ? 0 : (z < e2 ? 1 : (z < e3 ? 2 : 3)); };
-    if (un == 0.0) return dt * tri_piece(branch(0.0), 0.0, e1, e2, e3, r31, r21, r32);
-    const double inv = 1.0 / un;
-    double s1 = e1 * inv, s2 = e2 * inv, s3 = e3 * inv;
-    if (un < 0.0) {  // breakpoints in increasing time
-        const double t = s1;
-        s1 = s3;
-        s3 = t;
-    }
-    const double bk[3] = {s1, s2, s3};
-    double I = 0.0, a0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double a1 = k < 3 ? fmin(fmax(bk[k], 0.0), dt) : dt;
-        if (a1 > a0) {
-            const double m = 0.5 * (a0 + a1);
-            const int br = branch(un * m);
-            const double fa = tri_piece(br, un * a0, e1, e2, e3, r31, r21, r32);
-            const double fm = tri_piece(br, un * m, e1, e2, e3, r31, r21, r32);
-            const double fb = tri_piece(br, un * a1, e1, e2, e3, r31, r21, r32);
-            I += (a1 - a0) * (fa + 4.0 * fm + fb) * (1.0 / 6.0);
-            a0 = a1;
-        }
-    }
-    return I;
-}
-
 // Six times the wet sub-volume of the cell (all lanes of the group take part and get the result).
 // The isoface's fan apex is the perimeter centroid of its edges; when they all have zero length
 // every s0 x s1 is exactly zero, so the apex does not enter and is left at the origin.
@@ -516,6 +465,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
     for (int idx = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; idx < n; idx += ngrp) {
         const int c = A.list[idx];
         if constexpr (kGeneric) {
+            if (m.cbig && m.cbig[c] >= 0) continue;  // a general polyhedron: k_surface_big takes it
             const int32_t L = lv < 6 ? m.cloop[6 * (size_t)c + lv] : 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) fv[i] = (L >> (3 * i)) & 7;
@@ -1297,12 +1247,19 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
             default: hipLaunchKernelGGL((k_surface<2, false, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
         }
     }
+    if (m.cbig) {
+        BigArgs bg{m, a.alpha, a.phi, a.U, a.phi1, a.U1, a.dt, p.flat_tol, p.root_max_iter, w.surf, w.counters,
+                   w.cap, w.dvs, want_stats ? 1 : 0, tr};
+        const hipError_t e = launch_surface_big(bg, s);
+        if (e != hipSuccess) return e;
+    }
     if (ev) (void)hipEventRecord(ev[2], s);
     UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist,
                w.counters, tr.dV, tr.alpha_raw, p.n_bound_iter, w, a.phi1};
     BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
                  a.alpha_new, w, a.phi1};
     const bool avg = a.phi1 != nullptr;
+    // more than six flux faces (general polyhedra): the plan pads the slots to width 8, 12 or 16
     switch (m.W * 2 + (avg ? 1 : 0)) {
         case 2: launch_wide<1, false>(m, ua, ba, cfg, s, ev); break;
         case 3: launch_wide<1, true>(m, ua, ba, cfg, s, ev); break;
@@ -1315,6 +1272,12 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
         case 10: launch_wide<5, false>(m, ua, ba, cfg, s, ev); break;
         case 11: launch_wide<5, true>(m, ua, ba, cfg, s, ev); break;
         case 13: launch_wide<6, true>(m, ua, ba, cfg, s, ev); break;
+        case 16: launch_wide<8, false>(m, ua, ba, cfg, s, ev); break;
+        case 17: launch_wide<8, true>(m, ua, ba, cfg, s, ev); break;
+        case 24: launch_wide<12, false>(m, ua, ba, cfg, s, ev); break;
+        case 25: launch_wide<12, true>(m, ua, ba, cfg, s, ev); break;
+        case 32: launch_wide<16, false>(m, ua, ba, cfg, s, ev); break;
+        case 33: launch_wide<16, true>(m, ua, ba, cfg, s, ev); break;
         default: launch_wide<6, false>(m, ua, ba, cfg, s, ev); break;
     }
     if (ev) (void)hipEventRecord(ev[4], s);

@@ -185,30 +185,34 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
 
     auto P = [&](int32_t i) { return V3{px[i], py[i], pz[i]}; };
 
-    // ---- cells: hexahedra (six quadrilaterals, the canonical vertex order below), or other cells
-    // of at most six faces of three or four points and at most eight distinct points
-    // (tetrahedra, pyramids, prisms), whose faces are listed with their own vertex loops
+    // ---- cells: hexahedra (six quadrilaterals, the canonical vertex order below); other cells of
+    // at most six faces of three or four points and at most eight distinct points (tetrahedra,
+    // pyramids, prisms), whose faces are listed with their own vertex loops; and general polyhedra
+    // up to kBigFaces faces of up to kBigFacePts points over up to kBigPts points
     std::vector<int32_t> ncf(n_cells, 0);
     for (int32_t f = 0; f < n_faces; ++f) {
         ncf[owner[f]]++;
         if (f < n_internal) ncf[neighbour[f]]++;
     }
     for (int32_t c = 0; c < n_cells; ++c)
-        if (ncf[c] < 4 || ncf[c] > 6)
+        if (ncf[c] < 4 || ncf[c] > kBigFaces)
             return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has " + std::to_string(ncf[c]) +
-                                              " faces (4 to 6 are taken)");
+                                              " faces (4 to " + std::to_string(kBigFaces) + " are taken)");
     for (int32_t f = 0; f < n_faces; ++f) {
         const int32_t np = face_ptr[f + 1] - face_ptr[f];
-        if (np < 3 || np > 4)
+        if (np < 3 || np > kBigFacePts)
             return fail(ISO_EUNSUPPORTED, "face " + std::to_string(f) + " has " + std::to_string(np) +
-                                              " points (3 or 4 are taken)");
+                                              " points (3 to " + std::to_string(kBigFacePts) + " are taken)");
     }
-    std::vector<int32_t> cfaces(6 * (size_t)n_cells, -1);
+    std::vector<int32_t> cf_ptr(n_cells + 1, 0);
+    for (int32_t c = 0; c < n_cells; ++c) cf_ptr[c + 1] = cf_ptr[c] + ncf[c];
+    std::vector<int32_t> cf_list(cf_ptr[n_cells], -1);
     std::fill(ncf.begin(), ncf.end(), 0);
     for (int32_t f = 0; f < n_faces; ++f) {  // ascending face id per cell
-        cfaces[6 * (size_t)owner[f] + ncf[owner[f]]++] = f;
-        if (f < n_internal) cfaces[6 * (size_t)neighbour[f] + ncf[neighbour[f]]++] = f;
+        cf_list[cf_ptr[owner[f]] + ncf[owner[f]]++] = f;
+        if (f < n_internal) cf_list[cf_ptr[neighbour[f]] + ncf[neighbour[f]]++] = f;
     }
+    auto cface = [&](int32_t c, int k) { return cf_list[cf_ptr[c] + k]; };
     // a face's points counter-clockwise seen from outside cell c (a triangle repeats its first point)
     auto outward = [&](int32_t f, int32_t c, std::array<int32_t, 4> &q) {
         const int32_t *fp = face_pts + face_ptr[f];
@@ -218,6 +222,13 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         if (np == 3) q[3] = q[0];
     };
     auto npts = [&](int32_t f) { return face_ptr[f + 1] - face_ptr[f]; };
+    // any face's points counter-clockwise seen from outside cell c
+    auto outward_n = [&](int32_t f, int32_t c, int32_t *q) {
+        const int32_t *fp = face_pts + face_ptr[f];
+        const int np = npts(f);
+        if (owner[f] == c) for (int i = 0; i < np; ++i) q[i] = fp[i];
+        else for (int i = 0; i < np; ++i) q[i] = fp[np - 1 - i];
+    };
 
     iso_mesh *m = new iso_mesh();
     m->n_points = n_points; m->n_faces = n_faces; m->n_internal = n_internal; m->n_cells = n_cells;
@@ -237,7 +248,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         bool ok = true;
         for (int k = 0; k < ncf[c] && ok; ++k) {
             std::array<int32_t, 4> q;
-            const int32_t f = cfaces[6 * (size_t)c + k];
+            const int32_t f = cface(c, k);
             outward(f, c, q);
             for (int i = 0; i < npts(f) && ok; ++i) {
                 int j = 0;
@@ -252,14 +263,17 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
             gnp[6 * (size_t)c + k] = (int8_t)npts(f);
             lface_actual[6 * (size_t)c + k] = f;
         }
-        if (!ok || nv < 4) return false;  // more than eight points (or a degenerate cell)
+        if (!ok || nv < 4) {  // more than eight points (or a degenerate cell): leave nothing behind
+            for (int k = 0; k < 6; ++k) { gnp[6 * (size_t)c + k] = 0; lface_actual[6 * (size_t)c + k] = -1; }
+            return false;
+        }
         for (int i = 0; i < 8; ++i) m->cell_pts[8 * (size_t)c + i] = v[i < nv ? i : 0];
         // closed: the outward area vectors of the faces sum to zero
         V3 sum{0, 0, 0};
         double mag = 0;
         for (int k = 0; k < ncf[c]; ++k) {
             std::array<int32_t, 4> q;
-            const int32_t f = cfaces[6 * (size_t)c + k];
+            const int32_t f = cface(c, k);
             outward(f, c, q);
             const V3 a = 0.5 * cross(P(q[2]) - P(q[0]), P(q[3]) - P(q[1]));
             sum = sum + a;
@@ -271,18 +285,71 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         return true;
     };
 
+    // general polyhedra: their distinct points, and each face's loop of local point indices
+    std::vector<int32_t> cbig(n_cells, -1), bv_ptr{0}, bv_pts, bf_ptr{0}, bf_fid, bl_ptr{0}, bl_vtx;
+    auto make_big = [&](int32_t c) -> bool {
+        std::vector<int32_t> v;
+        int32_t q[kBigFacePts];
+        for (int k = 0; k < ncf[c]; ++k) {
+            const int32_t f = cface(c, k);
+            outward_n(f, c, q);
+            for (int i = 0; i < npts(f); ++i) {
+                int j = 0;
+                while (j < (int)v.size() && v[j] != q[i]) ++j;
+                if (j == (int)v.size()) {
+                    if ((int)v.size() == kBigPts) return false;
+                    v.push_back(q[i]);
+                }
+                bl_vtx.push_back(j);
+            }
+            bl_ptr.push_back((int32_t)bl_vtx.size());
+            bf_fid.push_back(f);
+        }
+        cbig[c] = (int32_t)bv_ptr.size() - 1;
+        bv_pts.insert(bv_pts.end(), v.begin(), v.end());
+        bv_ptr.push_back((int32_t)bv_pts.size());
+        bf_ptr.push_back((int32_t)bf_fid.size());
+        for (int i = 0; i < 8; ++i) m->cell_pts[8 * (size_t)c + i] = v[i < (int)v.size() ? i : 0];
+        m->nvtx[c] = 0;  // the stencils take the points from the lists above
+        m->generic = true;
+        // closed: the outward area vectors of the faces sum to zero (Newell's area vector)
+        V3 sum{0, 0, 0};
+        double mag = 0;
+        for (int k = 0; k < ncf[c]; ++k) {
+            const int32_t f = cface(c, k);
+            outward_n(f, c, q);
+            V3 a{0, 0, 0};
+            for (int i = 0; i < npts(f); ++i) a = a + 0.5 * cross(P(q[i]), P(q[(i + 1) % npts(f)]));
+            sum = sum + a;
+            mag += norm(a);
+        }
+        if (!(norm(sum) <= 1e-9 * mag)) closed_ok = false;
+        return true;
+    };
+
     for (int32_t c = 0; c < n_cells; ++c) {
-        bool hex = ncf[c] == 6;
-        for (int k = 0; k < ncf[c] && hex; ++k) hex = npts(cfaces[6 * (size_t)c + k]) == 4;
-        if (!hex) {
-            if (!make_generic(c)) {
+        bool small = ncf[c] <= 6;
+        for (int k = 0; k < ncf[c] && small; ++k) small = npts(cface(c, k)) <= 4;
+        if (!small) {
+            if (!make_big(c)) {
                 iso_mesh_destroy(m);
-                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points or fewer than 4");
+                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than " +
+                                                  std::to_string(kBigPts) + " points");
+            }
+            continue;
+        }
+        bool hex = ncf[c] == 6;
+        for (int k = 0; k < ncf[c] && hex; ++k) hex = npts(cface(c, k)) == 4;
+        if (!hex) {
+            if (!make_generic(c) && !make_big(c)) {
+                iso_mesh_destroy(m);
+                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than " +
+                                                  std::to_string(kBigPts) + " points or fewer than 4");
             }
             continue;
         }
         std::array<std::array<int32_t, 4>, 6> fq;
-        for (int k = 0; k < 6; ++k) outward(cfaces[6 * (size_t)c + k], c, fq[k]);
+        for (int k = 0; k < 6; ++k) outward(cface(c, k), c, fq[k]);
         // bottom = first face; its outward loop is canonical (0,3,2,1)
         int32_t v[8];
         v[0] = fq[0][0]; v[3] = fq[0][1]; v[2] = fq[0][2]; v[1] = fq[0][3];
@@ -310,9 +377,10 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
             ok = std::adjacent_find(s, s + 8) == s + 8;
         }
         if (!ok) {  // six quadrilaterals that do not make a hexahedron
-            if (!make_generic(c)) {
+            if (!make_generic(c) && !make_big(c)) {
                 iso_mesh_destroy(m);
-                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than 8 points or fewer than 4");
+                return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than " +
+                                                  std::to_string(kBigPts) + " points or fewer than 4");
             }
             continue;
         }
@@ -330,7 +398,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
                 iso_mesh_destroy(m);
                 return fail(ISO_EMESH, "cell " + std::to_string(c) + ": faces inconsistently oriented");
             }
-            lface_actual[6 * (size_t)c + k] = cfaces[6 * (size_t)c + found];
+            lface_actual[6 * (size_t)c + k] = cface(c, found);
         }
         for (int i = 0; i < 8; ++i) m->cell_pts[8 * (size_t)c + i] = v[i];
     }
@@ -341,6 +409,35 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     m->vol.resize(n_cells);
     m->xc.resize(3 * (size_t)n_cells);
     for (int32_t c = 0; c < n_cells; ++c) {
+        if (cbig[c] >= 0) {
+            // general polyhedron: the same pyramid decomposition over its point list and face loops
+            const int b = cbig[c];
+            const int32_t *v = &bv_pts[bv_ptr[b]];
+            const int nv = bv_ptr[b + 1] - bv_ptr[b];
+            V3 xm{0, 0, 0};
+            for (int i = 0; i < nv; ++i) xm = xm + P(v[i]);
+            xm = (1.0 / nv) * xm;
+            double vol = 0;
+            V3 mom{0, 0, 0};
+            for (int k = bf_ptr[b]; k < bf_ptr[b + 1]; ++k) {
+                const int l0 = bl_ptr[k], np = bl_ptr[k + 1] - l0;
+                V3 ap{0, 0, 0};
+                for (int i = 0; i < np; ++i) ap = ap + P(v[bl_vtx[l0 + i]]);
+                ap = (1.0 / np) * ap;
+                for (int i = 0; i < np; ++i) {
+                    const V3 qi = P(v[bl_vtx[l0 + i]]), qj = P(v[bl_vtx[l0 + (i + 1) % np]]);
+                    V3 a = ap - xm, bb = qi - xm, cc = qj - xm;
+                    double tv = dot(a, cross(bb, cc)) / 6.0;
+                    vol += tv;
+                    mom = mom + (tv * 0.25) * (xm + ap + qi + qj);
+                }
+            }
+            if (!(vol > 0)) { iso_mesh_destroy(m); return fail(ISO_EMESH, "cell " + std::to_string(c) + " has non-positive volume"); }
+            m->vol[c] = vol;
+            V3 x = (1.0 / vol) * mom;
+            m->xc[3 * c] = x.x; m->xc[3 * c + 1] = x.y; m->xc[3 * c + 2] = x.z;
+            continue;
+        }
         const int32_t *v = &m->cell_pts[8 * (size_t)c];
         const int nv = m->nvtx[c];
         V3 xm{0, 0, 0};
@@ -408,8 +505,8 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     int W = 0;
     std::vector<std::vector<std::array<int32_t, 3>>> slots(n_cells);
     for (int32_t c = 0; c < n_cells; ++c) {
-        for (int k = 0; k < 6; ++k) {
-            int32_t f = cfaces[6 * (size_t)c + k];
+        for (int k = 0; k < ncf[c]; ++k) {
+            int32_t f = cface(c, k);
             if (f < 0 || f_fid[f] < 0) continue;
             int s; int32_t other;
             if (f < n_internal) { s = owner[f] == c ? 1 : -1; other = owner[f] == c ? neighbour[f] : owner[f]; }
@@ -420,6 +517,8 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         W = std::max<int>(W, (int)slots[c].size());
     }
     W = std::max(W, 1);
+    // more than six flux faces: the update kernels come in widths 8, 12 and 16; empty slots pad
+    if (W > 6) W = W <= 8 ? 8 : (W <= 12 ? 12 : 16);
     m->W = W;
     std::vector<int32_t> slot_face((size_t)W * n_cells, kEmpty), slot_nbr((size_t)W * n_cells, -1);
     for (int32_t c = 0; c < n_cells; ++c)
@@ -480,16 +579,19 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     m->n_classes = n_classes;
     // stencil of each class: every (cell, vertex) whose point is in the class, centre in the root frame
     std::vector<int32_t> cnt(n_classes + 1, 0);
+    // the distinct points of cell c (a general polyhedron's from its list)
+    auto cell_point = [&](int32_t c, int i) { return cbig[c] >= 0 ? bv_pts[bv_ptr[cbig[c]] + i] : m->cell_pts[8 * (size_t)c + i]; };
+    auto cell_npts = [&](int32_t c) { return cbig[c] >= 0 ? bv_ptr[cbig[c] + 1] - bv_ptr[cbig[c]] : m->nvtx[c]; };
     for (int32_t c = 0; c < n_cells; ++c)
-        for (int i = 0; i < m->nvtx[c]; ++i) cnt[cls[m->cell_pts[8 * (size_t)c + i]] + 1]++;
+        for (int i = 0; i < cell_npts(c); ++i) cnt[cls[cell_point(c, i)] + 1]++;
     for (int32_t k = 0; k < n_classes; ++k) cnt[k + 1] += cnt[k];
     m->st_nnz = cnt[n_classes];
     std::vector<int32_t> st_cell(cnt[n_classes]);
     std::vector<double> st_w(cnt[n_classes]);
     std::vector<int32_t> fillc(n_classes, 0);
     for (int32_t c = 0; c < n_cells; ++c)  // ascending cell id within each stencil
-        for (int i = 0; i < m->nvtx[c]; ++i) {
-            int32_t p = m->cell_pts[8 * (size_t)c + i];
+        for (int i = 0; i < cell_npts(c); ++i) {
+            int32_t p = cell_point(c, i);
             int32_t k = cls[p];
             int32_t e = cnt[k] + fillc[k]++;
             st_cell[e] = c;
@@ -525,6 +627,8 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
             for (int i = 0; i < 4 && planar; ++i) planar = std::fabs(dot(q[i] - mean, nrm)) <= 1e-12 * size * ln;
             if (planar) cflags[c] |= 1 << k;
         }
+    for (int32_t c = 0; c < n_cells; ++c)  // general polyhedra: bits 8 and 10, nothing per face
+        if (cbig[c] >= 0) cflags[c] = (1 << 8) | (1 << 10);
     for (int32_t c = 0; c < n_cells; ++c) {
         if (gnp[6 * (size_t)c] == 0) continue;
         bool all = true;
@@ -551,6 +655,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         for (int32_t c = 0; c < n_cells; ++c)
             for (int k = 0; k < 6; ++k) {
                 int lv[4];
+                if (cbig[c] >= 0) continue;  // taken by the general-polyhedron kernel
                 if (gnp[6 * (size_t)c] == 0) {
                     for (int i = 0; i < 4; ++i) lv[i] = kHexFace[k][i];
                 } else {
@@ -564,6 +669,43 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
                 }
                 cloop[6 * (size_t)c + k] = word;
             }
+    }
+    // general polyhedra on the device: point classes and coordinates, each face's packed flux face,
+    // planarity (every point within 1e-12 of the face size of the mean plane, normal by Newell)
+    const bool any_big = bv_ptr.size() > 1;
+    std::vector<int32_t> bv_cls(bv_pts.size()), bf_face(bf_fid.size(), kEmpty), bf_planar(bf_fid.size(), 0);
+    std::vector<double> bv_xyz(3 * bv_pts.size());
+    for (size_t i = 0; i < bv_pts.size(); ++i) {
+        bv_cls[i] = cls[bv_pts[i]];
+        const V3 x = P(bv_pts[i]);
+        bv_xyz[3 * i] = x.x; bv_xyz[3 * i + 1] = x.y; bv_xyz[3 * i + 2] = x.z;
+    }
+    for (int32_t c = 0; c < n_cells; ++c) {
+        if (cbig[c] < 0) continue;
+        const int b = cbig[c];
+        const int32_t *v = &bv_pts[bv_ptr[b]];
+        for (int k = bf_ptr[b]; k < bf_ptr[b + 1]; ++k) {
+            const int32_t f = bf_fid[k];
+            if (f_fid[f] >= 0) {
+                const int sg = f < n_internal ? (owner[f] == c ? 1 : -1) : f_sign[f];
+                bf_face[k] = pack_face(f_fid[f], sg);
+            }
+            const int l0 = bl_ptr[k], np = bl_ptr[k + 1] - l0;
+            V3 nrm{0, 0, 0}, mean{0, 0, 0};
+            double size = 0;
+            for (int i = 0; i < np; ++i) {
+                const V3 qi = P(v[bl_vtx[l0 + i]]), qj = P(v[bl_vtx[l0 + (i + 1) % np]]);
+                nrm = nrm + cross(qi, qj);
+                mean = mean + qi;
+                size += norm(qj - qi);
+            }
+            mean = (1.0 / np) * mean;
+            const double ln = norm(nrm);
+            bool planar = ln > 0;
+            for (int i = 0; i < np && planar; ++i)
+                planar = std::fabs(dot(P(v[bl_vtx[l0 + i]]) - mean, nrm)) <= 1e-12 * size * ln;
+            bf_planar[k] = planar ? 1 : 0;
+        }
     }
     m->patch_alpha.assign(std::max(n_patches, 1), 0.0);
     for (int32_t p = 0; p < n_patches; ++p) m->patch_alpha[p] = patch_alpha_in[p];
@@ -579,7 +721,12 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         (st = upload(m, lface, &d.lface)) || (st = upload(m, cflags, &d.cflags)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
         (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha)) ||
         (st = upload(m, m->xc, &d.ccen)) || (st = upload(m, fcell, &d.fcell)) || (st = upload(m, bpatch, &d.bpatch)) ||
-        (st = upload(m, ptrans, &d.ptrans)) || (m->generic && (st = upload(m, cloop, &d.cloop)))) {
+        (st = upload(m, ptrans, &d.ptrans)) || (m->generic && (st = upload(m, cloop, &d.cloop))) ||
+        (any_big && ((st = upload(m, cbig, &d.cbig)) || (st = upload(m, bv_ptr, &d.bv_ptr)) ||
+                     (st = upload(m, bv_cls, &d.bv_cls)) || (st = upload(m, bv_xyz, &d.bv_xyz)) ||
+                     (st = upload(m, bf_ptr, &d.bf_ptr)) || (st = upload(m, bf_face, &d.bf_face)) ||
+                     (st = upload(m, bf_planar, &d.bf_planar)) || (st = upload(m, bl_ptr, &d.bl_ptr)) ||
+                     (st = upload(m, bl_vtx, &d.bl_vtx))))) {
         iso_mesh_destroy(m);
         return st;
     }

@@ -48,10 +48,10 @@ def test_mesh_validation_errors_before_device():
     with pytest.raises(B.IsoError) as e:
         _create(m, pp=pp2)
     assert e.value.status == B.ISO_EMESH
-    with pytest.raises(B.IsoError) as e:  # a face of five points
+    with pytest.raises(B.IsoError) as e:  # a face of seventeen points
         fp = m.face_pts.copy()
-        fptr = np.concatenate([[0], np.cumsum([5] + [4] * (m.n_faces - 1))]).astype(np.int32)
-        fp = np.concatenate([fp[:4], fp[:1], fp[4:]])
+        fptr = np.concatenate([[0], np.cumsum([17] + [4] * (m.n_faces - 1))]).astype(np.int32)
+        fp = np.concatenate([fp[:4], np.repeat(fp[:1], 13), fp[4:]])
         _create(m, face_ptr=fptr, face_pts=fp)
     assert e.value.status == B.ISO_EUNSUPPORTED
     with pytest.raises(B.IsoError) as e:  # a cell whose faces do not close it
@@ -62,10 +62,17 @@ def test_mesh_validation_errors_before_device():
     assert e.value.status == B.ISO_EMESH
 
 
-@pytest.mark.parametrize("build", [W.tet_block, W.prism_block, W.pyramid_block])
-def test_cells_with_triangular_faces_pass_the_host_checks(build):
-    """Tetrahedra, prisms and pyramids are taken: without a GPU the only failure left is the
-    device one, after every host-side check."""
+def _merged(xs, ys, zs, periodic_x=True):
+    """2 x 2 hexahedra joined into one cell wherever i and j are even: 18 points, 16 faces."""
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    return W.merged_block(xs, ys, zs, merge_xy=[(i, j, k) for k in range(nz) for j in range(0, ny - 1, 2)
+                                                for i in range(0, nx - 1, 2)], periodic_x=periodic_x)
+
+
+@pytest.mark.parametrize("build", [W.tet_block, W.prism_block, W.pyramid_block, _merged])
+def test_cells_other_than_hexahedra_pass_the_host_checks(build):
+    """Tetrahedra, prisms, pyramids and polyhedra of merged hexahedra are taken: without a GPU the
+    only failure left is the device one, after every host-side check."""
     m = build(np.linspace(0, 2, 5), np.linspace(0, 1, 3), np.linspace(0, 1, 3), periodic_x=True)
     with pytest.raises(B.IsoError) as e:
         _create(m)

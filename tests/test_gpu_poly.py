@@ -1,5 +1,6 @@
-"""Cells other than hexahedra on the GPU: tetrahedra, square pyramids, triangular prisms, and
-hexahedra next to prisms in one mesh, against the oracle.  Same seeded inputs on both sides (the
+"""Cells other than hexahedra on the GPU: tetrahedra, square pyramids, triangular prisms,
+hexahedra next to prisms in one mesh, and polyhedra of merged hexahedra (10 or 16 faces, 12 or 18
+points, split faces) among hexahedra, against the oracle.  Same seeded inputs on both sides (the
 workloads of wavegen.poly); |delta alpha| <= 1e-10 after the whole run, per-face dV of one traced
 step within 1e-13 of max|phi| dt, interface cells the same on both sides.
 """
@@ -24,6 +25,9 @@ def _cases():
         # bent quadrilaterals: those prisms and hexahedra take the generic search
         "prism_perturbed_12x6x6": W.poly_violent("prism", nx=12, ny=6, nz=6, steps=8, perturb=0.15),
         "mixed_perturbed_12x6x6": W.poly_violent("mixed", nx=12, ny=6, nz=6, steps=8, perturb=0.15),
+        # general polyhedra: the one-thread-per-cell kernel, flat and bent faces
+        "merged_16x8x8": W.poly_violent("merged", nx=16, ny=8, nz=8, steps=8),
+        "merged_perturbed_16x8x8": W.poly_violent("merged", nx=16, ny=8, nz=8, steps=8, perturb=0.1),
     }
 
 
@@ -61,7 +65,8 @@ def test_trajectory_matches_oracle(oracle_lib, name):
     assert g.min() >= 0.0 and g.max() <= 1.0
 
 
-@pytest.mark.parametrize("name", ["tet_12x6x6", "pyramid_8x4x4", "mixed_16x8x8"])
+@pytest.mark.parametrize("name", ["tet_12x6x6", "pyramid_8x4x4", "mixed_16x8x8", "merged_16x8x8",
+                                  "merged_perturbed_16x8x8"])
 def test_traced_step_matches_oracle(oracle_lib, name):
     w = CASES[name]
     phi, U = w.phi_U(0)
@@ -80,13 +85,13 @@ def test_traced_step_matches_oracle(oracle_lib, name):
     assert np.abs(out - o_new).max() <= 1e-13
 
 
-@pytest.mark.parametrize("seed", [61, 62])
-def test_random_fields_on_tetrahedra(oracle_lib, seed):
+@pytest.mark.parametrize("kind,seed", [("tet", 61), ("tet", 62), ("merged", 63), ("merged", 64)])
+def test_random_fields(oracle_lib, kind, seed):
     """alpha ~ U[0.02, 0.98] per cell: every cell an interface cell, arbitrary vertex patterns on
-    triangular faces."""
-    w = W.poly_violent("tet", nx=8, ny=4, nz=4, steps=3)
+    triangular faces and on the many faces of the merged polyhedra."""
+    w = W.poly_violent(kind, nx=8, ny=4, nz=4, steps=3)
     a0 = np.random.default_rng(seed).uniform(0.02, 0.98, w.mesh.n_cells)
-    say(f"[gpu] random field on tetrahedra: seed={seed}")
+    say(f"[gpu] random field on {kind} cells: seed={seed}")
     gm, plan = gpu_plan(w.mesh)
     g = _gpu_run(plan, w, 3, a0)
     o = _oracle_run(oracle_lib.OracleMesh(w.mesh), w, 3, a0)
@@ -95,8 +100,9 @@ def test_random_fields_on_tetrahedra(oracle_lib, seed):
     assert err <= TOL
 
 
-def test_launch_shapes_give_the_same_bits():
-    w = CASES["mixed_16x8x8"]
+@pytest.mark.parametrize("name", ["mixed_16x8x8", "merged_16x8x8"])
+def test_launch_shapes_give_the_same_bits(name):
+    w = CASES[name]
     ref = None
     for opts in ({}, {"block_cells": 64}, {"surface_waves": 1}, {"surface_blocks": 7, "bound_blocks": 3}):
         gm, plan = gpu_plan(w.mesh, **opts)
