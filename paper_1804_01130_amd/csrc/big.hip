@@ -3,19 +3,20 @@
 // than six faces, more than eight points, or faces of more than four points), up to kBigPts
 // points, kBigFaces faces and kBigFacePts points per face.
 //
-// One thread per such cell, grid-stride over the interface-cell list (the other cells are left to
-// the eight-lane kernel, which skips these).  The thread follows the same construction as the
-// eight-lane kernel's generic path, with loops over the cell's faces and each face's points:
-//   vertex values through the inverse-distance stencils; the isovalue bracketed between two
-//   consecutive sorted vertex values (the limit from above at each) and found by Illinois with a
-//   bisection guard to round-off, or taken at a vertex value where the sub-volume jumps; the
-//   sub-volume by the divergence theorem, each face's wet loop fanned about a face point (planar
-//   faces) or its perimeter centroid, the isoface fanned about the perimeter centroid of its
-//   edges; the isoface's normal, centre and U_P . n_S; and for each outflow face the swept
-//   integral over the triangles that fan the face about its vertex mean.
-// These cells are expected to be few (hexahedra-dominant meshes), so the work is laid out for
-// clarity: the cell's points and values wait in the thread's private memory, its face loops are
-// read where they lie.
+// Sixteen lanes per cell, one per face (the eight-lane kernel skips these cells).  The cell's
+// points, relative to their mean, and their vertex values sit in LDS, where every lane of the
+// group reads them; each lane keeps its face's loop of local point indices in registers.  The
+// construction is the eight-lane kernel's generic path:
+//   vertex values through the inverse-distance stencils (two points per lane); the sorted values
+//   by rank; the isovalue bracketed between two consecutive sorted values (the limit from above
+//   at each) and found by Illinois with a bisection guard to round-off, or taken at a vertex value
+//   where the sub-volume jumps; the sub-volume by the divergence theorem, each lane's wet loop
+//   fanned about a face point (planar faces) or its perimeter centroid, the isoface fanned about
+//   the perimeter centroid of its edges; the isoface's normal, centre and U_P . n_S; and each
+//   lane's swept integral of its face, over the triangles that fan it about its vertex mean.
+// Face sums are reduced over the sixteen lanes by a butterfly in which partner lanes add the same
+// two partial sums, so every lane holds bitwise the same totals and takes the same branches of
+// the root search.
 #include "device_common.h"
 #include "internal.h"
 
@@ -23,75 +24,109 @@ namespace isoadv {
 
 namespace {
 
-struct BigPart {
+constexpr int kGrp = 16;         // lanes per cell, one per face
+constexpr int kGrpPerBlock = 16; // 256 threads
+static_assert(kBigFaces == kGrp, "one lane per face");
+static_assert(kBigPts == 2 * kGrp, "two points per lane");
+static_assert(kBigFacePts <= 16, "a face loop packs into four words of bytes");
+
+struct Pt {
+    double x, y, z, a;  // point relative to the cell's point mean, and its vertex value
+};
+
+// This lane's face: its loop of local point indices (byte i of the four words: position i).
+struct FaceLoop {
+    int n;  // points; 0 when the lane has no face
+    int planar;
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ int loop_at(const FaceLoop &L, int i) { return (L.w[i >> 2] >> (8 * (i & 3))) & 0xff; }
+
+// Sum over the sixteen lanes of a group: the eight-lane butterfly, then the two halves of the row
+// swapped by mirroring (lane i <- lane 15 - i).
+constexpr int kDppRowMirror = 0x140;
+__device__ __forceinline__ double g16(double v) {
+    v = grp_sum(v);
+    return v + dpp_move<kDppRowMirror>(v);
+}
+__device__ __forceinline__ D3 g16_3(D3 v) { return D3{g16(v.x), g16(v.y), g16(v.z)}; }
+
+// Order the group's LDS writes before the reads of other lanes of the same wave.
+__device__ __forceinline__ void grp_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ D3 xyz(const Pt &p) { return D3{p.x, p.y, p.z}; }
+
+// Cut point on the edge between two points of which exactly one is wet: from the wet end, so that
+// the two faces sharing the edge compute the same point.
+__device__ __forceinline__ D3 edge_cut(const Pt &w, const Pt &d, double iso) {
+    const double lam = (iso - w.a) / (d.a - w.a);
+    return xyz(w) + lam * (xyz(d) - xyz(w));
+}
+
+struct FacePart {
     double v6;
     D3 cseg, oacc;
     double oL;
 };
 
-struct BigCell {
-    int nv, nf;
-    D3 x[kBigPts];         // points relative to their mean
-    double a[kBigPts];     // vertex values
-    const int32_t *fptr;   // [nf+1] loop positions of each face (offsets into loop)
-    const int32_t *loop;   // local point at each loop position
-    const int32_t *planar; // [nf]
-};
-
-// Cut point on the edge from point p to point q of a face: from the wet end, so that the two faces
-// sharing the edge compute the same point.
-__device__ __forceinline__ D3 big_cut(const BigCell &B, int p, int q, bool wet_p, double iso) {
-    const int w = wet_p ? p : q, d = wet_p ? q : p;
-    const double lam = (iso - B.a[w]) / (B.a[d] - B.a[w]);
-    return B.x[w] + lam * (B.x[d] - B.x[w]);
+__device__ __forceinline__ void iso_edge(FacePart &r, D3 s0, D3 s1) {
+    const double l = norm3(s1 - s0);
+    r.cseg = r.cseg + cross(s0, s1);
+    r.oacc = r.oacc + (0.5 * l) * (s0 + s1);
+    r.oL += l;
 }
 
-// Face k's share of six times the wet sub-volume and of the isoface sums (as the eight-lane
-// kernel's face share, for any number of points).
-__device__ BigPart big_face_part(const BigCell &B, int k, double iso, bool tie_wet) {
-    BigPart r{0.0, {0, 0, 0}, {0, 0, 0}, 0.0};
-    const int b = B.fptr[k], n = B.fptr[k + 1] - b;
-    auto wet = [&](int i) {
-        const double av = B.a[B.loop[b + i]];
-        return tie_wet ? av >= iso : av > iso;
-    };
-    // the last exit before the start of the loop
-    D3 lastexit{0, 0, 0};
-    for (int i = 0; i < n; ++i) {
-        const int j = i + 1 < n ? i + 1 : 0;
-        if (wet(i) && !wet(j)) lastexit = big_cut(B, B.loop[b + i], B.loop[b + j], true, iso);
-    }
-    D3 C{0, 0, 0}, pacc{0, 0, 0}, psum{0, 0, 0};
+// This lane's face share of six times the wet sub-volume and of the isoface sums.  An entry into
+// the wet part closes the isoface edge from the preceding exit; an entry before the loop's first
+// exit pairs with its last one.
+__device__ FacePart face_part(const Pt *P, const FaceLoop &L, double iso, bool tie_wet) {
+    FacePart r{0.0, {0, 0, 0}, {0, 0, 0}, 0.0};
+    if (L.n == 0) return r;
+    D3 C{0, 0, 0}, pacc{0, 0, 0}, psum{0, 0, 0}, lastexit{0, 0, 0}, first_entry{0, 0, 0};
     double pl = 0.0;
     int cnt = 0;
-    for (int i = 0; i < n; ++i) {
-        const int j = i + 1 < n ? i + 1 : 0;
-        const int p = B.loop[b + i], q = B.loop[b + j];
-        const bool wi = wet(i), wj = wet(j);
-        const D3 cut = big_cut(B, p, q, wi, iso);
-        if (!wi && wj) {  // an entry: the isoface edge from here back to the preceding exit
-            const D3 s0 = cut, s1 = lastexit;
-            const double l = norm3(s1 - s0);
-            r.cseg = r.cseg + cross(s0, s1);
-            r.oacc = r.oacc + (0.5 * l) * (s0 + s1);
-            r.oL += l;
+    bool have_exit = false, pend = false;
+    const Pt p0 = P[loop_at(L, 0)];
+    Pt pi = p0;
+    bool wi = tie_wet ? p0.a >= iso : p0.a > iso;
+#pragma unroll
+    for (int i = 0; i < kBigFacePts; ++i) {
+        if (i < L.n) {
+            Pt pj = p0;
+            if (i + 1 < kBigFacePts && i + 1 < L.n) pj = P[loop_at(L, i + 1)];
+            const bool wj = tie_wet ? pj.a >= iso : pj.a > iso;
+            const D3 xi = xyz(pi), xj = xyz(pj);
+            D3 cut{0, 0, 0};
+            if (wi != wj) cut = wi ? edge_cut(pi, pj, iso) : edge_cut(pj, pi, iso);
+            if (!wi && wj) {
+                if (have_exit) iso_edge(r, cut, lastexit);
+                else { pend = true; first_entry = cut; }
+            }
+            if (wi && !wj) { lastexit = cut; have_exit = true; }
+            if (wi || wj) {
+                const D3 u = wi ? xi : cut, v = wj ? xj : cut;
+                C = C + cross(u, v);
+                const double l = norm3(v - u);
+                pacc = pacc + (0.5 * l) * (u + v);
+                pl += l;
+            }
+            if (wi) psum = psum + xi;
+            if (wi != wj) psum = psum + cut;
+            cnt += (wi ? 1 : 0) + (wi != wj ? 1 : 0);
+            pi = pj;
+            wi = wj;
         }
-        if (wi && !wj) lastexit = cut;
-        if (wi || wj) {
-            const D3 u = wi ? B.x[p] : cut, v = wj ? B.x[q] : cut;
-            C = C + cross(u, v);
-            const double l = norm3(v - u);
-            pacc = pacc + (0.5 * l) * (u + v);
-            pl += l;
-        }
-        if (wi) psum = psum + B.x[p];
-        if (wi != wj) psum = psum + cut;
-        cnt += (wi ? 1 : 0) + (wi != wj ? 1 : 0);
     }
+    if (pend) iso_edge(r, first_entry, lastexit);
     C = C - r.cseg;  // the isoface edges close the wet loop, walked exit to entry
     if (cnt >= 3) {
-        D3 ap = B.x[B.loop[b]];
-        if (!B.planar[k]) {
+        D3 ap = xyz(p0);
+        if (!L.planar) {
             const D3 tot = pacc + r.oacc;
             const double tl = pl + r.oL;
             ap = tl > 0.0 ? (1.0 / tl) * tot : (1.0 / cnt) * psum;
@@ -101,84 +136,172 @@ __device__ BigPart big_face_part(const BigCell &B, int k, double iso, bool tie_w
     return r;
 }
 
-__device__ double big_vsub6(const BigCell &B, double iso, bool tie_wet, D3 *o_out, D3 *cseg_out) {
-    double v6 = 0.0, oL = 0.0;
-    D3 cseg{0, 0, 0}, oacc{0, 0, 0};
-    for (int k = 0; k < B.nf; ++k) {
-        const BigPart p = big_face_part(B, k, iso, tie_wet);
-        v6 += p.v6;
-        cseg = cseg + p.cseg;
-        oacc = oacc + p.oacc;
-        oL += p.oL;
-    }
-    const D3 o = oL > 0.0 ? (1.0 / oL) * oacc : D3{0, 0, 0};
-    if (o_out) *o_out = o;
-    if (cseg_out) *cseg_out = cseg;
+// Six times the wet sub-volume of the cell at isovalue iso (every lane of the group calls it and
+// gets the same result), with the isoface's fan apex and area-vector sum.
+__device__ __forceinline__ double grp_vsub6(const Pt *P, const FaceLoop &L, double iso, bool tie_wet, D3 &o,
+                                            D3 &cseg) {
+    const FacePart r = face_part(P, L, iso, tie_wet);
+    const double v6 = g16(r.v6), oL = g16(r.oL);
+    cseg = g16_3(r.cseg);
+    const D3 oacc = g16_3(r.oacc);
+    o = oL > 0.0 ? (1.0 / oL) * oacc : D3{0, 0, 0};
     return v6 + dot(o, cseg);
 }
 
-__global__ void __launch_bounds__(64) k_surface_big(BigArgs A) {
+// This lane's share of the isoface centroid: the fan triangles (o, entry, preceding exit) of its
+// face's isoface edges, weighted by their area along n_S.
+__device__ void face_centre(const Pt *P, const FaceLoop &L, double iso, D3 o, D3 nS, D3 &acc, double &ws) {
+    acc = D3{0, 0, 0};
+    ws = 0.0;
+    if (L.n == 0) return;
+    D3 lastexit{0, 0, 0}, first_entry{0, 0, 0};
+    bool have_exit = false, pend = false;
+    const Pt p0 = P[loop_at(L, 0)];
+    Pt pi = p0;
+    bool wi = p0.a > iso;
+    auto tri = [&](D3 s0, D3 s1) {
+        const double wt = dot(cross(s0 - o, s1 - o), nS);
+        acc = acc + wt * (o + s0 + s1);
+        ws += wt;
+    };
+#pragma unroll
+    for (int i = 0; i < kBigFacePts; ++i) {
+        if (i < L.n) {
+            Pt pj = p0;
+            if (i + 1 < kBigFacePts && i + 1 < L.n) pj = P[loop_at(L, i + 1)];
+            const bool wj = pj.a > iso;
+            if (!wi && wj) {
+                const D3 cut = edge_cut(pj, pi, iso);
+                if (have_exit) tri(cut, lastexit);
+                else { pend = true; first_entry = cut; }
+            }
+            if (wi && !wj) { lastexit = edge_cut(pi, pj, iso); have_exit = true; }
+            pi = pj;
+            wi = wj;
+        }
+    }
+    if (pend) tri(first_entry, lastexit);
+}
+
+// The swept integral over the step of this lane's face (Eqs. dV, alphaf): the face fanned about
+// its vertex mean, each triangle's submerged fraction integrated in time exactly.
+__device__ double face_sweep(const Pt *P, const FaceLoop &L, D3 xS, D3 nS, double un, double dt) {
+    D3 ap{0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < kBigFacePts; ++i)
+        if (i < L.n) ap = ap + xyz(P[loop_at(L, i)]);
+    ap = (1.0 / L.n) * ap;
+    const double dap = dot(ap - xS, nS);
+    double accI = 0.0, Af = 0.0;
+    const D3 x0 = xyz(P[loop_at(L, 0)]);
+    D3 xi = x0;
+#pragma unroll
+    for (int i = 0; i < kBigFacePts; ++i) {
+        if (i < L.n) {
+            D3 xj = x0;
+            if (i + 1 < kBigFacePts && i + 1 < L.n) xj = xyz(P[loop_at(L, i + 1)]);
+            const double Ai = 0.5 * norm3(cross(xi - ap, xj - ap));
+            accI += Ai * tri_sweep(dap, dot(xi - xS, nS), dot(xj - xS, nS), un, dt);
+            Af += Ai;
+            xi = xj;
+        }
+    }
+    return accI / Af;
+}
+
+__global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) {
+    __shared__ Pt spt[kGrpPerBlock][kBigPts];
+    __shared__ double ssort[kGrpPerBlock][kBigPts];
     const DevMesh &m = A.m;
+    const int g = threadIdx.x / kGrp, lf = threadIdx.x % kGrp;
+    Pt *P = spt[g];
+    double *S = ssort[g];
     const int n = min(A.counters[kCntSurf], A.cap);
     int rounds_max = 0, flat = 0, nonconv = 0;
-    BigCell B;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
+    for (int idx = blockIdx.x * kGrpPerBlock + g; idx < n; idx += gridDim.x * kGrpPerBlock) {
         const int c = A.list[idx];
         const int bi = m.cbig[c];
-        if (bi < 0) continue;
+        if (bi < 0) continue;  // the same cell on all sixteen lanes
         const double aP = A.alpha[c];
         const double V6 = 6.0 * m.vol[c];
         const double dtc = A.dt;
-        // the cell's points, relative to their mean, and their values through the stencils
-        const int v0 = m.bv_ptr[bi];
-        B.nv = m.bv_ptr[bi + 1] - v0;
-        D3 xm{0, 0, 0};
-        for (int i = 0; i < B.nv; ++i) {
-            B.x[i] = D3{m.bv_xyz[3 * (size_t)(v0 + i)], m.bv_xyz[3 * (size_t)(v0 + i) + 1],
-                        m.bv_xyz[3 * (size_t)(v0 + i) + 2]};
-            xm = xm + B.x[i];
+        // points lf and lf + 16: coordinates, their mean over the group, vertex values
+        const int v0 = m.bv_ptr[bi], nv = m.bv_ptr[bi + 1] - v0;
+        D3 xp[2];
+        double ap[2];
+        D3 xs{0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lf + kGrp * h;
+            xp[h] = D3{0, 0, 0};
+            ap[h] = 0.0;
+            if (i < nv) {
+                const double *q = m.bv_xyz + 3 * (size_t)(v0 + i);
+                xp[h] = D3{q[0], q[1], q[2]};
+                const int k = m.bv_cls[v0 + i];
+                double av = 0.0;
+                for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e) av += m.st_w[e] * A.alpha[m.st_cell[e]];
+                ap[h] = av;
+                xs = xs + xp[h];
+            }
         }
-        xm = (1.0 / B.nv) * xm;
-        for (int i = 0; i < B.nv; ++i) {
-            B.x[i] = B.x[i] - xm;
-            const int k = m.bv_cls[v0 + i];
-            double av = 0.0;
-            for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e) av += m.st_w[e] * A.alpha[m.st_cell[e]];
-            B.a[i] = av;
+        const D3 xm = (1.0 / nv) * g16_3(xs);
+        grp_sync();  // the previous cell's reads of P and S are done
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lf + kGrp * h;
+            if (i < nv) {
+                const D3 x = xp[h] - xm;
+                P[i] = Pt{x.x, x.y, x.z, ap[h]};
+            }
         }
-        const int f0 = m.bf_ptr[bi];
-        B.nf = m.bf_ptr[bi + 1] - f0;
-        B.fptr = m.bl_ptr + f0;  // loop positions of face k: [fptr[k], fptr[k+1]) of bl_vtx
-        B.loop = m.bl_vtx;
-        B.planar = m.bf_planar + f0;
-        // sorted vertex values (insertion sort)
-        double s[kBigPts];
-        for (int i = 0; i < B.nv; ++i) {
-            double v = B.a[i];
-            int j = i;
-            while (j > 0 && s[j - 1] > v) { s[j] = s[j - 1]; --j; }
-            s[j] = v;
+        grp_sync();
+        // sorted vertex values: each point's rank (ties by index)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lf + kGrp * h;
+            if (i < nv) {
+                int rank = 0;
+                for (int j = 0; j < nv; ++j) {
+                    const double aj = P[j].a;
+                    rank += (aj < ap[h] || (aj == ap[h] && j < i)) ? 1 : 0;
+                }
+                S[rank] = ap[h];
+            }
         }
-        bool recon = s[B.nv - 1] - s[0] > A.flat_tol;
+        // this lane's face
+        const int f0 = m.bf_ptr[bi], nf = m.bf_ptr[bi + 1] - f0;
+        FaceLoop L{0, 0, {0u, 0u, 0u, 0u}};
+        if (lf < nf) {
+            const int b = m.bl_ptr[f0 + lf];
+            L.n = m.bl_ptr[f0 + lf + 1] - b;
+            L.planar = m.bf_planar[f0 + lf];
+#pragma unroll
+            for (int i = 0; i < kBigFacePts; ++i)
+                if (i < L.n) L.w[i >> 2] |= (uint32_t)m.bl_vtx[b + i] << (8 * (i & 3));
+        }
+        grp_sync();
+        bool recon = S[nv - 1] - S[0] > A.flat_tol;
         double iso = 0.0;
         int rounds = 0;
         D3 nS{0, 0, 0}, xS{0, 0, 0};
         double un = 0.0;
         if (recon) {
-            auto F = [&](double x, bool tie_wet) { return big_vsub6(B, x, tie_wet, nullptr, nullptr) / V6 - aP; };
-            int il = 0, ih = B.nv - 1;
+            D3 o, cseg;
+            auto F = [&](double x, bool tie_wet) { return grp_vsub6(P, L, x, tie_wet, o, cseg) / V6 - aP; };
+            int il = 0, ih = nv - 1;
             double fl = 1.0 - aP;
             bool exact = false;
             while (ih - il > 1) {
                 const int im = (il + ih) >> 1;
-                const double fm = F(s[im], false);
+                const double fm = F(S[im], false);
                 ++rounds;
                 if (fm > 0.0) { il = im; fl = fm; }
                 else if (fm < 0.0) { ih = im; }
-                else { iso = s[im]; exact = true; break; }
+                else { iso = S[im]; exact = true; break; }
             }
             if (!exact) {
-                double x0 = s[il], x1 = s[ih], f0v = fl;
+                double x0 = S[il], x1 = S[ih], f0v = fl;
                 double f1 = F(x1, true);  // limit from below at x1
                 ++rounds;
                 if (f1 > 0.0) {
@@ -214,33 +337,15 @@ __global__ void __launch_bounds__(64) k_surface_big(BigArgs A) {
                 }
             }
             // the isoface at the isovalue: normal from its area vector, centre from its fan
-            D3 o, cseg;
-            big_vsub6(B, iso, false, &o, &cseg);
+            grp_vsub6(P, L, iso, false, o, cseg);
             const double nrm = norm3(cseg);
             if (nrm > 0.0) {
                 nS = (1.0 / nrm) * cseg;
-                D3 acc{0, 0, 0};
-                double ws = 0.0;
-                for (int k = 0; k < B.nf; ++k) {
-                    const int b = B.fptr[k], nn = B.fptr[k + 1] - b;
-                    auto wet = [&](int i) { return B.a[B.loop[b + i]] > iso; };
-                    D3 lastexit{0, 0, 0};
-                    for (int i = 0; i < nn; ++i) {
-                        const int j = i + 1 < nn ? i + 1 : 0;
-                        if (wet(i) && !wet(j)) lastexit = big_cut(B, B.loop[b + i], B.loop[b + j], true, iso);
-                    }
-                    for (int i = 0; i < nn; ++i) {
-                        const int j = i + 1 < nn ? i + 1 : 0;
-                        const bool wi = wet(i), wj = wet(j);
-                        const D3 cut = big_cut(B, B.loop[b + i], B.loop[b + j], wi, iso);
-                        if (!wi && wj) {
-                            const double wt = dot(cross(cut - o, lastexit - o), nS);
-                            acc = acc + wt * (o + cut + lastexit);
-                            ws += wt;
-                        }
-                        if (wi && !wj) lastexit = cut;
-                    }
-                }
+                D3 acc;
+                double ws;
+                face_centre(P, L, iso, o, nS, acc, ws);
+                acc = g16_3(acc);
+                ws = g16(ws);
                 xS = (1.0 / (3.0 * ws)) * acc;
                 const size_t nc = m.n_cells;
                 D3 Up{A.U[c], A.U[nc + c], A.U[2 * nc + c]};
@@ -250,46 +355,29 @@ __global__ void __launch_bounds__(64) k_surface_big(BigArgs A) {
                 recon = false;
             }
         }
-        if (!recon) ++flat;
-        rounds_max = max(rounds_max, rounds);
-        if (A.tr.kind) A.tr.kind[c] = recon ? 1 : 2;
-        if (recon) {
-            if (A.tr.iso) A.tr.iso[c] = iso;
-            if (A.tr.iters) A.tr.iters[c] = rounds;
-            if (A.tr.rec) {
-                double *rr = A.tr.rec + 7 * (size_t)c;
-                rr[0] = xS.x + xm.x; rr[1] = xS.y + xm.y; rr[2] = xS.z + xm.z;
-                rr[3] = nS.x; rr[4] = nS.y; rr[5] = nS.z; rr[6] = un;
+        if (lf == 0) {
+            if (!recon) ++flat;
+            rounds_max = max(rounds_max, rounds);
+            if (A.tr.kind) A.tr.kind[c] = recon ? 1 : 2;
+            if (recon) {
+                if (A.tr.iso) A.tr.iso[c] = iso;
+                if (A.tr.iters) A.tr.iters[c] = rounds;
+                if (A.tr.rec) {
+                    double *rr = A.tr.rec + 7 * (size_t)c;
+                    rr[0] = xS.x + xm.x; rr[1] = xS.y + xm.y; rr[2] = xS.z + xm.z;
+                    rr[3] = nS.x; rr[4] = nS.y; rr[5] = nS.z; rr[6] = un;
+                }
             }
         }
-        // outflow faces: the swept integral over the triangles fanning each face about its
-        // vertex mean (a planar face's fan covers it whatever the apex)
-        for (int k = 0; k < B.nf; ++k) {
-            const int32_t v = m.bf_face[f0 + k];
-            if (v == kEmpty) continue;
-            const int32_t fid = v >= 0 ? v : ~v;
-            const double ph = A.phi1 ? 0.5 * (A.phi[fid] + A.phi1[fid]) : A.phi[fid];
-            const double out = v >= 0 ? ph : -ph;
-            if (!(out > 0.0)) continue;
-            double dv;
-            if (recon) {
-                const int b = B.fptr[k], nn = B.fptr[k + 1] - b;
-                D3 ap{0, 0, 0};
-                for (int i = 0; i < nn; ++i) ap = ap + B.x[B.loop[b + i]];
-                ap = (1.0 / nn) * ap;
-                const double dap = dot(ap - xS, nS);
-                double accI = 0.0, Af = 0.0;
-                for (int i = 0; i < nn; ++i) {
-                    const D3 p = B.x[B.loop[b + i]], q = B.x[B.loop[b + (i + 1 < nn ? i + 1 : 0)]];
-                    const double Ai = 0.5 * norm3(cross(p - ap, q - ap));
-                    accI += Ai * tri_sweep(dap, dot(p - xS, nS), dot(q - xS, nS), un, dtc);
-                    Af += Ai;
-                }
-                dv = ph * (accI / Af);
-            } else {
-                dv = aP * ph * dtc;
+        // this lane's face, if it carries outflow
+        if (lf < nf) {
+            const int32_t v = m.bf_face[f0 + lf];
+            if (v != kEmpty) {
+                const int32_t fid = v >= 0 ? v : ~v;
+                const double ph = A.phi1 ? 0.5 * (A.phi[fid] + A.phi1[fid]) : A.phi[fid];
+                const double out = v >= 0 ? ph : -ph;
+                if (out > 0.0) A.dvs[fid] = recon ? ph * face_sweep(P, L, xS, nS, un, dtc) : aP * ph * dtc;
             }
-            A.dvs[fid] = dv;
         }
     }
     if (A.want_stats) {
@@ -309,8 +397,8 @@ __global__ void __launch_bounds__(64) k_surface_big(BigArgs A) {
 }  // namespace
 
 hipError_t launch_surface_big(const BigArgs &a, hipStream_t s) {
-    const int blocks = std::max(1, std::min(256, (a.cap + 63) / 64));
-    hipLaunchKernelGGL(k_surface_big, dim3(blocks), dim3(64), 0, s, a);
+    const int blocks = std::max(1, std::min(1024, (a.cap + kGrpPerBlock - 1) / kGrpPerBlock));
+    hipLaunchKernelGGL(k_surface_big, dim3(blocks), dim3(kGrp * kGrpPerBlock), 0, s, a);
     return hipGetLastError();
 }
 
