@@ -31,9 +31,10 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 isoAdvector cell-steps/s + % HBM roofline; batched vs plain; adjoint/fwd ratio"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
+# sources of the kernels that the profiled commands launch (their meshes are hexahedra only, so the
+# polyhedron kernel of big.hip is not among them)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_01130_amd", "csrc", n) for n in ("kernels.hip", "device_common.h",
-                                                                                "internal.h", "gfm.hip", "relax.hip",
-                                                                                "big.hip")]
+                                                                                "internal.h", "gfm.hip", "relax.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 # FP64 operations credited per interface cell for vertex interpolation, the isovalue search, the
 # isoface and the swept-face integrals (a fixed per-unit figure, independent of the iteration
@@ -440,13 +441,15 @@ def poly_bench(steps, warmup):
     """The step on cells other than hexahedra: the violent 3D case's ingredients on 48x24x24
     hexahedra each cut into six tetrahedra (165,888 cells, steady flow), on 64x32x32 cut into
     prisms, and on 64x32x32 hexahedra mostly merged into polyhedra of 10 and 16 faces (26,112
-    cells, the one-thread-per-cell kernel); K steps from the sampled initial field, timed like the
-    main line."""
+    cells, the polyhedron kernel), also with the faces two polyhedra share joined into polygons of 6
+    and 8 points (the kernel's general face loops); K steps from the sampled initial field, timed
+    like the main line."""
     import torch
     import wavegen as W
     from paper_1804_01130_amd import Mesh, Plan, default_options
     out = {}
-    for kind, n in (("tet", (48, 24, 24)), ("prism", (64, 32, 32)), ("merged", (64, 32, 32))):
+    for kind, n in (("tet", (48, 24, 24)), ("prism", (64, 32, 32)), ("merged", (64, 32, 32)),
+                    ("merged_joined", (64, 32, 32))):
         t0 = time.time()
         w = W.poly_violent(kind, nx=n[0], ny=n[1], nz=n[2], steps=steps)
         gm = Mesh.from_arrays(w.mesh)

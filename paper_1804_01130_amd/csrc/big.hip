@@ -5,8 +5,10 @@
 //
 // Sixteen lanes per cell, one per face (the eight-lane kernel skips these cells).  The cell's
 // points, relative to their mean, and their vertex values sit in LDS, where every lane of the
-// group reads them; each lane keeps its face's loop of local point indices in registers.  The
-// construction is the eight-lane kernel's generic path:
+// group reads them; each lane keeps its face's loop of local point indices in registers, and,
+// when no face has more than four points, the face's points themselves and the reciprocal value
+// difference of each edge (the kFP = 4 instantiation: no LDS reads and no divisions in the
+// isovalue search).  The construction is the eight-lane kernel's generic path:
 //   vertex values through the inverse-distance stencils (two points per lane); the sorted values
 //   by rank; the isovalue bracketed between two consecutive sorted values (the limit from above
 //   at each) and found by Illinois with a bisection guard to round-off, or taken at a vertex value
@@ -34,14 +36,26 @@ struct Pt {
     double x, y, z, a;  // point relative to the cell's point mean, and its vertex value
 };
 
-// This lane's face: its loop of local point indices (byte i of the four words: position i).
+// This lane's face: its loop of local point indices (byte i of the four words: position i); for
+// faces of at most four points (kFP = 4) also the points and, for edge i (position i to i + 1),
+// 1 / (a_low - a_high) of its two vertex values (0 when they are equal).
+template <int kFP>
 struct FaceLoop {
     int n;  // points; 0 when the lane has no face
     int planar;
     uint32_t w[4];
+    Pt q[kFP <= 4 ? kFP : 1];
+    double r[kFP <= 4 ? kFP : 1];
 };
 
-__device__ __forceinline__ int loop_at(const FaceLoop &L, int i) { return (L.w[i >> 2] >> (8 * (i & 3))) & 0xff; }
+template <int kFP>
+__device__ __forceinline__ int loop_at(const FaceLoop<kFP> &L, int i) { return (L.w[i >> 2] >> (8 * (i & 3))) & 0xff; }
+
+template <int kFP>
+__device__ __forceinline__ Pt fetch(const Pt *P, const FaceLoop<kFP> &L, int i) {
+    if constexpr (kFP <= 4) return L.q[i];
+    else return P[loop_at(L, i)];
+}
 
 // Sum over the sixteen lanes of a group: the eight-lane butterfly, then the two halves of the row
 // swapped by mirroring (lane i <- lane 15 - i).
@@ -68,6 +82,15 @@ __device__ __forceinline__ D3 edge_cut(const Pt &w, const Pt &d, double iso) {
     return xyz(w) + lam * (xyz(d) - xyz(w));
 }
 
+// Cut point on edge i, from point pi to point pj, exactly one of them wet: from the wet end (the
+// one of higher value).
+template <int kFP>
+__device__ __forceinline__ D3 cut_at(const FaceLoop<kFP> &L, int i, const Pt &pi, const Pt &pj, bool wi, double iso) {
+    const Pt w = wi ? pi : pj, d = wi ? pj : pi;
+    if constexpr (kFP <= 4) return xyz(w) + ((iso - w.a) * L.r[i]) * (xyz(d) - xyz(w));
+    else return edge_cut(w, d, iso);
+}
+
 struct FacePart {
     double v6;
     D3 cseg, oacc;
@@ -84,25 +107,26 @@ __device__ __forceinline__ void iso_edge(FacePart &r, D3 s0, D3 s1) {
 // This lane's face share of six times the wet sub-volume and of the isoface sums.  An entry into
 // the wet part closes the isoface edge from the preceding exit; an entry before the loop's first
 // exit pairs with its last one.
-__device__ FacePart face_part(const Pt *P, const FaceLoop &L, double iso, bool tie_wet) {
+template <int kFP>
+__device__ FacePart face_part(const Pt *P, const FaceLoop<kFP> &L, double iso, bool tie_wet) {
     FacePart r{0.0, {0, 0, 0}, {0, 0, 0}, 0.0};
     if (L.n == 0) return r;
     D3 C{0, 0, 0}, pacc{0, 0, 0}, psum{0, 0, 0}, lastexit{0, 0, 0}, first_entry{0, 0, 0};
     double pl = 0.0;
     int cnt = 0;
     bool have_exit = false, pend = false;
-    const Pt p0 = P[loop_at(L, 0)];
+    const Pt p0 = fetch(P, L, 0);
     Pt pi = p0;
     bool wi = tie_wet ? p0.a >= iso : p0.a > iso;
 #pragma unroll
-    for (int i = 0; i < kBigFacePts; ++i) {
+    for (int i = 0; i < kFP; ++i) {
         if (i < L.n) {
             Pt pj = p0;
-            if (i + 1 < kBigFacePts && i + 1 < L.n) pj = P[loop_at(L, i + 1)];
+            if (i + 1 < kFP && i + 1 < L.n) pj = fetch(P, L, i + 1);
             const bool wj = tie_wet ? pj.a >= iso : pj.a > iso;
             const D3 xi = xyz(pi), xj = xyz(pj);
             D3 cut{0, 0, 0};
-            if (wi != wj) cut = wi ? edge_cut(pi, pj, iso) : edge_cut(pj, pi, iso);
+            if (wi != wj) cut = cut_at(L, i, pi, pj, wi, iso);
             if (!wi && wj) {
                 if (have_exit) iso_edge(r, cut, lastexit);
                 else { pend = true; first_entry = cut; }
@@ -138,7 +162,8 @@ __device__ FacePart face_part(const Pt *P, const FaceLoop &L, double iso, bool t
 
 // Six times the wet sub-volume of the cell at isovalue iso (every lane of the group calls it and
 // gets the same result), with the isoface's fan apex and area-vector sum.
-__device__ __forceinline__ double grp_vsub6(const Pt *P, const FaceLoop &L, double iso, bool tie_wet, D3 &o,
+template <int kFP>
+__device__ __forceinline__ double grp_vsub6(const Pt *P, const FaceLoop<kFP> &L, double iso, bool tie_wet, D3 &o,
                                             D3 &cseg) {
     const FacePart r = face_part(P, L, iso, tie_wet);
     const double v6 = g16(r.v6), oL = g16(r.oL);
@@ -150,13 +175,14 @@ __device__ __forceinline__ double grp_vsub6(const Pt *P, const FaceLoop &L, doub
 
 // This lane's share of the isoface centroid: the fan triangles (o, entry, preceding exit) of its
 // face's isoface edges, weighted by their area along n_S.
-__device__ void face_centre(const Pt *P, const FaceLoop &L, double iso, D3 o, D3 nS, D3 &acc, double &ws) {
+template <int kFP>
+__device__ void face_centre(const Pt *P, const FaceLoop<kFP> &L, double iso, D3 o, D3 nS, D3 &acc, double &ws) {
     acc = D3{0, 0, 0};
     ws = 0.0;
     if (L.n == 0) return;
     D3 lastexit{0, 0, 0}, first_entry{0, 0, 0};
     bool have_exit = false, pend = false;
-    const Pt p0 = P[loop_at(L, 0)];
+    const Pt p0 = fetch(P, L, 0);
     Pt pi = p0;
     bool wi = p0.a > iso;
     auto tri = [&](D3 s0, D3 s1) {
@@ -165,17 +191,17 @@ __device__ void face_centre(const Pt *P, const FaceLoop &L, double iso, D3 o, D3
         ws += wt;
     };
 #pragma unroll
-    for (int i = 0; i < kBigFacePts; ++i) {
+    for (int i = 0; i < kFP; ++i) {
         if (i < L.n) {
             Pt pj = p0;
-            if (i + 1 < kBigFacePts && i + 1 < L.n) pj = P[loop_at(L, i + 1)];
+            if (i + 1 < kFP && i + 1 < L.n) pj = fetch(P, L, i + 1);
             const bool wj = pj.a > iso;
             if (!wi && wj) {
-                const D3 cut = edge_cut(pj, pi, iso);
+                const D3 cut = cut_at(L, i, pi, pj, false, iso);
                 if (have_exit) tri(cut, lastexit);
                 else { pend = true; first_entry = cut; }
             }
-            if (wi && !wj) { lastexit = edge_cut(pi, pj, iso); have_exit = true; }
+            if (wi && !wj) { lastexit = cut_at(L, i, pi, pj, true, iso); have_exit = true; }
             pi = pj;
             wi = wj;
         }
@@ -185,21 +211,22 @@ __device__ void face_centre(const Pt *P, const FaceLoop &L, double iso, D3 o, D3
 
 // The swept integral over the step of this lane's face (Eqs. dV, alphaf): the face fanned about
 // its vertex mean, each triangle's submerged fraction integrated in time exactly.
-__device__ double face_sweep(const Pt *P, const FaceLoop &L, D3 xS, D3 nS, double un, double dt) {
+template <int kFP>
+__device__ double face_sweep(const Pt *P, const FaceLoop<kFP> &L, D3 xS, D3 nS, double un, double dt) {
     D3 ap{0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < kBigFacePts; ++i)
-        if (i < L.n) ap = ap + xyz(P[loop_at(L, i)]);
+    for (int i = 0; i < kFP; ++i)
+        if (i < L.n) ap = ap + xyz(fetch(P, L, i));
     ap = (1.0 / L.n) * ap;
     const double dap = dot(ap - xS, nS);
     double accI = 0.0, Af = 0.0;
-    const D3 x0 = xyz(P[loop_at(L, 0)]);
+    const D3 x0 = xyz(fetch(P, L, 0));
     D3 xi = x0;
 #pragma unroll
-    for (int i = 0; i < kBigFacePts; ++i) {
+    for (int i = 0; i < kFP; ++i) {
         if (i < L.n) {
             D3 xj = x0;
-            if (i + 1 < kBigFacePts && i + 1 < L.n) xj = xyz(P[loop_at(L, i + 1)]);
+            if (i + 1 < kFP && i + 1 < L.n) xj = xyz(fetch(P, L, i + 1));
             const double Ai = 0.5 * norm3(cross(xi - ap, xj - ap));
             accI += Ai * tri_sweep(dap, dot(xi - xS, nS), dot(xj - xS, nS), un, dt);
             Af += Ai;
@@ -209,6 +236,7 @@ __device__ double face_sweep(const Pt *P, const FaceLoop &L, D3 xS, D3 nS, doubl
     return accI / Af;
 }
 
+template <int kFP>
 __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) {
     __shared__ Pt spt[kGrpPerBlock][kBigPts];
     __shared__ double ssort[kGrpPerBlock][kBigPts];
@@ -271,14 +299,24 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
         }
         // this lane's face
         const int f0 = m.bf_ptr[bi], nf = m.bf_ptr[bi + 1] - f0;
-        FaceLoop L{0, 0, {0u, 0u, 0u, 0u}};
+        FaceLoop<kFP> L{};
         if (lf < nf) {
             const int b = m.bl_ptr[f0 + lf];
             L.n = m.bl_ptr[f0 + lf + 1] - b;
             L.planar = m.bf_planar[f0 + lf];
 #pragma unroll
-            for (int i = 0; i < kBigFacePts; ++i)
+            for (int i = 0; i < kFP; ++i)
                 if (i < L.n) L.w[i >> 2] |= (uint32_t)m.bl_vtx[b + i] << (8 * (i & 3));
+            if constexpr (kFP <= 4) {
+#pragma unroll
+                for (int i = 0; i < kFP; ++i)
+                    if (i < L.n) L.q[i] = P[loop_at(L, i)];
+#pragma unroll
+                for (int i = 0; i < kFP; ++i) {
+                    const double ai = L.q[i].a, aj = (i + 1 < L.n ? L.q[(i + 1) % kFP] : L.q[0]).a;
+                    L.r[i] = (i < L.n && ai != aj) ? 1.0 / (fmin(ai, aj) - fmax(ai, aj)) : 0.0;
+                }
+            }
         }
         grp_sync();
         bool recon = S[nv - 1] - S[0] > A.flat_tol;
@@ -398,7 +436,10 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
 
 hipError_t launch_surface_big(const BigArgs &a, hipStream_t s) {
     const int blocks = std::max(1, std::min(1024, (a.cap + kGrpPerBlock - 1) / kGrpPerBlock));
-    hipLaunchKernelGGL(k_surface_big, dim3(blocks), dim3(kGrp * kGrpPerBlock), 0, s, a);
+    if (a.m.big_face_pts <= 4)
+        hipLaunchKernelGGL(k_surface_big<4>, dim3(blocks), dim3(kGrp * kGrpPerBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_surface_big<kBigFacePts>, dim3(blocks), dim3(kGrp * kGrpPerBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct DevMesh {
     const int32_t *bf_planar = nullptr;  //   1 if planar
     const int32_t *bl_ptr = nullptr;     // [faces+1] loop positions of each face
     const int32_t *bl_vtx = nullptr;     //   local point at each loop position, outward
+    int32_t big_face_pts = 0;            // most points of a face of any of them
     // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;

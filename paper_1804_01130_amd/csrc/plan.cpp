@@ -673,6 +673,8 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     // general polyhedra on the device: point classes and coordinates, each face's packed flux face,
     // planarity (every point within 1e-12 of the face size of the mean plane, normal by Newell)
     const bool any_big = bv_ptr.size() > 1;
+    int32_t big_face_pts = 0;
+    for (size_t k = 0; k + 1 < bl_ptr.size(); ++k) big_face_pts = std::max(big_face_pts, bl_ptr[k + 1] - bl_ptr[k]);
     std::vector<int32_t> bv_cls(bv_pts.size()), bf_face(bf_fid.size(), kEmpty), bf_planar(bf_fid.size(), 0);
     std::vector<double> bv_xyz(3 * bv_pts.size());
     for (size_t i = 0; i < bv_pts.size(); ++i) {
@@ -714,6 +716,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     if (hipGetDevice(&m->device) != hipSuccess) { iso_mesh_destroy(m); return fail(ISO_EDEVICE, "no HIP device"); }
     DevMesh &d = m->dev;
     d.n_cells = n_cells; d.n_faces = n_faces; d.n_classes = n_classes; d.W = W; d.n_patches = n_patches;
+    d.big_face_pts = big_face_pts;
     d.n_internal = n_internal;
     iso_status st = ISO_OK;
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||

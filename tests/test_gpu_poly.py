@@ -1,6 +1,7 @@
 """Cells other than hexahedra on the GPU: tetrahedra, square pyramids, triangular prisms,
 hexahedra next to prisms in one mesh, and polyhedra of merged hexahedra (10 or 16 faces, 12 or 18
-points, split faces) among hexahedra, against the oracle.  Same seeded inputs on both sides (the
+points, split faces; or the faces two of them share joined into polygons of 6 and 8 points) among
+hexahedra, against the oracle.  Same seeded inputs on both sides (the
 workloads of wavegen.poly); |delta alpha| <= 1e-10 after the whole run, per-face dV of one traced
 step within 1e-13 of max|phi| dt, interface cells the same on both sides.
 """
@@ -28,6 +29,9 @@ def _cases():
         # general polyhedra: the one-thread-per-cell kernel, flat and bent faces
         "merged_16x8x8": W.poly_violent("merged", nx=16, ny=8, nz=8, steps=8),
         "merged_perturbed_16x8x8": W.poly_violent("merged", nx=16, ny=8, nz=8, steps=8, perturb=0.1),
+        # faces of 6 and 8 points: the kernel's general face loops
+        "merged_joined_16x8x8": W.poly_violent("merged_joined", nx=16, ny=8, nz=8, steps=8),
+        "merged_joined_perturbed_16x8x8": W.poly_violent("merged_joined", nx=16, ny=8, nz=8, steps=8, perturb=0.1),
     }
 
 
@@ -66,7 +70,8 @@ def test_trajectory_matches_oracle(oracle_lib, name):
 
 
 @pytest.mark.parametrize("name", ["tet_12x6x6", "pyramid_8x4x4", "mixed_16x8x8", "merged_16x8x8",
-                                  "merged_perturbed_16x8x8"])
+                                  "merged_perturbed_16x8x8", "merged_joined_16x8x8",
+                                  "merged_joined_perturbed_16x8x8"])
 def test_traced_step_matches_oracle(oracle_lib, name):
     w = CASES[name]
     phi, U = w.phi_U(0)
@@ -85,7 +90,8 @@ def test_traced_step_matches_oracle(oracle_lib, name):
     assert np.abs(out - o_new).max() <= 1e-13
 
 
-@pytest.mark.parametrize("kind,seed", [("tet", 61), ("tet", 62), ("merged", 63), ("merged", 64)])
+@pytest.mark.parametrize("kind,seed", [("tet", 61), ("tet", 62), ("merged", 63), ("merged", 64),
+                                       ("merged_joined", 65)])
 def test_random_fields(oracle_lib, kind, seed):
     """alpha ~ U[0.02, 0.98] per cell: every cell an interface cell, arbitrary vertex patterns on
     triangular faces and on the many faces of the merged polyhedra."""
@@ -100,7 +106,7 @@ def test_random_fields(oracle_lib, kind, seed):
     assert err <= TOL
 
 
-@pytest.mark.parametrize("name", ["mixed_16x8x8", "merged_16x8x8"])
+@pytest.mark.parametrize("name", ["mixed_16x8x8", "merged_16x8x8", "merged_joined_16x8x8"])
 def test_launch_shapes_give_the_same_bits(name):
     w = CASES[name]
     ref = None

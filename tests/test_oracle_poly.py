@@ -1,5 +1,6 @@
 """Pins of the oracle on tetrahedra, triangular prisms, square pyramids and polyhedra made of merged
-hexahedra (split faces, up to 18 points and 16 faces), against what elementary geometry and the
+hexahedra (split faces, up to 18 points and 16 faces, or the shared faces joined into polygons of 6
+and 8 points), against what elementary geometry and the
 method's invariants fix:
 
 * linear vertex data cut at an isovalue is exactly a plane clip of the cell (convex hull of the
@@ -38,8 +39,17 @@ def merged_xy(xs, ys, zs, **kw):
                                                 for i in range(0, nx - 1, 2)], **kw)
 
 
+def merged_joined(xs, ys, zs, **kw):
+    """Pairs along x merged in every row, the two quadrilaterals that neighbouring pairs share
+    joined into one face of 6 points: 12 points and 9 faces per cell."""
+    xs, ys = _refined(xs), _refined(ys)
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    return W.merged_block(xs, ys, zs, merge_x=[(i, j, k) for k in range(nz) for j in range(ny)
+                                              for i in range(0, nx - 1, 2)], join=True, **kw)
+
+
 BUILDERS = {"tet": W.tet_block, "prism": W.prism_block, "pyramid": W.pyramid_block, "merged_x": merged_x,
-            "merged_xy": merged_xy}
+            "merged_xy": merged_xy, "merged_joined": merged_joined}
 
 
 def _cell_faces(mesh, c):
@@ -115,6 +125,7 @@ def test_isoface_of_linear_data(oracle_lib, kind):
 def _workloads():
     return [W.poly_violent("tet", nx=8, ny=4, nz=4, steps=6), W.poly_violent("prism", nx=8, ny=4, nz=4, steps=6),
             W.poly_violent("merged", nx=16, ny=8, nz=8, steps=6),
+            W.poly_violent("merged_joined", nx=16, ny=8, nz=8, steps=6),
             W.poly_airy("prism", 32, 16, steps=6), W.poly_airy("tet", 24, 12, steps=6)]
 
 
@@ -147,7 +158,7 @@ def test_conservation_and_bounds(oracle_lib):
             assert a.min() >= 0.0 and a.max() <= 1.0
 
 
-@pytest.mark.parametrize("kind", ["tet", "prism", "pyramid", "merged_x"])
+@pytest.mark.parametrize("kind", ["tet", "prism", "pyramid", "merged_x", "merged_joined"])
 def test_surface_face_fluxes_brute_force(oracle_lib, kind):
     """A smooth field on a 3x3x3 block of cells of one kind: every flux of an interface cell equals
     phi times the exact space-time integral of the submerged part of the face (each face fanned

@@ -184,11 +184,38 @@ def mixed_block(xs, ys, zs, split_from, kinds=None, periodic_x=False, periodic_y
     return mesh_from_cells(_grid_points(xs, ys, zs), cells, xs, ys, zs, kinds, periodic_x, periodic_y)
 
 
-def merged_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False, merge_x=(), merge_xy=()):
+def _join_loop(quads):
+    """One polygon from faces that tile it, all oriented alike: the edges they share cancel, the
+    rest is walked from the smallest point id."""
+    edges = set()
+    for q in quads:
+        for a in range(len(q)):
+            e = (q[a], q[(a + 1) % len(q)])
+            if (e[1], e[0]) in edges:
+                edges.remove((e[1], e[0]))
+            else:
+                edges.add(e)
+    nxt = dict(edges)
+    if len(nxt) != len(edges):
+        raise ValueError("the joined faces do not bound one polygon")
+    start = min(nxt)
+    loop = [start]
+    p = nxt[start]
+    while p != start:
+        loop.append(p)
+        p = nxt[p]
+    if len(loop) != len(edges):
+        raise ValueError("the joined faces do not bound one polygon")
+    return tuple(loop)
+
+
+def merged_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False, merge_x=(), merge_xy=(), join=False):
     """Hexahedra, some of them merged into polyhedra whose sides are split faces: each (i, j, k) in
     merge_x joins hexahedra (i, j, k) and (i+1, j, k) into one cell of 12 points and 10
     quadrilateral faces; each (i, j, k) in merge_xy joins the 2 x 2 hexahedra from (i, j, k) into
-    one cell of 18 points and 16 faces.  The neighbours keep their faces, so the mesh conforms."""
+    one cell of 18 points and 16 faces.  The neighbours keep their faces, so the mesh conforms.
+    With join, the quadrilaterals that two merged cells share become one polygon (6 points for two
+    of them, 8 for a 2 x 2 patch, whose middle point then belongs to no face)."""
     xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
     nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
 
@@ -229,6 +256,22 @@ def merged_block(xs, ys, zs, kinds=None, periodic_x=False, periodic_y=False, mer
                     cells.append(list(faces.values()))
                 else:
                     cells.append(_hex_quads(P, i, j, k))
+    if join:
+        where = {}
+        for c, faces in enumerate(cells):
+            for q in faces:
+                where.setdefault(tuple(sorted(q)), []).append(c)
+        for c, faces in enumerate(cells):
+            by_nbr, keep = {}, []
+            for q in faces:
+                cs = where[tuple(sorted(q))]
+                if len(cs) == 2:
+                    by_nbr.setdefault(cs[0] if cs[1] == c else cs[1], []).append(q)
+                else:
+                    keep.append(q)
+            for qs in by_nbr.values():
+                keep += [_join_loop(qs)] if len(qs) > 1 else qs
+            cells[c] = keep
     return mesh_from_cells(_grid_points(xs, ys, zs), cells, xs, ys, zs, kinds, periodic_x, periodic_y)
 
 
@@ -398,8 +441,8 @@ class PolyWorkload:
 
 
 def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5, perturb=0.0, seed=4):
-    """The violent 3D workload's ingredients on tetrahedra, prisms, pyramids, or hexahedra and prisms
-    side by side ("mixed"), with the interior points optionally moved at random: the box [0,2]x[0,1]x[0,1],
+    """The violent 3D workload's ingredients on tetrahedra, prisms, pyramids, hexahedra and prisms
+    side by side ("mixed"), or hexahedra among merged polyhedra ("merged", "merged_joined"), with the interior points optionally moved at random: the box [0,2]x[0,1]x[0,1],
     periodic in x, a water column {x < 0.3, z < 0.6} joined to a wavy layer
     {z < 0.45 + 0.02 cos 4 pi x cos 4 pi y}, and the uniform + Taylor-Green flow (its fluxes from the
     vector potential along the straight edges)."""
@@ -407,11 +450,12 @@ def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5, perturb=0.0, se
     xs, ys, zs = np.linspace(0, 2, nx + 1), np.linspace(0, 1, ny + 1), np.linspace(0, 1, nz + 1)
     if kind == "mixed":
         mesh = mixed_block(xs, ys, zs, nx // 2, periodic_x=True)
-    elif kind == "merged":
-        # polyhedra: pairs along x in every fourth column, 2 x 2 blocks in another
+    elif kind in ("merged", "merged_joined"):
+        # polyhedra: pairs along x in every fourth column, 2 x 2 blocks in another; "merged_joined"
+        # makes the faces two of them share one polygon of 6 or 8 points
         mx = [(i, j, k) for k in range(nz) for j in range(ny) for i in range(1, nx - 1, 4)]
         mxy = [(i, j, k) for k in range(nz) for j in range(0, ny - 1, 2) for i in range(3, nx - 1, 4)]
-        mesh = merged_block(xs, ys, zs, periodic_x=True, merge_x=mx, merge_xy=mxy)
+        mesh = merged_block(xs, ys, zs, periodic_x=True, merge_x=mx, merge_xy=mxy, join=kind == "merged_joined")
     else:
         build = {"tet": tet_block, "prism": prism_block, "pyramid": pyramid_block}[kind]
         mesh = build(xs, ys, zs, periodic_x=True)
