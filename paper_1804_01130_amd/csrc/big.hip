@@ -97,9 +97,17 @@ struct FacePart {
     double oL;
 };
 
+// s0 x s1 rounded without contraction, so that s1 x s0 is its exact negative: when the wet part
+// around a point with only two edges in the cell is a sliver, the two faces at the point add
+// opposite isoface edges, which then cancel to an exact zero area (no isoface, a flat cell).
+__device__ __forceinline__ D3 cross_antisym(D3 a, D3 b) {
+#pragma clang fp contract(off)
+    return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
 __device__ __forceinline__ void iso_edge(FacePart &r, D3 s0, D3 s1) {
     const double l = norm3(s1 - s0);
-    r.cseg = r.cseg + cross(s0, s1);
+    r.cseg = r.cseg + cross_antisym(s0, s1);
     r.oacc = r.oacc + (0.5 * l) * (s0 + s1);
     r.oL += l;
 }
