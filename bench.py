@@ -54,6 +54,10 @@ PROFILE_COMMANDS = {
     "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
              "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} "
              "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-poly --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
+    "sq": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
+          "SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU -T -f csv -d /root/repo/gpurun_out/prof_sq "
+          "-o run -- python3 /root/repo/bench.py --workload {w} --steps 3 --warmup 1 --no-cpu-baseline --no-ensemble "
+          "--no-adjoint --no-variants --no-poly > /root/repo/gpurun_out/prof_sq/bench.json",
 }
 
 
@@ -241,6 +245,34 @@ def summarize_profiles(workload):
         lines += [f"{k}.dispatches: {len(fetch[k])}", f"{k}.fetch_kib: {fk:.1f}", f"{k}.write_kib: {wk:.1f}",
                   f"{k}.bytes_per_launch: {fk * 1024.0 * sf + wk * 1024.0 * sw:.0f}"]
     open(traffic_path(workload), "w").write("\n".join(lines) + "\n")
+
+    # instruction mix per wave from the SQ counter pass (when it was taken)
+    sq_dir = os.path.join(ROOT, "gpurun_out/prof_sq")
+    if os.path.isdir(sq_dir):
+        sq_sha = json.loads(open(os.path.join(sq_dir, "bench.json")).read())["kernel_source_sha"]
+        per = {}
+        for r in csv.DictReader(open(_find("gpurun_out/prof_sq", "counter_collection.csv"))):
+            k = _kernel_key(r["Kernel_Name"])
+            if k is not None:
+                did = r.get("Dispatch_Id", r.get("Correlation_Id"))
+                d = per.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+                d[did] = d.get(did, 0.0) + float(r["Counter_Value"])
+        lines = [f"# SQ instruction counters per dispatch (mean over dispatches), workload {workload}",
+                 f"# command (repository root): {cmds['sq']}",
+                 f"# kernel_source_sha: {sq_sha}",
+                 "# per-wave figures divide by SQ_WAVES; SQ_BUSY_CYCLES is summed over the shader engines",
+                 "# kernel | dispatches | waves | VALU/wave | SALU/wave | VMEM_RD/wave | LDS/wave | WAVE_CYCLES/wave | "
+                 "VALU instructions"]
+        for k in ("surface", "update", "find_surface", "bound_sweep", "bound_end", "gfm_faces", "relax_blend"):
+            if k not in per:
+                continue
+            mean = {n: sum(v.values()) / max(len(v), 1) for n, v in per[k].items()}
+            nd = len(per[k]["SQ_WAVES"])
+            wv = mean["SQ_WAVES"]
+            lines.append(f"k_{k} | {nd} | {wv:.0f} | {mean['SQ_INSTS_VALU'] / wv:.0f} | {mean['SQ_INSTS_SALU'] / wv:.0f} | "
+                         f"{mean['SQ_INSTS_VMEM_RD'] / wv:.1f} | {mean['SQ_INSTS_LDS'] / wv:.1f} | "
+                         f"{mean['SQ_WAVE_CYCLES'] / wv:.0f} | {mean['SQ_INSTS_VALU']:.4g}")
+        open(os.path.join(PROFILES, f"sq_counters_{workload}.txt"), "w").write("\n".join(lines) + "\n")
     log(f"[bench] wrote profiles for {workload}")
 
 

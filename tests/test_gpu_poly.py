@@ -185,3 +185,32 @@ def test_one_block_of_cells(oracle_lib, build):
     err = np.abs(a.cpu().numpy() - o).max()
     say(f"[gpu] one block of {build} cells: max |gpu - oracle| = {err:.3e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("name", ["prism_16x8x8", "merged_16x8x8", "merged_joined_perturbed_16x8x8"])
+def test_averaged_fields_on_other_cells(oracle_lib, name):
+    """The step with a second time level of the fields (phi1 = 0.7 phi, U1 = 0.7 U + a seeded
+    perturbation) is bit for bit the step with the averaged fields, on the eight-lane and the
+    polyhedron kernels, and its trajectory matches the oracle fed the averages."""
+    import torch
+    w = CASES[name]
+    phi, U = w.phi_U(0)
+    phi1 = 0.7 * phi
+    U1 = 0.7 * U + np.random.default_rng(81).uniform(-0.05, 0.05, U.shape)
+    say(f"[gpu] averaged fields on {name}")
+    gm, plan = gpu_plan(w.mesh)
+    a = to_dev(w.alpha0)
+    b, c = torch.empty_like(a), torch.empty_like(a)
+    tp, tu, tp1, tu1 = to_dev(phi), to_dev(U), to_dev(phi1), to_dev(U1)
+    tpa, tua = to_dev(0.5 * (phi + phi1)), to_dev(0.5 * (U + U1))
+    for n in range(6):
+        plan.step(a, tp, tu, w.dt, out=b, phi1=tp1, U1=tu1)
+        plan.step(a, tpa, tua, w.dt, out=c)
+        torch.cuda.synchronize()
+        assert torch.equal(b, c), n
+        a, b = b, a
+    om = oracle_lib.OracleMesh(w.mesh)
+    o = om.run(np.array(w.alpha0, copy=True), 0.5 * (phi + phi1), 0.5 * (U + U1), w.dt, 6)
+    err = np.abs(a.cpu().numpy() - o).max()
+    say(f"[gpu]   max |gpu - oracle| = {err:.3e}")
+    assert err <= TOL
