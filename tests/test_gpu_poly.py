@@ -159,16 +159,31 @@ def test_ghost_fluid_faces_and_relaxation_on_prisms(oracle_lib):
     assert np.abs(x.cpu().numpy() - om.relax_blend(zones, a, w.alpha0)).max() <= 1e-13
 
 
-@pytest.mark.parametrize("build", ["tet", "pyramid", "prism"])
+def _merged_pair(xs, ys, zs, **kw):
+    """2 x 2 x 1 hexahedra merged along x into two cells of 12 points that share one face of 6
+    points; every other face on the boundary."""
+    xs, ys = [xs[0], 0.5 * (xs[0] + xs[1]), xs[1]], [ys[0], 0.5 * (ys[0] + ys[1]), ys[1]]
+    return W.merged_block(xs, ys, zs, merge_x=[(0, 0, 0), (0, 1, 0)], join=True, **kw)
+
+
+def _merged_one(xs, ys, zs, **kw):
+    """2 x 2 x 1 hexahedra merged into one cell of 18 points and 16 faces, all on the boundary."""
+    xs, ys = [xs[0], 0.5 * (xs[0] + xs[1]), xs[1]], [ys[0], 0.5 * (ys[0] + ys[1]), ys[1]]
+    return W.merged_block(xs, ys, zs, merge_xy=[(0, 0, 0)], **kw)
+
+
+@pytest.mark.parametrize("build", ["tet", "pyramid", "prism", "merged_pair", "merged_one"])
 def test_one_block_of_cells(oracle_lib, build):
     """The smallest meshes: one hexahedron's worth of tetrahedra, pyramids or prisms (6, 6 and 2
-    cells, every cell touching the boundary), a steep field and a uniform flow, 4 steps."""
-    b = {"tet": W.tet_block, "pyramid": W.pyramid_block, "prism": W.prism_block}[build]
+    cells), two polyhedra sharing one joined face, or one polyhedron alone; every cell touches the
+    boundary; a steep field and a uniform flow, 4 steps."""
+    b = {"tet": W.tet_block, "pyramid": W.pyramid_block, "prism": W.prism_block, "merged_pair": _merged_pair,
+         "merged_one": _merged_one}[build]
     mesh = b([0.0, 1.0], [0.0, 1.0], [0.0, 1.0], kinds={"xmin": W.PATCH_INOUT, "xmax": W.PATCH_INOUT},
              periodic_x=False)
     om = oracle_lib.OracleMesh(mesh)
     xc, V = om.geometry()
-    a0 = np.clip(0.5 + 1.5 * (0.45 - xc[:, 2] + 0.3 * (xc[:, 0] - 0.5)), 0.0, 1.0)
+    a0 = np.clip(0.5 + 1.5 * (0.45 - xc[:, 2] + 0.3 * (xc[:, 0] - 0.5) + 0.4 * (xc[:, 1] - 0.5)), 0.0, 1.0)
     phi = W.fluxes_from_potential(mesh, lambda x, y, z: 0.3 * y * np.ones_like(z))
     U = np.concatenate([np.full(mesh.n_cells, 0.3), np.zeros(mesh.n_cells), np.zeros(mesh.n_cells)])
     dt = 0.2
