@@ -11,8 +11,9 @@
 // isovalue search).  The construction is the eight-lane kernel's generic path:
 //   vertex values through the inverse-distance stencils (two points per lane); the sorted values
 //   by rank; the isovalue bracketed between two consecutive sorted values (the limit from above
-//   at each) and found by Illinois with a bisection guard to round-off, or taken at a vertex value
-//   where the sub-volume jumps; the sub-volume by the divergence theorem, each lane's wet loop
+//   at each), then found by Newton on the bracket's functional form when every face is planar,
+//   by Illinois with a bisection guard otherwise, to round-off, or taken at a vertex value where
+//   the sub-volume jumps; the sub-volume by the divergence theorem, each lane's wet loop
 //   fanned about a face point (planar faces) or its perimeter centroid, the isoface fanned about
 //   the perimeter centroid of its edges; the isoface's normal, centre and U_P . n_S; and each
 //   lane's swept integral of its face, over the triangles that fan it about its vertex mean.
@@ -181,6 +182,81 @@ __device__ __forceinline__ double grp_vsub6(const Pt *P, const FaceLoop<kFP> &L,
     return v6 + dot(o, cseg);
 }
 
+// Inside a bracket (xr, xr + uhi) between consecutive vertex values the wet pattern is fixed
+// (wet: a > xr) and every cut point moves linearly with u = iso - xr.  On a planar face the
+// lane's share of six times the sub-volume is ap . C(u), a quadratic, and the isoface adds
+// o(u) . B(u) with B the sum of its edges' s x e; the lane returns its share of the value and
+// of the derivative in u of each sum, for Newton's method on the group totals.
+struct IntervalPart {
+    double v, dv;      // ap . C(u) and its derivative
+    D3 B, dB;          // this face's isoface edges: sum s x e, and its derivative
+    D3 oacc, doacc;    // their length x midpoint, and its derivative
+    double oL, doL;    // their length, and its derivative
+};
+
+template <int kFP>
+__device__ IntervalPart face_interval(const Pt *P, const FaceLoop<kFP> &L, double xr, double u) {
+    IntervalPart r{0.0, 0.0, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, 0.0, 0.0};
+    if (L.n == 0) return r;
+    const double iso = xr + u;
+    const D3 Z{0, 0, 0};
+    D3 C = Z, dC = Z, le0 = Z, le1 = Z, fe0 = Z, fe1 = Z;
+    int cnt = 0;
+    bool have_exit = false, pend = false;
+    auto seg = [&](D3 s0, D3 s1, D3 e0, D3 e1) {
+        const D3 d = e0 - s0, dd = e1 - s1;
+        const double l = norm3(d);
+        const double dl = l > 0.0 ? dot(d, dd) / l : 0.0;
+        r.B = r.B + cross_antisym(s0, e0);
+        r.dB = r.dB + cross(s1, e0) + cross(s0, e1);
+        r.oacc = r.oacc + (0.5 * l) * (s0 + e0);
+        r.doacc = r.doacc + (0.5 * dl) * (s0 + e0) + (0.5 * l) * (s1 + e1);
+        r.oL += l;
+        r.doL += dl;
+    };
+    const Pt p0 = fetch(P, L, 0);
+    Pt pi = p0;
+    bool wi = p0.a > xr;
+#pragma unroll
+    for (int i = 0; i < kFP; ++i) {
+        if (i < L.n) {
+            Pt pj = p0;
+            if (i + 1 < kFP && i + 1 < L.n) pj = fetch(P, L, i + 1);
+            const bool wj = pj.a > xr;
+            const D3 xi = xyz(pi), xj = xyz(pj);
+            D3 c0 = Z, c1 = Z;
+            if (wi != wj) {
+                const Pt w = wi ? pi : pj, d = wi ? pj : pi;
+                double rr;
+                if constexpr (kFP <= 4) rr = L.r[i];
+                else rr = 1.0 / (d.a - w.a);
+                c0 = xyz(w) + ((iso - w.a) * rr) * (xyz(d) - xyz(w));
+                c1 = rr * (xyz(d) - xyz(w));
+            }
+            if (!wi && wj) {
+                if (have_exit) seg(c0, c1, le0, le1);
+                else { pend = true; fe0 = c0; fe1 = c1; }
+            }
+            if (wi && !wj) { le0 = c0; le1 = c1; have_exit = true; }
+            if (wi || wj) {
+                const D3 U0 = wi ? xi : c0, U1 = wi ? Z : c1, V0 = wj ? xj : c0, V1 = wj ? Z : c1;
+                C = C + cross(U0, V0);
+                dC = dC + cross(U1, V0) + cross(U0, V1);
+            }
+            cnt += (wi ? 1 : 0) + (wi != wj ? 1 : 0);
+            pi = pj;
+            wi = wj;
+        }
+    }
+    if (pend) seg(fe0, fe1, le0, le1);
+    if (cnt >= 3) {
+        const D3 ap = xyz(p0);
+        r.v = dot(ap, C - r.B);
+        r.dv = dot(ap, dC - r.dB);
+    }
+    return r;
+}
+
 // This lane's share of the isoface centroid: the fan triangles (o, entry, preceding exit) of its
 // face's isoface edges, weighted by their area along n_S.
 template <int kFP>
@@ -327,6 +403,9 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
             }
         }
         grp_sync();
+        // every face planar: the bracket's Newton solve
+        const uint64_t pb = __ballot(L.n == 0 || L.planar != 0);
+        const bool planar_cell = ((pb >> (__lane_id() & ~(kGrp - 1))) & 0xFFFFull) == 0xFFFFull;
         bool recon = S[nv - 1] - S[0] > A.flat_tol;
         double iso = 0.0;
         int rounds = 0;
@@ -352,6 +431,58 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
                 ++rounds;
                 if (f1 > 0.0) {
                     iso = x1;  // the sub-volume jumps across alpha_P at this vertex value
+                } else if (planar_cell) {
+                    // Newton on the bracket's functional form (safeguarded by the bracket, a
+                    // power-law step when Newton leaves it, stopped at round-off or when the
+                    // change of slope shows the next step below it)
+                    const double xr = x0, uhi = x1 - x0, target = aP * V6;
+                    auto G = [&](double u, double &dG) {
+                        const IntervalPart q = face_interval(P, L, xr, u);
+                        const D3 oacc = g16_3(q.oacc), doacc = g16_3(q.doacc), Bs = g16_3(q.B), dBs = g16_3(q.dB);
+                        const double oL = g16(q.oL), doL = g16(q.doL), v = g16(q.v), dv = g16(q.dv);
+                        D3 oo{0, 0, 0}, od{0, 0, 0};
+                        if (oL > 0.0) {
+                            const double il = 1.0 / oL;
+                            oo = il * oacc;
+                            od = il * (doacc - doL * oo);
+                        }
+                        dG = dv + dot(od, Bs) + dot(oo, dBs);
+                        return v + dot(oo, Bs) - target;
+                    };
+                    double ua = 0.0, ub = uhi, ga = f0v * V6, gb = f1 * V6;
+                    double u = ua + (ub - ua) * (ga / (ga - gb));  // secant start
+                    double up = uhi, dGp = 0.0;
+                    bool conv = false, first = true;
+                    for (; rounds < A.max_rounds; ++rounds) {
+                        double dG;
+                        const double g = G(u, dG);
+                        if (g == 0.0) { conv = true; ++rounds; break; }
+                        if (g > 0.0) { ua = u; ga = g; } else { ub = u; gb = g; }
+                        double nu = dG < 0.0 ? u - g / dG : ua;
+                        const bool newton = nu > ua && nu < ub;
+                        if (!newton) {
+                            const bool left = ga <= -gb;
+                            const double wd = (ub - ua) * cbrt((left ? ga : -gb) / (ga - gb));
+                            nu = left ? ua + wd : ub - wd;
+                            if (!(nu > ua && nu < ub)) nu = 0.5 * (ua + ub);
+                        }
+                        const double tolu = 2.0 * __DBL_EPSILON__ * fmax(fabs(xr + nu), 1e-300);
+                        const double st = nu - u;
+                        bool done = fabs(st) <= tolu;
+                        if (newton && !done && !first && fabs(st) <= 1e-3 * uhi)
+                            done = fabs(dG - dGp) * st * st <= 0.25 * tolu * fabs(dG) * fabs(u - up);
+                        up = u;
+                        dGp = dG;
+                        u = nu;
+                        first = false;
+                        if (done || !(ub - ua > 2.0 * __DBL_EPSILON__ * fmax(fabs(xr + ua), fabs(xr + ub)))) {
+                            conv = true;
+                            ++rounds;
+                            break;
+                        }
+                    }
+                    if (!conv) ++nonconv;
+                    iso = xr + u;
                 } else {
                     int side = 0;
                     bool conv = false;
