@@ -352,6 +352,7 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
                 xp[h] = D3{q[0], q[1], q[2]};
                 const int k = m.bv_cls[v0 + i];
                 double av = 0.0;
+#pragma unroll 4
                 for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e) av += m.st_w[e] * A.alpha[m.st_cell[e]];
                 ap[h] = av;
                 xs = xs + xp[h];

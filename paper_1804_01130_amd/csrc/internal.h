@@ -75,6 +75,11 @@ struct DevWork {
     double *dvcur = nullptr;       // [n_faces] current dV of faces in flist
     double *red = nullptr;         // [64] reductions for stats
     int32_t cap = 0;
+    // meshes with general polyhedra: a second stream (default priority) for their interface
+    // kernel, forked once the interface list is built and joined before the update, so that it
+    // runs beside the eight-lane kernel
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 enum : int {

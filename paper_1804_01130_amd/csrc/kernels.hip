@@ -1225,6 +1225,19 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
     // persistent: groups loop over the list, which is only known on the device
     gs = std::max(1L, std::min(gs, cfg.surface_blocks > 0 ? (long)cfg.surface_blocks : 2048L));
+    if (m.cbig) {  // general polyhedra: their kernel on the side stream, beside the eight-lane one
+        hipStream_t sb = s;
+        if (w.side) {
+            hipError_t e = hipEventRecord(w.fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(w.side, w.fork, 0);
+            if (e != hipSuccess) return e;
+            sb = w.side;
+        }
+        BigArgs bg{m, a.alpha, a.phi, a.U, a.phi1, a.U1, a.dt, p.flat_tol, p.root_max_iter, w.surf, w.counters,
+                   w.cap, w.dvs, want_stats ? 1 : 0, tr};
+        const hipError_t e = launch_surface_big(bg, sb);
+        if (e != hipSuccess) return e;
+    }
     if (m.cloop) {
         switch (cfg.surface_waves) {
             case 1: hipLaunchKernelGGL((k_surface<1, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
@@ -1247,10 +1260,9 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
             default: hipLaunchKernelGGL((k_surface<2, false, false>), dim3((int)gs), dim3(bs), 0, s, sa); break;
         }
     }
-    if (m.cbig) {
-        BigArgs bg{m, a.alpha, a.phi, a.U, a.phi1, a.U1, a.dt, p.flat_tol, p.root_max_iter, w.surf, w.counters,
-                   w.cap, w.dvs, want_stats ? 1 : 0, tr};
-        const hipError_t e = launch_surface_big(bg, s);
+    if (m.cbig && w.side) {
+        hipError_t e = hipEventRecord(w.join, w.side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, w.join, 0);
         if (e != hipSuccess) return e;
     }
     if (ev) (void)hipEventRecord(ev[2], s);

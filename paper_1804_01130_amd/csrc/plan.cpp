@@ -760,6 +760,12 @@ iso_status iso_mesh_geometry(const iso_mesh *m, double *vol, double *xc) {
 void iso_plan_destroy(iso_plan *p) {
     if (!p) return;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->work.side) {
+        (void)hipStreamSynchronize(p->work.side);
+        (void)hipStreamDestroy(p->work.side);
+    }
+    if (p->work.fork) (void)hipEventDestroy(p->work.fork);
+    if (p->work.join) (void)hipEventDestroy(p->work.join);
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     for (void *a : p->allocations) (void)hipFree(a);
     if (p->rz_cell) (void)hipFree(p->rz_cell);
@@ -806,6 +812,12 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
         hipHostMalloc((void **)&p->host_red, 64 * sizeof(double)) != hipSuccess) {
         iso_plan_destroy(p);
         return fail(ISO_ENOMEM, "plan workspace allocation failed");
+    }
+    if (mesh->dev.cbig && (hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking) != hipSuccess ||
+                           hipEventCreateWithFlags(&w.fork, hipEventDisableTiming) != hipSuccess ||
+                           hipEventCreateWithFlags(&w.join, hipEventDisableTiming) != hipSuccess)) {
+        iso_plan_destroy(p);
+        return fail(ISO_EDEVICE, "side stream creation failed");
     }
     if (hipDeviceSynchronize() != hipSuccess) { iso_plan_destroy(p); return fail(ISO_EDEVICE, "device error at plan creation"); }
     *out = p;
