@@ -54,6 +54,7 @@ struct DevMesh {
     const int32_t *bl_ptr = nullptr;     // [faces+1] loop positions of each face
     const int32_t *bl_vtx = nullptr;     //   local point at each loop position, outward
     int32_t big_face_pts = 0;            // most points of a face of any of them
+    int32_t all_big = 0;                 // 1: every cell is taken as one of them (mostly polyhedra)
     // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;
@@ -168,7 +169,7 @@ hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_
 // adjoint.hip
 hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, const AdjInputs &in, const AdjWork &w,
                           hipStream_t s);
-// General polyhedra: limits of the one-thread-per-cell interface kernel (big.hip).
+// General polyhedra: limits of their sixteen-lanes-per-cell interface kernel (big.hip).
 constexpr int kBigPts = 32, kBigFaces = 16, kBigFacePts = 16;
 struct BigArgs {
     DevMesh m;

@@ -10,7 +10,8 @@
 //                  (one isoface edge per lane), Illinois otherwise.  It builds the isoface, and
 //                  lane k integrates the submerged fraction of face k over the step when it is an
 //                  outflow face (Eqs. tv .. intaplus) -> dV (each face has one upwind cell: no
-//                  atomics)
+//                  atomics).  Interface cells that are general polyhedra go to their own
+//                  kernel (big.hip), launched on a side stream beside this one
 //   update         per cell, gather over its flux faces in ascending face id: dV from the
 //                  interface kernel or alpha_upwind*phi*dt; alpha - sum/V; round-off chopping;
 //                  cells outside the bounds are listed and compute the first sweep's corrections
@@ -1238,7 +1239,9 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
         const hipError_t e = launch_surface_big(bg, sb);
         if (e != hipSuccess) return e;
     }
-    if (m.cloop) {
+    if (m.all_big) {
+        // every cell is taken by the polyhedron kernel: nothing for the eight-lane one
+    } else if (m.cloop) {
         switch (cfg.surface_waves) {
             case 1: hipLaunchKernelGGL((k_surface<1, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
             case 3: hipLaunchKernelGGL((k_surface<3, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;

@@ -403,6 +403,22 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         for (int i = 0; i < 8; ++i) m->cell_pts[8 * (size_t)c + i] = v[i];
     }
 
+    // a mesh that is mostly general polyhedra runs every cell through their kernel (one launch, no
+    // second stream): the other cells are taken as polyhedra of their own faces too
+    bool all_big = false;
+    {
+        int64_t nbig = 0;
+        for (int32_t c = 0; c < n_cells; ++c) nbig += cbig[c] >= 0 ? 1 : 0;
+        if (nbig > 0 && 2 * nbig >= n_cells) {
+            for (int32_t c = 0; c < n_cells; ++c)
+                if (cbig[c] < 0 && !make_big(c)) {
+                    iso_mesh_destroy(m);
+                    return fail(ISO_EUNSUPPORTED, "cell " + std::to_string(c) + " has more than " +
+                                                      std::to_string(kBigPts) + " points");
+                }
+            all_big = true;
+        }
+    }
     if (!closed_ok) { iso_mesh_destroy(m); return fail(ISO_EMESH, "a cell's faces do not close it"); }
 
     // ---- volumes and centroids: tetrahedra (vertex mean, face vertex mean, edge) over outward faces
@@ -717,6 +733,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     DevMesh &d = m->dev;
     d.n_cells = n_cells; d.n_faces = n_faces; d.n_classes = n_classes; d.W = W; d.n_patches = n_patches;
     d.big_face_pts = big_face_pts;
+    d.all_big = all_big ? 1 : 0;
     d.n_internal = n_internal;
     iso_status st = ISO_OK;
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||
@@ -813,7 +830,7 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
         iso_plan_destroy(p);
         return fail(ISO_ENOMEM, "plan workspace allocation failed");
     }
-    if (mesh->dev.cbig && (hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking) != hipSuccess ||
+    if (mesh->dev.cbig && !mesh->dev.all_big && (hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking) != hipSuccess ||
                            hipEventCreateWithFlags(&w.fork, hipEventDisableTiming) != hipSuccess ||
                            hipEventCreateWithFlags(&w.join, hipEventDisableTiming) != hipSuccess)) {
         iso_plan_destroy(p);

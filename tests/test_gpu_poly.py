@@ -32,6 +32,10 @@ def _cases():
         # faces of 6 and 8 points: the kernel's general face loops
         "merged_joined_16x8x8": W.poly_violent("merged_joined", nx=16, ny=8, nz=8, steps=8),
         "merged_joined_perturbed_16x8x8": W.poly_violent("merged_joined", nx=16, ny=8, nz=8, steps=8, perturb=0.1),
+        # polyhedra a minority: the eight-lane kernel and the polyhedron kernel side by side (two
+        # streams); the meshes above are mostly polyhedra, whose plans send every cell to the latter
+        "merged_sparse_16x8x8": W.poly_violent("merged_sparse", nx=16, ny=8, nz=8, steps=8),
+        "merged_sparse_perturbed_16x8x8": W.poly_violent("merged_sparse", nx=16, ny=8, nz=8, steps=8, perturb=0.1),
     }
 
 
@@ -71,7 +75,7 @@ def test_trajectory_matches_oracle(oracle_lib, name):
 
 @pytest.mark.parametrize("name", ["tet_12x6x6", "pyramid_8x4x4", "mixed_16x8x8", "merged_16x8x8",
                                   "merged_perturbed_16x8x8", "merged_joined_16x8x8",
-                                  "merged_joined_perturbed_16x8x8"])
+                                  "merged_joined_perturbed_16x8x8", "merged_sparse_16x8x8"])
 def test_traced_step_matches_oracle(oracle_lib, name):
     w = CASES[name]
     phi, U = w.phi_U(0)
@@ -106,7 +110,7 @@ def test_random_fields(oracle_lib, kind, seed):
     assert err <= TOL
 
 
-@pytest.mark.parametrize("name", ["mixed_16x8x8", "merged_16x8x8", "merged_joined_16x8x8"])
+@pytest.mark.parametrize("name", ["mixed_16x8x8", "merged_16x8x8", "merged_joined_16x8x8", "merged_sparse_16x8x8"])
 def test_launch_shapes_give_the_same_bits(name):
     w = CASES[name]
     ref = None
@@ -202,7 +206,8 @@ def test_one_block_of_cells(oracle_lib, build):
     assert err <= TOL
 
 
-@pytest.mark.parametrize("name", ["prism_16x8x8", "merged_16x8x8", "merged_joined_perturbed_16x8x8"])
+@pytest.mark.parametrize("name", ["prism_16x8x8", "merged_16x8x8", "merged_joined_perturbed_16x8x8",
+                                  "merged_sparse_16x8x8"])
 def test_averaged_fields_on_other_cells(oracle_lib, name):
     """The step with a second time level of the fields (phi1 = 0.7 phi, U1 = 0.7 U + a seeded
     perturbation) is bit for bit the step with the averaged fields, on the eight-lane and the

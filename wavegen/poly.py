@@ -442,7 +442,8 @@ class PolyWorkload:
 
 def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5, perturb=0.0, seed=4):
     """The violent 3D workload's ingredients on tetrahedra, prisms, pyramids, hexahedra and prisms
-    side by side ("mixed"), or hexahedra among merged polyhedra ("merged", "merged_joined"), with the interior points optionally moved at random: the box [0,2]x[0,1]x[0,1],
+    side by side ("mixed"), or hexahedra among merged polyhedra ("merged", "merged_joined",
+    "merged_sparse"), with the interior points optionally moved at random: the box [0,2]x[0,1]x[0,1],
     periodic in x, a water column {x < 0.3, z < 0.6} joined to a wavy layer
     {z < 0.45 + 0.02 cos 4 pi x cos 4 pi y}, and the uniform + Taylor-Green flow (its fluxes from the
     vector potential along the straight edges)."""
@@ -450,11 +451,14 @@ def poly_violent(kind="tet", nx=12, ny=6, nz=6, steps=8, co=0.5, perturb=0.0, se
     xs, ys, zs = np.linspace(0, 2, nx + 1), np.linspace(0, 1, ny + 1), np.linspace(0, 1, nz + 1)
     if kind == "mixed":
         mesh = mixed_block(xs, ys, zs, nx // 2, periodic_x=True)
-    elif kind in ("merged", "merged_joined"):
+    elif kind in ("merged", "merged_joined", "merged_sparse"):
         # polyhedra: pairs along x in every fourth column, 2 x 2 blocks in another; "merged_joined"
-        # makes the faces two of them share one polygon of 6 or 8 points
+        # makes the faces two of them share one polygon of 6 or 8 points; "merged_sparse" keeps
+        # only pairs in every eighth column (polyhedra a minority of the cells)
         mx = [(i, j, k) for k in range(nz) for j in range(ny) for i in range(1, nx - 1, 4)]
         mxy = [(i, j, k) for k in range(nz) for j in range(0, ny - 1, 2) for i in range(3, nx - 1, 4)]
+        if kind == "merged_sparse":
+            mx, mxy = [(i, j, k) for k in range(nz) for j in range(ny) for i in range(1, nx - 1, 8)], []
         mesh = merged_block(xs, ys, zs, periodic_x=True, merge_x=mx, merge_xy=mxy, join=kind == "merged_joined")
     else:
         build = {"tet": tet_block, "prism": prism_block, "pyramid": pyramid_block}[kind]
