@@ -205,3 +205,33 @@ def test_surface_face_fluxes_brute_force(oracle_lib, kind):
         assert abs(tr["dV"][f] - phi[f] * I) <= 1e-13 * abs(phi[f]) * dt, (f, tr["dV"][f], phi[f] * I)
         checked += 1
     assert checked >= 5, checked
+
+
+def test_point_wet_alone(oracle_lib):
+    """One point wet alone, on four pairs of hexahedra merged along x whose shared faces are
+    joined in y and in z.  A point with only two edges in its cell (where two joined faces meet)
+    bounds a sliver: the two faces at it hold the same wet triangle with opposite orientation, so
+    the sub-volume and the isoface area vector are exactly zero.  A point whose edges lie in one
+    plane bounds a flat region: zero sub-volume, an isoface of non-zero area.  Otherwise a corner
+    of positive volume is cut off."""
+    xs, ys, zs = [0.0, 0.5, 1.0], [0.0, 0.5, 1.0], [0.0, 0.5, 1.0]
+    mesh = W.merged_block(xs, ys, zs, merge_x=[(0, j, k) for k in range(2) for j in range(2)], join=True)
+    om = oracle_lib.OracleMesh(mesh)
+    seen = {"sliver": 0, "flat": 0, "corner": 0}
+    for c in range(mesh.n_cells):
+        ids, verts, edges = _cell_verts_edges(mesh, c)
+        for i, p in enumerate(ids):
+            dirs = np.array([verts[b] - verts[a] for a, b in edges if i in (a, b)])
+            a_pts = np.zeros(mesh.n_points)
+            a_pts[p] = 1.0
+            cut = om.cut(c, a_pts, 0.5)
+            if len(dirs) == 2:
+                assert cut["vsub"] == 0.0 and np.all(cut["S"] == 0.0), (c, p)
+                seen["sliver"] += 1
+            elif np.linalg.matrix_rank(dirs, tol=1e-12) == 2:
+                assert abs(cut["vsub"]) <= 1e-15 and np.linalg.norm(cut["S"]) > 1e-3, (c, p)
+                seen["flat"] += 1
+            else:
+                assert cut["vsub"] > 1e-4 and np.linalg.norm(cut["S"]) > 1e-3, (c, p)
+                seen["corner"] += 1
+    assert seen["sliver"] >= 4 and seen["flat"] >= 8 and seen["corner"] >= 16, seen
