@@ -94,12 +94,13 @@ def test_traced_step_matches_oracle(oracle_lib, name):
     assert np.abs(out - o_new).max() <= 1e-13
 
 
-@pytest.mark.parametrize("kind,seed", [("tet", 61), ("tet", 62), ("merged", 63), ("merged", 64),
-                                       ("merged_joined", 65)])
-def test_random_fields(oracle_lib, kind, seed):
+@pytest.mark.parametrize("kind,seed,perturb", [("tet", 61, 0.0), ("tet", 62, 0.0), ("merged", 63, 0.0),
+                                               ("merged", 64, 0.0), ("merged_joined", 65, 0.0),
+                                               ("merged_joined", 66, 0.1), ("merged_sparse", 67, 0.1)])
+def test_random_fields(oracle_lib, kind, seed, perturb):
     """alpha ~ U[0.02, 0.98] per cell: every cell an interface cell, arbitrary vertex patterns on
-    triangular faces and on the many faces of the merged polyhedra."""
-    w = W.poly_violent(kind, nx=8, ny=4, nz=4, steps=3)
+    triangular faces and on the many faces of the merged polyhedra, flat or bent."""
+    w = W.poly_violent(kind, nx=8, ny=4, nz=4, steps=3, perturb=perturb)
     a0 = np.random.default_rng(seed).uniform(0.02, 0.98, w.mesh.n_cells)
     say(f"[gpu] random field on {kind} cells: seed={seed}")
     gm, plan = gpu_plan(w.mesh)
