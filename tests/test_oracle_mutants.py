@@ -73,6 +73,15 @@ RELAX_MUTANTS = [
     ("relax_overlap_accepted", "if (hit >= 0) return -1;", "if (hit >= 0) continue;"),
 ]
 
+# mistakes that only cells other than hexahedra show: checked against the pins on tetrahedra,
+# prisms, pyramids and merged polyhedra
+POLY_MUTANTS = [
+    ("face_walk_wraparound_pair_dropped", "if (pending && first_is_entry) {", "if (0 && pending && first_is_entry) {"),
+    ("face_fan_about_first_point",
+     "double x9[9] = {ap[0], ap[1], ap[2], p0[0], p0[1], p0[2], p1[0], p1[1], p1[2]};",
+     "double x9[9] = {m->P[3 * fp[0]], m->P[3 * fp[0] + 1], m->P[3 * fp[0] + 2], p0[0], p0[1], p0[2], p1[0], p1[1], p1[2]};"),
+]
+
 
 TANGENT_HEADER = "Tangent of the step (directional derivative"
 
@@ -97,6 +106,18 @@ def test_pins_reject_planted_mistake(tmp_path, name, old, new):
     env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,old,new", POLY_MUTANTS, ids=[m[0] for m in POLY_MUTANTS])
+def test_poly_pins_reject_planted_mistake(tmp_path, name, old, new):
+    mutant_src = tmp_path / "mutant.c"
+    mutant_src.write_text(_plant(name, old, new, tangent=False))
+    lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_poly.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
 
