@@ -235,3 +235,17 @@ def test_averaged_fields_on_other_cells(oracle_lib, name):
     err = np.abs(a.cpu().numpy() - o).max()
     say(f"[gpu]   max |gpu - oracle| = {err:.3e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("kind", ["merged", "merged_joined"])
+def test_polyhedra_at_the_bench_size(oracle_lib, kind):
+    """The polyhedral bench meshes themselves (64x32x32 hexahedra, mostly merged: 26,112 cells),
+    in the launch configuration the bench times: 4 steps, every cell against the oracle."""
+    w = W.poly_violent(kind, nx=64, ny=32, nz=32, steps=4)
+    say(f"[gpu] polyhedra at the bench size: {w.name} cells={w.mesh.n_cells}")
+    gm, plan = gpu_plan(w.mesh)
+    g = _gpu_run(plan, w, 4)
+    o = _oracle_run(oracle_lib.OracleMesh(w.mesh), w, 4)
+    err = np.abs(g - o).max()
+    say(f"[gpu]   max |gpu - oracle| = {err:.3e}")
+    assert err <= TOL
