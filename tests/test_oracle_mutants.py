@@ -83,18 +83,42 @@ POLY_MUTANTS = [
 ]
 
 
+# planted mistakes in the bounding step (R13), the inflow boundary value (R11), the round-off chop
+# and the cell centre (the volume centroid), which the hand-derived channel states and the closed
+# forms of tests/test_oracle_bounding.py must reject.  A snippet may be a list of (old, new) pairs,
+# and "*" before old replaces every occurrence of it (the two capacity loops of a sweep).
+BOUNDING_MUTANTS = [
+    ("excess_capacity_is_outflow_volume", "*double cap = over ? outphi * dt - outv : outv;",
+     "double cap = over ? outv : outv;"),
+    ("redistribution_ratio_uncapped", "if (r > 1.0) r = 1.0;", "if (0) r = 1.0;"),
+    ("excess_spread_equally", [("if (cap > 0) sumcap += cap;", "if (cap > 0) sumcap += 1.0;"),
+                               ("double d = cap * r;", "double d = fmin(cap, need / sumcap);")], None),
+    ("first_sweep_halved", "double d = cap * r;", "double d = cap * r * (it == 0 ? 0.5 : 1.0);"),
+    ("capacity_sum_doubled", "if (cap > 0) sumcap += cap;", "if (cap > 0) sumcap += 2.0 * cap;"),
+    ("inflow_alpha_dropped", "dV[fid] = m->palpha[p] * ph * dt;", "dV[fid] = 0.0 * m->palpha[p] * ph * dt;"),
+    ("cell_centre_is_vertex_mean", "for (int d = 0; d < 3; ++d) m->xc[3 * c + d] = mom[d] / vol;",
+     "for (int d = 0; d < 3; ++d) m->xc[3 * c + d] = xr[d] + 0.0 * mom[d] / vol;"),
+    ("roundoff_tolerance_raised", "double tol = opt->bound_tol;", "double tol = 1e-6 + 0.0 * opt->bound_tol;"),
+]
+
 TANGENT_HEADER = "Tangent of the step (directional derivative"
 
 
 def _plant(name, old, new, tangent):
     """The oracle source with `old` replaced by `new` in the step (before the tangent section) or
-    in the tangent section, where the snippet must occur exactly once."""
+    in the tangent section, where the snippet must occur exactly once (every occurrence, and at
+    least one, if it starts with "*").  `old` may also be a list of (old, new) pairs."""
     src = open(O.SRC).read()
     cut = src.index(TANGENT_HEADER)
     head, tail = src[:cut], src[cut:]
     part = tail if tangent else head
-    assert part.count(old) == 1, f"snippet for mutant {name} no longer matches the oracle"
-    part = part.replace(old, new)
+    pairs = old if isinstance(old, list) else [(old, new)]
+    for o, n in pairs:
+        every = o.startswith("*")
+        o = o[1:] if every else o
+        k = part.count(o)
+        assert (k >= 1 if every else k == 1), f"snippet for mutant {name} no longer matches the oracle"
+        part = part.replace(o, n)
     return head + part if tangent else part + tail
 
 
@@ -154,5 +178,17 @@ def test_relax_pins_reject_planted_mistake(tmp_path, name, old, new):
     env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_relax.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,old,new", BOUNDING_MUTANTS, ids=[m[0] for m in BOUNDING_MUTANTS])
+def test_bounding_pins_reject_planted_mistake(tmp_path, name, old, new):
+    mutant_src = tmp_path / "mutant.c"
+    mutant_src.write_text(_plant(name, old, new, tangent=False))
+    lib = O.compile_oracle(str(mutant_src), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, ISOADV_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_bounding.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
