@@ -23,7 +23,7 @@ def _trace_buffers(n_cells, n_faces, device):
 class _Advect(torch.autograd.Function):
     @staticmethod
     def forward(ctx, alpha0, phis, plan, Us, dt, n_steps, every):
-        a = alpha0.detach().contiguous()
+        a = alpha0.detach().clone(memory_format=torch.contiguous_format)  # never the caller's storage
         b = torch.empty_like(a)
         checkpoints = {0: a.clone()}
         for n in range(n_steps):

@@ -166,15 +166,35 @@ def default_options(**kw) -> IsoOptions:
     return o
 
 
-def _ptr(t):
-    """Device pointer of a contiguous float64/int32 CUDA (HIP) tensor."""
+def _check(t, n=None, dtype="f64", name="tensor"):
+    """With n, the tensor must hold exactly n elements of dtype ("f64" float64, "i32" int32): the
+    kernels behind the C interface trust the sizes the mesh implies, so a short or mistyped
+    buffer is refused here."""
     import torch
     if not isinstance(t, torch.Tensor):
-        raise TypeError("expected a torch tensor")
+        raise TypeError(f"{name}: expected a torch tensor")
+    if n is not None:
+        want = torch.float64 if dtype == "f64" else torch.int32
+        if t.dtype != want:
+            raise ValueError(f"{name}: expected {want}, got {t.dtype}")
+        if t.numel() != int(n):
+            raise ValueError(f"{name}: expected {int(n)} elements, got {t.numel()}")
+
+
+def _ptrs(*specs):
+    """Device pointers of (tensor, n, dtype, name) specs: every size is checked before any device."""
+    for sp in specs:
+        _check(*sp)
+    return [_ptr(sp[0], name=sp[3]) for sp in specs]
+
+
+def _ptr(t, n=None, dtype="f64", name="tensor"):
+    """Device pointer of a contiguous CUDA (HIP) tensor (checked as in _check first)."""
+    _check(t, n, dtype, name)
     if not t.is_cuda:
-        raise ValueError("expected a device tensor")
+        raise ValueError(f"{name}: expected a device tensor")
     if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+        raise ValueError(f"{name}: expected a contiguous tensor")
     return C.c_void_p(t.data_ptr())
 
 
@@ -277,23 +297,37 @@ class Plan:
         if out is None:
             out = torch.empty_like(alpha)
         st = IsoStepStats() if stats else None
-        self.set_stream(None)
         if (phi1 is None) != (U1 is None):
             raise ValueError("phi1 and U1 go together")
+        nc, nf = self.mesh.n_cells, self.mesh.n_faces
+        specs = [(alpha, nc, "f64", "alpha"), (phi, nf, "f64", "phi"), (U, 3 * nc, "f64", "U"),
+                 (out, nc, "f64", "out")]
+        if phi1 is not None:
+            specs += [(phi1, nf, "f64", "phi1"), (U1, 3 * nc, "f64", "U1")]
+        pa, pp, pu, po, *p1 = _ptrs(*specs)
+        self.set_stream(None)
         if phi1 is not None:
             if trace is not None:
                 raise ValueError("the averaged-field step takes no trace")
-            check(lib().iso_advect_step_avg(self.h, _ptr(alpha), _ptr(phi), _ptr(phi1), _ptr(U), _ptr(U1), float(dt),
-                                            _ptr(out), C.byref(st) if st is not None else None))
+            check(lib().iso_advect_step_avg(self.h, pa, pp, p1[0], pu, p1[1], float(dt), po,
+                                            C.byref(st) if st is not None else None))
         elif trace is None:
-            check(lib().iso_advect_step(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt), _ptr(out),
-                                        C.byref(st) if st is not None else None))
+            check(lib().iso_advect_step(self.h, pa, pp, pu, float(dt), po, C.byref(st) if st is not None else None))
         else:
-            tr = IsoTrace(*[(_ptr(trace[k]).value if trace.get(k) is not None else None)
-                            for k in ("vert_alpha", "kind", "iso", "rec", "dV", "alpha_raw", "iters")])
-            check(lib().iso_advect_step_traced(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt), _ptr(out),
+            tr = self._trace(trace, self.TRACE_KEYS)
+            check(lib().iso_advect_step_traced(self.h, pa, pp, pu, float(dt), po,
                                                C.byref(st) if st is not None else None, C.byref(tr)))
         return out, (st.as_dict() if st is not None else None)
+
+    def _trace(self, trace, keys):
+        """iso_trace of the given device tensors, each checked against its size in the header."""
+        nc, nf = self.mesh.n_cells, self.mesh.n_faces
+        sizes = {"vert_alpha": (8 * nc, "f64"), "kind": (nc, "i32"), "iso": (nc, "f64"), "rec": (7 * nc, "f64"),
+                 "dV": (nf, "f64"), "alpha_raw": (nc, "f64"), "iters": (nc, "i32")}
+        specs = [(trace[k], *sizes[k], f"trace[{k}]") for k in self.TRACE_KEYS
+                 if k in keys and trace.get(k) is not None]
+        got = dict(zip([sp[3] for sp in specs], _ptrs(*specs)))
+        return IsoTrace(*[got[f"trace[{k}]"].value if f"trace[{k}]" in got else None for k in self.TRACE_KEYS])
 
     TRACE_KEYS = ("vert_alpha", "kind", "iso", "rec", "dV", "alpha_raw", "iters")
 
@@ -311,8 +345,10 @@ class Plan:
 
     def relax_blend(self, alpha, alpha_target):
         """alpha (device tensor) blended in place towards alpha_target in the plan's zones."""
+        nc = self.mesh.n_cells
+        pa, pt = _ptrs((alpha, nc, "f64", "alpha"), (alpha_target, nc, "f64", "alpha_target"))
         self.set_stream(None)
-        check(lib().iso_relax_blend(self.h, _ptr(alpha), _ptr(alpha_target)))
+        check(lib().iso_relax_blend(self.h, pa, pt))
         return alpha
     GFM_KEYS = ("lambda", "jump", "beta_w", "ghost_own", "ghost_nbr")
 
@@ -323,9 +359,11 @@ class Plan:
         if out is None:
             out = {k: torch.empty(self.mesh.n_faces, dtype=torch.float64, device=alpha.device) for k in self.GFM_KEYS}
         gx, gy, gz = (float(v) for v in g)
+        nc, nf = self.mesh.n_cells, self.mesh.n_faces
+        pa, pd, *ptrs = _ptrs((alpha, nc, "f64", "alpha"), (p_d, nc, "f64", "p_d"),
+                              *[(out[k], nf, "f64", f"out[{k}]") for k in self.GFM_KEYS])
         self.set_stream(None)
-        check(lib().iso_gfm_faces(self.h, _ptr(alpha), _ptr(p_d), float(rho_heavy), float(rho_light), gx, gy, gz,
-                                  *(_ptr(out[k]) for k in self.GFM_KEYS)))
+        check(lib().iso_gfm_faces(self.h, pa, pd, float(rho_heavy), float(rho_light), gx, gy, gz, *ptrs))
         return out
 
     def adjoint(self, alpha, phi, U, dt, alpha_new_bar, trace=None, alpha_bar=None, phi_bar=None):
@@ -337,13 +375,15 @@ class Plan:
             alpha_bar = torch.empty_like(alpha)
         if phi_bar is None:
             phi_bar = torch.empty_like(phi)
+        nc, nf = self.mesh.n_cells, self.mesh.n_faces
+        ptrs = _ptrs((alpha, nc, "f64", "alpha"), (phi, nf, "f64", "phi"), (U, 3 * nc, "f64", "U"),
+                     (alpha_new_bar, nc, "f64", "alpha_new_bar"), (alpha_bar, nc, "f64", "alpha_bar"),
+                     (phi_bar, nf, "f64", "phi_bar"))
+        tr = self._trace(trace, ("vert_alpha", "kind", "iso", "dV", "alpha_raw")) if trace is not None else None
+        args, bars = ptrs[:3], ptrs[3:]
         self.set_stream(None)
-        tr = None
-        if trace is not None:
-            tr = IsoTrace(*[(_ptr(trace[k]).value if trace.get(k) is not None else None) for k in self.TRACE_KEYS])
-        check(lib().iso_advect_step_adjoint(self.h, _ptr(alpha), _ptr(phi), _ptr(U), float(dt),
-                                            C.byref(tr) if tr is not None else None, _ptr(alpha_new_bar),
-                                            _ptr(alpha_bar), _ptr(phi_bar)))
+        check(lib().iso_advect_step_adjoint(self.h, *args, float(dt), C.byref(tr) if tr is not None else None,
+                                            *bars))
         return alpha_bar, phi_bar
 
     KERNELS = ("find_surface", "surface", "update", "bound")
@@ -415,9 +455,26 @@ class Batch:
         dts = np.ascontiguousarray(dt, dtype=np.float64)
         if dts.shape != (len(self.meshes),):
             raise ValueError("dt needs one time step per member")
-        check(lib().iso_batch_advect(self.h, _ptr(alpha), _ptr(phi), int(phi_stride), _ptr(U), int(U_stride),
-                                     dts.ctypes.data_as(_dp), int(n_steps)))
+        pa, pp, pu = self._fields(alpha, phi, U, n_steps, phi_stride, U_stride)
+        check(lib().iso_batch_advect(self.h, pa, pp, int(phi_stride), pu, int(U_stride), dts.ctypes.data_as(_dp),
+                                     int(n_steps)))
         return alpha
+
+    def _fields(self, alpha, phi, U, n_steps, phi_stride=0, U_stride=0):
+        """Pointers of the concatenated state and fields, each checked to hold what the steps read:
+        one step's fields (stride 0) or n_steps of them at the given element strides."""
+        import torch
+        last = max(int(n_steps) - 1, 0)
+        for t, name in ((phi, "phi"), (U, "U")):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+                raise ValueError(f"{name}: expected a float64 torch tensor")
+        need_phi = self.n_faces + last * int(phi_stride)
+        need_U = 3 * self.n_cells + last * int(U_stride)
+        if phi.numel() < need_phi:
+            raise ValueError(f"phi: expected at least {need_phi} elements, got {phi.numel()}")
+        if U.numel() < need_U:
+            raise ValueError(f"U: expected at least {need_U} elements, got {U.numel()}")
+        return _ptr(alpha, self.n_cells, name="alpha"), _ptr(phi, name="phi"), _ptr(U, name="U")
 
     def config(self):
         c = (C.c_int32 * 4)()
@@ -433,8 +490,11 @@ class Batch:
     def tune(self, alpha, phi, U, dt, n_trial=3, cache_path=None):
         """Autotune the launch shapes on n_trial steps (alpha is not modified).  Returns (config, ms/step)."""
         dts = np.ascontiguousarray(dt, dtype=np.float64)
+        if dts.shape != (len(self.meshes),):
+            raise ValueError("dt needs one time step per member")
         best = C.c_double(0.0)
-        check(lib().iso_batch_tune(self.h, _ptr(alpha), _ptr(phi), _ptr(U), dts.ctypes.data_as(_dp), int(n_trial),
+        pa, pp, pu = self._fields(alpha, phi, U, 1)
+        check(lib().iso_batch_tune(self.h, pa, pp, pu, dts.ctypes.data_as(_dp), int(n_trial),
                                    cache_path.encode() if cache_path else None, C.byref(best)))
         return self.config(), best.value
 

@@ -567,7 +567,8 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
         if (__lane_id() == 0) {
             if (rounds_max) atomicMax(&A.counters[kCntMaxIter], rounds_max);
             if (flat) atomicAdd(&A.counters[kCntFlat], flat);
-            if (nonconv) atomicAdd(&A.counters[kCntNonconv], nonconv);
+            // every lane of a group counts its cell's search: one count per group
+            if (nonconv) atomicAdd(&A.counters[kCntNonconv], nonconv / kGrp);
         }
     }
 }

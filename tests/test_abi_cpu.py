@@ -102,3 +102,47 @@ def test_batch_entry_points_reject_null_arguments():
     assert L.iso_batch_set_config(None, cfg) == B.ISO_EINVAL
     assert L.iso_batch_tune(None, None, None, None, dt, 1, None, None) == B.ISO_EINVAL
     assert L.iso_batch_layout(None, None, None) == B.ISO_EINVAL
+
+
+class _FakePlan:
+    """Stands in for a plan on the host: the binding checks buffers against the mesh's sizes
+    before it touches the library, so these checks run without a device."""
+
+    def __init__(self, nc, nf):
+        self.mesh = type("M", (), {"n_cells": nc, "n_faces": nf})()
+
+    _trace = B.Plan._trace
+    TRACE_KEYS = B.Plan.TRACE_KEYS
+    GFM_KEYS = B.Plan.GFM_KEYS
+
+
+def test_binding_rejects_mistyped_or_short_buffers():
+    """A buffer of the wrong dtype or length is refused before its pointer reaches the C interface
+    (the kernels size their accesses from the mesh, so such a buffer would be read out of bounds)."""
+    import torch
+    nc, nf = 12, 30
+    p = _FakePlan(nc, nf)
+    f64 = dict(dtype=torch.float64)
+    ok = dict(alpha=torch.zeros(nc, **f64), phi=torch.zeros(nf, **f64), U=torch.zeros(3 * nc, **f64),
+              out=torch.zeros(nc, **f64))
+    bad = {"alpha": torch.zeros(nc, dtype=torch.float32), "phi": torch.zeros(nf - 1, **f64),
+           "U": torch.zeros(nc, **f64), "out": torch.zeros(nc + 1, **f64)}
+    for k, t in bad.items():
+        args = dict(ok, **{k: t})
+        with pytest.raises(ValueError, match=k):
+            B.Plan.step(p, args["alpha"], args["phi"], args["U"], 0.1, out=args["out"])
+    # correct sizes and dtypes get as far as the device check
+    with pytest.raises(ValueError, match="device tensor"):
+        B.Plan.step(p, ok["alpha"], ok["phi"], ok["U"], 0.1, out=ok["out"])
+    with pytest.raises(ValueError, match="kind"):
+        p._trace({"kind": torch.zeros(nc, dtype=torch.int64)}, B.Plan.TRACE_KEYS)
+    with pytest.raises(ValueError, match="vert_alpha"):
+        p._trace({"vert_alpha": torch.zeros(nc, **f64)}, B.Plan.TRACE_KEYS)
+    with pytest.raises(ValueError, match="p_d"):
+        B.Plan.gfm_faces(p, ok["alpha"], torch.zeros(nc - 1, **f64), 1000.0, 1.2, (0, 0, -9.81),
+                         out={k: torch.zeros(nf, **f64) for k in B.Plan.GFM_KEYS})
+    with pytest.raises(ValueError, match="alpha_target"):
+        B.Plan.relax_blend(p, ok["alpha"], torch.zeros(nc, dtype=torch.float32))
+    with pytest.raises(ValueError, match="phi_bar"):
+        B.Plan.adjoint(p, ok["alpha"], ok["phi"], ok["U"], 0.1, ok["alpha"], alpha_bar=ok["out"],
+                       phi_bar=torch.zeros(nc, **f64))

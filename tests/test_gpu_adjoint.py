@@ -211,3 +211,20 @@ def test_adjoint_argument_errors():
     many = Plan(gm, default_options(n_bound_iter=40))
     with pytest.raises(IsoError):
         many.adjoint(a, p, u, w.dt, torch.zeros_like(a))
+
+
+def test_advect_leaves_the_callers_state_alone(misfit):
+    """The differentiable multi-step advection steps on its own buffers: the caller's initial state
+    (a leaf that requires grad) is unchanged after forward and backward."""
+    import torch
+    from paper_1804_01130_amd.autograd import advect
+    M = misfit
+    say("[gpu] advect keeps alpha0 unchanged")
+    a0 = to_dev(M["w"].alpha0).requires_grad_(True)
+    before = a0.detach().clone()
+    aT = advect(a0, M["phis"][:4].clone().requires_grad_(True), M["plan"], M["Us"][:4], M["w"].dt,
+                checkpoint_every=2)
+    ((aT - M["alpha_target"]) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    assert torch.equal(a0.detach(), before)
+    assert not torch.equal(aT.detach(), before)
