@@ -170,6 +170,21 @@ iso_status iso_advect_step_avg(iso_plan *plan, const double *alpha, const double
                                const double *U0, const double *U1, double dt, double *alpha_new,
                                iso_step_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the step of iso_advect_step without a plan, running the
+ * same kernels, bit for bit the same alpha_new.  Its workspace is a fixed array of 64 MiB per
+ * device inside the library, held from the first call on a device until the process ends; the call
+ * allocates nothing.  Limit: about 24 B per cell plus 60 B per face (meshes of up to ~400k cells of
+ * a 2D slab), ISO_ENOSPACE beyond.  mesh: created beforehand, on the current device; opt (nullable:
+ * defaults) as for a plan, except check_inputs (ISO_EINVAL), max_surface (ignored: every cell fits)
+ * and the statistics (none); stream: hipStream_t as void*, NULL = default stream.  alpha, phi, U,
+ * alpha_new: DEVICE arrays laid out as for iso_advect_step.  Every call on one device shares that
+ * device's workspace, whose contents the next call reuses: calls that overlap on one device (other
+ * streams or threads) race and must be serialised by the caller. */
+iso_status iso_advect_step_noalloc(const iso_mesh *mesh, const iso_options *opt, void *hip_stream,
+                                   const double *alpha, const double *phi, const double *U, double dt,
+                                   double *alpha_new);
+
 /* Ghost-fluid face data after advection (Section 3.1, Eqs. 12-20): what the interface-corrected
  * interpolation of the dynamic pressure needs from the new volume fractions.  A cell is wet
  * (heavy fluid, density rho_heavy) iff alpha > 1/2.  For every face with a cell on each side (an

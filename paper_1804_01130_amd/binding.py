@@ -102,6 +102,8 @@ def lib():
         L.iso_advect_step_traced.restype = C.c_int
         L.iso_advect_step_avg.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats)]
         L.iso_advect_step_avg.restype = C.c_int
+        L.iso_advect_step_noalloc.argtypes = [_vp, C.POINTER(IsoOptions), _vp, _vp, _vp, _vp, C.c_double, _vp]
+        L.iso_advect_step_noalloc.restype = C.c_int
         L.iso_gfm_faces.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                     _vp, _vp, _vp, _vp, _vp]
         L.iso_gfm_faces.restype = C.c_int
@@ -274,6 +276,18 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+
+def advect_step_noalloc(mesh, alpha, phi, U, dt, out, options: IsoOptions | None = None, stream=None):
+    """One step without a plan and without any device allocation (iso_advect_step_noalloc): out is
+    written on the given (default: current) stream.  The library's fixed workspace limits the mesh
+    to about 24 B per cell plus 60 B per face within 64 MiB."""
+    nc, nf = mesh.n_cells, mesh.n_faces
+    pa, pp, pu, po = _ptrs((alpha, nc, "f64", "alpha"), (phi, nf, "f64", "phi"), (U, 3 * nc, "f64", "U"),
+                           (out, nc, "f64", "out"))
+    check(lib().iso_advect_step_noalloc(mesh.h, C.byref(options) if options is not None else None,
+                                        _stream_handle(stream), pa, pp, pu, float(dt), po))
+    return out
 
 
 class Plan:

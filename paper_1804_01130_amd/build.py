@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libisoadv.so")
 SOURCES = [os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "batch.cpp"), os.path.join(CSRC, "kernels.hip"),
            os.path.join(CSRC, "adjoint.hip"), os.path.join(CSRC, "gfm.hip"),
-           os.path.join(CSRC, "relax.hip"), os.path.join(CSRC, "big.hip")]
+           os.path.join(CSRC, "relax.hip"), os.path.join(CSRC, "big.hip"), os.path.join(CSRC, "noalloc.hip")]
 HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "device_common.h"), os.path.join(INCLUDE, "isoadv.h")]
 ARCH = os.environ.get("ISOADV_ARCH", "gfx950")
 

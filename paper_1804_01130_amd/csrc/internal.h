@@ -246,4 +246,9 @@ namespace isoadv {
 iso_status fail(iso_status s, const std::string &msg);
 LaunchCfg launch_cfg(const iso_options &o);
 Params step_params(const iso_options &o);
+// option ranges, and what the mesh's cells support (ISO_EINVAL, ISO_EUNSUPPORTED)
+iso_status check_options(const iso_options &o, const iso_mesh *mesh);
+// non-null arrays, dt > 0 and finite, alpha_new overlapping no input (ISO_EINVAL)
+iso_status check_step_args(const iso_mesh *m, const double *alpha, const double *phi, const double *U, double dt,
+                           double *alpha_new, const double *phi1, const double *U1);
 }

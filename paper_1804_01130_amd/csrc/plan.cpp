@@ -99,6 +99,30 @@ LaunchCfg launch_cfg(const iso_options &o) {
 Params step_params(const iso_options &o) {
     return Params{o.eps_surf, o.flat_tol, o.bound_tol, o.root_max_iter, o.n_bound_iter, o.clip, o.us_mode};
 }
+iso_status check_options(const iso_options &o, const iso_mesh *mesh) {
+    if (!(o.eps_surf >= 0 && o.eps_surf < 0.5) || !(o.flat_tol >= 0) || !(o.bound_tol >= 0) || o.root_max_iter < 1 ||
+        o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 ||
+        o.surface_blocks < 0 || o.surface_blocks > 65535 || o.bound_blocks < 0 || o.bound_blocks > 65535 ||
+        o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1)
+        return fail(ISO_EINVAL, "bad options");
+    if (mesh->generic && o.us_mode != 0)
+        return fail(ISO_EUNSUPPORTED, "the interpolated isoface velocity (us_mode 1) takes meshes of hexahedra only");
+    return ISO_OK;
+}
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+iso_status check_step_args(const iso_mesh *m, const double *alpha, const double *phi, const double *U, double dt,
+                           double *alpha_new, const double *phi1, const double *U1) {
+    if (!alpha || !phi || !U || !alpha_new) return fail(ISO_EINVAL, "null array");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(ISO_EINVAL, "dt must be positive and finite");
+    size_t nc = (size_t)m->n_cells * 8, nf = (size_t)m->n_faces * 8;
+    if (overlaps(alpha_new, nc, alpha, nc) || overlaps(alpha_new, nc, phi, nf) || overlaps(alpha_new, nc, U, 3 * nc) ||
+        (phi1 && overlaps(alpha_new, nc, phi1, nf)) || (U1 && overlaps(alpha_new, nc, U1, 3 * nc)))
+        return fail(ISO_EINVAL, "alpha_new overlaps an input");
+    return ISO_OK;
+}
 }  // namespace isoadv
 
 extern "C" {
@@ -799,16 +823,9 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
     p->mesh = mesh;
     if (opt) p->opt = *opt; else iso_options_default(&p->opt);
     const iso_options &o = p->opt;
-    if (!(o.eps_surf >= 0 && o.eps_surf < 0.5) || !(o.flat_tol >= 0) || !(o.bound_tol >= 0) || o.root_max_iter < 1 ||
-        o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 ||
-        o.surface_blocks < 0 || o.surface_blocks > 65535 || o.bound_blocks < 0 || o.bound_blocks > 65535 ||
-        o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1) {
+    if (const iso_status so = check_options(o, mesh); so != ISO_OK) {
         delete p;
-        return fail(ISO_EINVAL, "bad options");
-    }
-    if (mesh->generic && o.us_mode != 0) {
-        delete p;
-        return fail(ISO_EUNSUPPORTED, "the interpolated isoface velocity (us_mode 1) takes meshes of hexahedra only");
+        return so;
     }
     p->stream = static_cast<hipStream_t>(stream);
     const int32_t nc = mesh->n_cells, nf = mesh->n_faces;
@@ -848,11 +865,6 @@ iso_status iso_plan_set_stream(iso_plan *p, void *stream) {
 }
 
 
-static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
-    auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-    return x < y + nb && y < x + na;
-}
-
 static iso_status check_inputs_host(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt) {
     const iso_mesh *m = p->mesh;
     std::vector<double> a(m->n_cells), f(m->n_faces), u(3 * (size_t)m->n_cells);
@@ -887,13 +899,8 @@ static iso_status step_impl(iso_plan *p, const double *alpha, const double *phi,
                             double *alpha_new, iso_step_stats *stats, const iso_trace *trace,
                             const double *phi1 = nullptr, const double *U1 = nullptr) {
     if (!p) return fail(ISO_EINVAL, "null plan");
-    if (!alpha || !phi || !U || !alpha_new) return fail(ISO_EINVAL, "null array");
-    if (!(dt > 0) || !std::isfinite(dt)) return fail(ISO_EINVAL, "dt must be positive and finite");
     const iso_mesh *m = p->mesh;
-    size_t nc = (size_t)m->n_cells * 8, nf = (size_t)m->n_faces * 8;
-    if (overlaps(alpha_new, nc, alpha, nc) || overlaps(alpha_new, nc, phi, nf) || overlaps(alpha_new, nc, U, 3 * nc) ||
-        (phi1 && overlaps(alpha_new, nc, phi1, nf)) || (U1 && overlaps(alpha_new, nc, U1, 3 * nc)))
-        return fail(ISO_EINVAL, "alpha_new overlaps an input");
+    if (const iso_status sa = check_step_args(m, alpha, phi, U, dt, alpha_new, phi1, U1); sa != ISO_OK) return sa;
     if (p->opt.check_inputs) {  // each level within the limits: so is their average
         iso_status s = check_inputs_host(p, alpha, phi, U, dt);
         if (s == ISO_OK && phi1) s = check_inputs_host(p, alpha, phi1, U1, dt);
