@@ -310,6 +310,68 @@ __device__ __forceinline__ double cell_vsub6(const FaceLane &f, double iso, bool
     return v6 + dot(o, cseg);
 }
 
+// ------------------------------------------------------------------------------------------ first guess
+__device__ __forceinline__ double pick8(const double (&v)[8], int i) {
+    double r = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) r = i == q ? v[q] : r;
+    return r;
+}
+
+// First guess of the interval (s_k, s_k+1) of the sorted vertex values s that holds the isovalue
+// (k in [0, 6], s_k < s_k+1), which orders the probes of the bracket search.  a: the vertex values
+// in canonical order.  Hexahedra: the vertex values are taken as a linear field over the cell in its
+// own coordinates (0 or 1 along each of its three edge directions, the rate along each the mean
+// difference over its four edges), whose volume fraction above x is one minus the distribution
+// function of a sum of three uniform variables, in closed form by inclusion and exclusion over the
+// eight corners; lane j evaluates it at s_j, and k counts s_1 .. s_6 whose fraction is at least
+// alpha_P.  Other cells: the point a fraction 1 - alpha_P of the way from s_0 to s_7.
+template <bool kGeneric>
+__device__ __forceinline__ int guess_interval(const double (&a)[8], const double (&s)[8], double aP, int lv) {
+    bool hit;
+    const double x = pick8(s, lv);
+    if constexpr (!kGeneric) {
+        // canonical vertices 0..3 the bottom loop (0 -> 1 along the first direction, 1 -> 2 along the
+        // second), 4..7 above them
+        double d1 = 0.25 * fabs((a[1] - a[0]) + (a[2] - a[3]) + (a[5] - a[4]) + (a[6] - a[7]));
+        double d2 = 0.25 * fabs((a[3] - a[0]) + (a[2] - a[1]) + (a[7] - a[4]) + (a[6] - a[5]));
+        double d3 = 0.25 * fabs((a[4] - a[0]) + (a[5] - a[1]) + (a[6] - a[2]) + (a[7] - a[3]));
+        double mean = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mean += a[i];
+        const double f0 = 0.125 * mean - 0.5 * (d1 + d2 + d3);  // the fitted field's lowest corner value
+        // a rate of zero (data constant along a direction) is lifted to a small fraction of the
+        // largest, which keeps the closed form finite and changes the fraction only slightly
+        const double dmin = 1e-3 * fmax(d1, fmax(d2, d3));
+        d1 = fmax(d1, dmin);
+        d2 = fmax(d2, dmin);
+        d3 = fmax(d3, dmin);
+        double below = 0.0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const double t = fmax(x - (f0 + ((b & 1) ? d1 : 0.0) + ((b & 2) ? d2 : 0.0) + ((b & 4) ? d3 : 0.0)), 0.0);
+            const double t3 = t * t * t;
+            below += (__popc(b) & 1) ? -t3 : t3;
+        }
+        hit = below <= (1.0 - aP) * (6.0 * d1 * d2 * d3);
+    } else {
+        hit = x <= s[0] + (1.0 - aP) * (s[7] - s[0]);
+    }
+    const uint32_t gm = (uint32_t)(__ballot(hit && lv >= 1 && lv <= 6) >> (__lane_id() & ~(kLanes - 1))) & 0xFFu;
+    int k = __popc(gm);
+    // an empty interval (tied values): the non-empty one that starts at the tied value, else the
+    // one below it
+    int up = -1, dn = -1;
+#pragma unroll
+    for (int q = 6; q >= 0; --q)
+        if (q > k && s[q] < s[q + 1]) up = q;
+#pragma unroll
+    for (int q = 0; q <= 6; ++q)
+        if (q < k && s[q] < s[q + 1]) dn = q;
+    if (!(pick8(s, k) < pick8(s, k + 1))) k = up >= 0 ? up : dn;
+    return k;
+}
+
 // ------------------------------------------------------------------------------------------ kernels
 constexpr int kFindBlock = 1024, kFindPerThread = 4;
 
@@ -553,12 +615,17 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                 for (int q = 1; q < 8; ++q) r = i == q ? s[q] : r;
                 return r;
             };
-            // bracket between consecutive sorted vertex values (the sub-volume is smooth in between)
+            // bracket between consecutive sorted vertex values (the sub-volume is smooth in between):
+            // the two ends of the guessed interval are probed first, then the search bisects what
+            // is left
             int il = 0, ih = 7;
             double fl = 1.0 - aP;
             bool exact = false;
+            int p1 = guess_interval<kGeneric>(a, s, aP, lv), p2 = p1 + 1;
             while (ih - il > 1) {
-                const int im = (il + ih) >> 1;
+                int im = (il + ih) >> 1;
+                if (p1 > il && p1 < ih) { im = p1; p1 = -1; }
+                else if (p2 > il && p2 < ih) { im = p2; p2 = -1; }
                 const double sm = sorted_at(im);
                 const double fm = F(sm, false);
                 ++rounds;

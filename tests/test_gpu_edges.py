@@ -100,3 +100,40 @@ def test_random_fields(oracle_lib, mesh, seed):
     err = np.abs(_gpu_run(plan, a0, phi, U, w.dt, 3) - _oracle_run(om, a0, phi, U, w.dt, 3)).max()
     say(f"[gpu]   max |gpu - oracle| after 3 steps = {err:.3e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("mesh,seed", [("graded", 21), ("perturbed", 22)])
+def test_isovalue_of_every_cell_near_its_extreme_vertices(oracle_lib, mesh, seed):
+    """Cells with alpha close to 0 or 1 next to cells far from it put the isovalue in the lowest or
+    highest interval of their sorted vertex values (next to one vertex).  Every reconstructed cell's
+    isovalue, not a sample of them, must cut off alpha V to 1e-12 by the oracle's sub-volume, or sit
+    at the same vertex value where the sub-volume jumps across alpha V."""
+    w = (W.violent_3d(nx=16, ny=12, nz=10, steps=1) if mesh == "graded"
+         else W.perturbed_box(nx=10, ny=8, nz=7, steps=1))
+    n = w.mesh.n_cells
+    rng = np.random.default_rng(seed)
+    pick = rng.uniform(size=n)
+    a0 = np.where(pick < 0.45, rng.uniform(1e-6, 0.03, n),
+                  np.where(pick < 0.9, rng.uniform(0.97, 1.0 - 1e-6, n), rng.uniform(0.0, 1.0, n)))
+    say(f"[gpu] isovalue of every cell, roots next to extreme vertices: {w.name} seed={seed}")
+    phi, U = w.phi_U(0)
+    gm, plan = gpu_plan(w.mesh)
+    _, g_st, g = gpu_traced_step(plan, gm, a0, phi, U, w.dt)
+    om = oracle_lib.OracleMesh(w.mesh)
+    _, _, o = om.step(a0, phi, U, w.dt, trace=True)
+    _, V = om.geometry()
+    assert np.array_equal(g["kind"], o["kind"])
+    cp = gm.cell_points()
+    rec = np.nonzero(o["kind"] == 1)[0]
+    end_intervals = 0
+    for c in rec:
+        s = np.sort(o["a_pts"][cp[c]])
+        end_intervals += int(o["iso"][c] < s[1] or o["iso"][c] > s[6])
+        fo = om.cut(c, o["a_pts"], o["iso"][c])["vsub"] / V[c] - a0[c]
+        if abs(fo) <= 1e-12:
+            err = abs(om.cut(c, o["a_pts"], g["iso"][c])["vsub"] / V[c] - a0[c])
+            assert err <= 1e-12, (c, a0[c], g["iso"][c], o["iso"][c], s)
+        else:
+            assert abs(g["iso"][c] - o["iso"][c]) <= 8 * np.finfo(float).eps, (c, g["iso"][c], o["iso"][c], s)
+    say(f"[gpu]   {len(rec)} reconstructed cells, {end_intervals} with the root in the lowest or highest interval")
+    assert end_intervals >= 50
