@@ -68,6 +68,9 @@
  *       beta_w (Eq. 18) from its heavy cell; the ghost values are the heavy fluid's p_d
  *       extended to the dry cell (Eq. 20) and the light fluid's extended to the wet cell
  *       (the mirror of Eqs. 17-20).
+ *   Loops over cells, points and faces whose iterations are independent run on OpenMP threads
+ *   (or_set_threads); every sum keeps its serial order, so results do not depend on the thread
+ *   count.
  *   R17 relaxation zones (Section 3, the paragraph on wave generation and absorption): the
  *       paper blends alpha explicitly towards a target after the advection step with the
  *       exponential weight of Jacobsen, Fuhrman & Fredsoe (2012), which it cites without
@@ -77,6 +80,7 @@
  *       length.  A zone is a slab: an inner-edge point, a direction and a length.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -481,7 +485,11 @@ void or_mesh_geometry(const or_mesh *m, double *xc, double *V) {
 }
 
 /* ------------------------------------------------------------------ R1 vertex values */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
+
 void or_point_values(const or_mesh *m, const double *alpha, double *a_pts) {
+#pragma omp parallel for schedule(static)
     for (int p = 0; p < m->n_points; ++p) {
         if (m->prep[p] != p) continue;
         const double *xp = m->P + 3 * p;
@@ -497,6 +505,7 @@ void or_point_values(const or_mesh *m, const double *alpha, double *a_pts) {
         }
         a_pts[p] = num / den;
     }
+#pragma omp parallel for schedule(static)
     for (int p = 0; p < m->n_points; ++p) a_pts[p] = a_pts[m->prep[p]];
 }
 
@@ -909,26 +918,29 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
     or_point_values(m, alpha, a_pts);
     double *U_pts = opt->us_mode == 1 ? point_velocities(m, U) : NULL;
 
-    /* R2, R3, R6: interface cells, their isovalue and isoface */
+    /* R2, R3, R6: interface cells, their isovalue and isoface (kind -1 marks a flat interface
+     * cell until the counts are taken) */
+    int *its = (int *)xmalloc(sizeof(int) * nc);
+#pragma omp parallel for schedule(dynamic, 64)
     for (int c = 0; c < nc; ++c) {
         kind[c] = 0;
+        its[c] = 0;
         double a = alpha[c];
         if (!(a > opt->eps_surf && a < 1.0 - opt->eps_surf)) continue;
-        ++s.n_surface;
         double lo = 1e300, hi = -1e300;
         for (int i = m->cpptr[c]; i < m->cpptr[c + 1]; ++i) {
             double v = a_pts[m->cpts[i]];
             if (v < lo) lo = v;
             if (v > hi) hi = v;
         }
-        if (!(hi - lo > opt->flat_tol)) { kind[c] = 2; ++s.n_flat; continue; }
+        if (!(hi - lo > opt->flat_tol)) { kind[c] = 2; continue; }
         int it = 0;
         double iso = or_cell_isovalue(m, c, a_pts, a, opt->max_bisect, &it);
-        if (it > s.max_iter) s.max_iter = it;
+        its[c] = it;
         or_cut cut;
         or_cell_cut(m, c, a_pts, iso, &cut);
         double nrm = v_norm(cut.S);
-        if (!(nrm > 0)) { kind[c] = 2; ++s.n_flat; continue; }
+        if (!(nrm > 0)) { kind[c] = 2; continue; }
         kind[c] = 1;
         double nS[3] = {cut.S[0] / nrm, cut.S[1] / nrm, cut.S[2] / nrm};
         double Uc[3] = {U[c], U[nc + c], U[2 * nc + c]};  /* U_S = U_P (R6) */
@@ -939,9 +951,17 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
         if (tr && tr->iso) tr->iso[c] = iso;
         if (tr && tr->iters) tr->iters[c] = it;
     }
+    for (int c = 0; c < nc; ++c) {
+        if (kind[c] != 0) ++s.n_surface;
+        if (kind[c] == 2) ++s.n_flat;
+        if (its[c] > s.max_iter) s.max_iter = its[c];
+    }
+    free(its);
 
     /* Eq. dV, R11: volume transported through each flux face, owner -> neighbour orientation */
     for (int f = 0; f < nf; ++f) dV[f] = 0.0;
+    /* each face is written by one cell only: its upwind cell, or the owner of an inflow face */
+#pragma omp parallel for schedule(dynamic, 256)
     for (int c = 0; c < nc; ++c) {
         for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) {
             int fid = m->ce_flux[e], sg = m->ce_sign[e];
@@ -964,12 +984,13 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
 
     /* flux-form update (R12) */
     double *cur = (double *)xmalloc(sizeof(double) * nc);
+#pragma omp parallel for schedule(static)
     for (int c = 0; c < nc; ++c) {
         double sum = 0.0;
         for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) sum += m->ce_sign[e] * dV[m->ce_flux[e]];
         cur[c] = alpha[c] - sum / m->V[c];
-        s.vol_before += alpha[c] * m->V[c];
     }
+    for (int c = 0; c < nc; ++c) s.vol_before += alpha[c] * m->V[c];
     for (int c = 0; c < nc; ++c)
         for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e)
             if (m->ce_other[e] < 0) s.vol_boundary += m->ce_sign[e] * dV[m->ce_flux[e]];
@@ -977,18 +998,31 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
 
     /* R13 bounding: chop round-off excursions, redistribute larger ones over outflow faces (Jacobi), chop */
     double tol = opt->bound_tol;
-    if (opt->clip) for (int c = 0; c < nc; ++c) cur[c] = chop_roundoff(cur[c], tol, m->V[c], &s.vol_clipped);
+    /* per-cell clipped volumes of one pass, summed afterwards in cell order */
+    double *clipc = (double *)xmalloc(sizeof(double) * nc);
+    int *offc = (int *)xmalloc(sizeof(int) * nc);
+    if (opt->clip) {
+#pragma omp parallel for schedule(static)
+        for (int c = 0; c < nc; ++c) {
+            clipc[c] = 0.0;
+            cur[c] = chop_roundoff(cur[c], tol, m->V[c], &clipc[c]);
+        }
+        for (int c = 0; c < nc; ++c) s.vol_clipped += clipc[c];
+    }
     double *delta = (double *)xmalloc(sizeof(double) * nf);
     double *dVc = (double *)xmalloc(sizeof(double) * nf);
     memcpy(dVc, dV, sizeof(double) * nf);
     for (int it = 0; it < opt->n_bound_iter; ++it) {
         for (int f = 0; f < nf; ++f) delta[f] = 0.0;
         int n_off = 0;
+        /* each outflow face's correction is written by its upwind cell only */
+#pragma omp parallel for schedule(dynamic, 256)
         for (int c = 0; c < nc; ++c) {
+            offc[c] = 0;
             double a = cur[c];
             int over = a > 1.0 + tol, under = a < -tol;
             if (!over && !under) continue;
-            ++n_off;
+            offc[c] = 1;
             double sumcap = 0.0;
             for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) {
                 int fid = m->ce_flux[e], sg = m->ce_sign[e];
@@ -1013,13 +1047,18 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
                 delta[fid] = over ? sg * d : -sg * d;
             }
         }
+        for (int c = 0; c < nc; ++c) n_off += offc[c];
         if (it == 0) s.n_bound_active = n_off;
+#pragma omp parallel for schedule(static)
         for (int c = 0; c < nc; ++c) {
             double sum = 0.0;
             for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e) sum += m->ce_sign[e] * delta[m->ce_flux[e]];
             cur[c] = cur[c] - sum / m->V[c];
-            if (opt->clip) cur[c] = chop_roundoff(cur[c], tol, m->V[c], &s.vol_clipped);
+            clipc[c] = 0.0;
+            if (opt->clip) cur[c] = chop_roundoff(cur[c], tol, m->V[c], &clipc[c]);
         }
+        for (int c = 0; c < nc; ++c) s.vol_clipped += clipc[c];
+#pragma omp parallel for schedule(static)
         for (int f = 0; f < nf; ++f) dVc[f] += delta[f];
     }
     if (opt->n_bound_iter == 0) {
@@ -1047,6 +1086,7 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
     }
     if (st) *st = s;
     free(a_pts); free(kind); free(rec); free(dV); free(cur); free(delta); free(dVc); free(U_pts);
+    free(clipc); free(offc);
     return 0;
 }
 

@@ -44,7 +44,7 @@ class Stats(C.Structure):
 def compile_oracle(src: str, out: str) -> str:
     """gcc build of an oracle source file (no FMA contraction, so rounding follows the source)."""
     tmp = f"{out}.tmp{os.getpid()}"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
                            "-shared", "-Wall", "-Wno-unused-function", "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
@@ -92,6 +92,10 @@ def lib():
         L.or_relax_blend.restype = C.c_int
         L.or_relax_weight.argtypes = [C.c_double]
         L.or_relax_weight.restype = C.c_double
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
+        L.or_get_threads.argtypes = []
+        L.or_get_threads.restype = C.c_int
         L.or_gfm_faces.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
@@ -103,6 +107,15 @@ def _d(a):
 
 def _i(a):
     return a.ctypes.data_as(_ip)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on the count)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
 
 
 def default_opts(**kw) -> Opts:
