@@ -97,6 +97,9 @@ typedef struct {
                                velocities, and the linear interpolant at x_S in the tetrahedron
                                with the largest smallest barycentric coordinate.  The adjoint
                                takes us_mode 0 only (ISO_EUNSUPPORTED). */
+    double root_tol;        /* isovalue tolerance (Section 3.2 leaves it to the user): the search
+                               stops once |V_sub/V_P - alpha_P| <= root_tol; 0 (default) converges
+                               to round-off.  In [0, 1). */
 } iso_options;
 
 typedef struct {
@@ -106,7 +109,12 @@ typedef struct {
     int64_t n_bound_active;  /* cells needing redistribution in the first sweep */
     int32_t max_root_iter;
     int32_t reserved;
-    double vol_before, vol_after, vol_clipped, alpha_min, alpha_max;
+    double vol_before, vol_after;  /* sum of alpha V before and after the step */
+    double vol_boundary_flux;      /* volume that left through boundary faces (inflow negative), with the
+                                      redistribution's corrections of boundary faces */
+    double vol_clipped;            /* volume the chops added (negative: removed), so that
+                                      vol_after = vol_before - vol_boundary_flux + vol_clipped */
+    double alpha_min, alpha_max;
 } iso_step_stats;
 
 /* Optional per-step intermediates (DEVICE pointers, each may be NULL), for testing. */

@@ -959,6 +959,7 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
     free(its);
 
     /* Eq. dV, R11: volume transported through each flux face, owner -> neighbour orientation */
+#pragma omp parallel for schedule(static)
     for (int f = 0; f < nf; ++f) dV[f] = 0.0;
     /* each face is written by one cell only: its upwind cell, or the owner of an inflow face */
 #pragma omp parallel for schedule(dynamic, 256)
@@ -991,9 +992,6 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
         cur[c] = alpha[c] - sum / m->V[c];
     }
     for (int c = 0; c < nc; ++c) s.vol_before += alpha[c] * m->V[c];
-    for (int c = 0; c < nc; ++c)
-        for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e)
-            if (m->ce_other[e] < 0) s.vol_boundary += m->ce_sign[e] * dV[m->ce_flux[e]];
     if (tr && tr->alpha_raw) memcpy(tr->alpha_raw, cur, sizeof(double) * nc);
 
     /* R13 bounding: chop round-off excursions, redistribute larger ones over outflow faces (Jacobi), chop */
@@ -1011,8 +1009,10 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
     }
     double *delta = (double *)xmalloc(sizeof(double) * nf);
     double *dVc = (double *)xmalloc(sizeof(double) * nf);
-    memcpy(dVc, dV, sizeof(double) * nf);
+#pragma omp parallel for schedule(static)
+    for (int f = 0; f < nf; ++f) dVc[f] = dV[f];
     for (int it = 0; it < opt->n_bound_iter; ++it) {
+#pragma omp parallel for schedule(static)
         for (int f = 0; f < nf; ++f) delta[f] = 0.0;
         int n_off = 0;
         /* each outflow face's correction is written by its upwind cell only */
@@ -1064,6 +1064,12 @@ int or_step(const or_mesh *m, const or_opts *opt, const double *alpha, const dou
     if (opt->n_bound_iter == 0) {
         for (int c = 0; c < nc; ++c) if (cur[c] > 1.0 + tol || cur[c] < -tol) ++s.n_bound_active;
     }
+    /* volume that left through the boundary, with the redistribution's corrections of boundary
+     * faces (the redistribution preserves volume: what it moves out of the domain leaves through
+     * an outflow boundary face), so that vol_after = vol_before - vol_boundary + vol_clipped */
+    for (int c = 0; c < nc; ++c)
+        for (int e = m->ceptr[c]; e < m->ceptr[c + 1]; ++e)
+            if (m->ce_other[e] < 0) s.vol_boundary += m->ce_sign[e] * dVc[m->ce_flux[e]];
     if (opt->clip) {
         for (int c = 0; c < nc; ++c) {
             double x = cur[c];

@@ -30,14 +30,14 @@ class IsoOptions(C.Structure):
                 ("max_courant", C.c_double), ("root_max_iter", C.c_int32), ("n_bound_iter", C.c_int32),
                 ("clip", C.c_int32), ("check_inputs", C.c_int32), ("block_cells", C.c_int32),
                 ("surface_blocks", C.c_int32), ("max_surface", C.c_int32), ("surface_waves", C.c_int32),
-                ("bound_blocks", C.c_int32), ("us_mode", C.c_int32)]
+                ("bound_blocks", C.c_int32), ("us_mode", C.c_int32), ("root_tol", C.c_double)]
 
 
 class IsoStepStats(C.Structure):
     _fields_ = [("n_surface", C.c_int64), ("n_flat", C.c_int64), ("n_nonconverged", C.c_int64),
                 ("n_bound_active", C.c_int64), ("max_root_iter", C.c_int32), ("reserved", C.c_int32),
-                ("vol_before", C.c_double), ("vol_after", C.c_double), ("vol_clipped", C.c_double),
-                ("alpha_min", C.c_double), ("alpha_max", C.c_double)]
+                ("vol_before", C.c_double), ("vol_after", C.c_double), ("vol_boundary_flux", C.c_double),
+                ("vol_clipped", C.c_double), ("alpha_min", C.c_double), ("alpha_max", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

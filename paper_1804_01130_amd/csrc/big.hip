@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
                     for (; rounds < A.max_rounds; ++rounds) {
                         double dG;
                         const double g = G(u, dG);
-                        if (g == 0.0) { conv = true; ++rounds; break; }
+                        if (fabs(g) <= A.root_tol * V6) { conv = true; ++rounds; break; }  // g == 0 at 0
                         if (g > 0.0) { ua = u; ga = g; } else { ub = u; gb = g; }
                         double nu = dG < 0.0 ? u - g / dG : ua;
                         const bool newton = nu > ua && nu < ub;
@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
                         double x = x1 - f1 * (x1 - x0) / (f1 - f0v);
                         if (!(x > x0 && x < x1) || (rounds & 7) == 7) x = x0 + 0.5 * wdt;
                         const double fx = F(x, false);
-                        if (fx == 0.0 || fabs(fx) <= 4.0 * __DBL_EPSILON__) {
+                        if (fabs(fx) <= fmax(4.0 * __DBL_EPSILON__, A.root_tol)) {
                             x0 = x1 = x;
                             f0v = f1 = fx;
                             conv = true;

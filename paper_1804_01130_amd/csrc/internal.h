@@ -74,7 +74,9 @@ struct DevWork {
     int32_t *fmark = nullptr;      // [n_faces] zero between steps
     double *delta = nullptr;       // [3*n_faces] correction buffers (sweep mod 3), zero between steps
     double *dvcur = nullptr;       // [n_faces] current dV of faces in flist
-    double *red = nullptr;         // [64] reductions for stats
+    double *red = nullptr;         // [kRedSize] statistics: the results, then per-work-group partial values
+    double *sbnd = nullptr;        // [n_cells] volume through the cell's boundary faces (statistics only)
+    double *sclip = nullptr;       // [n_cells] volume the chops added to the cell (statistics only)
     int32_t cap = 0;
     // meshes with general polyhedra: a second stream (default priority) for their interface
     // kernel, forked once the interface list is built and joined before the update, so that it
@@ -82,6 +84,8 @@ struct DevWork {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
+
+constexpr int kRedSize = 8 + 6 * 256;  // statistics reduction buffer (see launch_stats)
 
 enum : int {
     kCntSurf = 0,       // interface cells found
@@ -121,6 +125,7 @@ struct Params {
     double eps_surf, flat_tol, bound_tol;
     int32_t root_max_iter, n_bound_iter, clip;
     int32_t us_mode;  // 0: U_S = U_P; 1: cell-point interpolation to x_S
+    double root_tol;  // isovalue search stops at |V_sub/V - alpha| <= root_tol (0: to round-off)
 };
 
 // Adjoint workspace (device pointers; allocated by a plan on its first adjoint step).  S = number of
@@ -183,6 +188,7 @@ struct BigArgs {
     double *dvs;
     int want_stats;
     iso_trace tr;
+    double root_tol;  // as Params::root_tol
 };
 hipError_t launch_surface_big(const BigArgs &a, hipStream_t s);
 

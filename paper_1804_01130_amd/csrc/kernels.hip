@@ -444,6 +444,7 @@ struct SurfArgs {
     int want_stats;
     iso_trace tr;
     const double *phi1, *U1;  // second time level, or nullptr
+    double root_tol;          // stop the isovalue search at |V_sub/V - alpha| <= root_tol (0: round-off)
 };
 
 // U_S . n_S of interface cell c (all lanes of its group).  U_S = U_P, or with us_mode 1 the
@@ -686,7 +687,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                     bool conv = false;
                     for (; rounds < A.max_rounds; ++rounds) {
                         const double g = G(u, dG);
-                        if (g == 0.0) { conv = true; ++rounds; break; }
+                        if (fabs(g) <= A.root_tol * V6) { conv = true; ++rounds; break; }  // g == 0 at 0
                         if (g > 0.0) { ua = u; ga = g; } else { ub = u; gb = g; }
                         double nu = dG < 0.0 ? u - g / dG : ua;
                         const bool newton = nu > ua && nu < ub;
@@ -751,7 +752,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
                         double x = x1 - f1 * (x1 - x0) / (f1 - f0);
                         if (!(x > x0 && x < x1) || (rounds & 7) == 7) x = x0 + 0.5 * wdt;
                         const double fx = F(x, false);
-                        if (fx == 0.0 || fabs(fx) <= 4.0 * __DBL_EPSILON__) {
+                        if (fabs(fx) <= fmax(4.0 * __DBL_EPSILON__, A.root_tol)) {
                             x0 = x1 = x;
                             f0 = f1 = fx;
                             conv = true;
@@ -882,6 +883,7 @@ struct UpdArgs {
     int n_iter;  // redistribution sweeps; with one or more the update runs the first sweep's phase A
     DevWork w;
     const double *phi1;  // second time level of the fluxes, or nullptr
+    int stats;  // per-cell volume through boundary faces and clipped volume into w.sbnd, w.sclip
 };
 
 // Bounding counters of sweep `it` live in one of four rotating slots: a slot is filled by the
@@ -932,7 +934,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
         }
         const bool sP = interface_cell(aP, A.eps);
         dtc = cell_dt(A.m, A.dt_dom, A.dt, c);
-        double sum = 0.0;
+        double sum = 0.0, bnd = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             if (v[k] == kEmpty) continue;
@@ -946,13 +948,19 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
                 dv = (o[k] >= 0 && interface_cell(ao[k], A.eps)) ? A.dvs[fid] : ao[k] * ph[k] * dtc;
             }
             sum += v[k] >= 0 ? dv : -dv;
+            if (o[k] < 0) bnd += dv;  // a boundary face: the cell owns it
             if (A.trace_dV && v[k] >= 0) A.trace_dV[fid] = dv;
         }
         x = aP - sum / V;
         if (A.trace_raw) A.trace_raw[c] = x;
+        const double x0 = x;
         if (A.clip) {
             if (x < 0.0 && x >= -A.tol) x = 0.0;
             else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
+        }
+        if (A.stats) {
+            A.w.sbnd[c] = bnd;
+            A.w.sclip[c] = (x - x0) * V;
         }
         offend = x > 1.0 + A.tol || x < -A.tol;
         __builtin_nontemporal_store(x, A.alpha_new + c);
@@ -994,6 +1002,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
         if (atomicExch(&A.w.cmark[c], 1) == 0) tsel[W] = c;
         const double need = over ? (x - 1.0) * V : -x * V;
         const double r = sumcap > 0.0 ? fmin(need / sumcap, 1.0) : 0.0;
+        double bcorr = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
@@ -1005,7 +1014,9 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             A.w.fmark[f] = 1;
             fsel[k] = f;
             if (o[k] >= 0 && atomicExch(&A.w.cmark[o[k]], 1) == 0) tsel[k] = o[k];
+            if (o[k] < 0) bcorr += dd;
         }
+        if (A.stats && bcorr != 0.0) A.w.sbnd[c] += bcorr;
 #pragma unroll
         for (int k = 0; k < W; ++k) ndl += fsel[k] >= 0 ? 1 : 0;
 #pragma unroll
@@ -1037,6 +1048,7 @@ struct BoundArgs {
     double *alpha_new;
     DevWork w;
     const double *phi1;  // second time level of the fluxes, or nullptr
+    int stats;  // add the sweeps' boundary-face corrections and clipped volumes to w.sbnd, w.sclip
 };
 
 // Redistribution sweeps (Jacobi), two phases per sweep.  (A) every cell out of bounds computes the
@@ -1093,11 +1105,13 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
             for (int k = 0; k < W; ++k)
                 if (v[k] != kEmpty) sum += v[k] >= 0 ? d[k] : -d[k];
             x = aq - sum / vq;
+            const double xb = x;
             if (A.clip) {
                 if (x < 0.0 && x >= -A.tol) x = 0.0;
                 else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
                 if (last) x = fmin(fmax(x, 0.0), 1.0);
             }
+            if (A.stats && x != xb) A.w.sclip[Q] += (x - xb) * vq;
             A.alpha_new[Q] = x;
             mark[Q] = 0;
             again = x > 1.0 + A.tol || x < -A.tol;
@@ -1150,6 +1164,7 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
             if (atomicExch(&mark_next[Q], 1) == 0) tsel[W] = Q;
             const double need = over ? (x - 1.0) * A.m.vol[Q] : -x * A.m.vol[Q];
             const double r = sumcap > 0.0 ? fmin(need / sumcap, 1.0) : 0.0;
+            double bcorr = 0.0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
@@ -1164,7 +1179,9 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
                     newf[k] = true;
                 }
                 if (nbr[k] >= 0 && atomicExch(&mark_next[nbr[k]], 1) == 0) tsel[k] = nbr[k];
+                if (nbr[k] < 0) bcorr += dd;
             }
+            if (A.stats && bcorr != 0.0) A.w.sbnd[Q] += bcorr;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 ndl += fsel[k] >= 0 ? 1 : 0;
@@ -1199,7 +1216,9 @@ __global__ void __launch_bounds__(1024) k_bound_end(BoundArgs A) {
             const int nO = counters[kCntOff];
             for (int i = tid; i < nO; i += nt) {
                 const int32_t P = A.w.olist[i];
-                A.alpha_new[P] = fmin(fmax(A.alpha_new[P], 0.0), 1.0);
+                const double x = A.alpha_new[P], y = fmin(fmax(x, 0.0), 1.0);
+                A.alpha_new[P] = y;
+                if (A.stats) A.w.sclip[P] += (y - x) * A.m.vol[P];
             }
         }
     } else {
@@ -1218,27 +1237,64 @@ __global__ void __launch_bounds__(1024) k_bound_end(BoundArgs A) {
     if (tid >= kCntBound && tid < kCntBound + 8) counters[tid] = 0;
 }
 
-__global__ void __launch_bounds__(1024) k_stats(const double *alpha, const double *alpha_new, const double *vol, int n,
-                                                double *red) {
-    __shared__ double sb[1024], sa[1024], smin[1024], smax[1024];
-    double b = 0, a = 0, mn = 1e300, mx = -1e300;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        b += alpha[c] * vol[c];
-        a += alpha_new[c] * vol[c];
-        mn = fmin(mn, alpha_new[c]);
-        mx = fmax(mx, alpha_new[c]);
-    }
+// Step statistics in two passes with a fixed order of summation (results do not depend on timing):
+// work-group b reduces the cells [b chunk, (b + 1) chunk) to six partial values, one work-group
+// then reduces those: volume before and after, smallest and largest alpha, clipped volume and the
+// volume that left through the boundary.
+constexpr int kStatBlocks = 256, kStatThreads = 256, kStatVals = 6;
+
+__device__ __forceinline__ void stat_reduce(double (&v)[kStatVals], double (*sh)[kStatThreads]) {
     const int t = threadIdx.x;
-    sb[t] = b; sa[t] = a; smin[t] = mn; smax[t] = mx;
+#pragma unroll
+    for (int i = 0; i < kStatVals; ++i) sh[i][t] = v[i];
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            sb[t] += sb[t + s]; sa[t] += sa[t + s];
-            smin[t] = fmin(smin[t], smin[t + s]); smax[t] = fmax(smax[t], smax[t + s]);
+    for (int h = kStatThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sh[0][t] += sh[0][t + h];
+            sh[1][t] += sh[1][t + h];
+            sh[2][t] = fmin(sh[2][t], sh[2][t + h]);
+            sh[3][t] = fmax(sh[3][t], sh[3][t + h]);
+            sh[4][t] += sh[4][t + h];
+            sh[5][t] += sh[5][t + h];
         }
         __syncthreads();
     }
-    if (t == 0) { red[0] = sb[0]; red[1] = sa[0]; red[2] = smin[0]; red[3] = smax[0]; red[4] = 0.0; }
+}
+
+__global__ void __launch_bounds__(kStatThreads) k_stats_part(const double *alpha, const double *alpha_new,
+                                                           const double *vol, const double *sclip,
+                                                           const double *sbnd, int n, double *part) {
+    __shared__ double sh[kStatVals][kStatThreads];
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int c0 = blockIdx.x * chunk, c1 = min(n, c0 + chunk);
+    double v[kStatVals] = {0.0, 0.0, 1e300, -1e300, 0.0, 0.0};
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += kStatThreads) {
+        const double V = vol[c], an = alpha_new[c];
+        v[0] += alpha[c] * V;
+        v[1] += an * V;
+        v[2] = fmin(v[2], an);
+        v[3] = fmax(v[3], an);
+        v[4] += sclip[c];
+        v[5] += sbnd[c];
+    }
+    stat_reduce(v, sh);
+    if (threadIdx.x < kStatVals) part[kStatVals * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kStatThreads) k_stats_final(const double *part, int nb, double *red) {
+    __shared__ double sh[kStatVals][kStatThreads];
+    double v[kStatVals] = {0.0, 0.0, 1e300, -1e300, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kStatThreads) {
+        const double *q = part + kStatVals * b;
+        v[0] += q[0];
+        v[1] += q[1];
+        v[2] = fmin(v[2], q[2]);
+        v[3] = fmax(v[3], q[3]);
+        v[4] += q[4];
+        v[5] += q[5];
+    }
+    stat_reduce(v, sh);
+    if (threadIdx.x < kStatVals) red[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 template <int W, bool kAvg>
@@ -1287,7 +1343,7 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
                        w.counters, tr.kind);
     if (ev) (void)hipEventRecord(ev[1], s);
     SurfArgs sa{m, a.alpha, a.phi, a.U, a.dt, a.dt_dom, p.eps_surf, p.flat_tol, p.root_max_iter, w.surf, w.counters,
-                w.cap, w.dvs, want_stats ? 1 : 0, tr, a.phi1, a.U1};
+                w.cap, w.dvs, want_stats ? 1 : 0, tr, a.phi1, a.U1, p.root_tol};
     const int bs = 256;  // the interface kernel's register budget assumes 256-thread work-groups
     const long groups_per_block = bs / kLanes;
     long gs = ((long)w.cap + groups_per_block - 1) / groups_per_block;
@@ -1302,7 +1358,7 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
             sb = w.side;
         }
         BigArgs bg{m, a.alpha, a.phi, a.U, a.phi1, a.U1, a.dt, p.flat_tol, p.root_max_iter, w.surf, w.counters,
-                   w.cap, w.dvs, want_stats ? 1 : 0, tr};
+                   w.cap, w.dvs, want_stats ? 1 : 0, tr, p.root_tol};
         const hipError_t e = launch_surface_big(bg, sb);
         if (e != hipSuccess) return e;
     }
@@ -1336,10 +1392,11 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
         if (e != hipSuccess) return e;
     }
     if (ev) (void)hipEventRecord(ev[2], s);
+    const int st = want_stats && w.sbnd && w.sclip ? 1 : 0;
     UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist,
-               w.counters, tr.dV, tr.alpha_raw, p.n_bound_iter, w, a.phi1};
+               w.counters, tr.dV, tr.alpha_raw, p.n_bound_iter, w, a.phi1, st};
     BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
-                 a.alpha_new, w, a.phi1};
+                 a.alpha_new, w, a.phi1, st};
     const bool avg = a.phi1 != nullptr;
     // more than six flux faces (general polyhedra): the plan pads the slots to width 8, 12 or 16
     switch (m.W * 2 + (avg ? 1 : 0)) {
@@ -1383,7 +1440,10 @@ hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_
 
 hipError_t launch_stats(const DevMesh &m, const DevWork &w, const double *alpha, const double *alpha_new,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, alpha, alpha_new, m.vol, m.n_cells, w.red);
+    // partial values after the eight results (the host copies red[0, 8))
+    hipLaunchKernelGGL(k_stats_part, dim3(kStatBlocks), dim3(kStatThreads), 0, s, alpha, alpha_new, m.vol, w.sclip,
+                       w.sbnd, m.n_cells, w.red + 8);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kStatThreads), 0, s, w.red + 8, kStatBlocks, w.red);
     return hipGetLastError();
 }
 

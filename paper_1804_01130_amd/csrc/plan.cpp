@@ -97,13 +97,14 @@ LaunchCfg launch_cfg(const iso_options &o) {
     return c;
 }
 Params step_params(const iso_options &o) {
-    return Params{o.eps_surf, o.flat_tol, o.bound_tol, o.root_max_iter, o.n_bound_iter, o.clip, o.us_mode};
+    return Params{o.eps_surf, o.flat_tol, o.bound_tol, o.root_max_iter, o.n_bound_iter, o.clip, o.us_mode, o.root_tol};
 }
 iso_status check_options(const iso_options &o, const iso_mesh *mesh) {
     if (!(o.eps_surf >= 0 && o.eps_surf < 0.5) || !(o.flat_tol >= 0) || !(o.bound_tol >= 0) || o.root_max_iter < 1 ||
         o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 ||
         o.surface_blocks < 0 || o.surface_blocks > 65535 || o.bound_blocks < 0 || o.bound_blocks > 65535 ||
-        o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1)
+        o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1 ||
+        !(o.root_tol >= 0 && o.root_tol < 1))
         return fail(ISO_EINVAL, "bad options");
     if (mesh->generic && o.us_mode != 0)
         return fail(ISO_EUNSUPPORTED, "the interpolated isoface velocity (us_mode 1) takes meshes of hexahedra only");
@@ -841,7 +842,8 @@ iso_status iso_plan_create(const iso_mesh *mesh, const iso_options *opt, void *s
               alloc((void **)&w.tlist, sizeof(int32_t) * 2 * (size_t)nc) && alloc((void **)&w.flist, sizeof(int32_t) * 4 * (size_t)nf) &&
               alloc((void **)&w.cmark, sizeof(int32_t) * 2 * (size_t)nc) && alloc((void **)&w.fmark, sizeof(int32_t) * nf) &&
               alloc((void **)&w.delta, sizeof(double) * 3 * (size_t)nf) && alloc((void **)&w.dvcur, sizeof(double) * nf) &&
-              alloc((void **)&w.red, sizeof(double) * 64);
+              alloc((void **)&w.red, sizeof(double) * kRedSize) && alloc((void **)&w.sbnd, sizeof(double) * (size_t)nc) &&
+              alloc((void **)&w.sclip, sizeof(double) * (size_t)nc);
     if (!ok || hipHostMalloc((void **)&p->host_counters, kCntNum * sizeof(int32_t)) != hipSuccess ||
         hipHostMalloc((void **)&p->host_red, 64 * sizeof(double)) != hipSuccess) {
         iso_plan_destroy(p);
@@ -941,6 +943,7 @@ static iso_status step_impl(iso_plan *p, const double *alpha, const double *phi,
         stats->alpha_min = hr[2];
         stats->alpha_max = hr[3];
         stats->vol_clipped = hr[4];
+        stats->vol_boundary_flux = hr[5];
         if (hc[kCntOverflow] > 0) return fail(ISO_ENOSPACE, "interface cells exceed max_surface");
     }
     return ISO_OK;

@@ -15,7 +15,8 @@ import wavegen as W
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 _PATCH = {"xmin": 0, "xmax": 1, "ymin": 2, "ymax": 3, "zmin": 4, "zmax": 5}
-_OPS = {ast.Add: operator.add, ast.Sub: operator.sub, ast.Mult: operator.mul, ast.Pow: operator.pow}
+_OPS = {ast.Add: operator.add, ast.Sub: operator.sub, ast.Mult: operator.mul, ast.Pow: operator.pow,
+        ast.Div: operator.truediv}
 
 
 def num(x):
@@ -78,6 +79,11 @@ def test_bounding_and_inflow_golden(oracle_lib, case, run):
     assert abs(st["vol_clipped"] - num(run["vol_clipped"])) <= 1e-14, st["vol_clipped"]
     if "n_bound_active" in run:
         assert st["n_bound_active"] == run["n_bound_active"]
+    assert abs(st["vol_boundary"] - num(run["vol_boundary"])) <= 1e-14, st["vol_boundary"]
+    # the step's volume balance: what is there after is what was there, less what left through
+    # the boundary, plus what the chop added
+    bal = st["vol_before"] - st["vol_boundary"] + st["vol_clipped"]
+    assert abs(st["vol_after"] - bal) <= 1e-14, (st["vol_after"], bal)
     # every cell is flat (equal vertex values), so none is reconstructed
     assert st["n_flat"] == st["n_surface"]
 

@@ -99,6 +99,8 @@ BOUNDING_MUTANTS = [
     ("cell_centre_is_vertex_mean", "for (int d = 0; d < 3; ++d) m->xc[3 * c + d] = mom[d] / vol;",
      "for (int d = 0; d < 3; ++d) m->xc[3 * c + d] = xr[d] + 0.0 * mom[d] / vol;"),
     ("roundoff_tolerance_raised", "double tol = opt->bound_tol;", "double tol = 1e-6 + 0.0 * opt->bound_tol;"),
+    ("boundary_volume_before_redistribution", "s.vol_boundary += m->ce_sign[e] * dVc[m->ce_flux[e]];",
+     "s.vol_boundary += m->ce_sign[e] * dV[m->ce_flux[e]];"),
 ]
 
 TANGENT_HEADER = "Tangent of the step (directional derivative"
