@@ -11,7 +11,8 @@ Prints ONE JSON line.  Fields beyond the basic contract:
                 over a second pass of the same K steps (the throughput pass has no event
                 between kernels: each event adds a dispatch gap); traffic from committed
                 rocprofv3 counters when they belong to the current kernel source, else null
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the same workload
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload, on every host CPU the
+                process may use (OpenMP over cells; the value) and on one thread, with the CPU model
   step_roofline the whole step's algorithmic bytes per cell-step x cell-steps/s / 8 TB/s
 """
 from __future__ import annotations
@@ -131,11 +132,29 @@ def step_bytes_per_cell(n_cells, n_flux, n_surface):
     return (24.0 * n_cells + 16.0 * n_flux + 1100.0 * n_surface) / n_cells
 
 
-def cpu_baseline(w, budget_s=20.0):
-    """The oracle as it stands on a bounded number of steps of the same workload."""
-    from oracle import oracle as O
-    O.build()
-    om = O.OracleMesh(w.mesh)
+def host_cpu():
+    """The host's logical CPU count, the CPUs this process may run on, and the CPU model."""
+    model = "unknown"
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except Exception:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count() or 1, "usable": usable, "model": model}
+
+
+def _oracle_rate(O, om, w, threads, budget_s):
+    """Cell-steps/s of the oracle on `threads` threads over the first steps of the workload that fit
+    in about budget_s seconds."""
+    O.set_threads(threads)
     phi, U = w.phi_U(0)
     a = np.array(w.alpha0, copy=True)
     t0 = time.perf_counter()
@@ -148,8 +167,24 @@ def cpu_baseline(w, budget_s=20.0):
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= w.n_steps or el / steps * (steps + 1) > 1.5 * budget_s:
             break
-    return {"value": w.mesh.n_cells * steps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} of {w.n_steps} steps of the same workload, single thread, {el:.1f} s"}
+    return w.mesh.n_cells * steps / el, steps, el
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The oracle as it stands on bounded samples of the same workload: on every CPU this process
+    may use (OpenMP over cells; the value reported) and on one thread."""
+    from oracle import oracle as O
+    O.build()
+    om = O.OracleMesh(w.mesh)
+    host = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", host["usable"]) or host["usable"])
+    v1, s1, e1 = _oracle_rate(O, om, w, 1, 0.35 * budget_s)
+    vn, sn, en = _oracle_rate(O, om, w, threads, 0.65 * budget_s)
+    return {"value": vn, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sn} of {w.n_steps} steps of the same workload on {threads} threads, {en:.1f} s",
+            "single_thread": {"value": v1, "unit": "cell-steps/s", "cores": 1,
+                              "sample": f"first {s1} of {w.n_steps} steps, {e1:.1f} s"},
+            "host": host}
 
 
 def copy_calibration(dev):
