@@ -45,20 +45,23 @@ COPY_N = 1 << 27  # doubles moved by the calibration copy (1 GiB read, 1 GiB wri
 KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update",
                "k_bound_sweep": "bound_sweep", "k_bound_end": "bound_end",
                "k_gfm_faces": "gfm_faces", "k_relax_blend": "relax_blend", "k_stats": "stats"}
-# the commands whose rocprofv3 output --summarize-profiles reads
+# the commands whose rocprofv3 output --summarize-profiles reads: the step window the default run
+# times (20 steps after 5 warm-up steps), with only the step's own kernels
+_PROF_ARGS = ("--steps 20 --warmup 5 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-gfm "
+              "--no-relax --no-poly")
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
-             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} --no-ensemble --no-adjoint --no-variants --no-poly",
+             "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS +
+             " > /root/repo/gpurun_out/prof_stats/bench.json",
     "fetch": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -T -f csv "
-             "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-poly --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
+             "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS +
+             " --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
     "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
-             "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} "
-             "--steps 5 --warmup 2 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-poly --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
+             "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS +
+             " --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
     "sq": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
           "SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU -T -f csv -d /root/repo/gpurun_out/prof_sq "
-          "-o run -- python3 /root/repo/bench.py --workload {w} --steps 3 --warmup 1 --no-cpu-baseline --no-ensemble "
-          "--no-adjoint --no-variants --no-poly > /root/repo/gpurun_out/prof_sq/bench.json",
+          "-o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS + " > /root/repo/gpurun_out/prof_sq/bench.json",
 }
 
 
@@ -236,12 +239,41 @@ def summarize_profiles(workload):
     import csv
     os.makedirs(PROFILES, exist_ok=True)
     cmds = {k: v.format(w=workload) for k, v in PROFILE_COMMANDS.items()}
-    stats = _find("gpurun_out/prof_stats", "kernel_stats.csv")
-    rows = list(csv.DictReader(open(stats)))
-    lines = [f"# rocprofv3 kernel statistics, workload {workload}",
+    run = json.loads(open(os.path.join(ROOT, "gpurun_out/prof_stats/bench.json")).read())
+    steps, warmup = int(run["steps"]), int(run["warmup"])
+    n_s = float(run["config"]["interface_cells"])
+    # every kernel of the step in launch order: warm-up steps, one step with statistics, the timed
+    # steps, the pass with an event around each kernel group (whose means the benchmark reports),
+    # and a pass with statistics
+    passes = warmup + 1 + 3 * steps
+    trace = list(csv.DictReader(open(_find("gpurun_out/prof_stats", "kernel_trace.csv"))))
+    by = {}
+    for r in sorted(trace, key=lambda r: int(r["Start_Timestamp"])):
+        k = _kernel_key(r["Kernel_Name"])
+        if k in ("find_surface", "surface", "update", "bound_sweep", "bound_end"):
+            by.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    lines = [f"# rocprofv3 kernel trace, workload {workload}: the window the benchmark line times",
              f"# command (repository root): {cmds['stats']}",
-             "# name | calls | total ms | average us | min us | max us | share %"]
-    for r in rows:
+             f"# kernel_source_sha: {run['kernel_source_sha']}",
+             f"# window: the {steps} steps after {warmup} warm-up steps, in the pass with an event around each "
+             f"kernel group; interface cells per step {n_s:.0f} on average "
+             f"({run['config']['interface_cells_range'][0]}-{run['config']['interface_cells_range'][1]})",
+             "# kernel | dispatches in the window | mean us | min us | max us"]
+    means = {}
+    for k, d in by.items():
+        per = len(d) // passes
+        if per * passes != len(d):
+            raise SystemExit(f"{k}: {len(d)} dispatches do not split into {passes} steps")
+        win = d[(warmup + 1 + steps) * per:(warmup + 1 + 2 * steps) * per]
+        means[k] = float(np.mean(win))
+        lines.append(f"k_{k} | {len(win)} | {means[k]:.2f} | {min(win):.2f} | {max(win):.2f}")
+    if "surface" in means:
+        tf = FLOP_PER_SURFACE_CELL * n_s / (means["surface"] * 1e-6) / 1e12
+        lines.append(f"# k_surface: {FLOP_PER_SURFACE_CELL:.0f} flop x {n_s:.0f} interface cells / {means['surface']:.2f} us"
+                     f" = {tf:.3f} TFLOP/s = {tf / FP64_VECTOR_TFLOPS:.4f} of the {FP64_VECTOR_TFLOPS} TFLOP/s FP64 peak"
+                     f" (the line reported {run['roofline']['frac']:.4f} from its own events)")
+    lines.append("# whole run (rocprofv3 --stats): name | calls | total ms | average us | min us | max us | share %")
+    for r in csv.DictReader(open(_find("gpurun_out/prof_stats", "kernel_stats.csv"))):
         lines.append(f"{r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}")
@@ -266,7 +298,10 @@ def summarize_profiles(workload):
              f"# FETCH_SIZE pass: {cmds['fetch']}",
              f"# WRITE_SIZE pass: {cmds['write']}",
              f"# calibration: elementwise copy of {COPY_N} doubles ({copy_bytes:.0f} B read, {copy_bytes:.0f} B "
-             f"written); counters read {cf:.0f} B fetched and {cw:.0f} B written",
+             f"written); counters read {cf:.0f} B fetched and {cw:.0f} B written.  The scales are these ratios, "
+             f"measured in the same run: FETCH_SIZE reports half of what the copy reads (consistent with the "
+             f"derived counter taking each read request as 64 B where this GPU moves 128 B per request; "
+             f"the ratio, not that reading, is what scales the kernels' counts)",
              "# <kernel>.fetch_kib / .write_kib: mean counter value per dispatch (KiB);"
              " bytes_per_launch = fetch x scale_fetch + write x scale_write",
              f"kernel_source_sha: {shas.pop()}",
@@ -677,6 +712,14 @@ def main():
         a, b = b, a
     torch.cuda.synchronize()
     kms, nrec = plan.timing()
+    # the interface cells of each step of the window: a third pass with statistics (untimed)
+    a.copy_(a_start)
+    ns = []
+    for n in range(args.warmup, n_steps_total):
+        _, stw = plan.step(a, phis[sel(n)], Us[sel(n)], w.dt, out=b, stats=True)
+        ns.append(stw["n_surface"])
+        a, b = b, a
+    n_surface = float(np.mean(ns))  # interface cells per step over the timed window
     variants = None if args.no_variants else variants_bench(gm, w, phis, Us, sel, a_start, args)
     gfm = None if args.no_gfm else gfm_bench(gm, plan, args.workload, a)
     relax = None if args.no_relax else relax_bench(plan, args.workload, a, torch.tensor(w.alpha0, device=dev))
@@ -731,6 +774,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "cells": cells, "flux_faces": n_flux, "interface_cells": n_surface,
+                   "interface_cells_range": [int(min(ns)), int(max(ns))],
                    "courant": 0.5 if args.workload != "cosine_2d" else 0.25, "dt": w.dt},
         "roofline": roof,
         "step_roofline": {"bytes_per_cell_step": b_alg, "achieved_GBs": b_alg * value / 1e9,
