@@ -698,16 +698,58 @@ __global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
                 }
             }
         }
+        // the adjoint along this direction: of vertex value dir (0..7) or of alpha_P (8); the
+        // transpose of the vertex interpolation gathers them (k_adj_points, k_adj_cells)
         const double gsum = grp_sum(contrib);
-        if (dir == 8) {
-            if (lv == 0) atomicAdd(&A.abar[c], gsum);
-        } else {
-            // transpose of the vertex interpolation: vertex dir's stencil cells
-            const int k = m.cpt[8 * (size_t)c + dir];
-            for (int e = m.st_ptr[k] + lv; e < m.st_ptr[k + 1]; e += kLanes)
-                atomicAdd(&A.abar[m.st_cell[e]], m.st_w[e] * gsum);
-        }
+        if (lv == 0) A.w.gbuf[9 * (size_t)c + dir] = gsum;
     }
+}
+
+// Transpose of the vertex interpolation, as two gathers in a fixed order (no atomics, so the
+// gradient is the same bits on every run): each point class sums the vertex adjoints of the
+// reconstructed cells that share it, then each cell adds its classes' sums times its weight in
+// their stencils.  A cell that shares a class twice (two of its vertices are periodic images of
+// one point) appears twice in the class's stencil, with one weight per image; its vertices are
+// summed at its first entry and each of its distinct classes is taken once.
+__global__ void __launch_bounds__(256) k_adj_points(AdjArgs A) {
+    const DevMesh &m = A.m;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m.n_classes) return;
+    const int e0 = m.st_ptr[k], e1 = m.st_ptr[k + 1];
+    double sum = 0.0;
+    for (int e = e0; e < e1; ++e) {
+        const int32_t c = m.st_cell[e];
+        bool first = true;
+        for (int e2 = e0; e2 < e; ++e2) first = first && m.st_cell[e2] != c;
+        if (!first || A.kind[c] != 1) continue;
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (m.cpt[8 * (size_t)c + v] == k) sum += A.w.gbuf[9 * (size_t)c + v];
+    }
+    A.w.pbar[k] = sum;
+}
+
+__global__ void __launch_bounds__(256) k_adj_cells(AdjArgs A) {
+    const DevMesh &m = A.m;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.n_cells) return;
+    double acc = A.abar[c];
+    if (A.kind[c] == 1) acc += A.w.gbuf[9 * (size_t)c + 8];
+    int32_t cls[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) cls[v] = m.cpt[8 * (size_t)c + v];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        bool seen = false;
+#pragma unroll
+        for (int u = 0; u < v; ++u) seen = seen || cls[u] == cls[v];
+        if (seen) continue;
+        const double pb = A.w.pbar[cls[v]];
+        if (pb == 0.0) continue;
+        for (int e = m.st_ptr[cls[v]]; e < m.st_ptr[cls[v] + 1]; ++e)
+            if (m.st_cell[e] == c) acc += m.st_w[e] * pb;
+    }
+    A.abar[c] = acc;
 }
 
 __global__ void k_fill_f64(double *p, int64_t n, double v) {
@@ -723,6 +765,8 @@ hipError_t launch_adj_w(const AdjArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_faces<W>, dim3(g), dim3(256), 0, s, a);
     const int gs = std::max(1, std::min(2048, (int)((9L * n * kLanes + 255) / 256)));
     hipLaunchKernelGGL(k_adj_surface, dim3(gs), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adj_points, dim3((a.m.n_classes + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adj_cells, dim3(g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

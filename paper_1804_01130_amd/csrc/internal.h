@@ -150,6 +150,8 @@ struct AdjWork {
     double *dvcurbar = nullptr;   // [nf]
     double *deltabar = nullptr;   // [nf]
     double *vbar = nullptr;       // [nf] adjoint of the swept integral of interface-upwind faces, times phi
+    double *gbuf = nullptr;       // [9 nc] reconstructed cells: adjoints of their 8 vertex values and of alpha_P
+    double *pbar = nullptr;       // [n_classes] adjoint of each point class's vertex value
 };
 struct AdjInputs {
     const double *vert_alpha;  // forward intermediates of the step

@@ -183,15 +183,19 @@ def test_gradient_of_fifty_steps_against_central_differences(misfit):
 
 
 def test_checkpoint_interval_does_not_change_the_gradient(misfit):
+    """The adjoint sums in a fixed order (no atomics), and the recomputed segments repeat the
+    forward bit for bit: the gradient is the same bits for every checkpoint interval, and on a
+    second run."""
+    import torch
     M = misfit
     alpha0 = to_dev(M["w"].alpha0)
     ref = _loss_and_grad(M, alpha0, M["phis"], every=10)
-    for every in (1, 7, 50):
+    for every in (1, 7, 50, 10):
         say(f"[gpu] checkpoint interval {every}")
         got = _loss_and_grad(M, alpha0, M["phis"], every=every)
         assert got[0] == ref[0]
         for g, r in ((got[1], ref[1]), (got[2], ref[2])):
-            assert float((g - r).abs().max()) <= 1e-12 * max(float(r.abs().max()), 1e-300)
+            assert torch.equal(g, r), float((g - r).abs().max())
 
 
 def test_adjoint_argument_errors():
