@@ -373,44 +373,60 @@ __device__ __forceinline__ int guess_interval(const double (&a)[8], const double
 }
 
 // ------------------------------------------------------------------------------------------ kernels
-constexpr int kFindBlock = 1024, kFindPerThread = 4;
+constexpr int kFindBlock = 1024, kFindPerThread = 8;
+constexpr int kFindWaves = kFindBlock / 64, kFindSlots = kFindPerThread * kFindWaves;  // 128 wave counts
+static_assert(kFindSlots == 128, "the block scan gives each lane of one wave two wave counts");
 
+// Interface cells into a list: every thread loads its kFindPerThread cells first (one coalesced
+// double per wave and round), each wave counts its hits per round with a ballot, one wave scans
+// the block's 128 counts (two per lane) and takes the block's slots with one atomic, and each hit
+// lands at its wave's offset plus its rank among the wave's hits.  List order does not affect any
+// result.
 __global__ void __launch_bounds__(kFindBlock) k_find_surface(const double *__restrict__ alpha, int n, double eps,
                                                              int32_t *__restrict__ list, int32_t cap,
                                                              int32_t *__restrict__ counters,
                                                              int32_t *__restrict__ kind) {
-    __shared__ int wcount[kFindPerThread * (kFindBlock / 64)];
-    __shared__ int block_base;
+    __shared__ int wcount[kFindSlots];
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     const size_t base = (size_t)blockIdx.x * kFindBlock * kFindPerThread;
+    double a[kFindPerThread];
+#pragma unroll
+    for (int k = 0; k < kFindPerThread; ++k) {
+        const size_t c = base + (size_t)k * kFindBlock + tid;
+        a[k] = c < (size_t)n ? alpha[c] : 0.0;
+    }
     bool s[kFindPerThread];
     uint64_t mask[kFindPerThread];
 #pragma unroll
     for (int k = 0; k < kFindPerThread; ++k) {
         const size_t c = base + (size_t)k * kFindBlock + tid;
-        s[k] = false;
-        if (c < (size_t)n) {
-            s[k] = interface_cell(alpha[c], eps);
-            if (kind) kind[c] = 0;
-        }
+        s[k] = c < (size_t)n && interface_cell(a[k], eps);
+        if (kind && c < (size_t)n) kind[c] = 0;
         mask[k] = __ballot(s[k]);
-        if (lane == 0) wcount[k * (kFindBlock / 64) + wid] = __popcll(mask[k]);
+        if (lane == 0) wcount[k * kFindWaves + wid] = __popcll(mask[k]);
     }
     __syncthreads();
-    if (tid == 0) {
-        int tot = 0;
-        for (int j = 0; j < kFindPerThread * (kFindBlock / 64); ++j) {
-            const int x = wcount[j];
-            wcount[j] = tot;
-            tot += x;
+    if (wid == 0) {
+        const int e0 = wcount[2 * lane], e1 = wcount[2 * lane + 1];
+        int incl = e0 + e1;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
         }
-        block_base = tot > 0 ? atomicAdd(&counters[kCntSurf], tot) : 0;
+        const int total = __shfl(incl, 63, 64);
+        int b = 0;
+        if (lane == 63 && total > 0) b = atomicAdd(&counters[kCntSurf], total);
+        b = __shfl(b, 63, 64);
+        const int ex = incl - e0 - e1;
+        wcount[2 * lane] = b + ex;
+        wcount[2 * lane + 1] = b + ex + e0;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kFindPerThread; ++k) {
         if (!s[k]) continue;
-        const int pos = block_base + wcount[k * (kFindBlock / 64) + wid] +
+        const int pos = wcount[k * kFindWaves + wid] +
                         (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask[k] >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask[k], 0u));
         if (pos < cap) list[pos] = (int32_t)(base + (size_t)k * kFindBlock + tid);
