@@ -632,29 +632,11 @@ __global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
             f.inv[i] = d.v != 0.0 ? dinv(d) : dc(0.0);
         }
         const double iso = A.iso[c];
-        // sub-volume at the isovalue and its rate along this direction at fixed isovalue
-        const Dl g0 = dcell_vsub6(f, dc(iso), nullptr, nullptr);
-        // rate with the isovalue (vertex values fixed)
-        DFace f0 = f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            f0.aq[i].d = 0.0;
-            f0.inv[i].d = 0.0;
-        }
-        const double gx = dcell_vsub6(f0, Dl{iso, 1.0}, nullptr, nullptr).d;
-        // at a jump of the sub-volume the isovalue is a vertex value and moves with it
-        const bool jump = fabs(g0.v - aP * V6) > 1e-9 * V6;
-        const uint64_t hit = __ballot(jump && lv < 8 && av == iso);
-        const int base = __lane_id() & ~(kLanes - 1);
-        const int mvert = (int)((hit >> base) & 0xFF);
-        const int vjump = mvert ? __ffs(mvert) - 1 : -1;
-        double xdot;
-        if (jump) xdot = (dir < 8 && dir == vjump) ? 1.0 : 0.0;
-        else xdot = gx != 0.0 ? -((dir < 8 ? g0.d : -V6)) / gx : 0.0;
-        // isoface along the direction
-        const Dl isod{iso, xdot};
+        // one pass along this direction: the sub-volume's rate (at fixed isovalue for a vertex
+        // value, along the isovalue for direction 8), and the isoface and swept integrals
+        const Dl isod{iso, dir == 8 ? 1.0 : 0.0};
         DV3 o, cseg;
-        dcell_vsub6(f, isod, &o, &cseg);
+        const Dl g0 = dcell_vsub6(f, isod, &o, &cseg);
         const Dl nrm = dnorm(cseg);
         double contrib = 0.0;
         if (nrm.v > 0.0) {
@@ -698,11 +680,43 @@ __global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
                 }
             }
         }
-        // the adjoint along this direction: of vertex value dir (0..7) or of alpha_P (8); the
-        // transpose of the vertex interpolation gathers them (k_adj_points, k_adj_cells)
+        // this direction's rate of six times the sub-volume and of the faces' adjoint-weighted swept
+        // integrals; k_adj_points and k_adj_cells combine them (adj_vertex, adj_alpha)
         const double gsum = grp_sum(contrib);
-        if (lv == 0) A.w.gbuf[9 * (size_t)c + dir] = gsum;
+        double *gb = A.w.gbuf + (size_t)kAdjG * c;
+        if (lv == 0) {
+            gb[dir] = g0.d;
+            gb[9 + dir] = gsum;
+        }
+        if (dir == 8) {
+            // at a jump of the sub-volume the isovalue is a vertex value and moves with it
+            const bool jump = fabs(g0.v - aP * V6) > 1e-9 * V6;
+            const uint64_t hit = __ballot(jump && av == iso);
+            const int mvert = (int)((hit >> (__lane_id() & ~(kLanes - 1))) & 0xFF);
+            if (lv == 0) {
+                gb[18] = jump ? (double)(mvert ? __ffs(mvert) - 1 : -1) : -2.0;
+                gb[19] = V6;
+            }
+        }
     }
+}
+
+// The isovalue moves with the volume constraint, so the adjoint of vertex value v is its rate at
+// fixed isovalue plus the isovalue's rate along v times the rate along the isovalue: with G the
+// rates of six times the sub-volume and C those of the adjoint-weighted swept integrals,
+// iso' = -G_v / G_iso, and alpha_P's is iso' = V6 / G_iso times C_iso.  At a jump the isovalue is
+// the jumping vertex's value (iso' = 1 for it, 0 otherwise, and 0 for alpha_P).
+__device__ __forceinline__ double adj_vertex(const double *gb, int v) {
+    const double jump = gb[18], gx = gb[8];
+    double xdot;
+    if (jump > -2.0) xdot = (double)v == jump ? 1.0 : 0.0;
+    else xdot = gx != 0.0 ? -gb[v] / gx : 0.0;
+    return gb[9 + v] + xdot * gb[17];
+}
+__device__ __forceinline__ double adj_alpha(const double *gb) {
+    const double gx = gb[8];
+    const double xdot = gb[18] > -2.0 ? 0.0 : (gx != 0.0 ? gb[19] / gx : 0.0);
+    return xdot * gb[17];
 }
 
 // Transpose of the vertex interpolation, as two gathers in a fixed order (no atomics, so the
@@ -724,7 +738,7 @@ __global__ void __launch_bounds__(256) k_adj_points(AdjArgs A) {
         if (!first || A.kind[c] != 1) continue;
 #pragma unroll
         for (int v = 0; v < 8; ++v)
-            if (m.cpt[8 * (size_t)c + v] == k) sum += A.w.gbuf[9 * (size_t)c + v];
+            if (m.cpt[8 * (size_t)c + v] == k) sum += adj_vertex(A.w.gbuf + (size_t)kAdjG * c, v);
     }
     A.w.pbar[k] = sum;
 }
@@ -734,7 +748,7 @@ __global__ void __launch_bounds__(256) k_adj_cells(AdjArgs A) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= m.n_cells) return;
     double acc = A.abar[c];
-    if (A.kind[c] == 1) acc += A.w.gbuf[9 * (size_t)c + 8];
+    if (A.kind[c] == 1) acc += adj_alpha(A.w.gbuf + (size_t)kAdjG * c);
     int32_t cls[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) cls[v] = m.cpt[8 * (size_t)c + v];

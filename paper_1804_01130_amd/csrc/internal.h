@@ -130,7 +130,7 @@ struct Params {
 
 // Adjoint workspace (device pointers; allocated by a plan on its first adjoint step).  S = number of
 // bounding sweeps (at least 1), nc cells, nf faces.
-enum : int { kAdjOff = 0, kAdjRecon = 1, kAdjNum = 8, kAdjMaxSweeps = 31 };
+enum : int { kAdjOff = 0, kAdjRecon = 1, kAdjNum = 8, kAdjMaxSweeps = 31, kAdjG = 20 };
 struct AdjWork {
     int32_t *counters = nullptr;  // [kAdjNum]
     double *x = nullptr;          // [nc] bounding state
@@ -150,7 +150,8 @@ struct AdjWork {
     double *dvcurbar = nullptr;   // [nf]
     double *deltabar = nullptr;   // [nf]
     double *vbar = nullptr;       // [nf] adjoint of the swept integral of interface-upwind faces, times phi
-    double *gbuf = nullptr;       // [9 nc] reconstructed cells: adjoints of their 8 vertex values and of alpha_P
+    double *gbuf = nullptr;       // [kAdjG nc] reconstructed cells: rates along their 8 vertex values and the
+                                  // isovalue (see adjoint.hip)
     double *pbar = nullptr;       // [n_classes] adjoint of each point class's vertex value
 };
 struct AdjInputs {

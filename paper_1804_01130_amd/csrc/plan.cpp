@@ -1080,7 +1080,7 @@ static iso_status adj_alloc(iso_plan *p) {
         alloc((void **)&w.dvcur, nf * 8) && alloc((void **)&w.touched, nf * 4) && alloc((void **)&w.delta, nf * 8) &&
         alloc((void **)&w.dVb, nf * 8) && alloc((void **)&w.phib, nf * 8) && alloc((void **)&w.dvcurbar, nf * 8) &&
         alloc((void **)&w.deltabar, nf * 8) && alloc((void **)&w.vbar, nf * 8) &&
-        alloc((void **)&w.gbuf, 9 * nc * 8) && alloc((void **)&w.pbar, std::max<size_t>(m->n_classes, 1) * 8) &&
+        alloc((void **)&w.gbuf, kAdjG * nc * 8) && alloc((void **)&w.pbar, std::max<size_t>(m->n_classes, 1) * 8) &&
         alloc((void **)&p->adj_vert, 8 * nc * 8) && alloc((void **)&p->adj_kind, nc * 4) &&
         alloc((void **)&p->adj_iso, nc * 8) && alloc((void **)&p->adj_dV, nf * 8) && alloc((void **)&p->adj_raw, nc * 8) &&
         alloc((void **)&p->adj_new, nc * 8);
