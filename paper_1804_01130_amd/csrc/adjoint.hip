@@ -300,22 +300,122 @@ struct AdjArgs {
     AdjWork w;
 };
 
-// per cell: start state of bounding, lists, per-face buffers cleared
+// Bounding replayed with a tape, then reversed, grid-wide: one kernel per forward sweep (phase B of
+// sweep s fused with phase A of sweep s+1, as in the step's own sweeps; phase A of sweep 0 runs in
+// k_adj_prep) and two per reversed sweep.  Tape per sweep s and listed cell (row s*nc + i, i its
+// place in the sweep's list): a, need, sumcap, r, then cap and dV-now per slot; flags: bit 0 over,
+// bit 1 r capped at 1, bit 2 sumcap > 0, bit 3+k slot k corrected, bit 10+k slot k read the running
+// dV (corrected in an earlier sweep).  List order never affects a result: each listed cell writes
+// only its own outflow faces and its own tape row, each touched cell only itself.
+//
+// Buffers that start every call at zero and are left so: the face marks (`touched`), two banks of
+// cell marks (sweep s uses bank s&1: phase B of sweep s clears what phase A of sweep s+1 sets in the
+// other bank), and three rotating correction buffers (sweep s writes s%3, the kernel of sweep s+1
+// reads it and clears s-1's).
+
+// Phase A of sweep s for listed cell P, row `row` of the sweep's list, with bounding state a: the
+// correction of each outflow face and the tape row; the cells it touches come back through tsel.
+template <int W>
+__device__ __forceinline__ void adj_correct(const AdjArgs &A, int s, int32_t P, int row, double a, int32_t *mark,
+                                            int32_t tsel[W + 1]) {
+    constexpr int R = 4 + 2 * W;
+    const int n = A.m.n_cells, nf = A.m.n_faces;
+    const DevMesh &m = A.m;
+    const AdjWork &w = A.w;
+    const bool over = a > 1.0 + A.tol;
+    const double dtc = cell_dt(m, A.dt_dom, A.dt, P);
+    int32_t v[W], fid[W];
+    double ph[W], cap[W], dvnow[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        v[k] = m.slot_face[(size_t)k * n + P];
+        fid[k] = v[k] >= 0 ? v[k] : ~v[k];
+        ph[k] = v[k] != kEmpty ? A.phi[fid[k]] : 0.0;
+    }
+    int flags = over ? 1 : 0;
+    double sumcap = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        cap[k] = 0.0;
+        dvnow[k] = 0.0;
+        if (v[k] == kEmpty) continue;
+        const double outphi = v[k] >= 0 ? ph[k] : -ph[k];
+        if (!(outphi > 0.0)) continue;
+        const bool tch = w.touched[fid[k]] != 0;
+        if (tch) flags |= 1 << (10 + k);
+        dvnow[k] = tch ? w.dvcur[fid[k]] : A.dV0[fid[k]];
+        const double outv = v[k] >= 0 ? dvnow[k] : -dvnow[k];
+        cap[k] = over ? outphi * dtc - outv : outv;
+        if (cap[k] > 0.0) sumcap += cap[k];
+    }
+    const double need = over ? (a - 1.0) * m.vol[P] : -a * m.vol[P];
+    double r = 0.0;
+    if (sumcap > 0.0) {
+        flags |= 4;
+        const double q = need / sumcap;
+        if (q > 1.0) flags |= 2;
+        r = fmin(q, 1.0);
+    }
+    if (atomicExch(&mark[P], 1) == 0) tsel[W] = P;
+    double *delta = w.delta + (size_t)(s % 3) * nf;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
+        flags |= 1 << (3 + k);
+        const double d = cap[k] * r;
+        const double dd = over ? (v[k] >= 0 ? d : -d) : (v[k] >= 0 ? -d : d);
+        delta[fid[k]] = dd;
+        w.dvcur[fid[k]] = dvnow[k] + dd;
+        w.touched[fid[k]] = 1;
+        const int32_t o = m.slot_nbr[(size_t)k * n + P];
+        if (o >= 0 && atomicExch(&mark[o], 1) == 0) tsel[k] = o;
+    }
+    double *rec = w.tape + ((size_t)s * n + row) * R;
+    rec[0] = a;
+    rec[1] = need;
+    rec[2] = sumcap;
+    rec[3] = r;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        rec[4 + k] = cap[k];
+        rec[4 + W + k] = dvnow[k];
+    }
+    w.tflag[(size_t)s * n + row] = flags;
+}
+
+// Append the cells a lane's corrections touched to sweep s's touched list (every lane of the wave).
+template <int W>
+__device__ __forceinline__ void adj_append_touched(const AdjArgs &A, int s, const int32_t tsel[W + 1]) {
+    int nt = 0;
+#pragma unroll
+    for (int k = 0; k <= W; ++k) nt += tsel[k] >= 0 ? 1 : 0;
+    int b = wave_append(nt, &A.w.counters[kAdjT + s]);
+    int32_t *T = A.w.tlist + (size_t)s * A.m.n_cells;
+#pragma unroll
+    for (int k = 0; k <= W; ++k)
+        if (tsel[k] >= 0) T[b++] = tsel[k];
+}
+
+// per cell: start state of bounding (and phase A of its first sweep), lists, per-face adjoint
+// buffers cleared
 template <int W>
 __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
     const int n = A.m.n_cells;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     bool offend = false, recon = false;
+    double x = 0.0;
     if (c < n) {
-        double x = A.raw[c];
+        x = A.raw[c];
         if (A.clip) {
             if (x < 0.0 && x >= -A.tol) x = 0.0;
             else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
         }
         A.w.x[c] = x;
-        A.w.xbar[c] = A.abar_new[c];
-        A.w.cflag[c] = 0;
         offend = x > 1.0 + A.tol || x < -A.tol;
+        // with no sweep, the final clip makes a cell out of bounds (beyond round-off) a constant
+        const bool clamped = A.n_iter == 0 && A.clip && offend && (x < -kRound || x > 1.0 + kRound);
+        A.w.xbar[c] = clamped ? 0.0 : A.abar_new[c];
+        A.w.cflag[c] = clamped ? 1 : 0;
         recon = A.kind[c] == 1;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -324,109 +424,70 @@ __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
                 A.w.dVb[v] = 0.0;
                 A.w.phib[v] = 0.0;
                 A.w.dvcurbar[v] = 0.0;
-                A.w.touched[v] = 0;
             }
         }
     }
-    const int bo = wave_append(offend ? 1 : 0, &A.w.counters[kAdjOff]);
-    if (offend) A.w.list[bo] = c;
     const int br = wave_append(recon ? 1 : 0, &A.w.counters[kAdjRecon]);
     if (recon) A.w.rlist[br] = c;
+    if (A.n_iter < 1) return;  // uniform
+    const int row = wave_append(offend ? 1 : 0, &A.w.counters[kAdjL]);
+    int32_t tsel[W + 1];
+#pragma unroll
+    for (int k = 0; k <= W; ++k) tsel[k] = -1;
+    if (offend) {
+        A.w.list[row] = c;
+        adj_correct<W>(A, 0, c, row, x, A.w.cmark, tsel);
+    }
+    adj_append_touched<W>(A, 0, tsel);
 }
 
-// Bounding replayed with a tape, then reversed (one work-group of 1024).  Tape per sweep s and
-// listed cell i (row s*nc + i): a, need, sumcap, r, then cap and dV-now per slot; flags: bit 0 over,
-// bit 1 r capped at 1, bit 2 sumcap > 0, bit 3+k slot k corrected, bit 10+k slot k read the
-// running dV (touched in an earlier sweep).
+// Phase B of sweep s: every touched cell applies its faces' corrections in ascending face order
+// (round-off chop; clamp on the last sweep); a cell still out of bounds runs phase A of sweep s+1.
 template <int W>
-__global__ void __launch_bounds__(1024) k_adj_bound(AdjArgs A) {
-    constexpr int R = 4 + 2 * W;
-    __shared__ int nL[32], nT[32];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int n = A.m.n_cells;
+__global__ void __launch_bounds__(256) k_adj_sweep(AdjArgs A, int s) {
+    const int n = A.m.n_cells, nf = A.m.n_faces;
     const DevMesh &m = A.m;
-    AdjWork &w = A.w;
-    if (tid == 0) {
-        nL[0] = w.counters[kAdjOff];
-        for (int s = 0; s < 32; ++s) nT[s] = 0;
-        for (int s = 1; s < 32; ++s) nL[s] = 0;
-    }
-    __syncthreads();
-    const int S = A.n_iter;
-    for (int s = 0; s < S; ++s) {
-        const int32_t *L = w.list + (size_t)s * n;
-        int32_t *T = w.tlist + (size_t)s * n;
-        const int nl = nL[s];
-        // corrections on the outflow faces of the listed cells
-        for (int i = tid; i < nl; i += nt) {
-            const int32_t P = L[i];
-            double *rec = w.tape + ((size_t)s * n + i) * R;
-            const double a = w.x[P];
-            const bool over = a > 1.0 + A.tol;
-            const double dtc = cell_dt(m, A.dt_dom, A.dt, P);
-            int32_t v[W], fid[W];
-            double ph[W], cap[W], dvnow[W];
-            int flags = over ? 1 : 0;
-            double sumcap = 0.0;
+    const AdjWork &w = A.w;
+    const int stride = gridDim.x * blockDim.x;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool last = s == A.n_iter - 1;
+    if (s >= 1) {  // sweep s-1's corrections were read by the previous kernel: clear them
+        const int np = w.counters[kAdjL + s - 1];
+        double *stale = w.delta + (size_t)((s - 1) % 3) * nf;
+        for (int i = t0; i < np; i += stride) {
+            const int32_t P = w.list[(size_t)(s - 1) * n + i];
+            const int flags = w.tflag[(size_t)(s - 1) * n + i];
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                v[k] = m.slot_face[(size_t)k * n + P];
-                fid[k] = v[k] >= 0 ? v[k] : ~v[k];
-                ph[k] = v[k] != kEmpty ? A.phi[fid[k]] : 0.0;
-                cap[k] = 0.0;
-                dvnow[k] = 0.0;
-                if (v[k] == kEmpty) continue;
-                const double outphi = v[k] >= 0 ? ph[k] : -ph[k];
-                if (!(outphi > 0.0)) continue;
-                const bool tch = w.touched[fid[k]] != 0;
-                if (tch) flags |= 1 << (10 + k);
-                dvnow[k] = tch ? w.dvcur[fid[k]] : A.dV0[fid[k]];
-                const double outv = v[k] >= 0 ? dvnow[k] : -dvnow[k];
-                cap[k] = over ? outphi * dtc - outv : outv;
-                if (cap[k] > 0.0) sumcap += cap[k];
-            }
-            const double need = over ? (a - 1.0) * m.vol[P] : -a * m.vol[P];
-            double r = 0.0;
-            if (sumcap > 0.0) {
-                flags |= 4;
-                const double q = need / sumcap;
-                if (q > 1.0) flags |= 2;
-                r = fmin(q, 1.0);
-            }
-            if (atomicExch(&w.cmark[P], 1) == 0) T[atomicAdd(&nT[s], 1)] = P;
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
-                flags |= 1 << (3 + k);
-                const double d = cap[k] * r;
-                const double dd = over ? (v[k] >= 0 ? d : -d) : (v[k] >= 0 ? -d : d);
-                w.delta[fid[k]] = dd;
-                w.dvcur[fid[k]] = dvnow[k] + dd;
-                w.touched[fid[k]] = 1;
-                const int32_t o = m.slot_nbr[(size_t)k * n + P];
-                if (o >= 0 && atomicExch(&w.cmark[o], 1) == 0) T[atomicAdd(&nT[s], 1)] = o;
-            }
-            rec[0] = a; rec[1] = need; rec[2] = sumcap; rec[3] = r;
-#pragma unroll
-            for (int k = 0; k < W; ++k) { rec[4 + k] = cap[k]; rec[4 + W + k] = dvnow[k]; }
-            w.tflag[(size_t)s * n + i] = flags;
+            for (int k = 0; k < W; ++k)
+                if (flags & (1 << (3 + k))) {
+                    const int32_t v = m.slot_face[(size_t)k * n + P];
+                    stale[v >= 0 ? v : ~v] = 0.0;
+                }
         }
-        __syncthreads();
-        // apply to every touched cell in ascending face order; chop; clamp on the last sweep
-        const bool last = s == S - 1;
-        const int ntc = nT[s];
-        for (int j = tid; j < ntc; j += nt) {
-            const int32_t Q = T[j];
+    }
+    const double *delta = w.delta + (size_t)(s % 3) * nf;
+    const int32_t *T = w.tlist + (size_t)s * n;
+    int32_t *mark = w.cmark + (size_t)(s & 1) * n;
+    int32_t *mark_next = w.cmark + (size_t)((s + 1) & 1) * n;
+    const int nT = w.counters[kAdjT + s];
+    const int nloop = (nT + 255) & ~255;  // whole work-groups iterate together
+    for (int i0 = blockIdx.x * blockDim.x; i0 < nloop; i0 += stride) {
+        const int i = i0 + threadIdx.x;
+        bool again = false;
+        int32_t Q = 0;
+        double x = 0.0;
+        if (i < nT) {
+            Q = T[i];
             double sum = 0.0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const int32_t vq = m.slot_face[(size_t)k * n + Q];
                 if (vq == kEmpty) continue;
-                const double d = w.delta[vq >= 0 ? vq : ~vq];
+                const double d = delta[vq >= 0 ? vq : ~vq];
                 sum += vq >= 0 ? d : -d;
             }
             const double x0 = w.x[Q] - sum / m.vol[Q];
-            double x = x0;
+            x = x0;
             if (A.clip) {
                 if (x < 0.0 && x >= -A.tol) x = 0.0;
                 else if (x > 1.0 && x <= 1.0 + A.tol) x = 1.0;
@@ -434,128 +495,119 @@ __global__ void __launch_bounds__(1024) k_adj_bound(AdjArgs A) {
             }
             if (fabs(x - x0) > kRound) w.cflag[Q] |= 1 << s;
             w.x[Q] = x;
-            w.cmark[Q] = 0;
-            if (x > 1.0 + A.tol || x < -A.tol) {
-                if (s + 1 < S) w.list[(size_t)(s + 1) * n + atomicAdd(&nL[s + 1], 1)] = Q;
-            }
+            mark[Q] = 0;
+            again = !last && (x > 1.0 + A.tol || x < -A.tol);
         }
-        __syncthreads();
-        // this sweep's corrections are applied: clear them
-        for (int i = tid; i < nl; i += nt) {
-            const int32_t P = L[i];
-            const int flags = w.tflag[(size_t)s * n + i];
+        if (last) continue;  // uniform
+        const int row = wave_append(again ? 1 : 0, &w.counters[kAdjL + s + 1]);
+        int32_t tsel[W + 1];
 #pragma unroll
-            for (int k = 0; k < W; ++k)
-                if (flags & (1 << (3 + k))) {
-                    const int32_t vp = m.slot_face[(size_t)k * n + P];
-                    w.delta[vp >= 0 ? vp : ~vp] = 0.0;
-                }
+        for (int k = 0; k <= W; ++k) tsel[k] = -1;
+        if (again) {
+            w.list[(size_t)(s + 1) * n + row] = Q;
+            adj_correct<W>(A, s + 1, Q, row, x, mark_next, tsel);
         }
-        __syncthreads();
+        adj_append_touched<W>(A, s + 1, tsel);
     }
-    if (S == 0 && A.clip) {
-        for (int i = tid; i < nL[0]; i += nt) {
-            const int32_t P = w.list[i];
-            const double x = w.x[P];
-            if (x < -kRound || x > 1.0 + kRound) w.cflag[P] |= 1;
+}
+
+// Reverse of sweep s, first half: the adjoint of each correction through the two cells it was
+// applied to (a cell chopped or clamped in sweep s passes nothing back: it was a constant), and the
+// chopped cells' adjoints zeroed.  The two sets are disjoint, so one kernel does both.  The forward
+// replay is over: its face marks and this sweep's corrections are cleared here.
+template <int W>
+__global__ void __launch_bounds__(256) k_adj_unsweep_apply(AdjArgs A, int s) {
+    const int n = A.m.n_cells, nf = A.m.n_faces;
+    const DevMesh &m = A.m;
+    const AdjWork &w = A.w;
+    const int stride = gridDim.x * blockDim.x;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nl = w.counters[kAdjL + s], nt = w.counters[kAdjT + s];
+    const int32_t *L = w.list + (size_t)s * n;
+    const int32_t *T = w.tlist + (size_t)s * n;
+    double *delta = w.delta + (size_t)(s % 3) * nf;
+    for (int i = t0; i < nl; i += stride) {
+        const int32_t P = L[i];
+        const int flags = w.tflag[(size_t)s * n + i];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (!(flags & (1 << (3 + k)))) continue;
+            const int32_t v = m.slot_face[(size_t)k * n + P];
+            const int32_t o = m.slot_nbr[(size_t)k * n + P];
+            const int32_t f = v >= 0 ? v : ~v;
+            const double sP = v >= 0 ? 1.0 : -1.0;
+            double db = 0.0;
+            if (!(w.cflag[P] & (1 << s))) db -= sP * w.xbar[P] / m.vol[P];
+            if (o >= 0 && !(w.cflag[o] & (1 << s))) db += sP * w.xbar[o] / m.vol[o];
+            w.deltabar[f] = db;
+            w.touched[f] = 0;
+            delta[f] = 0.0;
         }
-        __syncthreads();
-        for (int i = tid; i < nL[0]; i += nt) {
-            const int32_t P = w.list[i];
-            if (w.cflag[P] & 1) w.xbar[P] = 0.0;
-        }
-        return;
     }
-    // ---- reverse
-    for (int s = S - 1; s >= 0; --s) {
-        const int32_t *L = w.list + (size_t)s * n;
-        const int32_t *T = w.tlist + (size_t)s * n;
-        const int nl = nL[s], ntc = nT[s];
-        // adjoint of each correction through the cells it was applied to
-        for (int i = tid; i < nl; i += nt) {
-            const int32_t P = L[i];
-            const int flags = w.tflag[(size_t)s * n + i];
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                if (!(flags & (1 << (3 + k)))) continue;
-                const int32_t v = m.slot_face[(size_t)k * n + P];
-                const int32_t o = m.slot_nbr[(size_t)k * n + P];
-                const double sP = v >= 0 ? 1.0 : -1.0;
-                double db = 0.0;
-                if (!(w.cflag[P] & (1 << s))) db -= sP * w.xbar[P] / m.vol[P];
-                if (o >= 0 && !(w.cflag[o] & (1 << s))) db += sP * w.xbar[o] / m.vol[o];
-                w.deltabar[v >= 0 ? v : ~v] = db;
-            }
-        }
-        __syncthreads();
-        // through the apply: chopped or clamped cells are constants
-        for (int j = tid; j < ntc; j += nt) {
-            const int32_t Q = T[j];
-            if (w.cflag[Q] & (1 << s)) w.xbar[Q] = 0.0;
-        }
-        __syncthreads();
-        // through the corrections of each listed cell
-        for (int i = tid; i < nl; i += nt) {
-            const int32_t P = L[i];
-            const int flags = w.tflag[(size_t)s * n + i];
-            const double *rec = w.tape + ((size_t)s * n + i) * R;
-            const bool over = flags & 1;
-            const double need = rec[1], sumcap = rec[2], r = rec[3];
-            const double dtc = cell_dt(m, A.dt_dom, A.dt, P);
-            double capb[W], dvnb[W];
-            double rb = 0.0;
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                capb[k] = 0.0;
-                dvnb[k] = 0.0;
-                if (!(flags & (1 << (3 + k)))) continue;
-                const int32_t v = m.slot_face[(size_t)k * n + P];
-                const int32_t f = v >= 0 ? v : ~v;
-                const double s_ = v >= 0 ? 1.0 : -1.0;
-                const double ddb = w.deltabar[f] + w.dvcurbar[f];
-                const double d_b = over ? s_ * ddb : -s_ * ddb;
-                capb[k] = d_b * r;
-                rb += d_b * rec[4 + k];
-                dvnb[k] = w.dvcurbar[f];  // dvcur_after = dvnow + dd
-            }
-            double needb = 0.0, sumcapb = 0.0;
-            if ((flags & 4) && !(flags & 2)) {
-                needb = rb / sumcap;
-                sumcapb = -rb * r / sumcap;
-            }
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const double capk = rec[4 + k];
-                if (!(capk > 0.0) || !(flags & 4)) continue;
-                const int32_t v = m.slot_face[(size_t)k * n + P];
-                const int32_t f = v >= 0 ? v : ~v;
-                const double s_ = v >= 0 ? 1.0 : -1.0;
-                const double cb = capb[k] + sumcapb;
-                const double outvb = over ? -cb : cb;
-                if (over) w.phib[f] += cb * s_ * dtc;
-                dvnb[k] += s_ * outvb;
-                if (flags & (1 << (10 + k))) {
-                    w.dvcurbar[f] = dvnb[k];
-                } else {
-                    w.dVb[f] += dvnb[k];
-                    w.dvcurbar[f] = 0.0;
-                }
-            }
-            w.xbar[P] += needb * (over ? m.vol[P] : -m.vol[P]);
-        }
-        __syncthreads();
+    for (int j = t0; j < nt; j += stride) {
+        const int32_t Q = T[j];
+        if (w.cflag[Q] & (1 << s)) w.xbar[Q] = 0.0;
     }
-    // leave the running face state clean for the next call
-    for (int s = 0; s < S; ++s) {
-        const int32_t *L = w.list + (size_t)s * n;
-        for (int i = tid; i < nL[s]; i += nt) {
-            const int32_t P = L[i];
+}
+
+// Reverse of sweep s, second half: through the corrections of each listed cell, to its bounding
+// state, its outflow faces' fluxes and their dV (before bounding, or running from an earlier sweep).
+template <int W>
+__global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
+    constexpr int R = 4 + 2 * W;
+    const int n = A.m.n_cells;
+    const DevMesh &m = A.m;
+    const AdjWork &w = A.w;
+    const int stride = gridDim.x * blockDim.x;
+    const int nl = w.counters[kAdjL + s];
+    const int32_t *L = w.list + (size_t)s * n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += stride) {
+        const int32_t P = L[i];
+        const int flags = w.tflag[(size_t)s * n + i];
+        const double *rec = w.tape + ((size_t)s * n + i) * R;
+        const bool over = flags & 1;
+        const double sumcap = rec[2], r = rec[3];
+        const double dtc = cell_dt(m, A.dt_dom, A.dt, P);
+        double capb[W], dvnb[W];
+        double rb = 0.0;
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const int32_t v = m.slot_face[(size_t)k * n + P];
-                if (v != kEmpty) w.touched[v >= 0 ? v : ~v] = 0;
+        for (int k = 0; k < W; ++k) {
+            capb[k] = 0.0;
+            dvnb[k] = 0.0;
+            if (!(flags & (1 << (3 + k)))) continue;
+            const int32_t v = m.slot_face[(size_t)k * n + P];
+            const int32_t f = v >= 0 ? v : ~v;
+            const double s_ = v >= 0 ? 1.0 : -1.0;
+            const double ddb = w.deltabar[f] + w.dvcurbar[f];
+            const double d_b = over ? s_ * ddb : -s_ * ddb;
+            capb[k] = d_b * r;
+            rb += d_b * rec[4 + k];
+            dvnb[k] = w.dvcurbar[f];  // dvcur after = dV-now + correction
+        }
+        double needb = 0.0, sumcapb = 0.0;
+        if ((flags & 4) && !(flags & 2)) {
+            needb = rb / sumcap;
+            sumcapb = -rb * r / sumcap;
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const double capk = rec[4 + k];
+            if (!(capk > 0.0) || !(flags & 4)) continue;
+            const int32_t v = m.slot_face[(size_t)k * n + P];
+            const int32_t f = v >= 0 ? v : ~v;
+            const double s_ = v >= 0 ? 1.0 : -1.0;
+            const double cb = capb[k] + sumcapb;
+            const double outvb = over ? -cb : cb;
+            if (over) w.phib[f] += cb * s_ * dtc;
+            dvnb[k] += s_ * outvb;
+            if (flags & (1 << (10 + k))) {
+                w.dvcurbar[f] = dvnb[k];
+            } else {
+                w.dVb[f] += dvnb[k];
+                w.dvcurbar[f] = 0.0;
             }
         }
+        w.xbar[P] += needb * (over ? m.vol[P] : -m.vol[P]);
     }
 }
 
@@ -774,8 +826,13 @@ template <int W>
 hipError_t launch_adj_w(const AdjArgs &a, hipStream_t s) {
     const int n = a.m.n_cells;
     const int g = (n + 255) / 256;
+    const int gb = std::max(1, std::min(g, (int)kAdjBoundBlocks));
     hipLaunchKernelGGL(k_adj_prep<W>, dim3(g), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_adj_bound<W>, dim3(1), dim3(1024), 0, s, a);
+    for (int it = 0; it < a.n_iter; ++it) hipLaunchKernelGGL(k_adj_sweep<W>, dim3(gb), dim3(256), 0, s, a, it);
+    for (int it = a.n_iter - 1; it >= 0; --it) {
+        hipLaunchKernelGGL(k_adj_unsweep_apply<W>, dim3(gb), dim3(256), 0, s, a, it);
+        hipLaunchKernelGGL(k_adj_unsweep_correct<W>, dim3(gb), dim3(256), 0, s, a, it);
+    }
     hipLaunchKernelGGL(k_adj_faces<W>, dim3(g), dim3(256), 0, s, a);
     const int gs = std::max(1, std::min(2048, (int)((9L * n * kLanes + 255) / 256)));
     hipLaunchKernelGGL(k_adj_surface, dim3(gs), dim3(256), 0, s, a);

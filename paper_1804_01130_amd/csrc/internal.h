@@ -130,7 +130,10 @@ struct Params {
 
 // Adjoint workspace (device pointers; allocated by a plan on its first adjoint step).  S = number of
 // bounding sweeps (at least 1), nc cells, nf faces.
-enum : int { kAdjOff = 0, kAdjRecon = 1, kAdjNum = 8, kAdjMaxSweeps = 31, kAdjG = 20 };
+// adjoint counters: interface cells to reconstruct, then per sweep s the length of its list of
+// cells out of bounds (kAdjL + s) and of the cells its corrections touch (kAdjT + s)
+enum : int { kAdjRecon = 1, kAdjL = 8, kAdjT = 40, kAdjNum = 72, kAdjMaxSweeps = 31, kAdjG = 20,
+             kAdjBoundBlocks = 512 };
 struct AdjWork {
     int32_t *counters = nullptr;  // [kAdjNum]
     double *x = nullptr;          // [nc] bounding state
@@ -139,12 +142,12 @@ struct AdjWork {
     int32_t *list = nullptr;      // [S nc] cells listed in each sweep
     int32_t *tlist = nullptr;     // [S nc] cells touched in each sweep
     int32_t *rlist = nullptr;     // [nc] reconstructed interface cells
-    int32_t *cmark = nullptr;     // [nc] zero between calls
+    int32_t *cmark = nullptr;     // [2 nc] two banks of cell marks, zero between calls
     double *tape = nullptr;       // [S nc (4 + 2 W)]
     int32_t *tflag = nullptr;     // [S nc]
     double *dvcur = nullptr;      // [nf] running dV of corrected faces
-    int32_t *touched = nullptr;   // [nf]
-    double *delta = nullptr;      // [nf] zero between sweeps
+    int32_t *touched = nullptr;   // [nf] faces corrected in an earlier sweep, zero between calls
+    double *delta = nullptr;      // [3 nf] three rotating correction buffers, zero between calls
     double *dVb = nullptr;        // [nf] adjoint of dV before bounding, from bounding
     double *phib = nullptr;       // [nf] adjoint of phi, from bounding
     double *dvcurbar = nullptr;   // [nf]

@@ -1075,9 +1075,9 @@ static iso_status adj_alloc(iso_plan *p) {
     const bool ok =
         alloc((void **)&w.counters, kAdjNum * 4) && alloc((void **)&w.x, nc * 8) && alloc((void **)&w.xbar, nc * 8) &&
         alloc((void **)&w.cflag, nc * 4) && alloc((void **)&w.list, S * nc * 4) && alloc((void **)&w.tlist, S * nc * 4) &&
-        alloc((void **)&w.rlist, nc * 4) && alloc((void **)&w.cmark, nc * 4) &&
+        alloc((void **)&w.rlist, nc * 4) && alloc((void **)&w.cmark, 2 * nc * 4) &&
         alloc((void **)&w.tape, S * nc * (4 + 2 * (size_t)m->W) * 8) && alloc((void **)&w.tflag, S * nc * 4) &&
-        alloc((void **)&w.dvcur, nf * 8) && alloc((void **)&w.touched, nf * 4) && alloc((void **)&w.delta, nf * 8) &&
+        alloc((void **)&w.dvcur, nf * 8) && alloc((void **)&w.touched, nf * 4) && alloc((void **)&w.delta, 3 * nf * 8) &&
         alloc((void **)&w.dVb, nf * 8) && alloc((void **)&w.phib, nf * 8) && alloc((void **)&w.dvcurbar, nf * 8) &&
         alloc((void **)&w.deltabar, nf * 8) && alloc((void **)&w.vbar, nf * 8) &&
         alloc((void **)&w.gbuf, kAdjG * nc * 8) && alloc((void **)&w.pbar, std::max<size_t>(m->n_classes, 1) * 8) &&

@@ -54,6 +54,40 @@ def test_one_step_adjoint_matches_oracle_gradient(oracle_lib, name):
     assert np.abs(gp - op).max() <= 1e-9 * scale_p, (np.argmax(np.abs(gp - op)), np.abs(gp - op).max(), scale_p)
 
 
+@pytest.mark.parametrize("n_iter,clip", [(0, True), (0, False), (1, True), (2, False), (3, True), (5, True)])
+def test_adjoint_through_every_bounding_schedule(oracle_lib, n_iter, clip):
+    """The bounding adjoint (tape replay, then reversed sweeps, grid-wide) against the oracle's
+    gradient with the same options: no sweep (the final clip alone, or nothing), one sweep, several,
+    and more sweeps than the three rotating correction buffers; on a state where cells are out of
+    bounds after the update, through two calls in a row on one plan (its buffers must come back
+    clean)."""
+    O = oracle_lib
+    w = W.violent_3d(nx=8, ny=6, nz=6, steps=6)
+    opts = dict(n_bound_iter=n_iter, clip=clip)
+    a = _state_after(O, w, 3)
+    phi, U = w.phi_U(3)
+    om = O.OracleMesh(w.mesh)
+    _, st = om.step(a, phi, U, w.dt, opts=O.default_opts(**opts))
+    say(f"[gpu] adjoint through bounding: sweeps={n_iter} clip={clip} cells out of bounds {st['n_bound_active']}")
+    assert st["n_bound_active"] > 0
+    gm, plan = gpu_plan(w.mesh, **opts)
+    # the oracle's Jacobian, one exact tangent per input component, then two adjoint seeds
+    n, nf = w.mesh.n_cells, w.mesh.n_faces
+    oo = O.default_opts(**opts)
+    ja = np.array([om.step_tlm(a, phi, U, w.dt, dalpha=np.eye(1, n, k)[0], opts=oo)[1] for k in range(n)])
+    jp = np.array([om.step_tlm(a, phi, U, w.dt, dphi=np.eye(1, nf, f)[0], opts=oo)[1] for f in range(nf)])
+    seeds = [np.ones(n), np.random.default_rng(11).standard_normal(n)]
+    for bar in seeds:
+        ra, rp = ja @ bar, jp @ bar
+        ga, gp = _adjoint(plan, w, a, phi, U, bar)
+        # relative to the sum of the magnitudes the products add up (with the seed of ones and no
+        # clip, the flux gradient of the conserved total is zero up to round-off)
+        sa = max((np.abs(ja) @ np.abs(bar)).max(), 1e-300)
+        sp = max((np.abs(jp) @ np.abs(bar)).max(), 1e-300)
+        assert np.abs(ga - ra).max() <= 1e-9 * sa, (np.argmax(np.abs(ga - ra)), np.abs(ga - ra).max(), sa)
+        assert np.abs(gp - rp).max() <= 1e-9 * sp, (np.argmax(np.abs(gp - rp)), np.abs(gp - rp).max(), sp)
+
+
 def test_adjoint_keeps_each_rate_at_exact_ties(oracle_lib):
     """The small violent case is mirror-symmetric about y = 1/2: in the middle row of cells both
     ends of every y-edge carry the same value, so the distances of a face's vertices from the
