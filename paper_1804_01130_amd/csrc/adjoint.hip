@@ -383,6 +383,33 @@ __device__ __forceinline__ void adj_correct(const AdjArgs &A, int s, int32_t P, 
     w.tflag[(size_t)s * n + row] = flags;
 }
 
+// Append `count` entries per thread to a device-wide list with one atomic per work-group (whole
+// waves, at most 1024 threads, every one of which calls it).  Returns the index of this thread's first entry.
+__device__ __forceinline__ int block_append(int count, int32_t *counter) {
+    __shared__ int wsum[16];
+    __shared__ int base;
+    const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    int incl = count;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int j = 0; j < nw; ++j) {
+        const int t = wsum[j];
+        before += j < wid ? t : 0;
+        total += t;
+    }
+    if (threadIdx.x == 0) base = total > 0 ? atomicAdd(counter, total) : 0;
+    __syncthreads();
+    const int r = base + before + incl - count;
+    __syncthreads();  // wsum and base are reused by the next call
+    return r;
+}
+
 // Append the cells a lane's corrections touched to sweep s's touched list (every lane of the wave).
 template <int W>
 __device__ __forceinline__ void adj_append_touched(const AdjArgs &A, int s, const int32_t tsel[W + 1]) {
@@ -427,10 +454,10 @@ __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
             }
         }
     }
-    const int br = wave_append(recon ? 1 : 0, &A.w.counters[kAdjRecon]);
+    const int br = block_append(recon ? 1 : 0, &A.w.counters[kAdjRecon]);
     if (recon) A.w.rlist[br] = c;
     if (A.n_iter < 1) return;  // uniform
-    const int row = wave_append(offend ? 1 : 0, &A.w.counters[kAdjL]);
+    const int row = block_append(offend ? 1 : 0, &A.w.counters[kAdjL]);
     int32_t tsel[W + 1];
 #pragma unroll
     for (int k = 0; k <= W; ++k) tsel[k] = -1;
@@ -785,9 +812,10 @@ __global__ void __launch_bounds__(256) k_adj_points(AdjArgs A) {
     double sum = 0.0;
     for (int e = e0; e < e1; ++e) {
         const int32_t c = m.st_cell[e];
+        if (A.kind[c] != 1) continue;
         bool first = true;
         for (int e2 = e0; e2 < e; ++e2) first = first && m.st_cell[e2] != c;
-        if (!first || A.kind[c] != 1) continue;
+        if (!first) continue;
 #pragma unroll
         for (int v = 0; v < 8; ++v)
             if (m.cpt[8 * (size_t)c + v] == k) sum += adj_vertex(A.w.gbuf + (size_t)kAdjG * c, v);
