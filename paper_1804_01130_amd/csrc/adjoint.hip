@@ -2,18 +2,21 @@
 //
 // Given the adjoint of alpha_new, the step's inputs and its intermediates (vertex values, cell
 // kinds, isovalues, face volumes dV and the update before bounding, as the traced forward step
-// writes them), four launches produce the adjoints of alpha and phi:
-//   prep     per cell: the update's round-off chop, the cells the bounding sweeps start from, the
-//            list of reconstructed interface cells; per face buffers cleared
-//   bound    one work-group: the bounding sweeps are replayed with a tape (same arithmetic as the
-//            forward), then reversed (bounding step at the end of Section 3.2)
-//   faces    per cell, a gather over its flux faces: transposes of the flux-form update and of the
-//            bulk fluxes alpha_upwind phi dt; phi's adjoint through dV = phi * (dV/phi)
-//   surface  eight lanes per (interface cell, direction): the derivatives of the swept face
-//            integrals (Eqs. tv .. intaplus) with respect to the cell's 8 vertex values and
-//            alpha_P, by forward-mode dual numbers through the isoface, the isovalue moving with
-//            the volume constraint (implicit function); then the transpose of the vertex
-//            interpolation, scattered to the stencil cells
+// writes them), these launches produce the adjoints of alpha and phi:
+//   prep       per cell: the update's round-off chop, the cells the bounding sweeps start from
+//              (and their first corrections), the list of reconstructed interface cells; per
+//              face buffers cleared
+//   sweep      one per bounding sweep, grid-wide: the sweeps replayed with a tape (same
+//              arithmetic as the forward)
+//   unsweep    two per sweep, in reverse: the bounding step (end of Section 3.2) transposed
+//   faces      per cell, a gather over its flux faces: transposes of the flux-form update and of
+//              the bulk fluxes alpha_upwind phi dt; phi's adjoint through dV = phi * (dV/phi)
+//   surface    eight lanes per (interface cell, direction), nine directions (the cell's eight
+//              vertex values and its isovalue): rates of the sub-volume and of the swept face
+//              integrals (Eqs. tv .. intaplus) by forward-mode dual numbers through the isoface
+//   points     per point class, and cells, per cell: the isovalue moving with the volume
+//              constraint (implicit function) combines the rates, and the transpose of the
+//              vertex interpolation gathers them to the stencil cells in a fixed order
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
