@@ -100,6 +100,44 @@ def test_trajectory(O, name):
     assert err <= TOL_TRAJ
 
 
+@pytest.mark.parametrize("name", ["airy_128x64", "violent_32x16x16", "perturbed_10x7x6"])
+def test_root_tolerance_bounds_the_volume_error(O, name):
+    """root_tol (Section 3.2 leaves the isovalue's tolerance to the user): at 1e-6 the sub-volume
+    the oracle computes at each GPU isovalue meets alpha_P within 1e-6, the searches take fewer
+    rounds than at round-off, none fails to converge, and the step moves by at most a few times
+    the tolerance from the oracle's round-off step (each face's swept volume moves by at most
+    about the tolerance times the cell volume)."""
+    w = CASES[name]
+    say(f"[gpu] root_tol 1e-6: {name} cells={w.mesh.n_cells}")
+    gm, plan = gpu_plan(w.mesh, root_tol=1e-6)
+    _, plan0 = gpu_plan(w.mesh)
+    om = O.OracleMesh(w.mesh)
+    phi, U = w.phi_U(0)
+    g_new, g_st, g = gpu_traced_step(plan, gm, w.alpha0, phi, U, w.dt)
+    _, _, g0 = gpu_traced_step(plan0, gm, w.alpha0, phi, U, w.dt)
+    o_new, _, o = om.step(w.alpha0, phi, U, w.dt, trace=True)
+    _, V = om.geometry()
+    assert np.array_equal(g["kind"], o["kind"])
+    rec = np.nonzero(o["kind"] == 1)[0]
+    worst, at_jump = 0.0, 0
+    for c in rec:
+        fo = om.cut(c, o["a_pts"], o["iso"][c])["vsub"] / V[c] - w.alpha0[c]
+        if abs(fo) > 1e-12:  # the sub-volume jumps across alpha V: both sides take the vertex value
+            assert abs(g["iso"][c] - o["iso"][c]) <= 8 * np.finfo(float).eps
+            at_jump += 1
+            continue
+        e = abs(om.cut(c, o["a_pts"], g["iso"][c])["vsub"] / V[c] - w.alpha0[c])
+        worst = max(worst, e)
+        assert e <= 1e-6 + 1e-12, (c, e)
+    rounds, rounds0 = int(g["iters"][rec].sum()), int(g0["iters"][rec].sum())
+    err = float(np.abs(g_new - o_new).max())
+    say(f"[gpu]   worst |V_sub/V - alpha| {worst:.2e} over {len(rec)} cells ({at_jump} at a jump); "
+        f"rounds {rounds} vs {rounds0} at round-off; max |alpha_new - oracle| {err:.2e}")
+    assert g_st["n_nonconverged"] == 0
+    assert rounds < rounds0
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("n_iter,clip", [(0, 1), (0, 0), (1, 1), (2, 0), (5, 1)])
 def test_bounding_sweep_counts(O, n_iter, clip):
     """Every bounding schedule against the oracle with the same options: no sweep (chop only, or
