@@ -45,8 +45,9 @@ COPY_N = 1 << 27  # doubles moved by the calibration copy (1 GiB read, 1 GiB wri
 KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_update": "update",
                "k_bound_sweep": "bound_sweep", "k_bound_end": "bound_end",
                "k_gfm_faces": "gfm_faces", "k_relax_blend": "relax_blend", "k_stats": "stats"}
-# the commands whose rocprofv3 output --summarize-profiles reads: the step window the default run
-# times (20 steps after 5 warm-up steps), with only the step's own kernels
+# the commands whose rocprofv3 output --summarize-profiles reads: a window of 20 steps after 5
+# warm-up steps, with only the step's own kernels (the summaries record the window's interface-cell
+# count, so a line timed over another window compares at its own count)
 _PROF_ARGS = ("--steps 20 --warmup 5 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-gfm "
               "--no-relax --no-poly")
 PROFILE_COMMANDS = {

@@ -123,6 +123,23 @@ def test_launch_shapes_give_the_same_bits(name):
         assert np.array_equal(g, ref), opts
 
 
+@pytest.mark.parametrize("name", ["mixed_16x8x8", "merged_16x8x8", "merged_joined_perturbed_16x8x8",
+                                  "merged_sparse_16x8x8"])
+def test_capped_searches_are_counted_once_per_cell(name):
+    """With root_max_iter too small for the isovalue searches to finish, n_nonconverged counts each
+    capped cell once, in the eight-lane kernel and in the sixteen-lane polyhedron kernel alike: at
+    least one, and no more than the reconstructed cells whose trace shows the cap reached."""
+    w = CASES[name]
+    phi, U = w.phi_U(0)
+    cap = 4
+    gm, plan = gpu_plan(w.mesh, root_max_iter=cap)
+    _, st, tr = gpu_traced_step(plan, gm, w.alpha0, phi, U, w.dt)
+    capped = int(np.count_nonzero((tr["kind"] == 1) & (tr["iters"] >= cap)))
+    say(f"[gpu] root_max_iter {cap}: {name}: not converged {st['n_nonconverged']}, cells at the cap {capped}, "
+        f"interface cells {st['n_surface']}")
+    assert 1 <= st["n_nonconverged"] <= capped
+
+
 def test_hexahedra_only_entry_points_refuse_other_cells():
     import torch
     from paper_1804_01130_amd import Batch, IsoError, Mesh, Plan, default_options
