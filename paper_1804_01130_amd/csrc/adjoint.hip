@@ -4,16 +4,17 @@
 // kinds, isovalues, face volumes dV and the update before bounding, as the traced forward step
 // writes them), these launches produce the adjoints of alpha and phi:
 //   prep       per cell: the update's round-off chop, the cells the bounding sweeps start from
-//              (and their first corrections), the list of reconstructed interface cells; per
-//              face buffers cleared
+//              (and their first corrections); per face buffers cleared
 //   sweep      one per bounding sweep, grid-wide: the sweeps replayed with a tape (same
 //              arithmetic as the forward)
 //   unsweep    two per sweep, in reverse: the bounding step (end of Section 3.2) transposed
 //   faces      per cell, a gather over its flux faces: transposes of the flux-form update and of
-//              the bulk fluxes alpha_upwind phi dt; phi's adjoint through dV = phi * (dV/phi)
-//   surface    eight lanes per (interface cell, direction), nine directions (the cell's eight
-//              vertex values and its isovalue): rates of the sub-volume and of the swept face
-//              integrals (Eqs. tv .. intaplus) by forward-mode dual numbers through the isoface
+//              the bulk fluxes alpha_upwind phi dt; phi's adjoint through dV = phi * (dV/phi); and
+//              the interface cells' directions (their isovalue, and each vertex value a cut edge
+//              touches)
+//   surface    eight lanes per (interface cell, direction): rates of the sub-volume and of the
+//              swept face integrals (Eqs. tv .. intaplus) by forward-mode dual numbers through
+//              the isoface
 //   points     per point class, and cells, per cell: the isovalue moving with the volume
 //              constraint (implicit function) combines the rates, and the transpose of the
 //              vertex interpolation gathers them to the stencil cells in a fixed order
@@ -432,7 +433,7 @@ template <int W>
 __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
     const int n = A.m.n_cells;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    bool offend = false, recon = false;
+    bool offend = false;
     double x = 0.0;
     if (c < n) {
         x = A.raw[c];
@@ -446,7 +447,6 @@ __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
         const bool clamped = A.n_iter == 0 && A.clip && offend && (x < -kRound || x > 1.0 + kRound);
         A.w.xbar[c] = clamped ? 0.0 : A.abar_new[c];
         A.w.cflag[c] = clamped ? 1 : 0;
-        recon = A.kind[c] == 1;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const int32_t v = A.m.slot_face[(size_t)k * n + c];
@@ -457,8 +457,6 @@ __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
             }
         }
     }
-    const int br = block_append(recon ? 1 : 0, &A.w.counters[kAdjRecon]);
-    if (recon) A.w.rlist[br] = c;
     if (A.n_iter < 1) return;  // uniform
     const int row = block_append(offend ? 1 : 0, &A.w.counters[kAdjL]);
     int32_t tsel[W + 1];
@@ -643,10 +641,8 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
 
 // per cell: transposes of the update (through the round-off chop) and of the bulk fluxes
 template <int W>
-__global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
+__device__ __forceinline__ void adj_faces_cell(const AdjArgs &A, int c) {
     const int n = A.m.n_cells;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
     const DevMesh &m = A.m;
     auto pre = [&](int q) {  // adjoint of the update before its round-off chop
         const double x = A.raw[q];
@@ -680,17 +676,49 @@ __global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
     A.abar[c] = acc;
 }
 
-// interface cells: derivatives of the swept integrals along each vertex value and alpha_P
+// per cell: transposes of the update and the bulk fluxes; the interface cells' work list
+template <int W>
+__global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
+    const int n = A.m.n_cells;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) adj_faces_cell<W>(A, c);
+    // the interface-cell directions k_adj_surface differentiates along: the isovalue, and each vertex
+    // value that moves a cut point (a vertex no cut edge touches moves nothing: its rates are zero)
+    uint32_t need = 0;
+    if (c < n && A.kind[c] == 1) {
+        const double iso = A.iso[c];
+        uint32_t wet = 0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) wet |= (A.vert_alpha[8 * (size_t)c + v] > iso ? 1u : 0u) << v;
+#pragma unroll
+        for (int t = 0; t < 12; ++t)
+            if (((wet >> kEdge[t][0]) ^ (wet >> kEdge[t][1])) & 1u) need |= (1u << kEdge[t][0]) | (1u << kEdge[t][1]);
+        double *gb = A.w.gbuf + (size_t)kAdjG * c;
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (!((need >> v) & 1u)) {
+                gb[v] = 0.0;
+                gb[9 + v] = 0.0;
+            }
+        need |= 1u << 8;
+    }
+    int b = block_append(__popc(need), &A.w.counters[kAdjDirs]);
+    for (int d = 0; d < 9; ++d)
+        if ((need >> d) & 1u) A.w.dlist[b++] = ((int64_t)c << 4) | d;
+}
+
+// interface cells: rates of the sub-volume and the swept integrals along each listed direction
 __global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
     const DevMesh &m = A.m;
     const int lv = threadIdx.x & (kLanes - 1);
     const int ngrp = (gridDim.x * blockDim.x) / kLanes;
-    const int nrec = A.w.counters[kAdjRecon];
+    const int npair = A.w.counters[kAdjDirs];
     int fv[4];
     const int fwd = lane_face_loop(lv, fv);
-    for (int g = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; g < 9 * nrec; g += ngrp) {
-        const int c = A.w.rlist[g / 9];
-        const int dir = g % 9;  // 0..7: vertex value dir, 8: alpha_P
+    for (int g = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; g < npair; g += ngrp) {
+        const int64_t pr = A.w.dlist[g];
+        const int c = (int)(pr >> 4);
+        const int dir = (int)(pr & 15);  // 0..7: vertex value dir, 8: the isovalue
         const double aP = A.alpha[c];
         const double V6 = 6.0 * m.vol[c];
         const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
@@ -813,15 +841,24 @@ __global__ void __launch_bounds__(256) k_adj_points(AdjArgs A) {
     if (k >= m.n_classes) return;
     const int e0 = m.st_ptr[k], e1 = m.st_ptr[k + 1];
     double sum = 0.0;
-    for (int e = e0; e < e1; ++e) {
-        const int32_t c = m.st_cell[e];
-        if (A.kind[c] != 1) continue;
-        bool first = true;
-        for (int e2 = e0; e2 < e; ++e2) first = first && m.st_cell[e2] != c;
-        if (!first) continue;
+    // stencil entries eight at a time, their cells' kinds all in flight together; most classes
+    // have no reconstructed cell, and those skip the rest
+    for (int eb = e0; eb < e1; eb += 8) {
+        int32_t sc[8], kd[8];
 #pragma unroll
-        for (int v = 0; v < 8; ++v)
-            if (m.cpt[8 * (size_t)c + v] == k) sum += adj_vertex(A.w.gbuf + (size_t)kAdjG * c, v);
+        for (int j = 0; j < 8; ++j) sc[j] = eb + j < e1 ? m.st_cell[eb + j] : -1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) kd[j] = sc[j] >= 0 ? A.kind[sc[j]] : 0;
+        for (int j = 0; j < 8; ++j) {
+            if (kd[j] != 1) continue;
+            const int32_t c = sc[j];
+            bool first = true;
+            for (int e2 = e0; e2 < eb + j; ++e2) first = first && m.st_cell[e2] != c;
+            if (!first) continue;
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+                if (m.cpt[8 * (size_t)c + v] == k) sum += adj_vertex(A.w.gbuf + (size_t)kAdjG * c, v);
+        }
     }
     A.w.pbar[k] = sum;
 }
@@ -833,18 +870,19 @@ __global__ void __launch_bounds__(256) k_adj_cells(AdjArgs A) {
     double acc = A.abar[c];
     if (A.kind[c] == 1) acc += adj_alpha(A.w.gbuf + (size_t)kAdjG * c);
     int32_t cls[8];
+    double pb[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) cls[v] = m.cpt[8 * (size_t)c + v];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) pb[v] = A.w.pbar[cls[v]];  // all eight in flight together
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         bool seen = false;
 #pragma unroll
         for (int u = 0; u < v; ++u) seen = seen || cls[u] == cls[v];
-        if (seen) continue;
-        const double pb = A.w.pbar[cls[v]];
-        if (pb == 0.0) continue;
+        if (seen || pb[v] == 0.0) continue;
         for (int e = m.st_ptr[cls[v]]; e < m.st_ptr[cls[v] + 1]; ++e)
-            if (m.st_cell[e] == c) acc += m.st_w[e] * pb;
+            if (m.st_cell[e] == c) acc += m.st_w[e] * pb[v];
     }
     A.abar[c] = acc;
 }

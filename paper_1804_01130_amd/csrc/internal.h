@@ -130,9 +130,10 @@ struct Params {
 
 // Adjoint workspace (device pointers; allocated by a plan on its first adjoint step).  S = number of
 // bounding sweeps (at least 1), nc cells, nf faces.
-// adjoint counters: interface cells to reconstruct, then per sweep s the length of its list of
+// adjoint counters: the interface cells' (cell, direction) pairs to differentiate along, then per
+// sweep s the length of its list of
 // cells out of bounds (kAdjL + s) and of the cells its corrections touch (kAdjT + s)
-enum : int { kAdjRecon = 1, kAdjL = 8, kAdjT = 40, kAdjNum = 72, kAdjMaxSweeps = 31, kAdjG = 20,
+enum : int { kAdjDirs = 2, kAdjL = 8, kAdjT = 40, kAdjNum = 72, kAdjMaxSweeps = 31, kAdjG = 20,
              kAdjBoundBlocks = 512 };
 struct AdjWork {
     int32_t *counters = nullptr;  // [kAdjNum]
@@ -141,7 +142,6 @@ struct AdjWork {
     int32_t *cflag = nullptr;     // [nc] bit s: chopped or clamped in sweep s
     int32_t *list = nullptr;      // [S nc] cells listed in each sweep
     int32_t *tlist = nullptr;     // [S nc] cells touched in each sweep
-    int32_t *rlist = nullptr;     // [nc] reconstructed interface cells
     int32_t *cmark = nullptr;     // [2 nc] two banks of cell marks, zero between calls
     double *tape = nullptr;       // [S nc (4 + 2 W)]
     int32_t *tflag = nullptr;     // [S nc]
@@ -156,6 +156,7 @@ struct AdjWork {
     double *gbuf = nullptr;       // [kAdjG nc] reconstructed cells: rates along their 8 vertex values and the
                                   // isovalue (see adjoint.hip)
     double *pbar = nullptr;       // [n_classes] adjoint of each point class's vertex value
+    int64_t *dlist = nullptr;     // [9 nc] (cell << 4 | direction) pairs of the interface cells
 };
 struct AdjInputs {
     const double *vert_alpha;  // forward intermediates of the step

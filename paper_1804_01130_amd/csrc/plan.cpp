@@ -1075,12 +1075,13 @@ static iso_status adj_alloc(iso_plan *p) {
     const bool ok =
         alloc((void **)&w.counters, kAdjNum * 4) && alloc((void **)&w.x, nc * 8) && alloc((void **)&w.xbar, nc * 8) &&
         alloc((void **)&w.cflag, nc * 4) && alloc((void **)&w.list, S * nc * 4) && alloc((void **)&w.tlist, S * nc * 4) &&
-        alloc((void **)&w.rlist, nc * 4) && alloc((void **)&w.cmark, 2 * nc * 4) &&
+        alloc((void **)&w.cmark, 2 * nc * 4) &&
         alloc((void **)&w.tape, S * nc * (4 + 2 * (size_t)m->W) * 8) && alloc((void **)&w.tflag, S * nc * 4) &&
         alloc((void **)&w.dvcur, nf * 8) && alloc((void **)&w.touched, nf * 4) && alloc((void **)&w.delta, 3 * nf * 8) &&
         alloc((void **)&w.dVb, nf * 8) && alloc((void **)&w.phib, nf * 8) && alloc((void **)&w.dvcurbar, nf * 8) &&
         alloc((void **)&w.deltabar, nf * 8) && alloc((void **)&w.vbar, nf * 8) &&
         alloc((void **)&w.gbuf, kAdjG * nc * 8) && alloc((void **)&w.pbar, std::max<size_t>(m->n_classes, 1) * 8) &&
+        alloc((void **)&w.dlist, 9 * nc * 8) &&
         alloc((void **)&p->adj_vert, 8 * nc * 8) && alloc((void **)&p->adj_kind, nc * 4) &&
         alloc((void **)&p->adj_iso, nc * 8) && alloc((void **)&p->adj_dV, nf * 8) && alloc((void **)&p->adj_raw, nc * 8) &&
         alloc((void **)&p->adj_new, nc * 8);
