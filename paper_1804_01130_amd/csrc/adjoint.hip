@@ -284,6 +284,12 @@ __device__ __forceinline__ Dl dtri_sweep(Dl d0, Dl d1, Dl d2, Dl un, double dt) 
 // larger one makes the value a constant.
 constexpr double kRound = 1e-14;
 
+// The update's round-off chop (a move of at most the bounding tolerance) passes the derivative
+// unless it moves the value by more than kRound: then the update is a constant there.
+__device__ __forceinline__ bool raw_chopped(double x, int clip, double tol) {
+    return clip && ((x < -kRound && x >= -tol) || (x > 1.0 + kRound && x <= 1.0 + tol));
+}
+
 struct AdjArgs {
     DevMesh m;
     const double *alpha, *phi, *U;
@@ -445,7 +451,9 @@ __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
         offend = x > 1.0 + A.tol || x < -A.tol;
         // with no sweep, the final clip makes a cell out of bounds (beyond round-off) a constant
         const bool clamped = A.n_iter == 0 && A.clip && offend && (x < -kRound || x > 1.0 + kRound);
-        A.w.xbar[c] = clamped ? 0.0 : A.abar_new[c];
+        const double xb = clamped ? 0.0 : A.abar_new[c];
+        A.w.xbar[c] = xb;
+        A.w.pv[c] = raw_chopped(A.raw[c], A.clip, A.tol) ? 0.0 : xb / A.m.vol[c];
         A.w.cflag[c] = clamped ? 1 : 0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -574,7 +582,10 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_apply(AdjArgs A, int s) {
     }
     for (int j = t0; j < nt; j += stride) {
         const int32_t Q = T[j];
-        if (w.cflag[Q] & (1 << s)) w.xbar[Q] = 0.0;
+        if (w.cflag[Q] & (1 << s)) {
+            w.xbar[Q] = 0.0;
+            w.pv[Q] = 0.0;
+        }
     }
 }
 
@@ -635,7 +646,9 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
                 w.dvcurbar[f] = 0.0;
             }
         }
-        w.xbar[P] += needb * (over ? m.vol[P] : -m.vol[P]);
+        const double xb = w.xbar[P] + needb * (over ? m.vol[P] : -m.vol[P]);
+        w.xbar[P] = xb;
+        w.pv[P] = raw_chopped(A.raw[P], A.clip, A.tol) ? 0.0 : xb / m.vol[P];
     }
 }
 
@@ -644,12 +657,9 @@ template <int W>
 __device__ __forceinline__ void adj_faces_cell(const AdjArgs &A, int c) {
     const int n = A.m.n_cells;
     const DevMesh &m = A.m;
-    auto pre = [&](int q) {  // adjoint of the update before its round-off chop
-        const double x = A.raw[q];
-        const bool chopped = A.clip && ((x < -kRound && x >= -A.tol) || (x > 1.0 + kRound && x <= 1.0 + A.tol));
-        return chopped ? 0.0 : A.w.xbar[q];
-    };
-    const double bc = pre(c);
+    // adjoint of the update before its round-off chop, and the same over the volume (kept per cell
+    // by the kernels that change it, so a neighbour costs one load)
+    const double bc = raw_chopped(A.raw[c], A.clip, A.tol) ? 0.0 : A.w.xbar[c];
     const double Vc = m.vol[c];
     const bool recon = A.kind[c] == 1;
     const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
@@ -663,8 +673,8 @@ __device__ __forceinline__ void adj_faces_cell(const AdjArgs &A, int c) {
         const double ph = A.phi[f];
         // alpha_raw(owner) -= dV/V_owner, alpha_raw(neighbour) += dV/V_neighbour
         double dvb;
-        if (v >= 0) dvb = -bc / Vc + (o >= 0 ? pre(o) / m.vol[o] : 0.0);
-        else dvb = -(o >= 0 ? pre(o) / m.vol[o] : 0.0) + bc / Vc;
+        if (v >= 0) dvb = -bc / Vc + (o >= 0 ? A.w.pv[o] : 0.0);
+        else dvb = -(o >= 0 ? A.w.pv[o] : 0.0) + bc / Vc;
         dvb += A.w.dVb[f];
         const double out = v >= 0 ? ph : -ph;
         if (out > 0.0) {
@@ -680,7 +690,7 @@ __device__ __forceinline__ void adj_faces_cell(const AdjArgs &A, int c) {
 template <int W>
 __global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
     const int n = A.m.n_cells;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;  // contiguous ranges per XCD
     if (c < n) adj_faces_cell<W>(A, c);
     // the interface-cell directions k_adj_surface differentiates along: the isovalue, and each vertex
     // value that moves a cut point (a vertex no cut edge touches moves nothing: its rates are zero)

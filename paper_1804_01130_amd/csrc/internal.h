@@ -139,6 +139,7 @@ struct AdjWork {
     int32_t *counters = nullptr;  // [kAdjNum]
     double *x = nullptr;          // [nc] bounding state
     double *xbar = nullptr;       // [nc] its adjoint
+    double *pv = nullptr;         // [nc] adjoint of the update before its round-off chop, over the volume
     int32_t *cflag = nullptr;     // [nc] bit s: chopped or clamped in sweep s
     int32_t *list = nullptr;      // [S nc] cells listed in each sweep
     int32_t *tlist = nullptr;     // [S nc] cells touched in each sweep

@@ -1073,7 +1073,7 @@ static iso_status adj_alloc(iso_plan *p) {
         return hipMemset(*ptr, 0, std::max<size_t>(bytes, 256)) == hipSuccess;
     };
     const bool ok =
-        alloc((void **)&w.counters, kAdjNum * 4) && alloc((void **)&w.x, nc * 8) && alloc((void **)&w.xbar, nc * 8) &&
+        alloc((void **)&w.counters, kAdjNum * 4) && alloc((void **)&w.x, nc * 8) && alloc((void **)&w.xbar, nc * 8) && alloc((void **)&w.pv, nc * 8) &&
         alloc((void **)&w.cflag, nc * 4) && alloc((void **)&w.list, S * nc * 4) && alloc((void **)&w.tlist, S * nc * 4) &&
         alloc((void **)&w.cmark, 2 * nc * 4) &&
         alloc((void **)&w.tape, S * nc * (4 + 2 * (size_t)m->W) * 8) && alloc((void **)&w.tflag, S * nc * 4) &&
