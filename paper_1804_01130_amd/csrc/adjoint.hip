@@ -700,9 +700,22 @@ __global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
         uint32_t wet = 0;
 #pragma unroll
         for (int v = 0; v < 8; ++v) wet |= (A.vert_alpha[8 * (size_t)c + v] > iso ? 1u : 0u) << v;
+        if (A.m.cloop) {  // the edges of the cell's own face loops (a triangle's repeated point: none)
+            for (int k = 0; k < 6; ++k) {
+                const int32_t L = A.m.cloop[6 * (size_t)c + k];
+                if (!((L >> 12) & 1)) continue;
 #pragma unroll
-        for (int t = 0; t < 12; ++t)
-            if (((wet >> kEdge[t][0]) ^ (wet >> kEdge[t][1])) & 1u) need |= (1u << kEdge[t][0]) | (1u << kEdge[t][1]);
+                for (int i = 0; i < 4; ++i) {
+                    const int p = (L >> (3 * i)) & 7, q = (L >> (3 * ((i + 1) & 3))) & 7;
+                    if (((wet >> p) ^ (wet >> q)) & 1u) need |= (1u << p) | (1u << q);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 12; ++t)
+                if (((wet >> kEdge[t][0]) ^ (wet >> kEdge[t][1])) & 1u)
+                    need |= (1u << kEdge[t][0]) | (1u << kEdge[t][1]);
+        }
         double *gb = A.w.gbuf + (size_t)kAdjG * c;
 #pragma unroll
         for (int v = 0; v < 8; ++v)
@@ -724,11 +737,19 @@ __global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
     const int ngrp = (gridDim.x * blockDim.x) / kLanes;
     const int npair = A.w.counters[kAdjDirs];
     int fv[4];
-    const int fwd = lane_face_loop(lv, fv);
+    int fwd = lane_face_loop(lv, fv);
+    bool face_on = lv < 6;
     for (int g = (blockIdx.x * blockDim.x + threadIdx.x) / kLanes; g < npair; g += ngrp) {
         const int64_t pr = A.w.dlist[g];
         const int c = (int)(pr >> 4);
         const int dir = (int)(pr & 15);  // 0..7: vertex value dir, 8: the isovalue
+        if (m.cloop) {  // cells other than hexahedra: the cell's own face loops, as in the step
+            const int32_t L = lv < 6 ? m.cloop[6 * (size_t)c + lv] : 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fv[i] = (L >> (3 * i)) & 7;
+            fwd = (L >> 16) & 15;
+            face_on = (L >> 12) & 1;
+        }
         const double aP = A.alpha[c];
         const double V6 = 6.0 * m.vol[c];
         const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
@@ -738,7 +759,7 @@ __global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
         const D3 xm = 0.125 * grp_sum3(xv);
         xv = xv - xm;
         DFace f;
-        f.active = lv < 6;
+        f.active = face_on;
         f.planar = (m.cflags[c] >> min(lv, 5)) & 1;
         f.fwd = fwd;
 #pragma unroll

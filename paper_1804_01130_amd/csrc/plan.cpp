@@ -1100,7 +1100,8 @@ iso_status iso_advect_step_adjoint(iso_plan *p, const double *alpha, const doubl
     if (p->opt.n_bound_iter > kAdjMaxSweeps)
         return fail(ISO_EUNSUPPORTED, "the adjoint takes at most " + std::to_string(kAdjMaxSweeps) + " bounding sweeps");
     if (p->opt.us_mode != 0) return fail(ISO_EUNSUPPORTED, "the adjoint takes U_S = U_P (us_mode 0) only");
-    if (p->mesh->generic) return fail(ISO_EUNSUPPORTED, "the adjoint takes meshes of hexahedra only");
+    if (p->mesh->dev.cbig)
+        return fail(ISO_EUNSUPPORTED, "the adjoint takes hexahedra, tetrahedra, pyramids and prisms, not general polyhedra");
     if (fwd && (!fwd->vert_alpha || !fwd->kind || !fwd->iso || !fwd->dV || !fwd->alpha_raw))
         return fail(ISO_EINVAL, "forward trace needs vert_alpha, kind, iso, dV and alpha_raw");
     const iso_mesh *m = p->mesh;

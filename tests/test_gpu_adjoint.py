@@ -88,6 +88,33 @@ def test_adjoint_through_every_bounding_schedule(oracle_lib, n_iter, clip):
         assert np.abs(gp - rp).max() <= 1e-9 * sp, (np.argmax(np.abs(gp - rp)), np.abs(gp - rp).max(), sp)
 
 
+@pytest.mark.parametrize("kind,perturb", [("tet", 0.0), ("pyramid", 0.0), ("prism", 0.0), ("prism", 0.15),
+                                          ("mixed", 0.0)])
+def test_adjoint_on_cells_other_than_hexahedra(oracle_lib, kind, perturb):
+    """Tetrahedra, pyramids, prisms (flat, or with bent quadrilaterals) and hexahedra next to prisms:
+    every component of the adjoint against the oracle's Jacobian (one exact tangent per input
+    component), for two seeds."""
+    O = oracle_lib
+    w = W.poly_violent(kind, nx=8, ny=4, nz=4, steps=4, perturb=perturb)
+    n, nf = w.mesh.n_cells, w.mesh.n_faces
+    a = _state_after(O, w, 2)
+    phi, U = w.phi_U(2)
+    om = O.OracleMesh(w.mesh)
+    _, st = om.step(a, phi, U, w.dt)
+    say(f"[gpu] adjoint on {kind} (perturb {perturb}): {n} cells, {st['n_surface']} interface cells")
+    assert st["n_surface"] > 10
+    ja = np.array([om.step_tlm(a, phi, U, w.dt, dalpha=np.eye(1, n, k)[0])[1] for k in range(n)])
+    jp = np.array([om.step_tlm(a, phi, U, w.dt, dphi=np.eye(1, nf, f)[0])[1] for f in range(nf)])
+    gm, plan = gpu_plan(w.mesh)
+    for bar in (np.ones(n), np.random.default_rng(13).standard_normal(n)):
+        ga, gp = _adjoint(plan, w, a, phi, U, bar)
+        ra, rp = ja @ bar, jp @ bar
+        sa = max((np.abs(ja) @ np.abs(bar)).max(), 1e-300)
+        sp = max((np.abs(jp) @ np.abs(bar)).max(), 1e-300)
+        assert np.abs(ga - ra).max() <= 1e-9 * sa, (np.argmax(np.abs(ga - ra)), np.abs(ga - ra).max(), sa)
+        assert np.abs(gp - rp).max() <= 1e-9 * sp, (np.argmax(np.abs(gp - rp)), np.abs(gp - rp).max(), sp)
+
+
 def test_adjoint_keeps_each_rate_at_exact_ties(oracle_lib):
     """The small violent case is mirror-symmetric about y = 1/2: in the middle row of cells both
     ends of every y-edge carry the same value, so the distances of a face's vertices from the

@@ -140,7 +140,7 @@ def test_capped_searches_are_counted_once_per_cell(name):
     assert 1 <= st["n_nonconverged"] <= capped
 
 
-def test_hexahedra_only_entry_points_refuse_other_cells():
+def test_entry_points_that_refuse_other_cells():
     import torch
     from paper_1804_01130_amd import Batch, IsoError, Mesh, Plan, default_options
     w = CASES["pyramid_8x4x4"]
@@ -149,11 +149,13 @@ def test_hexahedra_only_entry_points_refuse_other_cells():
         Plan(gm, default_options(us_mode=1))
     with pytest.raises(IsoError):
         Batch([gm], default_options())
-    plan = Plan(gm, default_options())
-    phi, U = w.phi_U(0)
-    a = to_dev(w.alpha0)
+    # the adjoint takes tetrahedra, pyramids and prisms, but not general polyhedra
+    wm = CASES["merged_16x8x8"]
+    plan = Plan(Mesh.from_arrays(wm.mesh), default_options())
+    phi, U = wm.phi_U(0)
+    a = to_dev(wm.alpha0)
     with pytest.raises(IsoError):
-        plan.adjoint(a, to_dev(phi), to_dev(U), w.dt, torch.ones_like(a))
+        plan.adjoint(a, to_dev(phi), to_dev(U), wm.dt, torch.ones_like(a))
 
 
 def test_ghost_fluid_faces_and_relaxation_on_prisms(oracle_lib):
