@@ -490,8 +490,11 @@ __device__ __forceinline__ double isoface_speed(const SurfArgs &A, int32_t c, in
         double best = -INFINITY;
         D3 val = Up;
         if (f.active) {
-            const D3 fc = 0.25 * (f.q[0] + f.q[1] + f.q[2] + f.q[3]);
-            const D3 uf = 0.25 * (uq[0] + uq[1] + uq[2] + uq[3]);
+            // the face's mean point and mean point velocity over its distinct points (a triangle
+            // repeats its first point last; its fourth tetrahedron is degenerate and skipped)
+            const bool tri = fv[3] == fv[0];
+            const D3 fc = tri ? (1.0 / 3.0) * (f.q[0] + f.q[1] + f.q[2]) : 0.25 * (f.q[0] + f.q[1] + f.q[2] + f.q[3]);
+            const D3 uf = tri ? (1.0 / 3.0) * (uq[0] + uq[1] + uq[2]) : 0.25 * (uq[0] + uq[1] + uq[2] + uq[3]);
             const D3 e1 = fc - cc, r = xS - cc;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -1380,12 +1383,19 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     }
     if (m.all_big) {
         // every cell is taken by the polyhedron kernel: nothing for the eight-lane one
-    } else if (m.cloop) {
+    } else if (m.cloop && p.us_mode == 0) {
         switch (cfg.surface_waves) {
             case 1: hipLaunchKernelGGL((k_surface<1, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
             case 3: hipLaunchKernelGGL((k_surface<3, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
             case 4: hipLaunchKernelGGL((k_surface<4, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
             default: hipLaunchKernelGGL((k_surface<2, false, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+        }
+    } else if (m.cloop && p.us_mode == 1) {
+        switch (cfg.surface_waves) {
+            case 1: hipLaunchKernelGGL((k_surface<1, true, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 3: hipLaunchKernelGGL((k_surface<3, true, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            case 4: hipLaunchKernelGGL((k_surface<4, true, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
+            default: hipLaunchKernelGGL((k_surface<2, true, true>), dim3((int)gs), dim3(bs), 0, s, sa); break;
         }
     } else if (p.us_mode == 1) {
         switch (cfg.surface_waves) {

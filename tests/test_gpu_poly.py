@@ -146,12 +146,13 @@ def test_entry_points_that_refuse_other_cells():
     w = CASES["pyramid_8x4x4"]
     gm = Mesh.from_arrays(w.mesh)
     with pytest.raises(IsoError):
-        Plan(gm, default_options(us_mode=1))
-    with pytest.raises(IsoError):
         Batch([gm], default_options())
-    # the adjoint takes tetrahedra, pyramids and prisms, but not general polyhedra
+    # us_mode 1 and the adjoint take tetrahedra, pyramids and prisms, but not general polyhedra
     wm = CASES["merged_16x8x8"]
-    plan = Plan(Mesh.from_arrays(wm.mesh), default_options())
+    gmm = Mesh.from_arrays(wm.mesh)
+    with pytest.raises(IsoError):
+        Plan(gmm, default_options(us_mode=1))
+    plan = Plan(gmm, default_options())
     phi, U = wm.phi_U(0)
     a = to_dev(wm.alpha0)
     with pytest.raises(IsoError):

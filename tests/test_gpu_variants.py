@@ -54,6 +54,22 @@ def test_interpolated_isoface_velocity(oracle_lib, name):
         assert np.abs(o - o0).max() > 1e-8
 
 
+@pytest.mark.parametrize("kind,perturb", [("tet", 0.0), ("pyramid", 0.0), ("prism", 0.15), ("mixed", 0.0)])
+def test_interpolated_isoface_velocity_on_other_cells(oracle_lib, kind, perturb):
+    """us_mode 1 on tetrahedra, pyramids, bent prisms and hexahedra next to prisms: triangular faces
+    are fanned about the mean of their three points, as in the oracle."""
+    w = W.poly_violent(kind, nx=12, ny=6, nz=6, steps=8, perturb=perturb)
+    say(f"[gpu] us_mode 1 trajectory on {kind} (perturb {perturb}): {w.mesh.n_cells} cells, {w.n_steps} steps")
+    gm, plan = gpu_plan(w.mesh, us_mode=1)
+    g = gpu_trajectory(plan, w, w.n_steps)
+    o = _oracle_run(oracle_lib, w, w.n_steps, oracle_lib.default_opts(us_mode=1))
+    o0 = _oracle_run(oracle_lib, w, w.n_steps, oracle_lib.default_opts(us_mode=0))
+    err = np.abs(g - o).max()
+    say(f"[gpu]   max |gpu - oracle| = {err:.3e}; us_mode 1 vs 0 in the oracle: {np.abs(o - o0).max():.3e}")
+    assert err <= TOL
+    assert np.abs(o - o0).max() > 1e-8
+
+
 def test_interpolated_isoface_velocity_in_the_trace(oracle_lib):
     """One step from the same state: the GPU's U_S . n_S per interface cell against the oracle's."""
     w = CASES["violent_32x16x16"]
