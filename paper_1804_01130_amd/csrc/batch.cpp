@@ -135,11 +135,13 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     if (hipGetDevice(&dev) != hipSuccess) return fail(ISO_EDEVICE, "no HIP device");
     int64_t N = 0, F = 0, K = 0, S = 0, P = 0, NF = 0;
     int32_t W = 1;
+    bool generic = false;
     for (int32_t i = 0; i < n; ++i) {
         const iso_mesh *m = meshes[i];
         if (!m) return fail(ISO_EINVAL, "null mesh in the ensemble");
         if (m->device != dev) return fail(ISO_EINVAL, "ensemble members must live on the current device");
-        if (m->generic) return fail(ISO_EUNSUPPORTED, "ensemble members must be meshes of hexahedra");
+        if (m->dev.cbig) return fail(ISO_EUNSUPPORTED, "ensemble members must not hold general polyhedra");
+        generic = generic || m->generic;
         N += m->n_cells; F += m->n_faces; K += m->n_classes; S += m->st_nnz; P += m->dev.n_patches;
         NF += m->n_flux;
         W = std::max(W, m->W);
@@ -171,6 +173,15 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         iso_batch_destroy(b);
         return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
     }
+    // members with cells other than hexahedra: every cell of the union takes its face loops from
+    // cloop, a hexahedron's in the directions the hexahedron kernels take, so that each member still
+    // computes bit for bit what it computes alone
+    int32_t *cloop = nullptr;
+    if (generic && !dev_alloc(u, &cloop, 6 * N)) {
+        iso_batch_destroy(b);
+        return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
+    }
+    std::vector<std::vector<int32_t>> hex_loops;  // host staging, alive until the copies are done
     hipStream_t s = b->stream;
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t x) {
@@ -199,6 +210,15 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
             }
         }
         ok(launch_offset_copy(md.lface, lface + 6 * co, 6 * nc, 1, (int32_t)fo, 0, s));
+        if (cloop && md.cloop) {
+            ok(hipMemcpyAsync(cloop + 6 * co, md.cloop, 6 * nc * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        } else if (cloop) {
+            hex_loops.emplace_back(6 * (size_t)nc);
+            std::vector<int32_t> &h = hex_loops.back();
+            for (int64_t c = 0; c < nc; ++c)
+                for (int k = 0; k < 6; ++k) h[6 * (size_t)c + k] = hex_loop_word(k);
+            ok(hipMemcpyAsync(cloop + 6 * co, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        }
         ok(launch_offset_copy(md.st_ptr, st_ptr + ko, m->n_classes, 0, (int32_t)so, 0, s));
         ok(launch_offset_copy(md.st_cell, st_cell + so, m->st_nnz, 0, (int32_t)co, 0, s));
         ok(hipMemcpyAsync(st_w + so, md.st_w, m->st_nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -221,7 +241,9 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     d.cxyz = cxyz; d.cpt = cpt; d.vol = vol; d.slot_face = sface; d.slot_nbr = snbr; d.lface = lface;
     d.cflags = cflags; d.st_ptr = st_ptr; d.st_cell = st_cell; d.st_w = st_w; d.patch_alpha = palpha;
     d.ccen = ccen;
+    d.cloop = cloop;
     d.n_dom = n; d.dom_off = dom_off;
+    u->generic = generic;
     u->n_cells = (int32_t)N; u->n_faces = (int32_t)F; u->n_classes = (int32_t)K; u->W = W;
     u->n_flux = (int32_t)NF; u->st_nnz = S;
 

@@ -41,9 +41,6 @@ __device__ __forceinline__ double cell_dt(const DevMesh &m, const double *dt_dom
 }
 
 // edges of the canonical hexahedron, and for each face loop position the edge to the next vertex
-constexpr int kEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
-                              {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
-constexpr int kFaceEdge[6][4] = {{3, 2, 1, 0}, {4, 5, 6, 7}, {0, 9, 4, 8}, {1, 10, 5, 9}, {2, 11, 6, 10}, {3, 8, 7, 11}};
 
 constexpr bool face_edges_consistent() {
     for (int k = 0; k < 6; ++k)

@@ -19,6 +19,22 @@ __host__ __device__ inline int32_t pack_face(int32_t fid, int sign) { return sig
 // Canonical hexahedron: vertices 0-3 bottom loop, 4-7 above them; faces listed counter-clockwise
 // seen from outside (bottom, top, y-, x+, y+, x- for an axis-aligned box).
 constexpr int kHexFace[6][4] = {{0, 3, 2, 1}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}};
+// Its edges (each with the end the cut computations start from first), and the edge under each
+// face's loop position.
+constexpr int kEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
+                              {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+constexpr int kFaceEdge[6][4] = {{3, 2, 1, 0}, {4, 5, 6, 7}, {0, 9, 4, 8}, {1, 10, 5, 9}, {2, 11, 6, 10}, {3, 8, 7, 11}};
+// A face's loop as one word (bits 3i..3i+2 the vertex at loop position i, bit 12 a face, bit 16+i
+// position i runs along its edge's direction): the canonical hexahedron's face k in the
+// directions the hexahedron kernels take (kEdge).
+constexpr int32_t hex_loop_word(int k) {
+    int32_t w = 1 << 12;
+    for (int i = 0; i < 4; ++i) {
+        w |= kHexFace[k][i] << (3 * i);
+        if (kEdge[kFaceEdge[k][i]][0] == kHexFace[k][i]) w |= 1 << (16 + i);
+    }
+    return w;
+}
 
 // Device view of a mesh, passed to kernels by value.
 struct DevMesh {

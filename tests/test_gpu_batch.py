@@ -21,13 +21,22 @@ def members():
             W.airy_slab(128, 32, 32, 0.09, 0.5, STEPS, "m4")]
 
 
-@pytest.fixture(scope="module")
-def ensemble():
+def members_of_all_cells():
+    """Tetrahedra, pyramids, bent prisms and hexahedra next to prisms, beside meshes of hexahedra
+    (2D and 3D)."""
+    return [W.poly_violent("tet", nx=8, ny=4, nz=4, steps=STEPS),
+            W.airy_slab(64, 32, 32, 0.05, 0.35, STEPS, "h1"),
+            W.poly_violent("prism", nx=12, ny=6, nz=6, steps=STEPS, perturb=0.15),
+            W.violent_3d(nx=16, ny=8, nz=8, steps=STEPS),
+            W.poly_violent("pyramid", nx=8, ny=4, nz=4, steps=STEPS),
+            W.poly_violent("mixed", nx=12, ny=6, nz=6, steps=STEPS)]
+
+
+def _build(ws, **opts):
     import torch
     from paper_1804_01130_amd import Batch, Mesh, Plan, default_options
-    ws = members()
     meshes = [Mesh.from_arrays(w.mesh) for w in ws]
-    batch = Batch(meshes, default_options())
+    batch = Batch(meshes, default_options(**opts))
     S = STEPS
     phi = torch.stack([torch.cat([to_dev(w.phi_U(n)[0]) for w in ws]) for n in range(S)]).contiguous()
     U = torch.stack([to_dev(batch.concat_U([w.phi_U(n)[1] for w in ws])) for n in range(S)]).contiguous()
@@ -36,7 +45,7 @@ def ensemble():
     # each member alone, eagerly, through its own plan
     alone = []
     for w, m in zip(ws, meshes):
-        plan = Plan(m, default_options())
+        plan = Plan(m, default_options(**opts))
         a = to_dev(w.alpha0)
         b = torch.empty_like(a)
         for n in range(S):
@@ -47,6 +56,11 @@ def ensemble():
         alone.append(a.cpu().numpy())
         plan.close()
     return dict(ws=ws, meshes=meshes, batch=batch, phi=phi, U=U, alpha0=alpha0, dts=dts, alone=alone)
+
+
+@pytest.fixture(scope="module")
+def ensemble():
+    return _build(members())
 
 
 def _run(E, steps=STEPS, alpha=None):
@@ -73,6 +87,24 @@ def test_batch_members_match_oracle(ensemble, oracle_lib):
         say(f"[gpu] ensemble member {d} vs oracle: {w.name}")
         ref = oracle_trajectory(oracle_lib.OracleMesh(w.mesh), w, STEPS)
         assert np.abs(got[d] - ref).max() <= 1e-10, (d, np.abs(got[d] - ref).max())
+
+
+@pytest.mark.parametrize("us_mode", [0, 1])
+def test_members_of_every_cell_type(oracle_lib, us_mode):
+    """Members with tetrahedra, pyramids and prisms run the generic interface kernel over the whole
+    ensemble, the hexahedral members with their faces in the hexahedron kernel's edge directions:
+    every member still equals itself stepped alone, bit for bit, and matches the oracle."""
+    E = _build(members_of_all_cells(), us_mode=us_mode)
+    say(f"[gpu] ensemble of every cell type, us_mode {us_mode}: {len(E['ws'])} members, "
+        f"{E['batch'].n_cells} cells, {STEPS} steps")
+    got = E["batch"].split_cells(_run(E).cpu().numpy())
+    for d, (g, ref) in enumerate(zip(got, E["alone"])):
+        assert np.array_equal(g, ref), (d, np.abs(g - ref).max())
+    for d, w in enumerate(E["ws"]):
+        ref = oracle_trajectory(oracle_lib.OracleMesh(w.mesh), w, STEPS,
+                                opts=oracle_lib.default_opts(us_mode=us_mode))
+        assert np.abs(got[d] - ref).max() <= 1e-10, (d, np.abs(got[d] - ref).max())
+    E["batch"].close()
 
 
 def test_graph_replays_with_work_in_between(ensemble):
