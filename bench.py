@@ -50,15 +50,17 @@ KERNEL_KEYS = {"k_find_surface": "find_surface", "k_surface": "surface", "k_upda
 # count, so a line timed over another window compares at its own count)
 _PROF_ARGS = ("--steps 20 --warmup 5 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-gfm "
               "--no-relax --no-poly")
+# the traffic passes also take the ghost-fluid face data and the relaxation blend (after the steps)
+_PROF_ARGS_TRAFFIC = "--steps 20 --warmup 5 --no-cpu-baseline --no-ensemble --no-adjoint --no-variants --no-poly"
 PROFILE_COMMANDS = {
     "stats": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
              "-d /root/repo/gpurun_out/prof_stats -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS +
              " > /root/repo/gpurun_out/prof_stats/bench.json",
     "fetch": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -T -f csv "
-             "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS +
+             "-d /root/repo/gpurun_out/prof_fetch -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS_TRAFFIC +
              " --copy-calibration > /root/repo/gpurun_out/prof_fetch/bench.json",
     "write": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE -T -f csv "
-             "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS +
+             "-d /root/repo/gpurun_out/prof_write -o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS_TRAFFIC +
              " --copy-calibration > /root/repo/gpurun_out/prof_write/bench.json",
     "sq": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
           "SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU -T -f csv -d /root/repo/gpurun_out/prof_sq "
