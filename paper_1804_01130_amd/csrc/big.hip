@@ -320,10 +320,14 @@ __device__ double face_sweep(const Pt *P, const FaceLoop<kFP> &L, D3 xS, D3 nS, 
     return accI / Af;
 }
 
-template <int kFP>
+// kInterp: U_S by cell-point interpolation (us_mode 1): the points' velocities (the vertex values'
+// inverse-distance weights) sit in LDS beside the points, and each lane tests the tetrahedra that
+// fan its face about the face's mean point with the cell centroid.
+template <int kFP, bool kInterp>
 __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) {
     __shared__ Pt spt[kGrpPerBlock][kBigPts];
     __shared__ double ssort[kGrpPerBlock][kBigPts];
+    __shared__ D3 svel[kInterp ? kGrpPerBlock : 1][kInterp ? kBigPts : 1];
     const DevMesh &m = A.m;
     const int g = threadIdx.x / kGrp, lf = threadIdx.x % kGrp;
     Pt *P = spt[g];
@@ -339,13 +343,13 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
         const double dtc = A.dt;
         // points lf and lf + 16: coordinates, their mean over the group, vertex values
         const int v0 = m.bv_ptr[bi], nv = m.bv_ptr[bi + 1] - v0;
-        D3 xp[2];
+        D3 xp[2], up[2];
         double ap[2];
         D3 xs{0, 0, 0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int i = lf + kGrp * h;
-            xp[h] = D3{0, 0, 0};
+            xp[h] = up[h] = D3{0, 0, 0};
             ap[h] = 0.0;
             if (i < nv) {
                 const double *q = m.bv_xyz + 3 * (size_t)(v0 + i);
@@ -356,6 +360,17 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
                 for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e) av += m.st_w[e] * A.alpha[m.st_cell[e]];
                 ap[h] = av;
                 xs = xs + xp[h];
+                if constexpr (kInterp) {
+                    const size_t nc = m.n_cells;
+                    D3 u{0, 0, 0};
+                    for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e) {
+                        const int32_t sc = m.st_cell[e];
+                        D3 us{A.U[sc], A.U[nc + sc], A.U[2 * nc + sc]};
+                        if (A.U1) us = 0.5 * (us + D3{A.U1[sc], A.U1[nc + sc], A.U1[2 * nc + sc]});
+                        u = u + m.st_w[e] * us;
+                    }
+                    up[h] = u;
+                }
             }
         }
         const D3 xm = (1.0 / nv) * g16_3(xs);
@@ -366,6 +381,7 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
             if (i < nv) {
                 const D3 x = xp[h] - xm;
                 P[i] = Pt{x.x, x.y, x.z, ap[h]};
+                if constexpr (kInterp) svel[g][i] = up[h];
             }
         }
         grp_sync();
@@ -528,7 +544,61 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
                 const size_t nc = m.n_cells;
                 D3 Up{A.U[c], A.U[nc + c], A.U[2 * nc + c]};
                 if (A.U1) Up = 0.5 * (Up + D3{A.U1[c], A.U1[nc + c], A.U1[2 * nc + c]});
-                un = dot(Up, nS);
+                D3 Us = Up;
+                if constexpr (kInterp) {
+                    // each lane keeps the tetrahedron of its face whose smallest barycentric
+                    // coordinate of x_S (Cramer's rule) is largest; the group takes the best
+                    // (lowest lane on a tie)
+                    const D3 cc = D3{m.ccen[3 * (size_t)c], m.ccen[3 * (size_t)c + 1], m.ccen[3 * (size_t)c + 2]} - xm;
+                    const D3 *Uv = svel[g];
+                    double best = -INFINITY;
+                    D3 val = Up;
+                    if (lf < nf) {
+                        // loop positions as compile-time indices where the face's points are held
+                        // in registers (faces of at most four points)
+                        constexpr int kMax = kFP <= 4 ? 4 : kFP;
+                        D3 fc{0, 0, 0}, uf{0, 0, 0};
+#pragma unroll
+                        for (int i = 0; i < kMax; ++i) {
+                            if (i < L.n) {
+                                const Pt q = fetch(P, L, i);
+                                fc = fc + D3{q.x, q.y, q.z};
+                                uf = uf + Uv[loop_at(L, i)];
+                            }
+                        }
+                        fc = (1.0 / L.n) * fc;
+                        uf = (1.0 / L.n) * uf;
+                        const D3 e1 = fc - cc, r = xS - cc;
+                        const Pt q0 = fetch(P, L, 0);
+#pragma unroll
+                        for (int i = 0; i < kMax; ++i) {
+                            if (i >= L.n) continue;
+                            const Pt qi = fetch(P, L, i);
+                            const Pt qj = i + 1 < L.n ? fetch(P, L, i + 1 < kMax ? i + 1 : 0) : q0;
+                            const int j = i + 1 < L.n ? i + 1 : 0;
+                            const D3 e2 = D3{qi.x, qi.y, qi.z} - cc, e3 = D3{qj.x, qj.y, qj.z} - cc;
+                            const D3 k23 = cross(e2, e3);
+                            const double det = dot(e1, k23);
+                            if (det == 0.0) continue;
+                            const double l1 = dot(r, k23) / det, l2 = dot(e1, cross(r, e3)) / det,
+                                         l3 = dot(e1, cross(e2, r)) / det;
+                            const double l0 = 1.0 - l1 - l2 - l3;
+                            const double mn = fmin(fmin(l0, l1), fmin(l2, l3));
+                            if (mn > best) {
+                                best = mn;
+                                val = l0 * Up + l1 * uf + l2 * Uv[loop_at(L, i)] + l3 * Uv[loop_at(L, j)];
+                            }
+                        }
+                    }
+                    double gb = best;
+#pragma unroll
+                    for (int off = 1; off < kGrp; off <<= 1) gb = fmax(gb, __shfl_xor(gb, off, kGrp));
+                    const uint64_t bal = __ballot(best == gb);
+                    const uint32_t gm = (uint32_t)(bal >> (__lane_id() & ~(kGrp - 1))) & 0xFFFFu;
+                    const int win = __ffs(gm) - 1;
+                    Us = D3{__shfl(val.x, win, kGrp), __shfl(val.y, win, kGrp), __shfl(val.z, win, kGrp)};
+                }
+                un = dot(Us, nS);
             } else {
                 recon = false;
             }
@@ -577,10 +647,14 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
 
 hipError_t launch_surface_big(const BigArgs &a, hipStream_t s) {
     const int blocks = std::max(1, std::min(1024, (a.cap + kGrpPerBlock - 1) / kGrpPerBlock));
-    if (a.m.big_face_pts <= 4)
-        hipLaunchKernelGGL(k_surface_big<4>, dim3(blocks), dim3(kGrp * kGrpPerBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_surface_big<kBigFacePts>, dim3(blocks), dim3(kGrp * kGrpPerBlock), 0, s, a);
+    const dim3 g(blocks), b(kGrp * kGrpPerBlock);
+    if (a.m.big_face_pts <= 4) {
+        if (a.us_mode == 1) hipLaunchKernelGGL((k_surface_big<4, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_surface_big<4, false>), g, b, 0, s, a);
+    } else {
+        if (a.us_mode == 1) hipLaunchKernelGGL((k_surface_big<kBigFacePts, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_surface_big<kBigFacePts, false>), g, b, 0, s, a);
+    }
     return hipGetLastError();
 }
 

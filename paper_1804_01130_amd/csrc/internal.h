@@ -213,6 +213,7 @@ struct BigArgs {
     int want_stats;
     iso_trace tr;
     double root_tol;  // as Params::root_tol
+    int us_mode;      // as Params::us_mode
 };
 hipError_t launch_surface_big(const BigArgs &a, hipStream_t s);
 

@@ -106,8 +106,6 @@ iso_status check_options(const iso_options &o, const iso_mesh *mesh) {
         o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1 ||
         !(o.root_tol >= 0 && o.root_tol < 1))
         return fail(ISO_EINVAL, "bad options");
-    if (mesh->dev.cbig && o.us_mode != 0)
-        return fail(ISO_EUNSUPPORTED, "the interpolated isoface velocity (us_mode 1) does not take general polyhedra");
     return ISO_OK;
 }
 static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {

@@ -143,15 +143,11 @@ def test_capped_searches_are_counted_once_per_cell(name):
 def test_entry_points_that_refuse_other_cells():
     import torch
     from paper_1804_01130_amd import Batch, IsoError, Mesh, Plan, default_options
-    w = CASES["pyramid_8x4x4"]
-    gm = Mesh.from_arrays(w.mesh)
-    with pytest.raises(IsoError):
-        Batch([gm], default_options())
-    # us_mode 1 and the adjoint take tetrahedra, pyramids and prisms, but not general polyhedra
+    # ensembles and the adjoint take tetrahedra, pyramids and prisms, but not general polyhedra
     wm = CASES["merged_16x8x8"]
     gmm = Mesh.from_arrays(wm.mesh)
     with pytest.raises(IsoError):
-        Plan(gmm, default_options(us_mode=1))
+        Batch([gmm], default_options())
     plan = Plan(gmm, default_options())
     phi, U = wm.phi_U(0)
     a = to_dev(wm.alpha0)

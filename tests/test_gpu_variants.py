@@ -54,10 +54,15 @@ def test_interpolated_isoface_velocity(oracle_lib, name):
         assert np.abs(o - o0).max() > 1e-8
 
 
-@pytest.mark.parametrize("kind,perturb", [("tet", 0.0), ("pyramid", 0.0), ("prism", 0.15), ("mixed", 0.0)])
+@pytest.mark.parametrize("kind,perturb", [("tet", 0.0), ("pyramid", 0.0), ("prism", 0.15), ("mixed", 0.0),
+                                          ("merged", 0.1), ("merged_joined", 0.0), ("merged_sparse", 0.1)])
 def test_interpolated_isoface_velocity_on_other_cells(oracle_lib, kind, perturb):
-    """us_mode 1 on tetrahedra, pyramids, bent prisms and hexahedra next to prisms: triangular faces
-    are fanned about the mean of their three points, as in the oracle."""
+    """us_mode 1 on tetrahedra, pyramids, bent prisms, hexahedra next to prisms and general polyhedra
+    (mostly polyhedra, one kernel, bent; joined faces of 6 and 8 points; a minority of polyhedra
+    beside the eight-lane kernel, bent): every face is fanned about the mean of its points, as in
+    the oracle.  (Bent faces of 6 or 8 points give fans that overlap their neighbours', where the
+    choice of tetrahedron is discontinuous and rounding can flip it: one step of such a mesh is
+    compared in the next test.)"""
     w = W.poly_violent(kind, nx=12, ny=6, nz=6, steps=8, perturb=perturb)
     say(f"[gpu] us_mode 1 trajectory on {kind} (perturb {perturb}): {w.mesh.n_cells} cells, {w.n_steps} steps")
     gm, plan = gpu_plan(w.mesh, us_mode=1)
@@ -68,6 +73,24 @@ def test_interpolated_isoface_velocity_on_other_cells(oracle_lib, kind, perturb)
     say(f"[gpu]   max |gpu - oracle| = {err:.3e}; us_mode 1 vs 0 in the oracle: {np.abs(o - o0).max():.3e}")
     assert err <= TOL
     assert np.abs(o - o0).max() > 1e-8
+
+
+def test_interpolated_isoface_velocity_on_bent_joined_polyhedra(oracle_lib):
+    """One step of bent polyhedra with joined faces of 6 and 8 points from the same state: every
+    cell's U_S . n_S and the new state against the oracle's."""
+    w = W.poly_violent("merged_joined", nx=12, ny=6, nz=6, steps=8, perturb=0.1)
+    gm, plan = gpu_plan(w.mesh, us_mode=1)
+    phi, U = w.phi_U(0)
+    g_new, _, tr = gpu_traced_step(plan, gm, w.alpha0, phi, U, w.dt)
+    o_new, _, otr = oracle_lib.OracleMesh(w.mesh).step(w.alpha0, phi, U, w.dt, oracle_lib.default_opts(us_mode=1),
+                                                       trace=True)
+    rec = (tr["kind"] == 1) & (otr["kind"] == 1)
+    assert rec.sum() > 20
+    du = np.abs(tr["rec"][rec, 6] - otr["rec"][rec, 6]).max()
+    say(f"[gpu] us_mode 1, bent joined polyhedra, one step: max |un gpu - un oracle| = {du:.3e} over "
+        f"{rec.sum()} cells, max |alpha gpu - oracle| = {np.abs(g_new - o_new).max():.3e}")
+    assert du <= 1e-11 * np.abs(U).max()
+    assert np.abs(g_new - o_new).max() <= 1e-13
 
 
 def test_interpolated_isoface_velocity_in_the_trace(oracle_lib):
