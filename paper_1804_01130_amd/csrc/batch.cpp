@@ -3,6 +3,7 @@
 // so each kernel of a step is one launch over every member; a whole multi-step run is captured
 // once as a HIP graph and replayed.  Each member's cells read its own time step from a device
 // table, so every member computes bit for bit what its own plan computes.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -134,21 +135,30 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(ISO_EDEVICE, "no HIP device");
     int64_t N = 0, F = 0, K = 0, S = 0, P = 0, NF = 0;
-    int32_t W = 1;
-    bool generic = false;
+    int64_t NB = 0, NBV = 0, NBF = 0, NBL = 0;  // general polyhedra: cells, points, faces, loop entries
+    int32_t W = 1, big_face_pts = 0;
+    bool generic = false, any_big = false, all_big = true, narrow = false, wide = false;
     for (int32_t i = 0; i < n; ++i) {
         const iso_mesh *m = meshes[i];
         if (!m) return fail(ISO_EINVAL, "null mesh in the ensemble");
         if (m->device != dev) return fail(ISO_EINVAL, "ensemble members must live on the current device");
-        if (m->dev.cbig) return fail(ISO_EUNSUPPORTED, "ensemble members must not hold general polyhedra");
         generic = generic || m->generic;
+        if (m->dev.cbig) {
+            any_big = true;
+            big_face_pts = std::max(big_face_pts, m->dev.big_face_pts);
+            (m->dev.big_face_pts > 4 ? wide : narrow) = true;
+            NB += m->n_big; NBV += m->n_bv; NBF += m->n_bf; NBL += m->n_bl;
+        }
+        all_big = all_big && m->dev.all_big;
         N += m->n_cells; F += m->n_faces; K += m->n_classes; S += m->st_nnz; P += m->dev.n_patches;
         NF += m->n_flux;
         W = std::max(W, m->W);
     }
     const int64_t lim = std::numeric_limits<int32_t>::max() - 1;
-    if (N > lim || F > lim || K > lim || S > lim || P > lim || 24 * N > (int64_t)1 << 62)
+    if (N > lim || F > lim || K > lim || S > lim || P > lim || 3 * NBV > lim || NBF > lim || NBL > lim ||
+        24 * N > (int64_t)1 << 62)
         return fail(ISO_EINVAL, "ensemble too large for 32-bit indices");
+    all_big = all_big && any_big;
 
     iso_batch *b = new iso_batch();
     b->n = n;
@@ -182,6 +192,17 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
     }
     std::vector<std::vector<int32_t>> hex_loops;  // host staging, alive until the copies are done
+    // general polyhedra: their point, face and loop arrays concatenated, indices offset
+    int32_t *cbig = nullptr, *bv_ptr = nullptr, *bv_cls = nullptr, *bf_ptr = nullptr, *bf_face = nullptr,
+            *bf_planar = nullptr, *bl_ptr = nullptr, *bl_vtx = nullptr;
+    double *bv_xyz = nullptr;
+    if (any_big && (!dev_alloc(u, &cbig, N) || !dev_alloc(u, &bv_ptr, NB + 1) || !dev_alloc(u, &bv_cls, NBV) ||
+                    !dev_alloc(u, &bv_xyz, 3 * NBV) || !dev_alloc(u, &bf_ptr, NB + 1) || !dev_alloc(u, &bf_face, NBF) ||
+                    !dev_alloc(u, &bf_planar, NBF) || !dev_alloc(u, &bl_ptr, NBF + 1) || !dev_alloc(u, &bl_vtx, NBL))) {
+        iso_batch_destroy(b);
+        return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
+    }
+    int64_t bo = 0, vo = 0, bfo = 0, blo = 0;
     hipStream_t s = b->stream;
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t x) {
@@ -219,6 +240,20 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
                 for (int k = 0; k < 6; ++k) h[6 * (size_t)c + k] = hex_loop_word(k);
             ok(hipMemcpyAsync(cloop + 6 * co, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         }
+        if (any_big && md.cbig) {
+            ok(launch_offset_copy(md.cbig, cbig + co, nc, 0, (int32_t)bo, 0, s));
+            ok(launch_offset_copy(md.bv_ptr, bv_ptr + bo, m->n_big, 0, (int32_t)vo, 0, s));
+            ok(launch_offset_copy(md.bv_cls, bv_cls + vo, m->n_bv, 0, (int32_t)ko, 0, s));
+            ok(hipMemcpyAsync(bv_xyz + 3 * vo, md.bv_xyz, 3 * (size_t)m->n_bv * sizeof(double), hipMemcpyDeviceToDevice, s));
+            ok(launch_offset_copy(md.bf_ptr, bf_ptr + bo, m->n_big, 0, (int32_t)bfo, 0, s));
+            ok(launch_offset_copy(md.bf_face, bf_face + bfo, m->n_bf, 1, (int32_t)fo, 0, s));
+            ok(launch_offset_copy(md.bf_planar, bf_planar + bfo, m->n_bf, 0, 0, 0, s));
+            ok(launch_offset_copy(md.bl_ptr, bl_ptr + bfo, m->n_bf, 0, (int32_t)blo, 0, s));
+            ok(launch_offset_copy(md.bl_vtx, bl_vtx + blo, m->n_bl, 0, 0, 0, s));
+            bo += m->n_big; vo += m->n_bv; bfo += m->n_bf; blo += m->n_bl;
+        } else if (any_big) {
+            ok(launch_offset_copy(nullptr, cbig + co, nc, 0, -1, 0, s));  // no polyhedron here
+        }
         ok(launch_offset_copy(md.st_ptr, st_ptr + ko, m->n_classes, 0, (int32_t)so, 0, s));
         ok(launch_offset_copy(md.st_cell, st_cell + so, m->st_nnz, 0, (int32_t)co, 0, s));
         ok(hipMemcpyAsync(st_w + so, md.st_w, m->st_nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -232,6 +267,12 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     const int32_t snnz = (int32_t)S;
     ok(hipStreamSynchronize(s));
     ok(hipMemcpy(st_ptr + K, &snnz, sizeof(int32_t), hipMemcpyHostToDevice));
+    if (any_big) {  // the arrays' closing offsets
+        const int32_t nbv = (int32_t)NBV, nbf = (int32_t)NBF, nbl = (int32_t)NBL;
+        ok(hipMemcpy(bv_ptr + NB, &nbv, sizeof(int32_t), hipMemcpyHostToDevice));
+        ok(hipMemcpy(bf_ptr + NB, &nbf, sizeof(int32_t), hipMemcpyHostToDevice));
+        ok(hipMemcpy(bl_ptr + NBF, &nbl, sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     ok(hipMemcpy(dom_off, hoff.data(), hoff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (e != hipSuccess) {
         iso_batch_destroy(b);
@@ -244,6 +285,14 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     d.cloop = cloop;
     d.n_dom = n; d.dom_off = dom_off;
     u->generic = generic;
+    if (any_big) {
+        d.cbig = cbig; d.bv_ptr = bv_ptr; d.bv_cls = bv_cls; d.bv_xyz = bv_xyz; d.bf_ptr = bf_ptr;
+        d.bf_face = bf_face; d.bf_planar = bf_planar; d.bl_ptr = bl_ptr; d.bl_vtx = bl_vtx;
+        d.big_face_pts = big_face_pts;
+        d.all_big = all_big ? 1 : 0;
+        d.big_class = narrow && wide ? 2 : -1;
+        u->n_big = (int32_t)NB; u->n_bv = (int32_t)NBV; u->n_bf = (int32_t)NBF; u->n_bl = (int32_t)NBL;
+    }
     u->n_cells = (int32_t)N; u->n_faces = (int32_t)F; u->n_classes = (int32_t)K; u->W = W;
     u->n_flux = (int32_t)NF; u->st_nnz = S;
 

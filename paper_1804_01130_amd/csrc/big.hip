@@ -338,9 +338,10 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
         const int c = A.list[idx];
         const int bi = m.cbig[c];
         if (bi < 0) continue;  // the same cell on all sixteen lanes
+        if (A.only_class >= 0 && ((m.cflags[c] >> 11) & 1) != A.only_class) continue;  // the other launch's
         const double aP = A.alpha[c];
         const double V6 = 6.0 * m.vol[c];
-        const double dtc = A.dt;
+        const double dtc = cell_dt(m, A.dt_dom, A.dt, c);  // an ensemble member's own time step
         // points lf and lf + 16: coordinates, their mean over the group, vertex values
         const int v0 = m.bv_ptr[bi], nv = m.bv_ptr[bi + 1] - v0;
         D3 xp[2], up[2];
@@ -648,12 +649,24 @@ __global__ void __launch_bounds__(kGrp * kGrpPerBlock) k_surface_big(BigArgs A) 
 hipError_t launch_surface_big(const BigArgs &a, hipStream_t s) {
     const int blocks = std::max(1, std::min(1024, (a.cap + kGrpPerBlock - 1) / kGrpPerBlock));
     const dim3 g(blocks), b(kGrp * kGrpPerBlock);
-    if (a.m.big_face_pts <= 4) {
-        if (a.us_mode == 1) hipLaunchKernelGGL((k_surface_big<4, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_surface_big<4, false>), g, b, 0, s, a);
+    // a single mesh: the instantiation its largest face needs; an ensemble whose members need
+    // both: one launch of each, each taking its own members' polyhedra (as each member alone)
+    auto launch = [&](bool wide, int only) {
+        BigArgs x = a;
+        x.only_class = only;
+        if (!wide) {
+            if (x.us_mode == 1) hipLaunchKernelGGL((k_surface_big<4, true>), g, b, 0, s, x);
+            else hipLaunchKernelGGL((k_surface_big<4, false>), g, b, 0, s, x);
+        } else {
+            if (x.us_mode == 1) hipLaunchKernelGGL((k_surface_big<kBigFacePts, true>), g, b, 0, s, x);
+            else hipLaunchKernelGGL((k_surface_big<kBigFacePts, false>), g, b, 0, s, x);
+        }
+    };
+    if (a.m.big_class == 2) {
+        launch(false, 0);
+        launch(true, 1);
     } else {
-        if (a.us_mode == 1) hipLaunchKernelGGL((k_surface_big<kBigFacePts, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_surface_big<kBigFacePts, false>), g, b, 0, s, a);
+        launch(a.m.big_face_pts > 4, -1);
     }
     return hipGetLastError();
 }

@@ -71,6 +71,9 @@ struct DevMesh {
     const int32_t *bl_vtx = nullptr;     //   local point at each loop position, outward
     int32_t big_face_pts = 0;            // most points of a face of any of them
     int32_t all_big = 0;                 // 1: every cell is taken as one of them (mostly polyhedra)
+    int32_t big_class = -1;              // 2: polyhedra of both instantiation classes (cflags bit
+                                         // 11: the mesh they come from has faces of more than 4
+                                         // points), each launch taking its own class
     // ensembles: cells [dom_off[d], dom_off[d+1]) belong to member d, whose time step is
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;
@@ -206,6 +209,7 @@ struct BigArgs {
     const double *phi1, *U1;  // second time level of an outer iteration, or nullptr
     double dt, flat_tol;
     int max_rounds;
+    const double *dt_dom;     // ensembles: each member's time step (see DevMesh::n_dom), else nullptr
     const int32_t *list;
     int32_t *counters;
     int cap;
@@ -214,6 +218,7 @@ struct BigArgs {
     iso_trace tr;
     double root_tol;  // as Params::root_tol
     int us_mode;      // as Params::us_mode
+    int only_class = -1;  // >= 0: only polyhedra of this instantiation class (cflags bit 11)
 };
 hipError_t launch_surface_big(const BigArgs &a, hipStream_t s);
 
@@ -244,6 +249,8 @@ struct iso_mesh {
                                      // points repeats its first one after them)
     std::vector<int32_t> nvtx;       // [n_cells] distinct points of each cell
     bool generic = false;            // some cell is not a hexahedron
+    // general polyhedra: how many, and the lengths of their point, face and loop arrays
+    int32_t n_big = 0, n_bv = 0, n_bf = 0, n_bl = 0;
     std::vector<double> vol, xc;
     std::vector<double> patch_alpha;
     int64_t st_nnz = 0;              // entries of the vertex stencils

@@ -1376,8 +1376,8 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
             if (e != hipSuccess) return e;
             sb = w.side;
         }
-        BigArgs bg{m, a.alpha, a.phi, a.U, a.phi1, a.U1, a.dt, p.flat_tol, p.root_max_iter, w.surf, w.counters,
-                   w.cap, w.dvs, want_stats ? 1 : 0, tr, p.root_tol, p.us_mode};
+        BigArgs bg{m, a.alpha, a.phi, a.U, a.phi1, a.U1, a.dt, p.flat_tol, p.root_max_iter, a.dt_dom, w.surf,
+                   w.counters, w.cap, w.dvs, want_stats ? 1 : 0, tr, p.root_tol, p.us_mode};
         const hipError_t e = launch_surface_big(bg, sb);
         if (e != hipSuccess) return e;
     }

@@ -757,6 +757,17 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     d.n_cells = n_cells; d.n_faces = n_faces; d.n_classes = n_classes; d.W = W; d.n_patches = n_patches;
     d.big_face_pts = big_face_pts;
     d.all_big = all_big ? 1 : 0;
+    if (any_big) {
+        m->n_big = (int32_t)bv_ptr.size() - 1;
+        m->n_bv = (int32_t)bv_pts.size();
+        m->n_bf = (int32_t)bf_fid.size();
+        m->n_bl = (int32_t)bl_vtx.size();
+        // the class of the polyhedron kernel's instantiation that takes this mesh's polyhedra, kept
+        // per cell so that an ensemble can give each member's polyhedra their own
+        if (big_face_pts > 4)
+            for (int32_t c = 0; c < n_cells; ++c)
+                if (cbig[c] >= 0) cflags[c] |= 1 << 11;
+    }
     d.n_internal = n_internal;
     iso_status st = ISO_OK;
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||

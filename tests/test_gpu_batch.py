@@ -22,13 +22,18 @@ def members():
 
 
 def members_of_all_cells():
-    """Tetrahedra, pyramids, bent prisms and hexahedra next to prisms, beside meshes of hexahedra
-    (2D and 3D)."""
+    """Tetrahedra, pyramids, bent prisms, hexahedra next to prisms and general polyhedra (mostly
+    polyhedra with faces of at most 4 points; joined faces of 6 and 8 points, which take the other
+    instantiation of the polyhedron kernel; a minority of bent polyhedra), beside meshes of
+    hexahedra (2D and 3D)."""
     return [W.poly_violent("tet", nx=8, ny=4, nz=4, steps=STEPS),
             W.airy_slab(64, 32, 32, 0.05, 0.35, STEPS, "h1"),
             W.poly_violent("prism", nx=12, ny=6, nz=6, steps=STEPS, perturb=0.15),
+            W.poly_violent("merged", nx=12, ny=6, nz=6, steps=STEPS),
             W.violent_3d(nx=16, ny=8, nz=8, steps=STEPS),
+            W.poly_violent("merged_joined", nx=12, ny=6, nz=6, steps=STEPS),
             W.poly_violent("pyramid", nx=8, ny=4, nz=4, steps=STEPS),
+            W.poly_violent("merged_sparse", nx=16, ny=8, nz=8, steps=STEPS, perturb=0.1),
             W.poly_violent("mixed", nx=12, ny=6, nz=6, steps=STEPS)]
 
 
@@ -91,9 +96,11 @@ def test_batch_members_match_oracle(ensemble, oracle_lib):
 
 @pytest.mark.parametrize("us_mode", [0, 1])
 def test_members_of_every_cell_type(oracle_lib, us_mode):
-    """Members with tetrahedra, pyramids and prisms run the generic interface kernel over the whole
-    ensemble, the hexahedral members with their faces in the hexahedron kernel's edge directions:
-    every member still equals itself stepped alone, bit for bit, and matches the oracle."""
+    """Members of every cell type: the generic interface kernel over the whole ensemble (the
+    hexahedral members with their faces in the hexahedron kernel's edge directions), and the
+    polyhedron kernel once per instantiation its members take alone, on the side stream inside the
+    captured graph: every member still equals itself stepped alone, bit for bit, and matches the
+    oracle."""
     E = _build(members_of_all_cells(), us_mode=us_mode)
     say(f"[gpu] ensemble of every cell type, us_mode {us_mode}: {len(E['ws'])} members, "
         f"{E['batch'].n_cells} cells, {STEPS} steps")

@@ -140,14 +140,12 @@ def test_capped_searches_are_counted_once_per_cell(name):
     assert 1 <= st["n_nonconverged"] <= capped
 
 
-def test_entry_points_that_refuse_other_cells():
+def test_the_adjoint_refuses_general_polyhedra():
     import torch
-    from paper_1804_01130_amd import Batch, IsoError, Mesh, Plan, default_options
-    # ensembles and the adjoint take tetrahedra, pyramids and prisms, but not general polyhedra
+    from paper_1804_01130_amd import IsoError, Mesh, Plan, default_options
+    # the adjoint takes tetrahedra, pyramids and prisms, but not general polyhedra
     wm = CASES["merged_16x8x8"]
     gmm = Mesh.from_arrays(wm.mesh)
-    with pytest.raises(IsoError):
-        Batch([gmm], default_options())
     plan = Plan(gmm, default_options())
     phi, U = wm.phi_U(0)
     a = to_dev(wm.alpha0)
