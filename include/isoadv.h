@@ -260,8 +260,8 @@ iso_status iso_relax_blend(iso_plan *plan, double *alpha, const double *alpha_ta
  * iso_advect_step_traced with the same plan; vert_alpha, kind, iso, dV and alpha_raw are used.
  * NULL recomputes the forward step internally.  All arrays are DEVICE arrays; alpha_bar and
  * phi_bar must not overlap the inputs.  Asynchronous on the plan's stream.  The first call
- * allocates the adjoint workspace (about 380 + (44 + 16 W) S bytes per cell, for S bounding
- * sweeps and W flux faces per cell, and 84 bytes per face).  At most 31 bounding sweeps
+ * allocates the adjoint workspace (about 380 + (48 + 16 W) S bytes per cell, for S bounding
+ * sweeps and W flux slots per cell, 84 bytes per face and 800 per general polyhedron).  At most 31 bounding sweeps
  * (ISO_EUNSUPPORTED).  Every sum is taken in a fixed order (atomics only build work lists, whose
  * order changes no result): the same inputs give the same bits on every call. */
 iso_status iso_advect_step_adjoint(iso_plan *plan, const double *alpha, const double *phi, const double *U,

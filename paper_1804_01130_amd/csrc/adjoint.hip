@@ -283,6 +283,14 @@ __device__ __forceinline__ Dl dtri_sweep(Dl d0, Dl d1, Dl d2, Dl un, double dt) 
 // bound such a value lands on is decided by rounding order): its derivative passes through.  A
 // larger one makes the value a constant.
 constexpr double kRound = 1e-14;
+constexpr uint64_t kCorrBit = 1ull << 3, kTouchedBit = 1ull << 19;  // bounding tape flags, slot k: << k
+
+// General polyhedra: sixteen lanes per (polyhedron, direction); directions 0 .. 31 are point
+// values, kBigIsoDir the isovalue; per polyhedron the rates G at [0, kBigIsoDir], C at kBigC + the
+// same, then the jump and 6V (see k_adj_surface_big).
+constexpr int kBGrp = 16, kBGrpPerBlock = 16, kBPts = 32;
+constexpr int kBigIsoDir = 32, kBigC = 33, kBigJump = 66, kBigV6 = 67;
+static_assert(kAdjGBig == 68, "per-polyhedron rates: 33 + 33 + 2");
 
 // The update's round-off chop (a move of at most the bounding tolerance) passes the derivative
 // unless it moves the value by more than kRound: then the update is a constant there.
@@ -313,9 +321,9 @@ struct AdjArgs {
 // Bounding replayed with a tape, then reversed, grid-wide: one kernel per forward sweep (phase B of
 // sweep s fused with phase A of sweep s+1, as in the step's own sweeps; phase A of sweep 0 runs in
 // k_adj_prep) and two per reversed sweep.  Tape per sweep s and listed cell (row s*nc + i, i its
-// place in the sweep's list): a, need, sumcap, r, then cap and dV-now per slot; flags: bit 0 over,
-// bit 1 r capped at 1, bit 2 sumcap > 0, bit 3+k slot k corrected, bit 10+k slot k read the running
-// dV (corrected in an earlier sweep).  List order never affects a result: each listed cell writes
+// place in the sweep's list): a, need, sumcap, r, then cap and dV-now per slot; flags (64 bits, for
+// up to 16 slots): bit 0 over, bit 1 r capped at 1, bit 2 sumcap > 0, bit 3+k slot k corrected, bit
+// 19+k slot k read the running dV (corrected in an earlier sweep).  List order never affects a result: each listed cell writes
 // only its own outflow faces and its own tape row, each touched cell only itself.
 //
 // Buffers that start every call at zero and are left so: the face marks (`touched`), two banks of
@@ -342,7 +350,7 @@ __device__ __forceinline__ void adj_correct(const AdjArgs &A, int s, int32_t P, 
         fid[k] = v[k] >= 0 ? v[k] : ~v[k];
         ph[k] = v[k] != kEmpty ? A.phi[fid[k]] : 0.0;
     }
-    int flags = over ? 1 : 0;
+    uint64_t flags = over ? 1 : 0;
     double sumcap = 0.0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
@@ -352,7 +360,7 @@ __device__ __forceinline__ void adj_correct(const AdjArgs &A, int s, int32_t P, 
         const double outphi = v[k] >= 0 ? ph[k] : -ph[k];
         if (!(outphi > 0.0)) continue;
         const bool tch = w.touched[fid[k]] != 0;
-        if (tch) flags |= 1 << (10 + k);
+        if (tch) flags |= kTouchedBit << k;
         dvnow[k] = tch ? w.dvcur[fid[k]] : A.dV0[fid[k]];
         const double outv = v[k] >= 0 ? dvnow[k] : -dvnow[k];
         cap[k] = over ? outphi * dtc - outv : outv;
@@ -371,7 +379,7 @@ __device__ __forceinline__ void adj_correct(const AdjArgs &A, int s, int32_t P, 
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         if (!(sumcap > 0.0) || !(cap[k] > 0.0)) continue;
-        flags |= 1 << (3 + k);
+        flags |= kCorrBit << k;
         const double d = cap[k] * r;
         const double dd = over ? (v[k] >= 0 ? d : -d) : (v[k] >= 0 ? -d : d);
         delta[fid[k]] = dd;
@@ -492,10 +500,10 @@ __global__ void __launch_bounds__(256) k_adj_sweep(AdjArgs A, int s) {
         double *stale = w.delta + (size_t)((s - 1) % 3) * nf;
         for (int i = t0; i < np; i += stride) {
             const int32_t P = w.list[(size_t)(s - 1) * n + i];
-            const int flags = w.tflag[(size_t)(s - 1) * n + i];
+            const uint64_t flags = w.tflag[(size_t)(s - 1) * n + i];
 #pragma unroll
             for (int k = 0; k < W; ++k)
-                if (flags & (1 << (3 + k))) {
+                if (flags & (kCorrBit << k)) {
                     const int32_t v = m.slot_face[(size_t)k * n + P];
                     stale[v >= 0 ? v : ~v] = 0.0;
                 }
@@ -564,10 +572,10 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_apply(AdjArgs A, int s) {
     double *delta = w.delta + (size_t)(s % 3) * nf;
     for (int i = t0; i < nl; i += stride) {
         const int32_t P = L[i];
-        const int flags = w.tflag[(size_t)s * n + i];
+        const uint64_t flags = w.tflag[(size_t)s * n + i];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            if (!(flags & (1 << (3 + k)))) continue;
+            if (!(flags & (kCorrBit << k))) continue;
             const int32_t v = m.slot_face[(size_t)k * n + P];
             const int32_t o = m.slot_nbr[(size_t)k * n + P];
             const int32_t f = v >= 0 ? v : ~v;
@@ -602,7 +610,7 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
     const int32_t *L = w.list + (size_t)s * n;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += stride) {
         const int32_t P = L[i];
-        const int flags = w.tflag[(size_t)s * n + i];
+        const uint64_t flags = w.tflag[(size_t)s * n + i];
         const double *rec = w.tape + ((size_t)s * n + i) * R;
         const bool over = flags & 1;
         const double sumcap = rec[2], r = rec[3];
@@ -613,7 +621,7 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
         for (int k = 0; k < W; ++k) {
             capb[k] = 0.0;
             dvnb[k] = 0.0;
-            if (!(flags & (1 << (3 + k)))) continue;
+            if (!(flags & (kCorrBit << k))) continue;
             const int32_t v = m.slot_face[(size_t)k * n + P];
             const int32_t f = v >= 0 ? v : ~v;
             const double s_ = v >= 0 ? 1.0 : -1.0;
@@ -639,7 +647,7 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
             const double outvb = over ? -cb : cb;
             if (over) w.phib[f] += cb * s_ * dtc;
             dvnb[k] += s_ * outvb;
-            if (flags & (1 << (10 + k))) {
+            if (flags & (kTouchedBit << k)) {
                 w.dvcurbar[f] = dvnb[k];
             } else {
                 w.dVb[f] += dvnb[k];
@@ -695,7 +703,12 @@ __global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
     // the interface-cell directions k_adj_surface differentiates along: the isovalue, and each vertex
     // value that moves a cut point (a vertex no cut edge touches moves nothing: its rates are zero)
     uint32_t need = 0;
-    if (c < n && A.kind[c] == 1) {
+    int nbig = 0;  // a general polyhedron: every point value and the isovalue (kBigIsoDir)
+    const bool big = c < n && A.m.cbig && A.m.cbig[c] >= 0;
+    if (big && A.kind[c] == 1) {
+        const int bi = A.m.cbig[c];
+        nbig = A.m.bv_ptr[bi + 1] - A.m.bv_ptr[bi] + 1;
+    } else if (c < n && A.kind[c] == 1) {
         const double iso = A.iso[c];
         uint32_t wet = 0;
 #pragma unroll
@@ -728,6 +741,10 @@ __global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
     int b = block_append(__popc(need), &A.w.counters[kAdjDirs]);
     for (int d = 0; d < 9; ++d)
         if ((need >> d) & 1u) A.w.dlist[b++] = ((int64_t)c << 4) | d;
+    if (!A.m.cbig) return;  // uniform: no polyhedra in this mesh
+    int bb = block_append(nbig, &A.w.counters[kAdjDirsBig]);
+    for (int d = 0; d + 1 < nbig; ++d) A.w.dlist_big[bb++] = ((int64_t)c << 6) | d;
+    if (nbig) A.w.dlist_big[bb] = ((int64_t)c << 6) | kBigIsoDir;
 }
 
 // interface cells: rates of the sub-volume and the swept integrals along each listed direction
@@ -860,6 +877,235 @@ __device__ __forceinline__ double adj_alpha(const double *gb) {
     return xdot * gb[17];
 }
 
+// ------------------------------------------------------------------ general polyhedra (16 lanes)
+// One group of sixteen lanes per (polyhedron, direction), lane lf on the cell's face lf, as in the
+// forward polyhedron kernel: the cell's points (relative to their mean) and vertex values sit in
+// LDS, the vertex values recomputed through the same stencils in the same order, so they are the
+// forward's bits.  Directions 0 .. nv-1 are the points' values, kBigIsoDir the isovalue; the rates
+// are stored per polyhedron: G (six times the sub-volume) at [0, kBigIsoDir], C (the faces'
+// adjoint-weighted swept integrals) at kBigC + [0, kBigIsoDir], then the jump and 6V.
+
+struct BPt {
+    double x, y, z, a;
+};
+__device__ __forceinline__ double a16(double v) {  // the 8-lane butterfly, then the row's halves
+    v = grp_sum(v);
+    return v + dpp_move<0x140>(v);
+}
+__device__ __forceinline__ Dl da16(Dl a) { return {a16(a.v), a16(a.d)}; }
+__device__ __forceinline__ DV3 da16_3(DV3 a) { return {da16(a.x), da16(a.y), da16(a.z)}; }
+__device__ __forceinline__ void adj_grp_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(kBGrp * kBGrpPerBlock) k_adj_surface_big(AdjArgs A) {
+    __shared__ BPt spt[kBGrpPerBlock][kBPts];
+    const DevMesh &m = A.m;
+    const int g = threadIdx.x / kBGrp, lf = threadIdx.x % kBGrp;
+    BPt *P = spt[g];
+    const int npair = A.w.counters[kAdjDirsBig];
+    const size_t nc = m.n_cells;
+    const DV3 Z = dv(D3{0, 0, 0});
+    for (int idx = blockIdx.x * kBGrpPerBlock + g; idx < npair; idx += gridDim.x * kBGrpPerBlock) {
+        const int64_t pr = A.w.dlist_big[idx];
+        const int c = (int)(pr >> 6), dir = (int)(pr & 63);
+        const int bi = m.cbig[c];
+        const double aP = A.alpha[c];
+        const double V6 = 6.0 * m.vol[c];
+        const double dtc = cell_dt(m, A.dt_dom, A.dt, c);
+        const int v0 = m.bv_ptr[bi], nv = m.bv_ptr[bi + 1] - v0;
+        D3 xp[2];
+        double ap[2];
+        D3 xs{0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lf + kBGrp * h;
+            xp[h] = D3{0, 0, 0};
+            ap[h] = 0.0;
+            if (i < nv) {
+                const double *q = m.bv_xyz + 3 * (size_t)(v0 + i);
+                xp[h] = D3{q[0], q[1], q[2]};
+                const int k = m.bv_cls[v0 + i];
+                double av = 0.0;
+                for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e) av += m.st_w[e] * A.alpha[m.st_cell[e]];
+                ap[h] = av;
+                xs = xs + xp[h];
+            }
+        }
+        const D3 xm = (1.0 / nv) * D3{a16(xs.x), a16(xs.y), a16(xs.z)};
+        adj_grp_sync();  // the previous pair's reads of P are done
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = lf + kBGrp * h;
+            if (i < nv) P[i] = BPt{xp[h].x - xm.x, xp[h].y - xm.y, xp[h].z - xm.z, ap[h]};
+        }
+        adj_grp_sync();
+        const double iso = A.iso[c];
+        const Dl isod{iso, dir == kBigIsoDir ? 1.0 : 0.0};
+        // this lane's face: its loop of local points (outward), planarity, flux face
+        const int f0 = m.bf_ptr[bi], nf = m.bf_ptr[bi + 1] - f0;
+        const bool face = lf < nf;
+        const int lb = face ? m.bl_ptr[f0 + lf] : 0;
+        const int ln = face ? m.bl_ptr[f0 + lf + 1] - lb : 0;
+        const bool planar = face && m.bf_planar[f0 + lf];
+        auto loc = [&](int pos) { return m.bl_vtx[lb + pos]; };
+        auto dpt = [&](int l) { return DV3{dc(P[l].x), dc(P[l].y), dc(P[l].z)}; };
+        auto dval = [&](int l) { return Dl{P[l].a, l == dir ? 1.0 : 0.0}; };
+        // cut point of the edge between local points l1 and l2, exactly one of them wet: from the
+        // wet end, as the forward computes it
+        auto cut = [&](int l1, int l2, bool w1) {
+            const int lw = w1 ? l1 : l2, ld = w1 ? l2 : l1;
+            const Dl lam = (isod - dval(lw)) / (dval(ld) - dval(lw));
+            return dpt(lw) + lam * (dpt(ld) - dpt(lw));
+        };
+        // the face's share of six times the sub-volume and of the isoface sums (wet iff a > iso)
+        DV3 C = Z, pacc = Z, psum = Z, lastexit = Z, first_entry = Z, cseg = Z, oacc = Z;
+        Dl pl = dc(0.0), oL = dc(0.0);
+        int cnt = 0;
+        bool have_exit = false, pend = false;
+        auto iso_edge = [&](DV3 s0, DV3 s1) {
+            const Dl l = dnorm(s1 - s0);
+            cseg = cseg + dcross(s0, s1);
+            oacc = oacc + (0.5 * l) * (s0 + s1);
+            oL = oL + l;
+        };
+        for (int i = 0; i < ln; ++i) {
+            const int li = loc(i), lj = loc(i + 1 < ln ? i + 1 : 0);
+            const bool wi = P[li].a > iso, wj = P[lj].a > iso;
+            const DV3 xi = dpt(li), xj = dpt(lj);
+            DV3 ct = Z;
+            if (wi != wj) ct = cut(li, lj, wi);
+            if (!wi && wj) {
+                if (have_exit) iso_edge(ct, lastexit);
+                else { pend = true; first_entry = ct; }
+            }
+            if (wi && !wj) { lastexit = ct; have_exit = true; }
+            if (wi || wj) {
+                const DV3 u = wi ? xi : ct, v = wj ? xj : ct;
+                C = C + dcross(u, v);
+                const Dl l = dnorm(v - u);
+                pacc = pacc + (0.5 * l) * (u + v);
+                pl = pl + l;
+            }
+            if (wi) psum = psum + xi;
+            if (wi != wj) psum = psum + ct;
+            cnt += (wi ? 1 : 0) + (wi != wj ? 1 : 0);
+        }
+        if (pend) iso_edge(first_entry, lastexit);
+        C = C - cseg;  // the isoface edges close the wet loop, walked exit to entry
+        Dl v6 = dc(0.0);
+        if (cnt >= 3) {
+            DV3 apx = dpt(loc(0));
+            if (!planar) {
+                const DV3 tot = pacc + oacc;
+                const Dl tl = pl + oL;
+                apx = tl.v > 0.0 ? dinv(tl) * tot : (1.0 / cnt) * psum;
+            }
+            v6 = ddot(apx, C);
+        }
+        const DV3 gcseg = da16_3(cseg), goacc = da16_3(oacc);
+        const Dl goL = da16(oL);
+        const DV3 o = goL.v > 0.0 ? dinv(goL) * goacc : Z;
+        const Dl g0 = da16(v6) + ddot(o, gcseg);
+        const Dl nrm = dnorm(gcseg);
+        double contrib = 0.0;
+        if (nrm.v > 0.0) {
+            const DV3 nS = dinv(nrm) * gcseg;
+            // the isoface centre: fan triangles (o, entry, preceding exit) weighted along n_S
+            DV3 acc = Z;
+            Dl ws = dc(0.0);
+            DV3 le = Z, fe = Z;
+            bool hx = false, pd = false;
+            auto tri = [&](DV3 s0, DV3 s1) {
+                const Dl wt = ddot(dcross(s0 - o, s1 - o), nS);
+                acc = acc + wt * (o + s0 + s1);
+                ws = ws + wt;
+            };
+            for (int i = 0; i < ln; ++i) {
+                const int li = loc(i), lj = loc(i + 1 < ln ? i + 1 : 0);
+                const bool wi = P[li].a > iso, wj = P[lj].a > iso;
+                if (!wi && wj) {
+                    const DV3 ct = cut(li, lj, false);
+                    if (hx) tri(ct, le);
+                    else { pd = true; fe = ct; }
+                }
+                if (wi && !wj) { le = cut(li, lj, true); hx = true; }
+            }
+            if (pd) tri(fe, le);
+            acc = da16_3(acc);
+            ws = da16(ws);
+            const DV3 xS = dinv(3.0 * ws) * acc;
+            const Dl un = A.U[c] * nS.x + A.U[nc + c] * nS.y + A.U[2 * nc + c] * nS.z;
+            if (face) {
+                const int32_t v = m.bf_face[f0 + lf];
+                if (v != kEmpty) {
+                    const int32_t fid = v >= 0 ? v : ~v;
+                    const double ph = A.phi[fid];
+                    const double out = v >= 0 ? ph : -ph;
+                    if (out > 0.0) {
+                        // the face fanned about its vertex mean, each triangle's swept fraction
+                        D3 fm{0, 0, 0};
+                        for (int i = 0; i < ln; ++i) {
+                            const int l = loc(i);
+                            fm = fm + D3{P[l].x, P[l].y, P[l].z};
+                        }
+                        fm = (1.0 / ln) * fm;
+                        const Dl dap = ddot(dv(fm) - xS, nS);
+                        Dl accI = dc(0.0);
+                        double Af = 0.0;
+                        for (int i = 0; i < ln; ++i) {
+                            const int li = loc(i), lj = loc(i + 1 < ln ? i + 1 : 0);
+                            const D3 xi{P[li].x, P[li].y, P[li].z}, xj{P[lj].x, P[lj].y, P[lj].z};
+                            const double Ai = 0.5 * norm3(cross(xi - fm, xj - fm));
+                            accI = accI + Ai * dtri_sweep(dap, ddot(dv(xi) - xS, nS), ddot(dv(xj) - xS, nS), un, dtc);
+                            Af += Ai;
+                        }
+                        contrib = A.w.vbar[fid] * (accI.d / Af);
+                    }
+                }
+            }
+        }
+        const double gsum = a16(contrib);
+        double *gb = A.w.gbig + (size_t)kAdjGBig * bi;
+        const int slot = dir == kBigIsoDir ? kBigIsoDir : dir;
+        if (lf == 0) {
+            gb[slot] = g0.d;
+            gb[kBigC + slot] = gsum;
+        }
+        if (dir == kBigIsoDir) {
+            // at a jump of the sub-volume the isovalue is a vertex value and moves with it: the
+            // lowest point at the isovalue
+            const bool jump = fabs(g0.v - aP * V6) > 1e-9 * V6;
+            const int base = __lane_id() & ~(kBGrp - 1);
+            const uint32_t lo = (uint32_t)(__ballot(lf < nv && P[lf].a == iso) >> base) & 0xFFFFu;
+            const uint32_t hi = (uint32_t)(__ballot(lf + kBGrp < nv && P[lf + kBGrp].a == iso) >> base) & 0xFFFFu;
+            const uint32_t at = lo | (hi << 16);
+            if (lf == 0) {
+                gb[kBigJump] = jump ? (double)(at ? __ffs((int)at) - 1 : -1) : -2.0;
+                gb[kBigV6] = V6;
+            }
+        }
+        // zero rates for the unused point slots, so that the gathers may read any of them
+        if (dir == kBigIsoDir && lf == 0)
+            for (int v = nv; v < kBigIsoDir; ++v) gb[v] = gb[kBigC + v] = 0.0;
+    }
+}
+
+__device__ __forceinline__ double adj_vertex_big(const double *gb, int v) {
+    const double jump = gb[kBigJump], gx = gb[kBigIsoDir];
+    double xdot;
+    if (jump > -2.0) xdot = (double)v == jump ? 1.0 : 0.0;
+    else xdot = gx != 0.0 ? -gb[v] / gx : 0.0;
+    return gb[kBigC + v] + xdot * gb[kBigC + kBigIsoDir];
+}
+__device__ __forceinline__ double adj_alpha_big(const double *gb) {
+    const double gx = gb[kBigIsoDir];
+    const double xdot = gb[kBigJump] > -2.0 ? 0.0 : (gx != 0.0 ? gb[kBigV6] / gx : 0.0);
+    return xdot * gb[kBigC + kBigIsoDir];
+}
+
 // Transpose of the vertex interpolation, as two gathers in a fixed order (no atomics, so the
 // gradient is the same bits on every run): each point class sums the vertex adjoints of the
 // reconstructed cells that share it, then each cell adds its classes' sums times its weight in
@@ -886,6 +1132,12 @@ __global__ void __launch_bounds__(256) k_adj_points(AdjArgs A) {
             bool first = true;
             for (int e2 = e0; e2 < eb + j; ++e2) first = first && m.st_cell[e2] != c;
             if (!first) continue;
+            if (m.cbig && m.cbig[c] >= 0) {
+                const int bi = m.cbig[c], v0 = m.bv_ptr[bi], nv = m.bv_ptr[bi + 1] - v0;
+                for (int v = 0; v < nv; ++v)
+                    if (m.bv_cls[v0 + v] == k) sum += adj_vertex_big(A.w.gbig + (size_t)kAdjGBig * bi, v);
+                continue;
+            }
 #pragma unroll
             for (int v = 0; v < 8; ++v)
                 if (m.cpt[8 * (size_t)c + v] == k) sum += adj_vertex(A.w.gbuf + (size_t)kAdjG * c, v);
@@ -899,6 +1151,22 @@ __global__ void __launch_bounds__(256) k_adj_cells(AdjArgs A) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= m.n_cells) return;
     double acc = A.abar[c];
+    if (m.cbig && m.cbig[c] >= 0) {
+        // a general polyhedron: the distinct classes of all its points
+        const int bi = m.cbig[c], v0 = m.bv_ptr[bi], nv = m.bv_ptr[bi + 1] - v0;
+        if (A.kind[c] == 1) acc += adj_alpha_big(A.w.gbig + (size_t)kAdjGBig * bi);
+        for (int v = 0; v < nv; ++v) {
+            const int32_t k = m.bv_cls[v0 + v];
+            bool seen = false;
+            for (int u = 0; u < v; ++u) seen = seen || m.bv_cls[v0 + u] == k;
+            const double pbk = A.w.pbar[k];
+            if (seen || pbk == 0.0) continue;
+            for (int e = m.st_ptr[k]; e < m.st_ptr[k + 1]; ++e)
+                if (m.st_cell[e] == c) acc += m.st_w[e] * pbk;
+        }
+        A.abar[c] = acc;
+        return;
+    }
     if (A.kind[c] == 1) acc += adj_alpha(A.w.gbuf + (size_t)kAdjG * c);
     int32_t cls[8];
     double pb[8];
@@ -924,6 +1192,7 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
 
 template <int W>
 hipError_t launch_adj_w(const AdjArgs &a, hipStream_t s) {
+    static_assert(W <= 16, "the bounding tape's flags hold 16 slots");
     const int n = a.m.n_cells;
     const int g = (n + 255) / 256;
     const int gb = std::max(1, std::min(g, (int)kAdjBoundBlocks));
@@ -936,6 +1205,10 @@ hipError_t launch_adj_w(const AdjArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_faces<W>, dim3(g), dim3(256), 0, s, a);
     const int gs = std::max(1, std::min(2048, (int)((9L * n * kLanes + 255) / 256)));
     hipLaunchKernelGGL(k_adj_surface, dim3(gs), dim3(256), 0, s, a);
+    if (a.m.cbig) {
+        const int gb = std::max(1, std::min(1024, (int)((33L * a.w.big_cap + kBGrpPerBlock - 1) / kBGrpPerBlock)));
+        hipLaunchKernelGGL(k_adj_surface_big, dim3(gb), dim3(kBGrp * kBGrpPerBlock), 0, s, a);
+    }
     hipLaunchKernelGGL(k_adj_points, dim3((a.m.n_classes + 255) / 256), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_adj_cells, dim3(g), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -953,13 +1226,17 @@ hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, 
     if (e != hipSuccess) return e;
     AdjArgs A{m, a.alpha, a.phi, a.U, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
               in.vert_alpha, in.kind, in.iso, in.dV, in.raw, in.abar_new, in.abar, in.phibar, w};
-    switch (m.W) {
+    switch (m.W) {  // the slot widths of the step's update (polyhedra pad theirs to 8, 12 or 16)
         case 1: return launch_adj_w<1>(A, s);
         case 2: return launch_adj_w<2>(A, s);
         case 3: return launch_adj_w<3>(A, s);
         case 4: return launch_adj_w<4>(A, s);
         case 5: return launch_adj_w<5>(A, s);
-        default: return launch_adj_w<6>(A, s);
+        case 6: return launch_adj_w<6>(A, s);
+        case 8: return launch_adj_w<8>(A, s);
+        case 12: return launch_adj_w<12>(A, s);
+        case 16: return launch_adj_w<16>(A, s);
+        default: return hipErrorInvalidValue;
     }
 }
 

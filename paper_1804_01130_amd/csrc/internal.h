@@ -152,7 +152,7 @@ struct Params {
 // adjoint counters: the interface cells' (cell, direction) pairs to differentiate along, then per
 // sweep s the length of its list of
 // cells out of bounds (kAdjL + s) and of the cells its corrections touch (kAdjT + s)
-enum : int { kAdjDirs = 2, kAdjL = 8, kAdjT = 40, kAdjNum = 72, kAdjMaxSweeps = 31, kAdjG = 20,
+enum : int { kAdjDirs = 2, kAdjDirsBig = 3, kAdjGBig = 68, kAdjL = 8, kAdjT = 40, kAdjNum = 72, kAdjMaxSweeps = 31, kAdjG = 20,
              kAdjBoundBlocks = 512 };
 struct AdjWork {
     int32_t *counters = nullptr;  // [kAdjNum]
@@ -164,7 +164,7 @@ struct AdjWork {
     int32_t *tlist = nullptr;     // [S nc] cells touched in each sweep
     int32_t *cmark = nullptr;     // [2 nc] two banks of cell marks, zero between calls
     double *tape = nullptr;       // [S nc (4 + 2 W)]
-    int32_t *tflag = nullptr;     // [S nc]
+    uint64_t *tflag = nullptr;    // [S nc]
     double *dvcur = nullptr;      // [nf] running dV of corrected faces
     int32_t *touched = nullptr;   // [nf] faces corrected in an earlier sweep, zero between calls
     double *delta = nullptr;      // [3 nf] three rotating correction buffers, zero between calls
@@ -177,6 +177,10 @@ struct AdjWork {
                                   // isovalue (see adjoint.hip)
     double *pbar = nullptr;       // [n_classes] adjoint of each point class's vertex value
     int64_t *dlist = nullptr;     // [9 nc] (cell << 4 | direction) pairs of the interface cells
+    // general polyhedra: (cell << 6 | direction) pairs, and the rates per polyhedron
+    int64_t *dlist_big = nullptr;  // [33 n_big]
+    double *gbig = nullptr;        // [kAdjGBig n_big]
+    int32_t big_cap = 0;           // n_big
 };
 struct AdjInputs {
     const double *vert_alpha;  // forward intermediates of the step

@@ -1085,16 +1085,19 @@ static iso_status adj_alloc(iso_plan *p) {
         alloc((void **)&w.counters, kAdjNum * 4) && alloc((void **)&w.x, nc * 8) && alloc((void **)&w.xbar, nc * 8) && alloc((void **)&w.pv, nc * 8) &&
         alloc((void **)&w.cflag, nc * 4) && alloc((void **)&w.list, S * nc * 4) && alloc((void **)&w.tlist, S * nc * 4) &&
         alloc((void **)&w.cmark, 2 * nc * 4) &&
-        alloc((void **)&w.tape, S * nc * (4 + 2 * (size_t)m->W) * 8) && alloc((void **)&w.tflag, S * nc * 4) &&
+        alloc((void **)&w.tape, S * nc * (4 + 2 * (size_t)m->W) * 8) && alloc((void **)&w.tflag, S * nc * 8) &&
         alloc((void **)&w.dvcur, nf * 8) && alloc((void **)&w.touched, nf * 4) && alloc((void **)&w.delta, 3 * nf * 8) &&
         alloc((void **)&w.dVb, nf * 8) && alloc((void **)&w.phib, nf * 8) && alloc((void **)&w.dvcurbar, nf * 8) &&
         alloc((void **)&w.deltabar, nf * 8) && alloc((void **)&w.vbar, nf * 8) &&
         alloc((void **)&w.gbuf, kAdjG * nc * 8) && alloc((void **)&w.pbar, std::max<size_t>(m->n_classes, 1) * 8) &&
         alloc((void **)&w.dlist, 9 * nc * 8) &&
+        alloc((void **)&w.dlist_big, 33 * std::max<size_t>(m->n_big, 1) * 8) &&
+        alloc((void **)&w.gbig, kAdjGBig * std::max<size_t>(m->n_big, 1) * 8) &&
         alloc((void **)&p->adj_vert, 8 * nc * 8) && alloc((void **)&p->adj_kind, nc * 4) &&
         alloc((void **)&p->adj_iso, nc * 8) && alloc((void **)&p->adj_dV, nf * 8) && alloc((void **)&p->adj_raw, nc * 8) &&
         alloc((void **)&p->adj_new, nc * 8);
     if (!ok) return fail(ISO_ENOMEM, "adjoint workspace allocation failed");
+    w.big_cap = m->n_big;
     if (hipDeviceSynchronize() != hipSuccess) return fail(ISO_EDEVICE, "device error at adjoint workspace setup");
     p->adj_ready = true;
     return ISO_OK;
@@ -1109,8 +1112,6 @@ iso_status iso_advect_step_adjoint(iso_plan *p, const double *alpha, const doubl
     if (p->opt.n_bound_iter > kAdjMaxSweeps)
         return fail(ISO_EUNSUPPORTED, "the adjoint takes at most " + std::to_string(kAdjMaxSweeps) + " bounding sweeps");
     if (p->opt.us_mode != 0) return fail(ISO_EUNSUPPORTED, "the adjoint takes U_S = U_P (us_mode 0) only");
-    if (p->mesh->dev.cbig)
-        return fail(ISO_EUNSUPPORTED, "the adjoint takes hexahedra, tetrahedra, pyramids and prisms, not general polyhedra");
     if (fwd && (!fwd->vert_alpha || !fwd->kind || !fwd->iso || !fwd->dV || !fwd->alpha_raw))
         return fail(ISO_EINVAL, "forward trace needs vert_alpha, kind, iso, dV and alpha_raw");
     const iso_mesh *m = p->mesh;

@@ -89,11 +89,13 @@ def test_adjoint_through_every_bounding_schedule(oracle_lib, n_iter, clip):
 
 
 @pytest.mark.parametrize("kind,perturb", [("tet", 0.0), ("pyramid", 0.0), ("prism", 0.0), ("prism", 0.15),
-                                          ("mixed", 0.0)])
+                                          ("mixed", 0.0), ("merged", 0.0), ("merged", 0.1),
+                                          ("merged_joined", 0.1), ("merged_sparse", 0.1)])
 def test_adjoint_on_cells_other_than_hexahedra(oracle_lib, kind, perturb):
-    """Tetrahedra, pyramids, prisms (flat, or with bent quadrilaterals) and hexahedra next to prisms:
-    every component of the adjoint against the oracle's Jacobian (one exact tangent per input
-    component), for two seeds."""
+    """Tetrahedra, pyramids, prisms (flat, or with bent quadrilaterals), hexahedra next to prisms and
+    general polyhedra (mostly polyhedra, flat or bent; joined faces of 6 and 8 points; a minority
+    beside the eight-lane kernels): every component of the adjoint against the oracle's Jacobian
+    (one exact tangent per input component), for two seeds."""
     O = oracle_lib
     w = W.poly_violent(kind, nx=8, ny=4, nz=4, steps=4, perturb=perturb)
     n, nf = w.mesh.n_cells, w.mesh.n_faces

@@ -140,19 +140,6 @@ def test_capped_searches_are_counted_once_per_cell(name):
     assert 1 <= st["n_nonconverged"] <= capped
 
 
-def test_the_adjoint_refuses_general_polyhedra():
-    import torch
-    from paper_1804_01130_amd import IsoError, Mesh, Plan, default_options
-    # the adjoint takes tetrahedra, pyramids and prisms, but not general polyhedra
-    wm = CASES["merged_16x8x8"]
-    gmm = Mesh.from_arrays(wm.mesh)
-    plan = Plan(gmm, default_options())
-    phi, U = wm.phi_U(0)
-    a = to_dev(wm.alpha0)
-    with pytest.raises(IsoError):
-        plan.adjoint(a, to_dev(phi), to_dev(U), wm.dt, torch.ones_like(a))
-
-
 def test_ghost_fluid_faces_and_relaxation_on_prisms(oracle_lib):
     """The face and cell kernels after the step need no hexahedra: ghost-fluid face data and the
     relaxation blend on the prism mesh against the oracle."""
