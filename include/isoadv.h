@@ -26,8 +26,8 @@
  *    faces of 3 or 4 points over at most 8 points (tetrahedra, square
  *    pyramids, triangular prisms); and general polyhedra of 4 to 16 faces of 3
  *    to 16 points over at most 32 points (e.g. hexahedra merged across split
- *    faces).  Larger cells give ISO_EUNSUPPORTED.  us_mode 1 and ensembles take
- *    every cell type, the adjoint every type but general polyhedra.
+ *    faces).  Larger cells give ISO_EUNSUPPORTED.  Every entry point takes
+ *    every cell type.
  *  - Patch kinds: WALL and EMPTY faces carry no flux (their phi is ignored);
  *    INOUT faces carry flux, inflow carrying the patch's alpha_in; CYCLIC
  *    patches come in pairs (face n of a patch matches face n of its partner,
