@@ -442,11 +442,12 @@ __device__ __forceinline__ void adj_append_touched(const AdjArgs &A, int s, cons
 }
 
 // per cell: start state of bounding (and phase A of its first sweep), lists, per-face adjoint
-// buffers cleared
+// buffers and phi_bar cleared
 template <int W>
 __global__ void __launch_bounds__(256) k_adj_prep(AdjArgs A) {
     const int n = A.m.n_cells;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t f = c; f < A.m.n_faces; f += (int64_t)gridDim.x * blockDim.x) A.phibar[f] = 0.0;
     bool offend = false;
     double x = 0.0;
     if (c < n) {
@@ -1149,6 +1150,8 @@ __global__ void __launch_bounds__(256) k_adj_points(AdjArgs A) {
 __global__ void __launch_bounds__(256) k_adj_cells(AdjArgs A) {
     const DevMesh &m = A.m;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    // nothing reads the counters after the surface kernels: leave them zero for the next call
+    if (blockIdx.x == 0 && threadIdx.x < kAdjNum) A.w.counters[threadIdx.x] = 0;
     if (c >= m.n_cells) return;
     double acc = A.abar[c];
     if (m.cbig && m.cbig[c] >= 0) {
@@ -1186,9 +1189,6 @@ __global__ void __launch_bounds__(256) k_adj_cells(AdjArgs A) {
     A.abar[c] = acc;
 }
 
-__global__ void k_fill_f64(double *p, int64_t n, double v) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
-}
 
 template <int W>
 hipError_t launch_adj_w(const AdjArgs &a, hipStream_t s) {
@@ -1219,11 +1219,8 @@ hipError_t launch_adj_w(const AdjArgs &a, hipStream_t s) {
 hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, const AdjInputs &in, const AdjWork &w,
                           hipStream_t s) {
     if (p.n_bound_iter > kAdjMaxSweeps) return hipErrorInvalidValue;
-    const int64_t nf = m.n_faces;
-    const int g = (int)std::min<int64_t>((nf + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_f64, dim3(g), dim3(256), 0, s, in.phibar, nf, 0.0);
-    hipError_t e = launch_offset_copy(nullptr, w.counters, kAdjNum, 0, 0, 0, s);
-    if (e != hipSuccess) return e;
+    // phi_bar starts at zero in k_adj_prep (faces that carry no flux keep it); the counters are
+    // zero from the workspace's allocation and left zero by k_adj_cells at the end of every call
     AdjArgs A{m, a.alpha, a.phi, a.U, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
               in.vert_alpha, in.kind, in.iso, in.dV, in.raw, in.abar_new, in.abar, in.phibar, w};
     switch (m.W) {  // the slot widths of the step's update (polyhedra pad theirs to 8, 12 or 16)
