@@ -749,7 +749,7 @@ __global__ void __launch_bounds__(256) k_adj_faces(AdjArgs A) {
 }
 
 // interface cells: rates of the sub-volume and the swept integrals along each listed direction
-__global__ void __launch_bounds__(256) k_adj_surface(AdjArgs A) {
+__global__ void __launch_bounds__(256, 2) k_adj_surface(AdjArgs A) {
     const DevMesh &m = A.m;
     const int lv = threadIdx.x & (kLanes - 1);
     const int ngrp = (gridDim.x * blockDim.x) / kLanes;
