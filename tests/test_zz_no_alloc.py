@@ -45,6 +45,21 @@ def test_no_alloc_step_matches_the_plan_step_bit_for_bit():
         assert not np.array_equal(ref[0], w.alpha0)
 
 
+def test_no_alloc_step_on_cells_other_than_hexahedra():
+    # polyhedra among hexahedra: the plan runs the polyhedron kernel on its side stream, this entry
+    # on the caller's stream; then polyhedra only, then tetrahedra and pyramids, each mesh smaller
+    cases = [W.poly_violent("merged_sparse", nx=16, ny=8, nz=8, steps=4, perturb=0.1),
+             W.poly_violent("merged_joined", nx=12, ny=6, nz=6, steps=4, perturb=0.1),
+             W.poly_violent("mixed", nx=12, ny=6, nz=6, steps=4),
+             W.poly_violent("tet", nx=8, ny=4, nz=4, steps=4)]
+    for w in cases:
+        say(f"[gpu] no-allocation step vs plan step: {w.name} ({w.mesh.n_cells} cells, 4 steps)")
+        ref, got = _both(w, 4)
+        for n in range(4):
+            assert np.array_equal(ref[n], got[n]), (w.name, n, np.abs(ref[n] - got[n]).max())
+        assert not np.array_equal(ref[0], w.alpha0)
+
+
 def test_no_alloc_step_refuses_what_it_cannot_hold():
     import torch
     from paper_1804_01130_amd import IsoError, Mesh, default_options
