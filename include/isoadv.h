@@ -100,6 +100,9 @@ typedef struct {
     double root_tol;        /* isovalue tolerance (Section 3.2 leaves it to the user): the search
                                stops once |V_sub/V_P - alpha_P| <= root_tol; 0 (default) converges
                                to round-off.  In [0, 1). */
+    int32_t full_slots;     /* 1: the update reads every flux slot from the mesh's full-width
+                               tables; 0 (default): from its 32-bit slot words where the mesh has
+                               them (iso_mesh_info).  The same bits either way. */
 } iso_options;
 
 typedef struct {
@@ -144,7 +147,11 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
                            const double *patch_alpha_in /* [n_patches] */, iso_mesh **out);
 void iso_mesh_destroy(iso_mesh *mesh);
 /* info[0..7] = n_cells, n_points, n_faces, n_flux_faces, n_point_classes, slots per cell,
- *              device bytes held, reserved */
+ *              device bytes held, and the flux slots that the update reads from the full-width
+ *              tables beside its 32-bit slot words (-1: the mesh has no such words, because more
+ *              than a tenth of its flux slots would not fit them; they fit where the internal
+ *              faces are numbered by owner, each owner below its neighbour, and neighbours lie
+ *              within 32768 cells) */
 iso_status iso_mesh_info(const iso_mesh *mesh, int64_t *info);
 /* host out[8*n_cells]: user point id of each canonical vertex of each cell (hexahedra: the
  * canonical order; other cells: their distinct points in order of first appearance over their

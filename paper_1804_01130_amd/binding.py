@@ -30,7 +30,8 @@ class IsoOptions(C.Structure):
                 ("max_courant", C.c_double), ("root_max_iter", C.c_int32), ("n_bound_iter", C.c_int32),
                 ("clip", C.c_int32), ("check_inputs", C.c_int32), ("block_cells", C.c_int32),
                 ("surface_blocks", C.c_int32), ("max_surface", C.c_int32), ("surface_waves", C.c_int32),
-                ("bound_blocks", C.c_int32), ("us_mode", C.c_int32), ("root_tol", C.c_double)]
+                ("bound_blocks", C.c_int32), ("us_mode", C.c_int32), ("root_tol", C.c_double),
+                ("full_slots", C.c_int32)]
 
 
 class IsoStepStats(C.Structure):
@@ -252,7 +253,8 @@ class Mesh:
     def info(self):
         out = (C.c_int64 * 8)()
         check(lib().iso_mesh_info(self.h, out))
-        keys = ["n_cells", "n_points", "n_faces", "n_flux_faces", "n_point_classes", "slots", "device_bytes"]
+        keys = ["n_cells", "n_points", "n_faces", "n_flux_faces", "n_point_classes", "slots", "device_bytes",
+                "wide_slots"]
         return {k: int(out[i]) for i, k in enumerate(keys)}
 
     def cell_points(self):

@@ -44,6 +44,15 @@ struct DevMesh {
     const double *vol = nullptr;       // [n_cells]
     const int32_t *slot_face = nullptr;  // [W][n_cells] packed flux faces, ascending face id, kEmpty last
     const int32_t *slot_nbr = nullptr;   // [W][n_cells] cell across the face, or -1-patch on the boundary
+    // [W][n_cells] the same slots in one 32-bit word each, which the update reads instead (null
+    // when more than a tenth of the flux slots do not fit).  Upper half: the neighbour's offset from
+    // the cell, positive offsets less one (an offset in [-32768, 32768] other than 0).  Lower half:
+    // the face id less floor(owner * nar_S / 2^28), where the owner is the lower-numbered of the two
+    // cells (which fixes the side) and nar_S = floor(n_internal 2^28 / n_cells).  0xFFFE: an empty
+    // slot; 0xFFFF: read this slot from slot_face and slot_nbr (boundary faces, cyclic pairs, and
+    // internal faces whose owner is the higher-numbered cell or whose offsets do not fit).
+    const uint32_t *slot_nar = nullptr;
+    uint32_t nar_S = 0;
     const int32_t *lface = nullptr;      // [6*n_cells] packed flux face of each canonical face, or kEmpty
     const int32_t *cflags = nullptr;     // [n_cells] bit k: canonical face k is planar
     const int32_t *st_ptr = nullptr;     // [n_classes+1] vertex stencils
@@ -138,6 +147,7 @@ struct LaunchCfg {
     int surface_blocks; // work-groups of the interface kernel (0: from the list capacity)
     int surface_waves;  // register budget of the interface kernel, waves per SIMD (1-4)
     int bound_blocks;   // work-groups of the bounding sweeps
+    int compact_slots;  // the update reads the mesh's 32-bit slot words where it has them
 };
 
 struct Params {
@@ -255,6 +265,7 @@ struct iso_mesh {
     bool generic = false;            // some cell is not a hexahedron
     // general polyhedra: how many, and the lengths of their point, face and loop arrays
     int32_t n_big = 0, n_bv = 0, n_bf = 0, n_bl = 0;
+    int64_t n_wide_slots = -1;       // flux slots the 32-bit words send to the full tables (-1: no words)
     std::vector<double> vol, xc;
     std::vector<double> patch_alpha;
     int64_t st_nnz = 0;              // entries of the vertex stencils

@@ -937,10 +937,36 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
         ph[k] = dvo[k] = 0.0;
     }
     if (c < n) {
+        if (A.m.slot_nar) {
+            // the 32-bit slot words: all loaded before any is decoded, then the slots they send
+            // to the full tables
+            uint32_t wd[W];
+            bool wide[W];
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-            v[k] = __builtin_nontemporal_load(A.m.slot_face + (size_t)k * n + c);
-            o[k] = __builtin_nontemporal_load(A.m.slot_nbr + (size_t)k * n + c);
+            for (int k = 0; k < W; ++k) wd[k] = __builtin_nontemporal_load(A.m.slot_nar + (size_t)k * n + c);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const uint32_t h = wd[k] & 0xFFFFu;
+                const int32_t up = (int32_t)(int16_t)(uint16_t)(wd[k] >> 16);
+                const int32_t nb = c + (up >= 0 ? up + 1 : up);
+                const uint32_t owner = (uint32_t)min(c, nb);
+                const int32_t f = (int32_t)(((uint64_t)owner * A.m.nar_S) >> 28) + (int32_t)h;
+                wide[k] = h == 0xFFFFu;
+                v[k] = h == 0xFFFEu ? kEmpty : (c < nb ? f : ~f);
+                o[k] = h == 0xFFFEu ? -1 : nb;
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (wide[k]) {
+                    v[k] = __builtin_nontemporal_load(A.m.slot_face + (size_t)k * n + c);
+                    o[k] = __builtin_nontemporal_load(A.m.slot_nbr + (size_t)k * n + c);
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                v[k] = __builtin_nontemporal_load(A.m.slot_face + (size_t)k * n + c);
+                o[k] = __builtin_nontemporal_load(A.m.slot_nbr + (size_t)k * n + c);
+            }
         }
         const double aP = A.alpha[c];
         V = __builtin_nontemporal_load(A.m.vol + c);
@@ -1421,6 +1447,7 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
     const int st = want_stats && w.sbnd && w.sclip ? 1 : 0;
     UpdArgs ua{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, a.alpha_new, w.olist,
                w.counters, tr.dV, tr.alpha_raw, p.n_bound_iter, w, a.phi1, st};
+    if (!cfg.compact_slots) ua.m.slot_nar = nullptr;
     BoundArgs ba{m, a.alpha, a.phi, w.dvs, a.dt, a.dt_dom, p.eps_surf, p.bound_tol, p.clip, p.n_bound_iter,
                  a.alpha_new, w, a.phi1, st};
     const bool avg = a.phi1 != nullptr;

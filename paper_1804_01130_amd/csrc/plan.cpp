@@ -94,6 +94,7 @@ LaunchCfg launch_cfg(const iso_options &o) {
     c.surface_blocks = o.surface_blocks;
     c.surface_waves = o.surface_waves > 0 ? o.surface_waves : 2;
     c.bound_blocks = o.bound_blocks > 0 ? o.bound_blocks : 512;
+    c.compact_slots = o.full_slots ? 0 : 1;
     return c;
 }
 Params step_params(const iso_options &o) {
@@ -104,7 +105,7 @@ iso_status check_options(const iso_options &o, const iso_mesh *mesh) {
         o.n_bound_iter < 0 || o.block_cells < 0 || o.block_cells > 1024 ||
         o.surface_blocks < 0 || o.surface_blocks > 65535 || o.bound_blocks < 0 || o.bound_blocks > 65535 ||
         o.max_surface < 0 || o.surface_waves < 0 || o.surface_waves > 4 || o.us_mode < 0 || o.us_mode > 1 ||
-        !(o.root_tol >= 0 && o.root_tol < 1))
+        !(o.root_tol >= 0 && o.root_tol < 1) || o.full_slots < 0 || o.full_slots > 1)
         return fail(ISO_EINVAL, "bad options");
     return ISO_OK;
 }
@@ -565,6 +566,38 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
             slot_face[k * n_cells + c] = pack_face(slots[c][k][0], slots[c][k][1]);
             slot_nbr[k * n_cells + c] = slots[c][k][2];
         }
+    // the update's 32-bit slot words (the layout is described with DevMesh::slot_nar): half the
+    // bytes of slot_face + slot_nbr on meshes whose internal faces are numbered by owner, each owner
+    // below its neighbour, and whose neighbours lie within 32768 cells
+    std::vector<uint32_t> slot_nar;
+    uint32_t nar_S = 0;
+    {
+        int64_t n_slots = 0, n_wide = 0;
+        if (n_internal > 0) {
+            nar_S = (uint32_t)(((uint64_t)n_internal << 28) / (uint64_t)n_cells);
+            slot_nar.assign((size_t)W * n_cells, 0xFFFEu);
+            for (int32_t c = 0; c < n_cells; ++c)
+                for (size_t k = 0; k < slots[c].size(); ++k) {
+                    const int32_t fid = slots[c][k][0], o = slots[c][k][2];
+                    const bool own_side = slots[c][k][1] > 0;
+                    const int64_t dn = (int64_t)o - c;
+                    uint32_t wd = 0xFFFFu;
+                    if (fid < n_internal && o >= 0 && dn != 0 && dn >= -32768 && dn <= 32768 && own_side == (c < o)) {
+                        const uint32_t owner = (uint32_t)std::min(c, o);
+                        const int64_t d = (int64_t)fid - (int64_t)(((uint64_t)owner * nar_S) >> 28);
+                        if (d >= 0 && d <= 0xFFFD) {
+                            const int32_t up = dn > 0 ? (int32_t)dn - 1 : (int32_t)dn;
+                            wd = ((uint32_t)(uint16_t)(int16_t)up << 16) | (uint32_t)d;
+                        }
+                    }
+                    slot_nar[k * (size_t)n_cells + c] = wd;
+                    ++n_slots;
+                    n_wide += wd == 0xFFFFu ? 1 : 0;
+                }
+        }
+        if (n_slots > 0 && n_wide * 10 <= n_slots) m->n_wide_slots = n_wide;
+        else slot_nar.clear();
+    }
     std::vector<int32_t> lface(6 * (size_t)n_cells, kEmpty);
     for (int32_t c = 0; c < n_cells; ++c)
         for (int k = 0; k < 6; ++k) {
@@ -769,9 +802,11 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
                 if (cbig[c] >= 0) cflags[c] |= 1 << 11;
     }
     d.n_internal = n_internal;
+    d.nar_S = nar_S;
     iso_status st = ISO_OK;
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||
         (st = upload(m, slot_face, &d.slot_face)) || (st = upload(m, slot_nbr, &d.slot_nbr)) ||
+        (!slot_nar.empty() && (st = upload(m, slot_nar, &d.slot_nar))) ||
         (st = upload(m, lface, &d.lface)) || (st = upload(m, cflags, &d.cflags)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
         (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha)) ||
         (st = upload(m, m->xc, &d.ccen)) || (st = upload(m, fcell, &d.fcell)) || (st = upload(m, bpatch, &d.bpatch)) ||
@@ -791,7 +826,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
 iso_status iso_mesh_info(const iso_mesh *m, int64_t *info) {
     if (!m || !info) return fail(ISO_EINVAL, "null argument");
     info[0] = m->n_cells; info[1] = m->n_points; info[2] = m->n_faces; info[3] = m->n_flux;
-    info[4] = m->n_classes; info[5] = m->W; info[6] = m->device_bytes; info[7] = 0;
+    info[4] = m->n_classes; info[5] = m->W; info[6] = m->device_bytes; info[7] = m->n_wide_slots;
     return ISO_OK;
 }
 

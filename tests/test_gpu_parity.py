@@ -177,6 +177,40 @@ def test_planar_transport_exact_on_gpu(O):
     assert np.abs(a - exact).max() <= 1e-12
 
 
+def _slot_word_cases():
+    # (workload, flux slots expected to be read from the full tables: the cyclic pair in x of each
+    # row of the box, the inflow and outflow faces of the perturbed box; None: not checked)
+    v = W.violent_3d(nx=24, ny=13, nz=16, steps=5)
+    p = W.perturbed_box()
+    return {"violent_24x13x16": (v, 2 * 13 * 16), "perturbed_10x7x6": (p, 2 * 7 * 6),
+            "airy_128x64": (CASES["airy_128x64"], None),
+            "tet_12x6x6": (W.poly_violent("tet", nx=12, ny=6, nz=6, steps=5), None),
+            "mixed_16x8x8": (W.poly_violent("mixed", nx=16, ny=8, nz=8, steps=5), None),
+            "merged_16x8x8": (W.poly_violent("merged", nx=16, ny=8, nz=8, steps=5), None)}
+
+
+SLOT_WORD_CASES = _slot_word_cases()
+
+
+@pytest.mark.parametrize("name", list(SLOT_WORD_CASES))
+def test_slot_words_give_the_same_bits_as_the_full_tables(name):
+    w, wide = SLOT_WORD_CASES[name]
+    say(f"[gpu] update through 32-bit slot words vs the full tables: {name} ({w.mesh.n_cells} cells)")
+    gm, plan = gpu_plan(w.mesh)
+    info = gm.info()
+    say(f"[gpu]   slots per cell {info['slots']}, slots read from the full tables {info['wide_slots']}")
+    assert info["wide_slots"] >= 0  # every mesh here has the words
+    if wide is not None:
+        assert info["wide_slots"] == wide
+    a = gpu_trajectory(plan, w, 5)
+    plan.close()
+    _, full = gpu_plan(w.mesh, full_slots=1)
+    b = gpu_trajectory(full, w, 5)
+    full.close()
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, w.alpha0)
+
+
 def test_determinism_across_launch_shapes():
     w = CASES["violent_32x16x16"]
     say("[gpu] determinism across block sizes")
