@@ -202,6 +202,19 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         iso_batch_destroy(b);
         return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
     }
+    // the update's 32-bit slot words, each member's as its own mesh has them, when every member has
+    // them (they are relative to the member's cells, so they need no offsets: the member's first
+    // cell and face offset go beside them)
+    bool words = true;
+    for (int32_t i = 0; i < n; ++i) words = words && meshes[i]->dev.slot_nar != nullptr;
+    int32_t *snar = nullptr, *nar_dom = nullptr, *nar_blk = nullptr;
+    const int64_t n_blk = (N + 63) / 64;
+    if (words && (!dev_alloc(u, &snar, (int64_t)W * N) || !dev_alloc(u, &nar_dom, 3 * (int64_t)n) ||
+                  !dev_alloc(u, &nar_blk, 8 * n_blk))) {
+        iso_batch_destroy(b);
+        return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
+    }
+    std::vector<int32_t> hnar_dom;
     int64_t bo = 0, vo = 0, bfo = 0, blo = 0;
     hipStream_t s = b->stream;
     hipError_t e = hipSuccess;
@@ -229,6 +242,18 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
                 ok(launch_offset_copy(nullptr, df, nc, 0, kEmpty, 0, s));
                 ok(launch_offset_copy(nullptr, dn, nc, 0, -1, 0, s));
             }
+        }
+        if (words) {
+            for (int k = 0; k < W; ++k) {
+                int32_t *dw = snar + (size_t)k * N + co;
+                if (k < m->W)
+                    ok(hipMemcpyAsync(dw, md.slot_nar + (size_t)k * nc, nc * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+                else
+                    ok(launch_offset_copy(nullptr, dw, nc, 0, 0xFFFE, 0, s));  // empty slots
+            }
+            hnar_dom.push_back((int32_t)md.nar_S);
+            hnar_dom.push_back((int32_t)fo);
+            hnar_dom.push_back((int32_t)co);
         }
         ok(launch_offset_copy(md.lface, lface + 6 * co, 6 * nc, 1, (int32_t)fo, 0, s));
         if (cloop && md.cloop) {
@@ -274,6 +299,25 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         ok(hipMemcpy(bl_ptr + NBF, &nbl, sizeof(int32_t), hipMemcpyHostToDevice));
     }
     ok(hipMemcpy(dom_off, hoff.data(), hoff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (words) {
+        // the record of each 64-cell block (the layout is described with DevMesh::nar_blk)
+        std::vector<int32_t> hblk(8 * n_blk, 0);
+        int32_t dm = 0;
+        for (int64_t bk = 0; bk < n_blk; ++bk) {
+            const int64_t c = 64 * bk, e = std::min<int64_t>(c + 64, N);
+            while (dm + 1 < n && hoff[dm + 1] <= c) ++dm;
+            int32_t split = 64;
+            if (dm + 1 < n && hoff[dm + 1] < e) split = dm + 2 < n && hoff[dm + 2] < e ? -1 : (int32_t)(hoff[dm + 1] - c);
+            int32_t *r = &hblk[8 * bk];
+            for (int j = 0; j < 3; ++j) r[j] = hnar_dom[3 * dm + j];
+            r[3] = split;
+            if (dm + 1 < n)
+                for (int j = 0; j < 3; ++j) r[4 + j] = hnar_dom[3 * (dm + 1) + j];
+            r[7] = dm;
+        }
+        ok(hipMemcpy(nar_dom, hnar_dom.data(), hnar_dom.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        ok(hipMemcpy(nar_blk, hblk.data(), hblk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     if (e != hipSuccess) {
         iso_batch_destroy(b);
         return fail(ISO_EDEVICE, std::string("ensemble mesh assembly failed: ") + hipGetErrorString(e));
@@ -284,6 +328,11 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     d.ccen = ccen;
     d.cloop = cloop;
     d.n_dom = n; d.dom_off = dom_off;
+    if (words) {
+        d.slot_nar = reinterpret_cast<const uint32_t *>(snar);
+        d.nar_dom = nar_dom;
+        d.nar_blk = nar_blk;
+    }
     u->generic = generic;
     if (any_big) {
         d.cbig = cbig; d.bv_ptr = bv_ptr; d.bv_cls = bv_cls; d.bv_xyz = bv_xyz; d.bf_ptr = bf_ptr;

@@ -30,14 +30,18 @@ __device__ __forceinline__ bool interface_cell(double a, double eps) { return a 
 
 // Time step of cell c: the scalar one, or its ensemble member's (binary search over the members'
 // cell offsets, a table of at most a few hundred bytes that stays in cache).
-__device__ __forceinline__ double cell_dt(const DevMesh &m, const double *dt_dom, double dt, int c) {
-    if (m.n_dom <= 0) return dt;
+// the ensemble member holding cell c (0 for a single mesh)
+__device__ __forceinline__ int cell_dom(const DevMesh &m, int c) {
     int lo = 0, hi = m.n_dom;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (m.dom_off[mid] <= c) lo = mid; else hi = mid;
     }
-    return dt_dom[lo];
+    return lo;
+}
+
+__device__ __forceinline__ double cell_dt(const DevMesh &m, const double *dt_dom, double dt, int c) {
+    return m.n_dom <= 0 ? dt : dt_dom[cell_dom(m, c)];
 }
 
 // edges of the canonical hexahedron, and for each face loop position the edge to the next vertex

@@ -922,7 +922,7 @@ __device__ __forceinline__ int32_t *dlist_buf(const DevWork &w, int s, int nf) {
 // Any block size up to 1024 (the block_cells option) is valid.  A cell left out of bounds also
 // runs phase A of the first redistribution sweep (see k_bound_sweep) here: no face is marked yet,
 // so the current dV of each of its outflow faces is the one just computed.
-template <int W, bool kAvg>
+template <int W, bool kAvg, bool kDom>
 __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
     const int n = A.m.n_cells;
     const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -937,6 +937,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
         ph[k] = dvo[k] = 0.0;
     }
     if (c < n) {
+        int dom = -1;  // the ensemble member, when the slot words have given it
         if (A.m.slot_nar) {
             // the 32-bit slot words: all loaded before any is decoded, then the slots they send
             // to the full tables
@@ -944,16 +945,35 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             bool wide[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) wd[k] = __builtin_nontemporal_load(A.m.slot_nar + (size_t)k * n + c);
+            auto decode = [&](uint32_t S, int32_t c0, int32_t f0) {
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const uint32_t h = wd[k] & 0xFFFFu;
-                const int32_t up = (int32_t)(int16_t)(uint16_t)(wd[k] >> 16);
-                const int32_t nb = c + (up >= 0 ? up + 1 : up);
-                const uint32_t owner = (uint32_t)min(c, nb);
-                const int32_t f = (int32_t)(((uint64_t)owner * A.m.nar_S) >> 28) + (int32_t)h;
-                wide[k] = h == 0xFFFFu;
-                v[k] = h == 0xFFFEu ? kEmpty : (c < nb ? f : ~f);
-                o[k] = h == 0xFFFEu ? -1 : nb;
+                for (int k = 0; k < W; ++k) {
+                    const uint32_t h = wd[k] & 0xFFFFu;
+                    const int32_t up = (int32_t)(int16_t)(uint16_t)(wd[k] >> 16);
+                    const int32_t nb = c + (up >= 0 ? up + 1 : up);
+                    const uint32_t owner = (uint32_t)(min(c, nb) - c0);
+                    const int32_t f = f0 + (int32_t)(((uint64_t)owner * S) >> 28) + (int32_t)h;
+                    wide[k] = h == 0xFFFFu;
+                    v[k] = h == 0xFFFEu ? kEmpty : (c < nb ? f : ~f);
+                    o[k] = h == 0xFFFEu ? -1 : nb;
+                }
+            };
+            if constexpr (kDom) {
+                // the member's constants from the record of the cell's 64-cell block
+                const int4 *rec = reinterpret_cast<const int4 *>(A.m.nar_blk) + 2 * (size_t)(c >> 6);
+                const int4 ra = rec[0], rb = rec[1];
+                if (ra.w < 0) {
+                    dom = cell_dom(A.m, c);
+                    decode((uint32_t)A.m.nar_dom[3 * dom], A.m.nar_dom[3 * dom + 2], A.m.nar_dom[3 * dom + 1]);
+                } else if ((c & 63) >= ra.w) {
+                    dom = rb.w + 1;
+                    decode((uint32_t)rb.x, rb.z, rb.y);
+                } else {
+                    dom = rb.w;
+                    decode((uint32_t)ra.x, ra.z, ra.y);
+                }
+            } else {
+                decode(A.m.nar_S, 0, 0);
             }
 #pragma unroll
             for (int k = 0; k < W; ++k)
@@ -978,7 +998,8 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             ao[k] = o[k] >= 0 ? A.alpha[o[k]] : (v[k] != kEmpty ? A.m.patch_alpha[-1 - o[k]] : 0.0);
         }
         const bool sP = interface_cell(aP, A.eps);
-        dtc = cell_dt(A.m, A.dt_dom, A.dt, c);
+        if constexpr (kDom) dtc = dom >= 0 ? A.dt_dom[dom] : cell_dt(A.m, A.dt_dom, A.dt, c);
+        else dtc = cell_dt(A.m, A.dt_dom, A.dt, c);
         double sum = 0.0, bnd = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -1346,7 +1367,9 @@ template <int W, bool kAvg>
 void launch_wide(const DevMesh &m, const UpdArgs &ua, const BoundArgs &ba, const LaunchCfg &cfg, hipStream_t s,
                  hipEvent_t *ev) {
     const int gc = (m.n_cells + cfg.block_cells - 1) / cfg.block_cells;
-    hipLaunchKernelGGL((k_update<W, kAvg>), dim3(gc), dim3(cfg.block_cells), 0, s, ua);  // and sweep 0's phase A
+    // and sweep 0's phase A; ensembles take the members' constants and time steps per cell
+    if (m.n_dom > 0) hipLaunchKernelGGL((k_update<W, kAvg, true>), dim3(gc), dim3(cfg.block_cells), 0, s, ua);
+    else hipLaunchKernelGGL((k_update<W, kAvg, false>), dim3(gc), dim3(cfg.block_cells), 0, s, ua);
     if (ev) (void)hipEventRecord(ev[3], s);
     for (int it = 0; it < ba.n_iter; ++it)
         hipLaunchKernelGGL((k_bound_sweep<W, kAvg>), dim3(cfg.bound_blocks), dim3(256), 0, s, ba, it);
