@@ -202,11 +202,12 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         iso_batch_destroy(b);
         return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
     }
-    // the update's 32-bit slot words, each member's as its own mesh has them, when every member has
+    // the update's 32-bit slot words, each member's as its own mesh has them, when some member has
     // them (they are relative to the member's cells, so they need no offsets: the member's first
-    // cell and face offset go beside them)
-    bool words = true;
-    for (int32_t i = 0; i < n; ++i) words = words && meshes[i]->dev.slot_nar != nullptr;
+    // cell and face offset go beside them); a member without them sends every slot to the full
+    // tables
+    bool words = false;
+    for (int32_t i = 0; i < n; ++i) words = words || meshes[i]->dev.slot_nar != nullptr;
     int32_t *snar = nullptr, *nar_dom = nullptr, *nar_blk = nullptr;
     const int64_t n_blk = (N + 63) / 64;
     if (words && (!dev_alloc(u, &snar, (int64_t)W * N) || !dev_alloc(u, &nar_dom, 3 * (int64_t)n) ||
@@ -246,8 +247,10 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         if (words) {
             for (int k = 0; k < W; ++k) {
                 int32_t *dw = snar + (size_t)k * N + co;
-                if (k < m->W)
+                if (k < m->W && md.slot_nar)
                     ok(hipMemcpyAsync(dw, md.slot_nar + (size_t)k * nc, nc * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+                else if (k < m->W)
+                    ok(launch_offset_copy(nullptr, dw, nc, 0, 0xFFFF, 0, s));  // read from the full tables
                 else
                     ok(launch_offset_copy(nullptr, dw, nc, 0, 0xFFFE, 0, s));  // empty slots
             }

@@ -87,7 +87,8 @@ struct DevMesh {
     // dt_dom[d] (n_dom = 0 for a single mesh: one scalar time step)
     int32_t n_dom = 0;
     const int32_t *dom_off = nullptr;    // [n_dom+1]
-    // ensembles: each member's words, as its own mesh has them, decoded with the member's nar_S,
+    // ensembles: each member's words, as its own mesh has them (0xFFFF throughout for a member
+    // without them), decoded with the member's nar_S,
     // first cell c0 and face offset f0 (face = f0 + floor((owner - c0) nar_S / 2^28) + low half).
     // [8 per 64 cells]: nar_S, f0, c0 of the member holding the block's first cell, the position
     // in the block where the next member starts (64: none; -1: more than two members meet there),

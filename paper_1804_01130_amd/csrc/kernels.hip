@@ -327,10 +327,12 @@ __device__ __forceinline__ double pick8(const double (&v)[8], int i) {
 // eight corners; lane j evaluates it at s_j, and k counts s_1 .. s_6 whose fraction is at least
 // alpha_P.  Other cells: the point a fraction 1 - alpha_P of the way from s_0 to s_7.
 template <bool kGeneric>
-__device__ __forceinline__ int guess_interval(const double (&a)[8], const double (&s)[8], double aP, int lv) {
+__device__ __forceinline__ int guess_interval(const double (&a)[8], const double (&s)[8], double aP, int lv,
+                                              bool hexahedron) {
     bool hit;
     const double x = pick8(s, lv);
-    if constexpr (!kGeneric) {
+    // a hexahedron takes the same guess in either kernel, so that it searches, and ends, alike
+    if (!kGeneric || hexahedron) {
         // canonical vertices 0..3 the bottom loop (0 -> 1 along the first direction, 1 -> 2 along the
         // second), 4..7 above them
         double d1 = 0.25 * fabs((a[1] - a[0]) + (a[2] - a[3]) + (a[5] - a[4]) + (a[6] - a[7]));
@@ -641,7 +643,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_surface(SurfArgs A) {
             int il = 0, ih = 7;
             double fl = 1.0 - aP;
             bool exact = false;
-            int p1 = guess_interval<kGeneric>(a, s, aP, lv), p2 = p1 + 1;
+            int p1 = guess_interval<kGeneric>(a, s, aP, lv, !(m.cflags[c] & 0x100)), p2 = p1 + 1;
             while (ih - il > 1) {
                 int im = (il + ih) >> 1;
                 if (p1 > il && p1 < ih) { im = p1; p1 = -1; }
@@ -924,6 +926,9 @@ __device__ __forceinline__ int32_t *dlist_buf(const DevWork &w, int s, int nf) {
 // so the current dV of each of its outflow faces is the one just computed.
 template <int W, bool kAvg, bool kDom>
 __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
+    // no fused multiply-adds: the single-mesh and ensemble instantiations then round every
+    // operation alike, and an ensemble member gets the same bits as the member stepped alone
+#pragma clang fp contract(off)
     const int n = A.m.n_cells;
     const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     bool offend = false;

@@ -85,6 +85,32 @@ def test_batch_equals_members_alone_bitwise(ensemble):
         assert np.array_equal(g, ref), (d, np.abs(g - ref).max())
 
 
+def test_members_sharing_blocks_of_64_cells():
+    """Members of a few dozen cells: three of them meet in the first 64-cell block of the union's
+    slot-word records (there the update finds each cell's member by a search), and two have no
+    slot words of their own (more than a tenth of their slots are cyclic or inflow faces), so
+    every slot of theirs is read from the full tables; the same bits as each member alone, with
+    the words and without them."""
+    ws = [W.cosine_uniform(nx=8, ny=4, steps=STEPS), W.violent_3d(nx=4, ny=2, nz=2, steps=STEPS),
+          W.cosine_uniform(nx=6, ny=4, steps=STEPS), W.poly_violent("tet", nx=3, ny=2, nz=2, steps=STEPS),
+          W.airy_slab(16, 8, 4, 0.07, 0.45, STEPS, "s4"), W.perturbed_box(nx=4, ny=3, nz=3, steps=STEPS)]
+    off = np.cumsum([0] + [w.mesh.n_cells for w in ws])
+    assert off[2] < 64  # members 0, 1 and 2 in the first block
+    runs = []
+    for full in (0, 1):
+        say(f"[gpu] ensemble of {len(ws)} small members ({off[-1]} cells), full_slots={full}")
+        E = _build(ws, full_slots=full)
+        wide = [m.info()["wide_slots"] for m in E["meshes"]]
+        assert min(wide) < 0 <= max(wide), wide  # members with words and members without
+        got = E["batch"].split_cells(_run(E).cpu().numpy())
+        for d, (g, ref) in enumerate(zip(got, E["alone"])):
+            assert np.array_equal(g, ref), (full, d, np.abs(g - ref).max())
+        runs.append(got)
+        E["batch"].close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
 def test_batch_members_match_oracle(ensemble, oracle_lib):
     E = ensemble
     got = E["batch"].split_cells(_run(E).cpu().numpy())
