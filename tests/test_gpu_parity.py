@@ -211,6 +211,55 @@ def test_slot_words_give_the_same_bits_as_the_full_tables(name):
     assert not np.array_equal(a, w.alpha0)
 
 
+def _flipped(w, frac=0.04, seed=11):
+    """The workload with a seeded fraction of its internal faces turned around (owner and
+    neighbour swapped, the point loop reversed, the flux negated): the same flow on the same
+    cells, with those faces' owners numbered above their neighbours."""
+    import dataclasses
+    m = w.mesh
+    ni = m.n_internal
+    rng = np.random.default_rng(seed)
+    flip = np.zeros(m.n_faces, bool)
+    flip[:ni] = rng.random(ni) < frac
+    owner, neighbour = m.owner.copy(), m.neighbour.copy()
+    owner[:ni][flip[:ni]], neighbour[flip[:ni]] = m.neighbour[flip[:ni]], m.owner[:ni][flip[:ni]]
+    pts = m.face_pts.copy()
+    for f in np.flatnonzero(flip):
+        a, b = m.face_ptr[f], m.face_ptr[f + 1]
+        pts[a:b] = m.face_pts[a:b][::-1]
+    mesh = dataclasses.replace(m, face_pts=pts, owner=owner, neighbour=neighbour)
+    sign = np.where(flip, -1.0, 1.0)
+    fields = lambda n: (sign * w.phi_U(n)[0], w.phi_U(n)[1])
+    return dataclasses.replace(w, name=w.name + "_flipped", mesh=mesh, fields=fields), int(flip.sum())
+
+
+def test_slot_words_with_faces_owned_by_the_higher_cell(oracle_lib):
+    """Internal faces whose owner is numbered above the neighbour do not fit the slot words: those
+    slots (two per face) are read from the full tables, the others from the words, with the same
+    bits as the full tables alone and the oracle's trajectory."""
+    base = W.violent_3d(nx=24, ny=13, nz=16, steps=6)
+    w, n_flip = _flipped(base)
+    say(f"[gpu] slot words with {n_flip} faces turned around: {w.name} ({w.mesh.n_cells} cells)")
+    gm, plan = gpu_plan(w.mesh)
+    info = gm.info()
+    assert info["wide_slots"] == 2 * n_flip + 2 * 13 * 16  # the turned faces and the cyclic pairs
+    a = gpu_trajectory(plan, w, 6)
+    plan.close()
+    _, full = gpu_plan(w.mesh, full_slots=1)
+    b = gpu_trajectory(full, w, 6)
+    full.close()
+    assert np.array_equal(a, b)
+    ref = oracle_trajectory(oracle_lib.OracleMesh(w.mesh), w, 6)
+    err = np.abs(a - ref).max()
+    say(f"[gpu]   max |gpu - oracle| = {err:.3e}")
+    assert err <= 1e-10
+    # the turned mesh is the same flow on the same cells: its trajectory is the original's
+    _, orig = gpu_plan(base.mesh)
+    c = gpu_trajectory(orig, base, 6)
+    orig.close()
+    assert np.abs(a - c).max() <= 1e-12
+
+
 def test_determinism_across_launch_shapes():
     w = CASES["violent_32x16x16"]
     say("[gpu] determinism across block sizes")
