@@ -1034,7 +1034,7 @@ __global__ void __launch_bounds__(1024) k_update(UpdArgs A) {
             A.w.sclip[c] = (x - x0) * V;
         }
         offend = x > 1.0 + A.tol || x < -A.tol;
-        __builtin_nontemporal_store(x, A.alpha_new + c);
+        A.alpha_new[c] = x;  // a plain store: the next step's find kernel reads it from the caches
     }
     const uint64_t mask = __ballot(offend);
     if (mask == 0) return;
