@@ -260,6 +260,19 @@ def test_slot_words_with_faces_owned_by_the_higher_cell(oracle_lib):
     assert np.abs(a - c).max() <= 1e-12
 
 
+def test_no_slot_words_where_neighbours_lie_too_far_apart():
+    """A box two cells high whose z-neighbours are 256 x 130 = 33280 cells apart: a fifth of the
+    flux slots (both sides of every z-face, and the cyclic pairs) cannot take the words, more than
+    the tenth allowed, so the mesh gets none and the update reads the full tables."""
+    w = W.violent_3d(nx=256, ny=130, nz=2, steps=2)
+    say(f"[gpu] slot words refused: {w.name} ({w.mesh.n_cells} cells)")
+    gm, plan = gpu_plan(w.mesh)
+    assert gm.info()["wide_slots"] == -1
+    a = gpu_trajectory(plan, w, 2)
+    plan.close()
+    assert not np.array_equal(a, w.alpha0)
+
+
 def test_determinism_across_launch_shapes():
     w = CASES["violent_32x16x16"]
     say("[gpu] determinism across block sizes")
