@@ -65,6 +65,10 @@ PROFILE_COMMANDS = {
     "sq": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
           "SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU -T -f csv -d /root/repo/gpurun_out/prof_sq "
           "-o run -- python3 /root/repo/bench.py --workload {w} " + _PROF_ARGS + " > /root/repo/gpurun_out/prof_sq/bench.json",
+    # the batched ensemble alone (no plain comparison), whose timed run ends the process
+    "ensemble": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -T -f csv "
+                "-d /root/repo/gpurun_out/prof_ens -o run -- python3 /root/repo/bench.py --ensemble-only --steps 20 "
+                "--warmup 3 > /root/repo/gpurun_out/prof_ens/bench.json",
 }
 
 
@@ -235,6 +239,50 @@ def _pmc_per_dispatch(path, counter):
     return vals
 
 
+def summarize_ensemble_profile():
+    """profiles/kernel_stats_airy_ensemble_64.txt from the rocprofv3 kernel trace of the ensemble
+    command: the step kernels of the timed batched run (the last K steps of the process)."""
+    import csv
+    run = json.loads(open(os.path.join(ROOT, "gpurun_out/prof_ens/bench.json")).read())
+    steps, ens = int(run["steps"]), run["ensemble"]
+    trace = sorted(csv.DictReader(open(_find("gpurun_out/prof_ens", "kernel_trace.csv"))),
+                   key=lambda r: int(r["Start_Timestamp"]))
+    keys = [("surface_big" if "k_surface_big" in r["Kernel_Name"] else _kernel_key(r["Kernel_Name"]), r)
+            for r in trace]
+    finds = [int(r["Start_Timestamp"]) for k, r in keys if k == "find_surface"]
+    if len(finds) < steps:
+        raise SystemExit("fewer find_surface dispatches than timed steps in the ensemble trace")
+    t0 = finds[-steps]
+    by = {}
+    for k, r in keys:
+        if k in ("find_surface", "surface", "surface_big", "update", "bound_sweep", "bound_end") and \
+                int(r["Start_Timestamp"]) >= t0:
+            by.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    lines = [f"# rocprofv3 kernel trace, workload {ens['workload']}: the timed batched run",
+             f"# command (repository root): {PROFILE_COMMANDS['ensemble']}",
+             f"# kernel_source_sha: {run['kernel_source_sha']}",
+             f"# window: the last {steps} steps (the graph replay the benchmark times, after {run['warmup']} warm-up "
+             f"steps and the capture run); {ens['interface_cells']} interface cells at its start; launch shapes "
+             f"{ens['tuned_config']}",
+             "# kernel | dispatches | per step | mean us | min us | max us"]
+    tot = 0.0
+    for k in ("find_surface", "surface", "surface_big", "update", "bound_sweep", "bound_end"):
+        if k not in by:
+            continue
+        d = by[k]
+        tot += sum(d) / steps
+        lines.append(f"k_{k} | {len(d)} | {len(d) / steps:g} | {np.mean(d):.2f} | {min(d):.2f} | {max(d):.2f}")
+    lines.append(f"# kernels per step {tot:.1f} us; the run's events gave {ens['batched_ms_per_step'] * 1e3:.1f} us/step "
+                 f"({ens['batched_cell_steps_per_s']:.3e} cell-steps/s, {ens['hbm_frac']:.4f} of the HBM roofline at "
+                 f"{ens['bytes_per_cell_step']:.1f} B/cell-step)")
+    lines.append("# whole process (rocprofv3 --stats): name | calls | total ms | average us | min us | max us | share %")
+    for r in csv.DictReader(open(_find("gpurun_out/prof_ens", "kernel_stats.csv"))):
+        lines.append(f"{r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}")
+    open(os.path.join(PROFILES, "kernel_stats_airy_ensemble_64.txt"), "w").write("\n".join(lines) + "\n")
+
+
 def summarize_profiles(workload):
     """profiles/kernel_stats_<workload>.txt and profiles/hbm_traffic_<workload>.txt from the
     rocprofv3 output of PROFILE_COMMANDS (kernel trace; FETCH_SIZE and WRITE_SIZE counter passes,
@@ -349,7 +397,7 @@ def summarize_profiles(workload):
     log(f"[bench] wrote profiles for {workload}")
 
 
-def ensemble_bench(steps, warmup, tune_cache=None):
+def ensemble_bench(steps, warmup, tune_cache=None, plain=True):
     """64 Airy domains of uneven sizes: the batched path (one launch per kernel over all members,
     autotuned launch shapes, a captured graph of the whole run) against the plain path (each
     member's own plan, step by step), on the same per-step fields resident in HBM."""
@@ -391,6 +439,16 @@ def ensemble_bench(steps, warmup, tune_cache=None):
     ms_b = e0.elapsed_time(e1)
     n_s = int(((start > 1e-8) & (start < 1.0 - 1e-8)).sum().item())
     batched = a.cpu().numpy()
+    nflux = sum(m.info()["n_flux_faces"] for m in meshes)
+    b_alg = (24.0 * N + 16.0 * nflux + 1100.0 * n_s) / N
+    vb = N * steps / (ms_b * 1e-3)
+    if not plain:  # the batched run alone (its kernels are then the last ones of the process)
+        out = {"workload": f"airy_ensemble_64 ({len(ws)} members, {N} cells)", "steps": steps, "cells": N,
+               "interface_cells": n_s, "batched_cell_steps_per_s": vb, "batched_ms_per_step": ms_b / steps,
+               "tuned_config": cfg, "hbm_frac": b_alg * vb / (HBM_PEAK_GBS * 1e9), "bytes_per_cell_step": b_alg}
+        log(f"[bench] ensemble: batched {ms_b / steps * 1e3:.1f} us/step, config {cfg}")
+        batch.close()
+        return out
     # plain: every member through its own plan, step by step
     plans = [Plan(m, default_options()) for m in meshes]
     st = [start[co[d]:co[d + 1]].clone() for d in range(len(ws))]
@@ -417,9 +475,6 @@ def ensemble_bench(steps, warmup, tune_cache=None):
     torch.cuda.synchronize()
     ms_p = e0.elapsed_time(e1)
     plain = torch.cat(st).cpu().numpy()
-    nflux = sum(m.info()["n_flux_faces"] for m in meshes)
-    b_alg = (24.0 * N + 16.0 * nflux + 1100.0 * n_s) / N
-    vb = N * steps / (ms_b * 1e-3)
     out = {"workload": f"airy_ensemble_64 ({len(ws)} members, {N} cells)", "steps": steps, "cells": N,
            "interface_cells": n_s, "batched_cell_steps_per_s": vb,
            "plain_cell_steps_per_s": N * steps / (ms_p * 1e-3), "speedup": ms_p / ms_b,
@@ -700,16 +755,25 @@ def main():
     ap.add_argument("--no-gfm", action="store_true", help="skip the ghost-fluid face data timing")
     ap.add_argument("--no-relax", action="store_true", help="skip the relaxation-zone blending timing")
     ap.add_argument("--no-poly", action="store_true", help="skip the tetrahedral and prismatic meshes")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="time only the batched ensemble run (no plain comparison), for its kernel profile")
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write the profiles/ summaries from the rocprofv3 output of PROFILE_COMMANDS")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.workload)
+        if os.path.isdir(os.path.join(ROOT, "gpurun_out/prof_ens")):
+            summarize_ensemble_profile()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the step has no multi-GPU path in this "
               f"build", file=sys.stderr)
         sys.exit(2)
+    if args.ensemble_only:
+        ens = ensemble_bench(args.steps, args.warmup, plain=False)
+        print(json.dumps({"ensemble": ens, "steps": args.steps, "warmup": args.warmup,
+                          "kernel_source_sha": kernel_source_sha()}), flush=True)
+        return
 
     import torch
     from paper_1804_01130_amd import Mesh, Plan
