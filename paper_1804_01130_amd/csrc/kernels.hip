@@ -1155,6 +1155,12 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
     int32_t *mark = A.w.cmark + (size_t)(it & 1) * n;
     int32_t *mark_next = A.w.cmark + (size_t)((it + 1) & 1) * n;
     const int nT = slot[kSlotTouched];
+    if (last) {
+        // no phase A in the last sweep reads the face marks, and the list of marked faces is
+        // complete: clear them here, over the whole grid, rather than in the end kernel
+        const int nF = counters[kCntFaces];
+        for (int i = t0; i < nF; i += stride) A.w.fmark[A.w.flist[i]] = 0;
+    }
     const int nloop = (nT + 255) & ~255;  // whole work-groups iterate together
     for (int i0 = blockIdx.x * blockDim.x; i0 < nloop; i0 += stride) {
         const int i = i0 + threadIdx.x;
@@ -1276,8 +1282,8 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
 }
 
 // End of the step (one work-group): chop the listed cells when no sweep ran, clear the correction
-// buffer of the last sweep and the face marks, keep this step's counters for the statistics and
-// zero them for the next step.
+// buffer of the last sweep (the last sweep itself has cleared the face marks), keep this step's
+// counters for the statistics and zero them for the next step.
 __global__ void __launch_bounds__(1024) k_bound_end(BoundArgs A) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nf = A.m.n_faces;
@@ -1299,8 +1305,10 @@ __global__ void __launch_bounds__(1024) k_bound_end(BoundArgs A) {
         double *delta = delta_buf(A.w, it, nf);
         for (int i = tid; i < nd; i += nt) delta[dl[i]] = 0.0;
     }
-    const int nF = counters[kCntFaces];
-    for (int i = tid; i < nF; i += nt) A.w.fmark[A.w.flist[i]] = 0;
+    if (A.n_iter == 0) {  // (with sweeps, the last one has cleared the face marks)
+        const int nF = counters[kCntFaces];
+        for (int i = tid; i < nF; i += nt) A.w.fmark[A.w.flist[i]] = 0;
+    }
     __syncthreads();
     if (tid < 8) counters[8 + tid] = tid == kCntActive0 ? counters[kCntOff] : counters[tid];
     __syncthreads();
