@@ -208,6 +208,11 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     // tables
     bool words = false;
     for (int32_t i = 0; i < n; ++i) words = words || meshes[i]->dev.slot_nar != nullptr;
+    int2 *spair = nullptr;
+    if (!dev_alloc(u, &spair, (int64_t)W * N)) {
+        iso_batch_destroy(b);
+        return fail(ISO_ENOMEM, "ensemble mesh allocation failed");
+    }
     int32_t *snar = nullptr, *nar_dom = nullptr, *nar_blk = nullptr;
     const int64_t n_blk = (N + 63) / 64;
     if (words && (!dev_alloc(u, &snar, (int64_t)W * N) || !dev_alloc(u, &nar_dom, 3 * (int64_t)n) ||
@@ -301,6 +306,14 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
         ok(hipMemcpy(bf_ptr + NB, &nbf, sizeof(int32_t), hipMemcpyHostToDevice));
         ok(hipMemcpy(bl_ptr + NBF, &nbl, sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    {  // the union's slots cell-major, from its slot tables (filled on the stream above)
+        DevMesh t;
+        t.n_cells = (int32_t)N;
+        t.W = W;
+        t.slot_face = sface;
+        t.slot_nbr = snbr;
+        ok(launch_slot_pairs(t, spair, s));
+    }
     ok(hipMemcpy(dom_off, hoff.data(), hoff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (words) {
         // the record of each 64-cell block (the layout is described with DevMesh::nar_blk)
@@ -327,6 +340,7 @@ iso_status iso_batch_create(const iso_mesh *const *meshes, int32_t n, const iso_
     }
     d.n_cells = (int32_t)N; d.n_faces = (int32_t)F; d.n_classes = (int32_t)K; d.W = W; d.n_patches = (int32_t)P;
     d.cxyz = cxyz; d.cpt = cpt; d.vol = vol; d.slot_face = sface; d.slot_nbr = snbr; d.lface = lface;
+    d.slot_pair = spair;
     d.cflags = cflags; d.st_ptr = st_ptr; d.st_cell = st_cell; d.st_w = st_w; d.patch_alpha = palpha;
     d.ccen = ccen;
     d.cloop = cloop;

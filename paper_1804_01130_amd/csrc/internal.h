@@ -44,6 +44,9 @@ struct DevMesh {
     const double *vol = nullptr;       // [n_cells]
     const int32_t *slot_face = nullptr;  // [W][n_cells] packed flux faces, ascending face id, kEmpty last
     const int32_t *slot_nbr = nullptr;   // [W][n_cells] cell across the face, or -1-patch on the boundary
+    // [n_cells][W] the same two tables cell-major, (slot_face, slot_nbr) per slot: the bounding
+    // sweeps visit scattered cells, and find each one's slots in one run of 8 W bytes
+    const int2 *slot_pair = nullptr;
     // [W][n_cells] the same slots in one 32-bit word each, which the update reads instead (null
     // when more than a tenth of the flux slots do not fit).  Upper half: the neighbour's offset from
     // the cell, positive offsets less one (an offset in [-32768, 32768] other than 0).  Lower half:
@@ -221,6 +224,8 @@ hipError_t launch_step(const DevMesh &m, const DevWork &w, const Params &p, cons
 hipError_t launch_offset_copy(const int32_t *src, int32_t *dst, int64_t n, int mode, int32_t off1, int32_t off2,
                               hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
+// m.slot_pair from m.slot_face and m.slot_nbr (pairs: [n_cells * W] device array)
+hipError_t launch_slot_pairs(const DevMesh &m, int2 *pairs, hipStream_t s);
 // adjoint.hip
 hipError_t launch_adjoint(const DevMesh &m, const Params &p, const StepArgs &a, const AdjInputs &in, const AdjWork &w,
                           hipStream_t s);

@@ -1167,12 +1167,17 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
         bool again = false;
         int32_t Q = 0;
         double x = 0.0;
-        int32_t v[W];
+        int32_t v[W], nb[W];
         // phase B of sweep it
         if (i < nT) {
             Q = touched[i];
+            const int2 *sp = A.m.slot_pair + (size_t)Q * W;
 #pragma unroll
-            for (int k = 0; k < W; ++k) v[k] = A.m.slot_face[(size_t)k * n + Q];
+            for (int k = 0; k < W; ++k) {
+                const int2 q = sp[k];
+                v[k] = q.x;
+                nb[k] = q.y;
+            }
             const double aq = A.alpha_new[Q], vq = A.m.vol[Q];
             double d[W];
 #pragma unroll
@@ -1206,7 +1211,7 @@ __global__ void __launch_bounds__(256) k_bound_sweep(BoundArgs A, int it) {
             double ph[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-                nbr[k] = A.m.slot_nbr[(size_t)k * n + Q];
+                nbr[k] = nb[k];
                 fid[k] = v[k] >= 0 ? v[k] : ~v[k];
                 ph[k] = v[k] != kEmpty ? flux_at<kAvg>(A.phi, A.phi1, fid[k]) : 0.0;
             }
@@ -1402,6 +1407,15 @@ __global__ void k_offset_copy(const int32_t *__restrict__ src, int32_t *__restri
     }
 }
 
+__global__ void k_slot_pairs(DevMesh m, int2 *__restrict__ pairs) {
+    const int n = m.n_cells, W = m.W;
+    const int64_t tot = (int64_t)n * W;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t / W), k = (int)(t % W);
+        pairs[t] = make_int2(m.slot_face[(size_t)k * n + c], m.slot_nbr[(size_t)k * n + c]);
+    }
+}
+
 __global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -1517,6 +1531,14 @@ hipError_t launch_offset_copy(const int32_t *src, int32_t *dst, int64_t n, int m
     if (n <= 0) return hipSuccess;
     const int g = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_offset_copy, dim3(g), dim3(256), 0, s, src, dst, n, mode, off1, off2);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_pairs(const DevMesh &m, int2 *pairs, hipStream_t s) {
+    const int64_t n = (int64_t)m.n_cells * m.W;
+    if (n <= 0) return hipSuccess;
+    const int g = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_slot_pairs, dim3(g), dim3(256), 0, s, m, pairs);
     return hipGetLastError();
 }
 

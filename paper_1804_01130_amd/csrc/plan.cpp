@@ -598,6 +598,13 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         if (n_slots > 0 && n_wide * 10 <= n_slots) m->n_wide_slots = n_wide;
         else slot_nar.clear();
     }
+    // the same slots cell-major, (face, neighbour) per slot (DevMesh::slot_pair)
+    std::vector<int32_t> slot_pair(2 * (size_t)W * n_cells);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int k = 0; k < W; ++k) {
+            slot_pair[2 * ((size_t)c * W + k)] = slot_face[k * (size_t)n_cells + c];
+            slot_pair[2 * ((size_t)c * W + k) + 1] = slot_nbr[k * (size_t)n_cells + c];
+        }
     std::vector<int32_t> lface(6 * (size_t)n_cells, kEmpty);
     for (int32_t c = 0; c < n_cells; ++c)
         for (int k = 0; k < 6; ++k) {
@@ -803,10 +810,12 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
     }
     d.n_internal = n_internal;
     d.nar_S = nar_S;
+    const int32_t *pair_ptr = nullptr;
     iso_status st = ISO_OK;
     if ((st = upload(m, cxyz, &d.cxyz)) || (st = upload(m, cpt, &d.cpt)) || (st = upload(m, m->vol, &d.vol)) ||
         (st = upload(m, slot_face, &d.slot_face)) || (st = upload(m, slot_nbr, &d.slot_nbr)) ||
         (!slot_nar.empty() && (st = upload(m, slot_nar, &d.slot_nar))) ||
+        (st = upload(m, slot_pair, &pair_ptr)) ||
         (st = upload(m, lface, &d.lface)) || (st = upload(m, cflags, &d.cflags)) || (st = upload(m, cnt, &d.st_ptr)) || (st = upload(m, st_cell, &d.st_cell)) ||
         (st = upload(m, st_w, &d.st_w)) || (st = upload(m, m->patch_alpha, &d.patch_alpha)) ||
         (st = upload(m, m->xc, &d.ccen)) || (st = upload(m, fcell, &d.fcell)) || (st = upload(m, bpatch, &d.bpatch)) ||
@@ -819,6 +828,7 @@ iso_status iso_mesh_create(int32_t n_points, const double *px, const double *py,
         iso_mesh_destroy(m);
         return st;
     }
+    d.slot_pair = reinterpret_cast<const int2 *>(pair_ptr);
     *out = m;
     return ISO_OK;
 }
