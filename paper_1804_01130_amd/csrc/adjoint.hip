@@ -346,7 +346,7 @@ __device__ __forceinline__ void adj_correct(const AdjArgs &A, int s, int32_t P, 
     double ph[W], cap[W], dvnow[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        v[k] = m.slot_face[(size_t)k * n + P];
+        v[k] = m.slot_pair[(size_t)P * W + k].x;
         fid[k] = v[k] >= 0 ? v[k] : ~v[k];
         ph[k] = v[k] != kEmpty ? A.phi[fid[k]] : 0.0;
     }
@@ -385,7 +385,7 @@ __device__ __forceinline__ void adj_correct(const AdjArgs &A, int s, int32_t P, 
         delta[fid[k]] = dd;
         w.dvcur[fid[k]] = dvnow[k] + dd;
         w.touched[fid[k]] = 1;
-        const int32_t o = m.slot_nbr[(size_t)k * n + P];
+        const int32_t o = m.slot_pair[(size_t)P * W + k].y;
         if (o >= 0 && atomicExch(&mark[o], 1) == 0) tsel[k] = o;
     }
     double *rec = w.tape + ((size_t)s * n + row) * R;
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(256) k_adj_sweep(AdjArgs A, int s) {
 #pragma unroll
             for (int k = 0; k < W; ++k)
                 if (flags & (kCorrBit << k)) {
-                    const int32_t v = m.slot_face[(size_t)k * n + P];
+                    const int32_t v = m.slot_pair[(size_t)P * W + k].x;
                     stale[v >= 0 ? v : ~v] = 0.0;
                 }
         }
@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(256) k_adj_sweep(AdjArgs A, int s) {
             double sum = 0.0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-                const int32_t vq = m.slot_face[(size_t)k * n + Q];
+                const int32_t vq = m.slot_pair[(size_t)Q * W + k].x;
                 if (vq == kEmpty) continue;
                 const double d = delta[vq >= 0 ? vq : ~vq];
                 sum += vq >= 0 ? d : -d;
@@ -577,8 +577,8 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_apply(AdjArgs A, int s) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             if (!(flags & (kCorrBit << k))) continue;
-            const int32_t v = m.slot_face[(size_t)k * n + P];
-            const int32_t o = m.slot_nbr[(size_t)k * n + P];
+            const int2 q = m.slot_pair[(size_t)P * W + k];
+            const int32_t v = q.x, o = q.y;
             const int32_t f = v >= 0 ? v : ~v;
             const double sP = v >= 0 ? 1.0 : -1.0;
             double db = 0.0;
@@ -623,7 +623,7 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
             capb[k] = 0.0;
             dvnb[k] = 0.0;
             if (!(flags & (kCorrBit << k))) continue;
-            const int32_t v = m.slot_face[(size_t)k * n + P];
+            const int32_t v = m.slot_pair[(size_t)P * W + k].x;
             const int32_t f = v >= 0 ? v : ~v;
             const double s_ = v >= 0 ? 1.0 : -1.0;
             const double ddb = w.deltabar[f] + w.dvcurbar[f];
@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(256) k_adj_unsweep_correct(AdjArgs A, int s) {
         for (int k = 0; k < W; ++k) {
             const double capk = rec[4 + k];
             if (!(capk > 0.0) || !(flags & 4)) continue;
-            const int32_t v = m.slot_face[(size_t)k * n + P];
+            const int32_t v = m.slot_pair[(size_t)P * W + k].x;
             const int32_t f = v >= 0 ? v : ~v;
             const double s_ = v >= 0 ? 1.0 : -1.0;
             const double cb = capb[k] + sumcapb;
