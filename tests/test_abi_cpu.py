@@ -24,6 +24,20 @@ def test_status_strings_and_defaults():
     o = B.default_options()
     assert o.eps_surf == 1e-8 and o.n_bound_iter == 3 and o.clip == 1 and o.root_max_iter == 100
     assert o.us_mode == 0  # U_S = U_P unless cell-point interpolation is asked for
+    assert o.root_tol == 0.0 and o.full_slots == 0  # round-off search; the update's slot words
+    # the binding's structure ends where the header's does: its size is what the library fills
+    assert C.sizeof(B.IsoOptions) == 88  # sizeof(iso_options) from the C compiler, padding included
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
 
 
 def _create(m, **over):
