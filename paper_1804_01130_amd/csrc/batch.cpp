@@ -48,7 +48,8 @@ namespace {
 
 bool same_cfg(const LaunchCfg &a, const LaunchCfg &b) {
     return a.block_cells == b.block_cells && a.surface_blocks == b.surface_blocks &&
-           a.surface_waves == b.surface_waves && a.bound_blocks == b.bound_blocks;
+           a.surface_waves == b.surface_waves && a.bound_blocks == b.bound_blocks &&
+           a.compact_slots == b.compact_slots;
 }
 
 void drop_graph(iso_batch *b) {
@@ -451,7 +452,12 @@ iso_status iso_batch_set_config(iso_batch *b, const int32_t *cfg) {
     if (cfg[0] < 1 || cfg[0] > 1024 || cfg[1] < 0 || cfg[1] > 65535 || cfg[2] < 1 || cfg[2] > 4 || cfg[3] < 1 ||
         cfg[3] > 65535)
         return fail(ISO_EINVAL, "launch shape out of range");
-    b->cfg = LaunchCfg{cfg[0], cfg[1], cfg[2], cfg[3]};
+    LaunchCfg c = b->cfg;  // the launch shapes only: the options' choices (slot words) stay
+    c.block_cells = cfg[0];
+    c.surface_blocks = cfg[1];
+    c.surface_waves = cfg[2];
+    c.bound_blocks = cfg[3];
+    b->cfg = c;
     return ISO_OK;
 }
 
