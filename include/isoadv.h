@@ -171,6 +171,20 @@ void iso_plan_destroy(iso_plan *plan);
  * not overlap alpha, phi or U.  stats (host, nullable): filled after a device sync. */
 iso_status iso_advect_step(iso_plan *plan, const double *alpha, const double *phi, const double *U, double dt,
                            double *alpha_new, iso_step_stats *stats);
+
+/* n_steps advection steps in place (Section 3.2, repeated), for callers that advance one mesh
+ * many steps: alpha [n_cells] (device) holds the state before and after.  Step k reads
+ * phi + k*phi_stride [n_faces] and U + k*U_stride [3*n_cells] (strides in elements: 0 = the same
+ * fields every step, else at least one step's fields).  Bit for bit n_steps calls of
+ * iso_advect_step.  A run of up to 256 steps is captured once as a HIP graph and replayed while
+ * alpha, the fields, the strides, dt and n_steps stay the same (one call, and a graph a caller's
+ * own capture can hold; on the 3D workload as fast as separate steps, not faster); it runs on a
+ * stream of the plan's own, ordered after the work before it on the plan's stream and before the
+ * work after it.  The first run allocates a
+ * second state buffer of n_cells doubles, held until the plan is destroyed.  Not with check_inputs
+ * (ISO_EINVAL) or a limited max_surface (ISO_EUNSUPPORTED); alpha must not overlap the fields. */
+iso_status iso_plan_run(iso_plan *plan, double *alpha, const double *phi, int64_t phi_stride, const double *U,
+                        int64_t U_stride, double dt, int32_t n_steps);
 /* Same step, also writing the intermediates named in trace (device pointers). */
 iso_status iso_advect_step_traced(iso_plan *plan, const double *alpha, const double *phi, const double *U,
                                   double dt, double *alpha_new, iso_step_stats *stats, const iso_trace *trace);

@@ -98,6 +98,8 @@ def lib():
         L.iso_plan_destroy.restype = None
         L.iso_advect_step.argtypes = [_vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats)]
         L.iso_advect_step.restype = C.c_int
+        L.iso_plan_run.argtypes = [_vp, _vp, _vp, C.c_int64, _vp, C.c_int64, C.c_double, C.c_int32]
+        L.iso_plan_run.restype = C.c_int
         L.iso_advect_step_traced.argtypes = [_vp, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(IsoStepStats),
                                              C.POINTER(IsoTrace)]
         L.iso_advect_step_traced.restype = C.c_int
@@ -304,6 +306,24 @@ class Plan:
 
     def set_stream(self, stream):
         check(lib().iso_plan_set_stream(self.h, _stream_handle(stream)))
+
+    def run(self, alpha, phi, U, dt, n_steps, phi_stride=0, U_stride=0):
+        """In place: alpha (device, float64 [n_cells]) after n_steps steps (iso_plan_run, replayed as a
+        captured graph while its arguments stay the same).  phi/U: one step's fields (strides 0) or
+        n_steps of them at the given element strides."""
+        import torch
+        m = self.mesh
+        last = max(int(n_steps) - 1, 0)
+        for t, name in ((phi, "phi"), (U, "U")):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+                raise ValueError(f"{name}: expected a float64 torch tensor")
+        if phi.numel() < m.n_faces + last * int(phi_stride):
+            raise ValueError(f"phi: expected at least {m.n_faces + last * int(phi_stride)} elements")
+        if U.numel() < 3 * m.n_cells + last * int(U_stride):
+            raise ValueError(f"U: expected at least {3 * m.n_cells + last * int(U_stride)} elements")
+        check(lib().iso_plan_run(self.h, _ptr(alpha, m.n_cells, name="alpha"), _ptr(phi, name="phi"),
+                                 int(phi_stride), _ptr(U, name="U"), int(U_stride), float(dt), int(n_steps)))
+        return alpha
 
     def step(self, alpha, phi, U, dt, out=None, stats=False, trace=None, phi1=None, U1=None):
         """alpha_new = isoAdvector step (device tensors, float64).  Returns (alpha_new, stats dict or None).

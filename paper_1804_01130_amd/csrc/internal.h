@@ -307,6 +307,22 @@ struct iso_plan {
     int32_t *rz_cell = nullptr;
     double *rz_w = nullptr;
     int64_t rz_n = 0;
+    // multi-step runs (iso_plan_run): the second state buffer (allocated on the first run), the
+    // run's own stream with the events that order it after and before the plan's stream, and the
+    // captured graph of the last run with the arguments it was captured for
+    double *run_tmp = nullptr;
+    hipStream_t run_stream = nullptr;
+    hipEvent_t run_in = nullptr, run_out = nullptr;
+    hipGraph_t run_graph = nullptr;
+    hipGraphExec_t run_exec = nullptr;
+    struct RunKey {
+        double *alpha = nullptr;
+        const double *phi = nullptr, *U = nullptr;
+        int64_t ps = 0, us = 0;
+        double dt = 0.0;
+        int32_t steps = 0;
+    } run_key;
+    bool run_have = false;
 };
 
 namespace isoadv {

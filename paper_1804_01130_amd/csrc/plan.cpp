@@ -863,6 +863,12 @@ void iso_plan_destroy(iso_plan *p) {
     if (p->work.fork) (void)hipEventDestroy(p->work.fork);
     if (p->work.join) (void)hipEventDestroy(p->work.join);
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    if (p->run_stream) (void)hipStreamSynchronize(p->run_stream);
+    if (p->run_exec) (void)hipGraphExecDestroy(p->run_exec);
+    if (p->run_graph) (void)hipGraphDestroy(p->run_graph);
+    if (p->run_in) (void)hipEventDestroy(p->run_in);
+    if (p->run_out) (void)hipEventDestroy(p->run_out);
+    if (p->run_stream) (void)hipStreamDestroy(p->run_stream);
     for (void *a : p->allocations) (void)hipFree(a);
     if (p->rz_cell) (void)hipFree(p->rz_cell);
     if (p->rz_w) (void)hipFree(p->rz_w);
@@ -1006,6 +1012,91 @@ static iso_status step_impl(iso_plan *p, const double *alpha, const double *phi,
 iso_status iso_advect_step(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt,
                            double *alpha_new, iso_step_stats *stats) {
     return step_impl(p, alpha, phi, U, dt, alpha_new, stats, nullptr);
+}
+
+namespace {
+constexpr int32_t kMaxRunGraphSteps = 256;  // longer runs are launched step by step
+
+hipError_t enqueue_run(iso_plan *p, double *alpha, const double *phi, int64_t ps, const double *U, int64_t us,
+                       double dt, int32_t n_steps) {
+    const iso_mesh *m = p->mesh;
+    const Params prm = step_params(p->opt);
+    const LaunchCfg cfg = launch_cfg(p->opt);
+    hipError_t e = hipSuccess;
+    for (int32_t n = 0; n < n_steps && e == hipSuccess; ++n) {
+        const double *in = (n & 1) ? p->run_tmp : alpha;
+        double *out = (n & 1) ? alpha : p->run_tmp;
+        StepArgs args{in, phi + (size_t)n * ps, U + (size_t)n * us, out, dt, nullptr, nullptr, nullptr};
+        e = launch_step(m->dev, p->work, prm, args, nullptr, cfg, false, p->run_stream, nullptr);
+    }
+    if (e == hipSuccess && (n_steps & 1)) e = launch_copy_f64(p->run_tmp, alpha, m->n_cells, p->run_stream);
+    return e;
+}
+}  // namespace
+
+iso_status iso_plan_run(iso_plan *p, double *alpha, const double *phi, int64_t phi_stride, const double *U,
+                        int64_t U_stride, double dt, int32_t n_steps) {
+    if (!p) return fail(ISO_EINVAL, "null plan");
+    if (!alpha || !phi || !U) return fail(ISO_EINVAL, "null array");
+    if (n_steps < 0) return fail(ISO_EINVAL, "negative step count");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(ISO_EINVAL, "dt must be positive and finite");
+    const iso_mesh *m = p->mesh;
+    const int64_t N = m->n_cells, F = m->n_faces;
+    if ((phi_stride != 0 && phi_stride < F) || (U_stride != 0 && U_stride < 3 * N) || phi_stride < 0 || U_stride < 0)
+        return fail(ISO_EINVAL, "field strides must be 0 or at least one step's fields");
+    if (p->opt.check_inputs) return fail(ISO_EINVAL, "check_inputs copies the inputs to the host: not on a run");
+    if (p->work.cap < N)
+        return fail(ISO_EUNSUPPORTED, "a run needs the interface-cell list at full capacity (max_surface 0)");
+    if (n_steps == 0) return ISO_OK;
+    if (overlaps(alpha, (size_t)N * 8, phi, ((size_t)(n_steps - 1) * phi_stride + F) * 8) ||
+        overlaps(alpha, (size_t)N * 8, U, ((size_t)(n_steps - 1) * U_stride + 3 * N) * 8))
+        return fail(ISO_EINVAL, "alpha overlaps the fields");
+    if (!p->run_stream) {
+        if (hipStreamCreateWithFlags(&p->run_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->run_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->run_out, hipEventDisableTiming) != hipSuccess)
+            return fail(ISO_EDEVICE, "stream or event creation failed");
+    }
+    if (!p->run_tmp) {
+        void *t = nullptr;
+        if (hipMalloc(&t, (size_t)N * sizeof(double)) != hipSuccess) return fail(ISO_ENOMEM, "hipMalloc failed");
+        p->allocations.push_back(t);
+        p->run_tmp = static_cast<double *>(t);
+    }
+    (void)hipGetLastError();
+    // order after the caller's work on the plan's stream
+    hipError_t e = hipEventRecord(p->run_in, p->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->run_stream, p->run_in, 0);
+    if (e != hipSuccess) return fail(ISO_EDEVICE, "stream ordering failed");
+    if (n_steps > kMaxRunGraphSteps) {
+        e = enqueue_run(p, alpha, phi, phi_stride, U, U_stride, dt, n_steps);
+    } else {
+        const iso_plan::RunKey &k = p->run_key;
+        const bool hit = p->run_have && k.alpha == alpha && k.phi == phi && k.U == U && k.ps == phi_stride &&
+                         k.us == U_stride && k.dt == dt && k.steps == n_steps;
+        if (!hit) {
+            if (p->run_exec) (void)hipGraphExecDestroy(p->run_exec);
+            if (p->run_graph) (void)hipGraphDestroy(p->run_graph);
+            p->run_exec = nullptr;
+            p->run_graph = nullptr;
+            p->run_have = false;
+            e = hipStreamBeginCapture(p->run_stream, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                const hipError_t el = enqueue_run(p, alpha, phi, phi_stride, U, U_stride, dt, n_steps);
+                e = hipStreamEndCapture(p->run_stream, &p->run_graph);
+                if (el != hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&p->run_exec, p->run_graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+            p->run_key = iso_plan::RunKey{alpha, phi, U, phi_stride, U_stride, dt, n_steps};
+            p->run_have = true;
+        }
+        e = hipGraphLaunch(p->run_exec, p->run_stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(p->run_out, p->run_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->run_out, 0);
+    if (e != hipSuccess) return fail(ISO_EDEVICE, std::string("run failed: ") + hipGetErrorString(e));
+    return ISO_OK;
 }
 
 iso_status iso_advect_step_traced(iso_plan *p, const double *alpha, const double *phi, const double *U, double dt,
