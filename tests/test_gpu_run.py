@@ -68,6 +68,24 @@ def test_run_with_per_step_fields():
     plan.close()
 
 
+def test_long_run_is_launched_step_by_step():
+    """More than 256 steps are not captured: the run launches them one by one, with the same bits."""
+    import torch
+    steps = 300
+    w = W.cosine_uniform(nx=32, ny=16, steps=steps)
+    say(f"[gpu] run of {steps} steps (no capture): {w.name}")
+    gm, plan = gpu_plan(w.mesh)
+    phi, U = (to_dev(x) for x in w.phi_U(0))
+    a0 = to_dev(w.alpha0)
+    ref = _single_steps(plan, a0, w.dt, steps, lambda n: (phi, U))
+    a = a0.clone()
+    plan.run(a, phi, U, w.dt, steps)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), ref)
+    assert not np.array_equal(ref, w.alpha0)
+    plan.close()
+
+
 def test_run_argument_errors():
     import torch
     from paper_1804_01130_amd import IsoError
